@@ -1,0 +1,263 @@
+/*
+ * rve.h -- C ABI of the MI355X variational FFT homogenization library.
+ *
+ * The library solves, increment by increment, the periodic boundary-value
+ * problem of a representative volume element (RVE) stated in Lucarini &
+ * Segurado, "On the accuracy of spectral solvers for micromechanics based
+ * fatigue modeling" (arXiv:1806.10599):
+ *
+ *   Sec. 2.1, Eq. 1     Div P = 0,  F = Fbar + Ftilde,  <F> = Fbar, Ftilde periodic
+ *   Sec. 2.1, Eq. 2     P = P(F, alpha) at every voxel (internal variables alpha)
+ *   Sec. 2.1, Eqs. 9-11 discrete equilibrium G(P) = F^-1{ Ghat : F(P) } = 0
+ *   Sec. 2.1, Eqs.12-16 Newton iterations; each linear step G(K:dF) = -G(P) is
+ *                       solved with conjugate gradients (text after Eq. 16)
+ *   Sec. 2.2, Eqs.18-21 continuous (Eq. 19) or discrete (Eq. 21) projection
+ *   Sec. 3.2, Eq. 22    crystal-plasticity flow rule of the grains
+ *   Sec. 3.3, Eqs.23-24 fatigue indicator fields accumulated per cycle
+ *
+ * Conventions (all entry points):
+ *   - Every function returns rve_status (0 = RVE_OK, < 0 = error).  No C++
+ *     exception crosses the ABI.  On error, rve_last_error(h) describes it.
+ *   - Grid: n[0] x n[1] x n[2] voxels (the GPU path requires a cubic grid,
+ *     n in {16, 24, 32, 40, 48, 64, 96, 128}); cell size L[3].
+ *   - Voxel (a, b, c) has flat index v = (a*n1 + b)*n2 + c (z fastest).
+ *   - Second-order tensor fields are SoA: component c = 3*i + j (row-major
+ *     3x3), stored as [9][N] doubles; c-th component of voxel v at c*N + v.
+ *   - Units: stresses and moduli in MPa, time in s.
+ *   - Pointers: host pointers unless an argument says otherwise.  The caller
+ *     owns all inputs and outputs; the library copies inputs during the call
+ *     and owns all device state, allocated through rve_config.dev_alloc (or
+ *     hipMalloc when NULL) and released by rve_destroy.
+ *   - Work is ordered on rve_config.stream.  Calls that return host results
+ *     synchronize that stream before returning.
+ *   - A HIP runtime error poisons the handle (RVE_EDEVICE); only
+ *     rve_last_error and rve_destroy are valid afterwards.
+ *   - One handle per host thread at a time; handles are independent.
+ */
+#ifndef RVE_H
+#define RVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rve_s* rve_t;
+
+typedef enum {
+  RVE_OK = 0,
+  RVE_EINVAL = -1,   /* bad argument; nothing was changed                   */
+  RVE_ENOMEM = -2,   /* device allocation failed                            */
+  RVE_EDEVICE = -3,  /* HIP runtime error; handle is poisoned               */
+  RVE_ENOTCONV = -4, /* Newton did not converge; committed state unchanged  */
+  RVE_ELOCAL = -5,   /* a voxel's return mapping failed; state unchanged    */
+  RVE_ESTATE = -6    /* call not valid in the current state                 */
+} rve_status;
+
+/* Device allocator hooks (e.g. a framework's caching allocator). */
+typedef void* (*rve_alloc_fn)(size_t bytes, void* stream, void* ctx);
+typedef void (*rve_free_fn)(void* ptr, void* ctx);
+
+enum { RVE_PROJ_CONTINUOUS = 0,   /* Ghat  of Sec. 2.2, Eq. 19 */
+       RVE_PROJ_DISCRETE = 1 };   /* Ghat' of Sec. 2.2, Eq. 21 */
+enum { RVE_PREC_FP64 = 0,         /* every pass in FP64                      */
+       RVE_PREC_MIXED = 1 };      /* FFT/projection/CG in FP32; return
+                                     mapping, residual, averages in FP64     */
+
+typedef struct {
+  int32_t n[3];          /* voxels per axis                                  */
+  double L[3];           /* cell edge lengths (only ratios matter)           */
+  int32_t projection;    /* RVE_PROJ_*                                       */
+  int32_t precision;     /* RVE_PREC_*                                       */
+  int32_t warm_start;    /* 0 = homogeneous predictor, 1 = learned (needs a
+                            network loaded with rve_ws_load)                  */
+  int32_t use_graph;     /* 1 = replay CG chunks from a captured hipGraph    */
+  double newton_tol;     /* equilibrium: ||G(P)||_2 <= tol ||P||_2 (FP64)     */
+  int32_t newton_max_iter;
+  double cg_tol;         /* CG stop: ||r||_2 <= cg_tol ||b||_2               */
+  int32_t cg_max_iter;
+  int32_t cg_chunk;      /* CG iterations between host convergence checks    */
+  void* stream;          /* hipStream_t; NULL = default stream               */
+  rve_alloc_fn dev_alloc;
+  rve_free_fn dev_free;
+  void* alloc_ctx;
+} rve_config;
+
+#define RVE_MAX_NEWTON_LOG 64
+
+typedef struct {
+  int32_t newton_iters;      /* Newton corrections performed                  */
+  int32_t cg_iters_total;    /* CG matvecs over the increment                 */
+  int32_t local_failures;    /* voxels whose return mapping failed            */
+  int32_t used_learned;      /* 1 if the learned warm start was accepted      */
+  int32_t cg_breakdowns;     /* CG solves stopped by p.Ap <= 0                 */
+  int32_t status;            /* rve_status of the increment                   */
+  double residual_rel;       /* final ||G(P)||/||P||                          */
+  double predictor_residual; /* ||G(P)||/||P|| of the accepted predictor     */
+  double plain_predictor_residual; /* same for the homogeneous predictor     */
+  double P_bar[9];           /* <P>, row-major                                */
+  double sigma_bar[9];       /* P_bar Fbar^T / det Fbar                       */
+  double residual_history[RVE_MAX_NEWTON_LOG];
+  int32_t cg_iters[RVE_MAX_NEWTON_LOG];
+  double seconds;            /* wall time of the call                          */
+} rve_increment_info;
+
+/* Fills *cfg with defaults: 16^3 cube of edge 1, discrete operator, FP64,
+   homogeneous predictor, tol 1e-6, 25 Newton, cg_tol 1e-4, 2000 CG,
+   chunk 8, default stream, hipMalloc. */
+rve_status rve_config_default(rve_config* cfg);
+
+/* Creates a handle and allocates all device buffers for the grid.
+   Errors: RVE_EINVAL (unsupported grid or options), RVE_ENOMEM, RVE_EDEVICE. */
+rve_status rve_create(const rve_config* cfg, rve_t* out);
+
+/* Releases every device buffer; NULL-safe.  Synchronizes the stream. */
+rve_status rve_destroy(rve_t h);
+
+/* Parameter block layout (params[nparams], nparams >= 10), MPa and s:
+     0 C11, 1 C12, 2 C44          cubic elastic constants of the grains
+     3 gdot0, 4 g, 5 n            flow rule of Eq. 22: gdot0 |(tau-chi)/g|^n
+     6 c, 7 d                     back stress: chi = (chi0 + c dg)/(1 + d|dg|)
+     8 E, 9 nu                    isotropic St-Venant-Kirchhoff second phase
+*/
+#define RVE_NPARAMS 10
+
+/* Microstructure (Sec. 2.1 text before Eq. 6; Sec. 3.1): phase[N] labels in
+   [0, G); quat[G*4] unit quaternions (w, x, y, z) rotating lattice to sample
+   frame; law[G] 0 = FCC crystal plasticity, 1 = isotropic SVK.  Resets the
+   state to F = I, Fp^-1 = I, chi = 0, indicator fields = 0, t = 0.
+   Errors: RVE_EINVAL for labels out of range, non-unit quaternions, unknown
+   laws or nparams < RVE_NPARAMS (state untouched). */
+rve_status rve_set_microstructure(rve_t h, const int32_t* phase, int32_t G,
+                                  const double* quat, const int32_t* law,
+                                  const double* params, int32_t nparams);
+
+/* One load increment to the macroscopic gradient F_bar_new[9] (row-major)
+   over the time step dt (Sec. 2.1, Eqs. 12-16 and the end of Sec. 2.1).
+   Predictor F = F_prev + (F_bar_new - F_bar_prev) (plus the projected
+   learned correction when enabled); Newton-CG to newton_tol; on success the
+   internal variables and fatigue indicators are committed.  On
+   RVE_ENOTCONV / RVE_ELOCAL nothing is committed.  info may be NULL. */
+rve_status rve_apply_macro_strain_increment(rve_t h, const double F_bar_new[9],
+                                            double dt,
+                                            rve_increment_info* info);
+
+/* Zeroes the per-cycle indicator accumulators (call at each cycle start). */
+rve_status rve_reset_fips(rve_t h);
+
+enum {
+  RVE_FIELD_F = 0,         /* [9][N] committed deformation gradient          */
+  RVE_FIELD_P = 1,         /* [9][N] first Piola-Kirchhoff stress             */
+  RVE_FIELD_SIGMA = 2,     /* [9][N] Cauchy stress P F^T / det F              */
+  RVE_FIELD_FPINV = 3,     /* [9][N] inverse plastic deformation gradient    */
+  RVE_FIELD_CHI = 4,       /* [12][N] back stresses (MPa)                     */
+  RVE_FIELD_DGAMMA = 5,    /* [12][N] slip increments of the last increment  */
+  RVE_FIELD_PCYC = 6,      /* [N] accumulated plastic slip, sum sqrt(2/3 dLp:dLp) */
+  RVE_FIELD_PCYC_LIT = 7,  /* [N] sum dLp:dLp / dt (Eq. 23 integrand)         */
+  RVE_FIELD_WCYC = 8,      /* [12][N] plastic work per system (Eq. 24), MPa   */
+  RVE_FIELD_COUNT = 9
+};
+
+/* Copies one committed field (float64, layout above) into dst (host, or
+   device memory when dst_on_device != 0).  dst_bytes must be at least the
+   field size.  Errors: RVE_EINVAL. */
+rve_status rve_get_fields(rve_t h, int32_t field, void* dst, size_t dst_bytes,
+                          int32_t dst_on_device);
+
+/* Macro state: F_bar (9), P_bar (9), sigma_bar (9), t, increments. */
+rve_status rve_get_macro(rve_t h, double out[29]);
+
+/* Checkpoint: the committed state (F, Fp^-1, chi, dgamma, indicators, macro
+   state, counters) as an opaque little-endian blob.  rve_state_size gives
+   the byte count; rve_set_state restores a blob from the same grid. */
+rve_status rve_state_size(rve_t h, size_t* bytes);
+rve_status rve_get_state(rve_t h, void* dst, size_t bytes);
+rve_status rve_set_state(rve_t h, const void* src, size_t bytes);
+
+const char* rve_last_error(rve_t h);
+
+/* ---- test hooks (same conventions) ---------------------------------------
+   rve_debug_apply_G: out = G(in) (Sec. 2.1, Eq. 11) for a [9][N] float64
+   field, in the given precision (RVE_PREC_FP64: FP64 passes; RVE_PREC_MIXED:
+   input rounded to FP32, FP32 passes, output widened).  Host pointers.
+   rve_debug_constitutive: evaluates the point law (Sec. 2.1, Eq. 2; Eq. 13
+   tangent) at F[9][N] with the committed internal variables and time step dt,
+   writing P[9][N], K[81][N] (component 9*(3i+j) + (3k+l) = dP_ij/dF_kl) and
+   the trial slips dg[12][N]; returns the failed-voxel count in *fails.
+   rve_debug_set_field: overwrites one committed field (F, FPINV or CHI) from
+   host memory, e.g. to inject a failure. */
+rve_status rve_debug_apply_G(rve_t h, const double* in, double* out,
+                             int32_t precision);
+rve_status rve_debug_constitutive(rve_t h, const double* F, double dt,
+                                  double* P, double* K, double* dg,
+                                  int32_t* fails);
+rve_status rve_debug_set_field(rve_t h, int32_t field, const double* src,
+                               size_t bytes);
+
+/* rve_bench_kernels: average duration in milliseconds of each hot-path
+   kernel over `reps` launches, timed with HIP events on the handle's
+   stream, using the launch configuration and buffers of the last increment
+   (needs at least one committed increment).  ms_out[count], count <= 8:
+   0 matvec pass A (K:p and the forward z/y FFTs), 1 pass B (x FFTs and the
+   projection of Sec. 2.2), 2 pass C (inverse y/z FFTs and p.Ap), 3 CG vector
+   update, 4 FP64 return mapping (Sec. 3.2, Eq. 22), 5 tangent (Eq. 13),
+   6 FP64 residual G(P) (Eq. 11).  Only scratch buffers are written; the
+   committed state is untouched. */
+rve_status rve_bench_kernels(rve_t h, int32_t reps, double* ms_out,
+                             int32_t count);
+
+/* ---- learned warm start -------------------------------------------------
+   A small network predicts the fluctuation increment of the next load
+   increment from the committed state, so that the Newton iteration of
+   Sec. 2.1 (Eqs. 12-16) starts nearer to equilibrium.  Its prediction is
+   projected by G (Sec. 2.1, Eq. 11) and kept only when its FP64
+   equilibrium residual is smaller than the homogeneous predictor's; Newton
+   then runs to the same tolerance either way.
+   Architecture: four 3x3x3 convolutions with periodic padding, 40 -> 32 ->
+   32 -> 32 -> 9 channels, ReLU after the first three; bf16 weights and
+   activations, FP32 accumulation on the matrix cores.  Grids need n % 16 == 0.
+   Parameters (float32, host order): for each layer W[27][cin][cout] (tap
+   t = (dx+1)*9 + (dy+1)*3 + (dz+1)) followed by b[cout].
+   Device buffers (caller-owned, dst/src on the device):
+     features  uint16 bf16 [N][48]  (channel list in the design notes)
+     targets   float [N][16] (first 9: fluctuation increment / |dFbar|)
+     outputs   float [N][16]
+   rve_ws_train_step: one Adam step (lr, betas 0.9/0.999, eps 1e-8) on the
+   mean squared error over the 9 real output channels of one sample; *loss
+   receives the loss before the step; grad_host (nullable) the FP32
+   gradient in parameter order.
+   rve_attach_warm_start: the handle uses the network when its config has
+   warm_start = 1 (pass NULL to detach; detach before destroying the
+   network).  rve_ws_features: input of the increment to F_bar_new from the
+   committed state.  rve_ws_target: target of the last committed increment.
+   Errors: RVE_EINVAL (bad sizes, n % 16 != 0), RVE_ESTATE (no increment
+   yet for rve_ws_target), RVE_ENOMEM. */
+typedef struct rve_ws_s* rve_ws_t;
+typedef struct {
+  void* stream;          /* hipStream_t used by training and rve_ws_forward */
+  rve_alloc_fn dev_alloc;
+  rve_free_fn dev_free;
+  void* alloc_ctx;
+} rve_ws_config;
+
+rve_status rve_ws_create(const rve_ws_config* cfg, rve_ws_t* out);
+rve_status rve_ws_destroy(rve_ws_t w);
+rve_status rve_ws_param_count(rve_ws_t w, int64_t* count);
+rve_status rve_ws_set_params(rve_ws_t w, const float* params, int64_t count);
+rve_status rve_ws_get_params(rve_ws_t w, float* params, int64_t count);
+rve_status rve_ws_forward(rve_ws_t w, const uint16_t* X, int32_t n, float* Y);
+rve_status rve_ws_train_step(rve_ws_t w, const uint16_t* X, const float* T,
+                             int32_t n, float lr, double* loss,
+                             float* grad_host);
+const char* rve_ws_last_error(rve_ws_t w);
+rve_status rve_attach_warm_start(rve_t h, rve_ws_t w);
+rve_status rve_ws_features(rve_t h, const double F_bar_new[9], uint16_t* X);
+rve_status rve_ws_target(rve_t h, float* T);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RVE_H */

@@ -1,0 +1,423 @@
+"""ctypes binding of the C ABI in include/rve.h (argument marshalling only).
+
+Every step of the solver runs in the HIP library; this module only converts
+Python/NumPy arguments to the C structs and pointers.  PyTorch provides the
+device memory (its caching allocator, through the ABI's allocator hooks) and
+the HIP stream.  Importing fails loudly when the built library is missing:
+there is no CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(_HERE, "libpaper_1806_10599_amd.so")
+
+RVE_OK, RVE_EINVAL, RVE_ENOMEM, RVE_EDEVICE = 0, -1, -2, -3
+RVE_ENOTCONV, RVE_ELOCAL, RVE_ESTATE = -4, -5, -6
+STATUS_NAMES = {0: "RVE_OK", -1: "RVE_EINVAL", -2: "RVE_ENOMEM",
+                -3: "RVE_EDEVICE", -4: "RVE_ENOTCONV", -5: "RVE_ELOCAL",
+                -6: "RVE_ESTATE"}
+PROJ = {"continuous": 0, "discrete": 1}
+PREC = {"fp64": 0, "mixed": 1}
+FIELDS = {"F": (0, 9), "P": (1, 9), "sigma": (2, 9), "Fpinv": (3, 9),
+          "chi": (4, 12), "dgamma": (5, 12), "pcyc": (6, 1),
+          "pcyc_lit": (7, 1), "wcyc": (8, 12)}
+NPARAMS = 10
+MAX_NEWTON_LOG = 64
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class RveConfig(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("L", C.c_double * 3),
+                ("projection", C.c_int32), ("precision", C.c_int32),
+                ("warm_start", C.c_int32), ("use_graph", C.c_int32),
+                ("newton_tol", C.c_double), ("newton_max_iter", C.c_int32),
+                ("cg_tol", C.c_double), ("cg_max_iter", C.c_int32),
+                ("cg_chunk", C.c_int32), ("stream", C.c_void_p),
+                ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
+                ("alloc_ctx", C.c_void_p)]
+
+
+class RveIncrementInfo(C.Structure):
+    _fields_ = [("newton_iters", C.c_int32), ("cg_iters_total", C.c_int32),
+                ("local_failures", C.c_int32), ("used_learned", C.c_int32),
+                ("cg_breakdowns", C.c_int32), ("status", C.c_int32),
+                ("residual_rel", C.c_double),
+                ("predictor_residual", C.c_double),
+                ("plain_predictor_residual", C.c_double),
+                ("P_bar", C.c_double * 9), ("sigma_bar", C.c_double * 9),
+                ("residual_history", C.c_double * MAX_NEWTON_LOG),
+                ("cg_iters", C.c_int32 * MAX_NEWTON_LOG),
+                ("seconds", C.c_double)]
+
+
+class RveWsConfig(C.Structure):
+    _fields_ = [("stream", C.c_void_p), ("dev_alloc", ALLOC_FN),
+                ("dev_free", FREE_FN), ("alloc_ctx", C.c_void_p)]
+
+
+def _load():
+    if not os.path.exists(LIBPATH):
+        raise ImportError(
+            f"{LIBPATH} is missing: build it with "
+            "`python -m paper_1806_10599_amd.build` (there is no CPU fallback)")
+    lib = C.CDLL(LIBPATH)
+    P = C.POINTER
+    sig = {
+        "rve_config_default": (C.c_int, [P(RveConfig)]),
+        "rve_create": (C.c_int, [P(RveConfig), P(C.c_void_p)]),
+        "rve_destroy": (C.c_int, [C.c_void_p]),
+        "rve_set_microstructure": (C.c_int, [C.c_void_p, P(C.c_int32),
+                                             C.c_int32, P(C.c_double),
+                                             P(C.c_int32), P(C.c_double),
+                                             C.c_int32]),
+        "rve_apply_macro_strain_increment": (
+            C.c_int, [C.c_void_p, P(C.c_double), C.c_double,
+                      P(RveIncrementInfo)]),
+        "rve_reset_fips": (C.c_int, [C.c_void_p]),
+        "rve_get_fields": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p,
+                                     C.c_size_t, C.c_int32]),
+        "rve_get_macro": (C.c_int, [C.c_void_p, P(C.c_double)]),
+        "rve_state_size": (C.c_int, [C.c_void_p, P(C.c_size_t)]),
+        "rve_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
+        "rve_set_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
+        "rve_last_error": (C.c_char_p, [C.c_void_p]),
+        "rve_debug_apply_G": (C.c_int, [C.c_void_p, P(C.c_double),
+                                        P(C.c_double), C.c_int32]),
+        "rve_debug_constitutive": (C.c_int, [C.c_void_p, P(C.c_double),
+                                             C.c_double, P(C.c_double),
+                                             P(C.c_double), P(C.c_double),
+                                             P(C.c_int32)]),
+        "rve_debug_set_field": (C.c_int, [C.c_void_p, C.c_int32,
+                                          P(C.c_double), C.c_size_t]),
+        "rve_bench_kernels": (C.c_int, [C.c_void_p, C.c_int32,
+                                        P(C.c_double), C.c_int32]),
+        "rve_ws_create": (C.c_int, [P(RveWsConfig), P(C.c_void_p)]),
+        "rve_ws_destroy": (C.c_int, [C.c_void_p]),
+        "rve_ws_param_count": (C.c_int, [C.c_void_p, P(C.c_int64)]),
+        "rve_ws_set_params": (C.c_int, [C.c_void_p, P(C.c_float), C.c_int64]),
+        "rve_ws_get_params": (C.c_int, [C.c_void_p, P(C.c_float), C.c_int64]),
+        "rve_ws_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32,
+                                     C.c_void_p]),
+        "rve_ws_train_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p,
+                                        C.c_int32, C.c_float, P(C.c_double),
+                                        P(C.c_float)]),
+        "rve_ws_last_error": (C.c_char_p, [C.c_void_p]),
+        "rve_attach_warm_start": (C.c_int, [C.c_void_p, C.c_void_p]),
+        "rve_ws_features": (C.c_int, [C.c_void_p, P(C.c_double), C.c_void_p]),
+        "rve_ws_target": (C.c_int, [C.c_void_p, C.c_void_p]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+LIB = _load()
+
+
+class RveError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _iptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+class _TorchAllocator:
+    """Allocator hooks that draw device memory from torch's caching allocator."""
+
+    def __init__(self, device):
+        self.device = device
+
+        def alloc(size, stream, ctx):
+            try:
+                return torch.cuda.caching_allocator_alloc(
+                    int(size), self.device, stream or 0)
+            except Exception:  # out of memory -> NULL -> RVE_ENOMEM
+                return None
+
+        def free(ptr, ctx):
+            torch.cuda.caching_allocator_delete(ptr)
+
+        self.alloc_fn = ALLOC_FN(alloc)
+        self.free_fn = FREE_FN(free)
+
+
+class Rve:
+    """One periodic RVE on the GPU (a handle of the C ABI)."""
+
+    def __init__(self, n, L=(1.0, 1.0, 1.0), projection="discrete",
+                 precision="fp64", newton_tol=1e-6, newton_max_iter=25,
+                 cg_tol=1e-4, cg_max_iter=2000, cg_chunk=8, use_graph=False,
+                 warm_start=False, stream=None, device=0,
+                 torch_allocator=True):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the library runs on the GPU only")
+        self._lib = LIB
+        self._h = None
+        cfg = RveConfig()
+        LIB.rve_config_default(C.byref(cfg))
+        nn = (n, n, n) if np.isscalar(n) else tuple(n)
+        cfg.n[:] = nn
+        cfg.L[:] = tuple(float(x) for x in L)
+        cfg.projection = PROJ[projection]
+        cfg.precision = PREC[precision]
+        cfg.newton_tol = newton_tol
+        cfg.newton_max_iter = newton_max_iter
+        cfg.cg_tol = cg_tol
+        cfg.cg_max_iter = cg_max_iter
+        cfg.cg_chunk = cg_chunk
+        cfg.use_graph = 1 if use_graph else 0
+        cfg.warm_start = 1 if warm_start else 0
+        torch.cuda.set_device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        cfg.stream = C.c_void_p(self.stream.cuda_stream or None)
+        self._alloc = None
+        if torch_allocator:
+            self._alloc = _TorchAllocator(device)
+            cfg.dev_alloc = self._alloc.alloc_fn
+            cfg.dev_free = self._alloc.free_fn
+        self.cfg = cfg
+        self.n = nn[0]
+        self.N = nn[0] * nn[1] * nn[2]
+        h = C.c_void_p()
+        rc = LIB.rve_create(C.byref(cfg), C.byref(h))
+        if rc != RVE_OK:
+            raise RveError(rc, LIB.rve_last_error(None).decode())
+        self._h = h
+
+    # ------------------------------------------------------------ lifecycle
+    def close(self):
+        if self._h is not None:
+            self._lib.rve_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, rc, ok=(RVE_OK,)):
+        if rc not in ok:
+            raise RveError(rc, self._lib.rve_last_error(self._h).decode())
+        return rc
+
+    # ------------------------------------------------------------- calls
+    def set_microstructure(self, phase, quat, law, params):
+        phase = np.ascontiguousarray(phase, dtype=np.int32).reshape(-1)
+        quat = np.ascontiguousarray(quat, dtype=np.float64).reshape(-1, 4)
+        law = np.ascontiguousarray(law, dtype=np.int32).reshape(-1)
+        params = np.ascontiguousarray(params, dtype=np.float64).reshape(-1)
+        if phase.size != self.N:
+            raise ValueError("phase must have n^3 entries")
+        self._check(LIB.rve_set_microstructure(
+            self._h, _iptr(phase), quat.shape[0], _dptr(quat), _iptr(law),
+            _dptr(params), params.size))
+
+    def increment(self, F_bar, dt):
+        """One load increment; returns a dict (status included, no raise on
+        ENOTCONV / ELOCAL, which leave the committed state unchanged)."""
+        Fb = np.ascontiguousarray(F_bar, dtype=np.float64).reshape(9)
+        info = RveIncrementInfo()
+        rc = LIB.rve_apply_macro_strain_increment(self._h, _dptr(Fb),
+                                                  float(dt), C.byref(info))
+        self._check(rc, ok=(RVE_OK, RVE_ENOTCONV, RVE_ELOCAL))
+        k = info.newton_iters
+        nlog = min(k + 1, MAX_NEWTON_LOG)
+        return dict(status=rc, newton_iters=k,
+                    cg_iters_total=info.cg_iters_total,
+                    cg_iters=list(info.cg_iters[:min(k, MAX_NEWTON_LOG)]),
+                    residuals=list(info.residual_history[:nlog]),
+                    local_failures=info.local_failures,
+                    used_learned=info.used_learned,
+                    cg_breakdowns=info.cg_breakdowns,
+                    residual_rel=info.residual_rel,
+                    predictor_residual=info.predictor_residual,
+                    plain_predictor_residual=info.plain_predictor_residual,
+                    P_bar=np.array(info.P_bar).reshape(3, 3),
+                    sigma_bar=np.array(info.sigma_bar).reshape(3, 3),
+                    seconds=info.seconds)
+
+    def reset_fips(self):
+        self._check(LIB.rve_reset_fips(self._h))
+
+    def field(self, name):
+        fid, comps = FIELDS[name]
+        out = np.empty((comps, self.N), dtype=np.float64)
+        self._check(LIB.rve_get_fields(self._h, fid, out.ctypes.data_as(
+            C.c_void_p), out.nbytes, 0))
+        return out if comps > 1 else out[0]
+
+    def field_device(self, name, out):
+        """Copy a field into a torch tensor on the GPU (float64, contiguous)."""
+        fid, comps = FIELDS[name]
+        assert out.is_cuda and out.dtype == torch.float64 and out.is_contiguous()
+        self._check(LIB.rve_get_fields(self._h, fid, C.c_void_p(out.data_ptr()),
+                                       out.numel() * 8, 1))
+        return out
+
+    def macro(self):
+        out = np.empty(29)
+        self._check(LIB.rve_get_macro(self._h, _dptr(out)))
+        return dict(F_bar=out[:9].reshape(3, 3), P_bar=out[9:18].reshape(3, 3),
+                    sigma_bar=out[18:27].reshape(3, 3), t=out[27],
+                    increments=int(out[28]))
+
+    def get_state(self) -> bytes:
+        sz = C.c_size_t()
+        self._check(LIB.rve_state_size(self._h, C.byref(sz)))
+        buf = C.create_string_buffer(sz.value)
+        self._check(LIB.rve_get_state(self._h, buf, sz.value))
+        return buf.raw
+
+    def set_state(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        self._check(LIB.rve_set_state(self._h, buf, len(blob)))
+
+    # --------------------------------------------------------------- hooks
+    def debug_apply_G(self, A, precision="fp64"):
+        A = np.ascontiguousarray(A, dtype=np.float64).reshape(9, self.N)
+        out = np.empty_like(A)
+        self._check(LIB.rve_debug_apply_G(self._h, _dptr(A), _dptr(out),
+                                          PREC[precision]))
+        return out
+
+    def debug_constitutive(self, F, dt, tangent=True):
+        F = np.ascontiguousarray(F, dtype=np.float64).reshape(9, self.N)
+        P = np.empty((9, self.N))
+        dg = np.empty((12, self.N))
+        K = np.empty((81, self.N)) if tangent else None
+        fails = C.c_int32()
+        self._check(LIB.rve_debug_constitutive(
+            self._h, _dptr(F), float(dt), _dptr(P),
+            _dptr(K) if tangent else None, _dptr(dg), C.byref(fails)))
+        return dict(P=P, K=K, dg=dg, fails=fails.value)
+
+    def debug_set_field(self, name, values):
+        fid, comps = FIELDS[name]
+        v = np.ascontiguousarray(values, dtype=np.float64).reshape(comps, self.N)
+        self._check(LIB.rve_debug_set_field(self._h, fid, _dptr(v), v.nbytes))
+
+    def bench_kernels(self, reps=20):
+        """Average ms per launch of the hot-path kernels (see rve.h)."""
+        out = np.zeros(7)
+        self._check(LIB.rve_bench_kernels(self._h, int(reps), _dptr(out), 7))
+        keys = ("matvec_pass_a", "matvec_pass_b", "matvec_pass_c",
+                "cg_update", "return_map", "tangent", "residual_fp64")
+        return dict(zip(keys, out.tolist()))
+
+    # --------------------------------------------------- learned warm start
+    def attach_warm_start(self, net):
+        self._check(LIB.rve_attach_warm_start(self._h, net._h if net else None))
+        self._net = net
+
+    def features(self, F_bar_new, out=None):
+        """Network input for the increment to F_bar_new (bf16 as int16 tensor
+        [N][48] on the GPU)."""
+        Fb = np.ascontiguousarray(F_bar_new, dtype=np.float64).reshape(9)
+        if out is None:
+            out = torch.empty((self.N, WS_FEAT), dtype=torch.int16,
+                              device="cuda")
+        self._check(LIB.rve_ws_features(self._h, _dptr(Fb),
+                                        C.c_void_p(out.data_ptr())))
+        return out
+
+    def target(self, out=None):
+        """Target of the last committed increment ([N][16] float32, GPU)."""
+        if out is None:
+            out = torch.empty((self.N, WS_OUT), dtype=torch.float32,
+                              device="cuda")
+        self._check(LIB.rve_ws_target(self._h, C.c_void_p(out.data_ptr())))
+        return out
+
+
+WS_FEAT = 48
+WS_OUT = 16
+
+
+class WarmStartNet:
+    """Handle of the warm-start network (parameters, Adam state, kernels)."""
+
+    def __init__(self, stream=None, device=0):
+        torch.cuda.set_device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        cfg = RveWsConfig()
+        cfg.stream = C.c_void_p(self.stream.cuda_stream or None)
+        self._alloc = _TorchAllocator(device)
+        cfg.dev_alloc = self._alloc.alloc_fn
+        cfg.dev_free = self._alloc.free_fn
+        h = C.c_void_p()
+        rc = LIB.rve_ws_create(C.byref(cfg), C.byref(h))
+        if rc != RVE_OK:
+            raise RveError(rc, LIB.rve_ws_last_error(None).decode())
+        self._h = h
+        n = C.c_int64()
+        self._check(LIB.rve_ws_param_count(self._h, C.byref(n)))
+        self.param_count = n.value
+
+    def _check(self, rc):
+        if rc != RVE_OK:
+            raise RveError(rc, LIB.rve_ws_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            LIB.rve_ws_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32).reshape(-1)
+        self._check(LIB.rve_ws_set_params(
+            self._h, p.ctypes.data_as(C.POINTER(C.c_float)), p.size))
+
+    def get_params(self):
+        p = np.empty(self.param_count, dtype=np.float32)
+        self._check(LIB.rve_ws_get_params(
+            self._h, p.ctypes.data_as(C.POINTER(C.c_float)), p.size))
+        return p
+
+    def forward(self, X, n, out=None):
+        if out is None:
+            out = torch.empty((n ** 3, WS_OUT), dtype=torch.float32,
+                              device="cuda")
+        self._check(LIB.rve_ws_forward(self._h, C.c_void_p(X.data_ptr()), n,
+                                       C.c_void_p(out.data_ptr())))
+        return out
+
+    def train_step(self, X, T, n, lr, want_grad=False):
+        loss = C.c_double()
+        g = np.empty(self.param_count, dtype=np.float32) if want_grad else None
+        self._check(LIB.rve_ws_train_step(
+            self._h, C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()), n,
+            float(lr), C.byref(loss),
+            g.ctypes.data_as(C.POINTER(C.c_float)) if want_grad else None))
+        return (loss.value, g) if want_grad else loss.value

@@ -1,0 +1,296 @@
+// extern "C" entry points declared in include/rve.h.  Every call converts
+// C++ errors to rve_status; a HIP runtime error poisons the handle.
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/rve.h"
+#include "engine.hpp"
+
+struct rve_s {
+  rve::Engine* eng = nullptr;
+  std::string err;
+  bool poisoned = false;
+};
+
+struct rve_ws_s {
+  rve::Net* net = nullptr;
+  std::string err;
+  bool poisoned = false;
+};
+
+namespace {
+
+thread_local std::string g_create_error;
+
+template <class H, class F>
+rve_status guarded(H* h, F&& f) {
+  if (!h) return RVE_EINVAL;
+  if (h->poisoned) {
+    h->err = "handle poisoned by an earlier device error: " + h->err;
+    return RVE_EDEVICE;
+  }
+  try {
+    h->err.clear();
+    return (rve_status)f();
+  } catch (const rve::Error& e) {
+    h->err = e.what();
+    if (e.code == RVE_EDEVICE) h->poisoned = true;
+    return (rve_status)e.code;
+  } catch (const std::bad_alloc&) {
+    h->err = "host allocation failed";
+    return RVE_ENOMEM;
+  } catch (const std::exception& e) {
+    h->err = e.what();
+    return RVE_EINVAL;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+rve_status rve_config_default(rve_config* cfg) {
+  if (!cfg) return RVE_EINVAL;
+  std::memset(cfg, 0, sizeof(*cfg));
+  cfg->n[0] = cfg->n[1] = cfg->n[2] = 16;
+  cfg->L[0] = cfg->L[1] = cfg->L[2] = 1.0;
+  cfg->projection = RVE_PROJ_DISCRETE;
+  cfg->precision = RVE_PREC_FP64;
+  cfg->warm_start = 0;
+  cfg->use_graph = 0;
+  cfg->newton_tol = 1e-6;
+  cfg->newton_max_iter = 25;
+  cfg->cg_tol = 1e-4;
+  cfg->cg_max_iter = 2000;
+  cfg->cg_chunk = 8;
+  return RVE_OK;
+}
+
+rve_status rve_create(const rve_config* cfg, rve_t* out) {
+  if (!cfg || !out) return RVE_EINVAL;
+  *out = nullptr;
+  rve_s* h = new (std::nothrow) rve_s();
+  if (!h) return RVE_ENOMEM;
+  try {
+    h->eng = new rve::Engine(*cfg);
+  } catch (const rve::Error& e) {
+    g_create_error = e.what();
+    delete h;
+    return (rve_status)e.code;
+  } catch (const std::exception& e) {
+    g_create_error = e.what();
+    delete h;
+    return RVE_ENOMEM;
+  }
+  *out = h;
+  return RVE_OK;
+}
+
+rve_status rve_destroy(rve_t h) {
+  if (!h) return RVE_OK;
+  delete h->eng;
+  delete h;
+  return RVE_OK;
+}
+
+rve_status rve_set_microstructure(rve_t h, const int32_t* phase, int32_t G,
+                                  const double* quat, const int32_t* law,
+                                  const double* params, int32_t nparams) {
+  return guarded(h, [&] {
+    h->eng->set_microstructure(phase, G, quat, law, params, nparams);
+    return RVE_OK;
+  });
+}
+
+rve_status rve_apply_macro_strain_increment(rve_t h, const double F_bar_new[9],
+                                            double dt,
+                                            rve_increment_info* info) {
+  return guarded(h, [&] {
+    if (!F_bar_new) throw rve::Error(RVE_EINVAL, "null F_bar_new");
+    return h->eng->increment(F_bar_new, dt, info);
+  });
+}
+
+rve_status rve_reset_fips(rve_t h) {
+  return guarded(h, [&] {
+    h->eng->reset_fips();
+    return RVE_OK;
+  });
+}
+
+rve_status rve_get_fields(rve_t h, int32_t field, void* dst, size_t dst_bytes,
+                          int32_t dst_on_device) {
+  return guarded(h, [&] {
+    h->eng->get_field(field, dst, dst_bytes, dst_on_device != 0);
+    return RVE_OK;
+  });
+}
+
+rve_status rve_get_macro(rve_t h, double out[29]) {
+  return guarded(h, [&] {
+    if (!out) throw rve::Error(RVE_EINVAL, "null output");
+    h->eng->get_macro(out);
+    return RVE_OK;
+  });
+}
+
+rve_status rve_state_size(rve_t h, size_t* bytes) {
+  return guarded(h, [&] {
+    if (!bytes) throw rve::Error(RVE_EINVAL, "null output");
+    *bytes = h->eng->state_size();
+    return RVE_OK;
+  });
+}
+
+rve_status rve_get_state(rve_t h, void* dst, size_t bytes) {
+  return guarded(h, [&] {
+    h->eng->get_state(dst, bytes);
+    return RVE_OK;
+  });
+}
+
+rve_status rve_set_state(rve_t h, const void* src, size_t bytes) {
+  return guarded(h, [&] {
+    h->eng->set_state(src, bytes);
+    return RVE_OK;
+  });
+}
+
+const char* rve_last_error(rve_t h) {
+  if (!h) return g_create_error.c_str();
+  return h->err.c_str();
+}
+
+rve_status rve_debug_apply_G(rve_t h, const double* in, double* out,
+                             int32_t precision) {
+  return guarded(h, [&] {
+    h->eng->debug_apply_G(in, out, precision);
+    return RVE_OK;
+  });
+}
+
+rve_status rve_debug_constitutive(rve_t h, const double* F, double dt,
+                                  double* P, double* K, double* dg,
+                                  int32_t* fails) {
+  return guarded(h, [&] {
+    h->eng->debug_constitutive(F, dt, P, K, dg, fails);
+    return RVE_OK;
+  });
+}
+
+rve_status rve_debug_set_field(rve_t h, int32_t field, const double* src,
+                               size_t bytes) {
+  return guarded(h, [&] {
+    h->eng->debug_set_field(field, src, bytes);
+    return RVE_OK;
+  });
+}
+
+rve_status rve_bench_kernels(rve_t h, int32_t reps, double* ms_out,
+                             int32_t count) {
+  return guarded(h, [&] {
+    h->eng->bench_kernels(reps, ms_out, count);
+    return RVE_OK;
+  });
+}
+
+rve_status rve_ws_create(const rve_ws_config* cfg, rve_ws_t* out) {
+  if (!cfg || !out) return RVE_EINVAL;
+  *out = nullptr;
+  if ((cfg->dev_alloc == nullptr) != (cfg->dev_free == nullptr)) return RVE_EINVAL;
+  rve_ws_s* h = new (std::nothrow) rve_ws_s();
+  if (!h) return RVE_ENOMEM;
+  try {
+    h->net = new rve::Net((hipStream_t)cfg->stream, cfg->dev_alloc, cfg->dev_free,
+                          cfg->alloc_ctx);
+  } catch (const rve::Error& e) {
+    g_create_error = e.what();
+    delete h;
+    return (rve_status)e.code;
+  } catch (const std::exception& e) {
+    g_create_error = e.what();
+    delete h;
+    return RVE_ENOMEM;
+  }
+  *out = h;
+  return RVE_OK;
+}
+
+rve_status rve_ws_destroy(rve_ws_t w) {
+  if (!w) return RVE_OK;
+  delete w->net;
+  delete w;
+  return RVE_OK;
+}
+
+rve_status rve_ws_param_count(rve_ws_t w, int64_t* count) {
+  return guarded(w, [&] {
+    if (!count) throw rve::Error(RVE_EINVAL, "null output");
+    *count = rve::Net::param_count();
+    return RVE_OK;
+  });
+}
+
+rve_status rve_ws_set_params(rve_ws_t w, const float* params, int64_t count) {
+  return guarded(w, [&] {
+    w->net->set_params(params, count);
+    return RVE_OK;
+  });
+}
+
+rve_status rve_ws_get_params(rve_ws_t w, float* params, int64_t count) {
+  return guarded(w, [&] {
+    w->net->get_params(params, count);
+    return RVE_OK;
+  });
+}
+
+rve_status rve_ws_forward(rve_ws_t w, const uint16_t* X, int32_t n, float* Y) {
+  return guarded(w, [&] {
+    if (!X || !Y) throw rve::Error(RVE_EINVAL, "null buffer");
+    w->net->forward(X, n, Y);
+    RVE_HIP(hipStreamSynchronize(w->net->stream()));
+    return RVE_OK;
+  });
+}
+
+rve_status rve_ws_train_step(rve_ws_t w, const uint16_t* X, const float* T,
+                             int32_t n, float lr, double* loss,
+                             float* grad_host) {
+  return guarded(w, [&] {
+    if (!X || !T) throw rve::Error(RVE_EINVAL, "null buffer");
+    const double L = w->net->train_step(X, T, n, lr, grad_host);
+    if (loss) *loss = L;
+    return RVE_OK;
+  });
+}
+
+const char* rve_ws_last_error(rve_ws_t w) {
+  if (!w) return g_create_error.c_str();
+  return w->err.c_str();
+}
+
+rve_status rve_attach_warm_start(rve_t h, rve_ws_t w) {
+  return guarded(h, [&] {
+    h->eng->attach_net(w ? w->net : nullptr);
+    return RVE_OK;
+  });
+}
+
+rve_status rve_ws_features(rve_t h, const double F_bar_new[9], uint16_t* X) {
+  return guarded(h, [&] {
+    if (!F_bar_new) throw rve::Error(RVE_EINVAL, "null F_bar_new");
+    h->eng->features(F_bar_new, X);
+    return RVE_OK;
+  });
+}
+
+rve_status rve_ws_target(rve_t h, float* T) {
+  return guarded(h, [&] {
+    h->eng->target(T);
+    return RVE_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,890 @@
+// RVE engine: buffers and the increment algorithm (see engine.hpp).
+#include "engine.hpp"
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "tables.hpp"
+
+namespace rve {
+
+namespace {
+
+bool supported_n(int n) {
+  switch (n) {
+    case 16: case 24: case 32: case 40: case 48: case 64: case 96: case 128:
+      return true;
+  }
+  return false;
+}
+
+double det3(const double* a) {
+  return a[0] * (a[4] * a[8] - a[5] * a[7]) - a[1] * (a[3] * a[8] - a[5] * a[6]) +
+         a[2] * (a[3] * a[7] - a[4] * a[6]);
+}
+
+constexpr uint64_t kStateMagic = 0x3153455645525652ull;  // "RVERVES1"
+
+struct StateHeader {
+  uint64_t magic;
+  int64_t n;
+  int64_t increments;
+  double t;
+  double Fbar[9];
+  double Pbar[9];
+};
+
+}  // namespace
+
+Engine::Engine(const rve_config& cfg) : cfg_(cfg) {
+  if (cfg.n[0] != cfg.n[1] || cfg.n[1] != cfg.n[2] || !supported_n(cfg.n[0]))
+    throw Error(RVE_EINVAL,
+                "grid must be cubic with n in {16,24,32,40,48,64,96,128}");
+  if (cfg.projection != RVE_PROJ_CONTINUOUS && cfg.projection != RVE_PROJ_DISCRETE)
+    throw Error(RVE_EINVAL, "unknown projection operator");
+  if (cfg.precision != RVE_PREC_FP64 && cfg.precision != RVE_PREC_MIXED)
+    throw Error(RVE_EINVAL, "unknown precision mode");
+  for (int d = 0; d < 3; ++d)
+    if (!(cfg.L[d] > 0.0)) throw Error(RVE_EINVAL, "cell lengths must be > 0");
+  if (!(cfg.newton_tol > 0.0) || cfg.newton_max_iter < 0 ||
+      cfg.newton_max_iter > RVE_MAX_NEWTON_LOG - 1 || !(cfg.cg_tol > 0.0) ||
+      cfg.cg_max_iter < 1 || cfg.cg_chunk < 1)
+    throw Error(RVE_EINVAL, "bad tolerance or iteration limits");
+  if ((cfg.dev_alloc == nullptr) != (cfg.dev_free == nullptr))
+    throw Error(RVE_EINVAL, "dev_alloc and dev_free must be given together");
+  n_ = cfg.n[0];
+  N_ = (int64_t)n_ * n_ * n_;
+  fp64_ = cfg.precision == RVE_PREC_FP64;
+  st_ = (hipStream_t)cfg.stream;
+  if (cfg_.use_graph && st_ == nullptr) {
+    // graph capture needs a non-legacy stream; this one is blocking with
+    // respect to the default stream, so ordering with it is preserved
+    RVE_HIP(hipStreamCreate(&own_stream_));
+    st_ = own_stream_;
+  }
+  if (cfg_.cg_chunk % 2) cfg_.cg_chunk += 1;  // p0/p1 parity per chunk
+
+  const size_t f9 = 9 * N_ * sizeof(double), f12 = 12 * N_ * sizeof(double),
+               f1 = N_ * sizeof(double);
+  const size_t tsz = fp64_ ? sizeof(double) : sizeof(float);
+  Fprev_ = (double*)alloc(f9);
+  Pc_ = (double*)alloc(f9);
+  Fpi_c_ = (double*)alloc(f9);
+  chi_c_ = (double*)alloc(f12);
+  dg_c_ = (double*)alloc(f12);
+  pcyc_ = (double*)alloc(f1);
+  pcyc_lit_ = (double*)alloc(f1);
+  wcyc_ = (double*)alloc(f12);
+  F_ = (double*)alloc(f9);
+  P_ = (double*)alloc(f9);
+  Fpi_t_ = (double*)alloc(f9);
+  chi_t_ = (double*)alloc(f12);
+  dg_t_ = (double*)alloc(f12);
+  r64_ = (double*)alloc(f9);
+  dFt_prev_ = (double*)alloc(f9);
+  K_ = alloc(81 * N_ * tsz);
+  x_ = alloc(9 * N_ * tsz);
+  r_ = alloc(9 * N_ * tsz);
+  p0_ = alloc(9 * N_ * tsz);
+  p1_ = alloc(9 * N_ * tsz);
+  Ap_ = alloc(9 * N_ * tsz);
+  spec_ = alloc(9 * N_ / 2 * 2 * tsz);
+  spec64_ = fp64_ ? spec_ : alloc(9 * N_ / 2 * 2 * sizeof(double));
+  nslab32_ = slab_blocks(n_, false);
+  nslab64_ = slab_blocks(n_, true);
+  const int nslab_max = nslab32_ > nslab64_ ? nslab32_ : nslab64_;
+  partial_inv_ = (double*)alloc(nslab_max * sizeof(double));
+  partial_red_ = (double*)alloc(kRedBlocks * sizeof(double));
+  psum_ = (double*)alloc(9 * n_ * sizeof(double));
+  psq_ = (double*)alloc(9 * n_ * sizeof(double));
+  sc_ = (Scalars*)alloc(sizeof(Scalars));
+  phase_ = (int32_t*)alloc(N_ * sizeof(int32_t));
+  table_ = nullptr;
+  RVE_HIP(hipHostMalloc((void**)&sc_host_, sizeof(Scalars), hipHostMallocDefault));
+
+  std::vector<double> tw = twiddles(n_);
+  std::vector<float> tw32(tw.begin(), tw.end());
+  std::vector<double> vt = wave_vectors(n_, cfg_.L, cfg_.projection);
+  std::vector<float> vt32(vt.begin(), vt.end());
+  tw64_ = alloc(tw.size() * sizeof(double));
+  tw32_ = alloc(tw32.size() * sizeof(float));
+  vt64_ = alloc(vt.size() * sizeof(double));
+  vt32_ = alloc(vt32.size() * sizeof(float));
+  RVE_HIP(hipMemcpyAsync(tw64_, tw.data(), tw.size() * sizeof(double),
+                         hipMemcpyHostToDevice, st_));
+  RVE_HIP(hipMemcpyAsync(tw32_, tw32.data(), tw32.size() * sizeof(float),
+                         hipMemcpyHostToDevice, st_));
+  RVE_HIP(hipMemcpyAsync(vt64_, vt.data(), vt.size() * sizeof(double),
+                         hipMemcpyHostToDevice, st_));
+  RVE_HIP(hipMemcpyAsync(vt32_, vt32.data(), vt32.size() * sizeof(float),
+                         hipMemcpyHostToDevice, st_));
+  RVE_HIP(hipStreamSynchronize(st_));
+  for (int i = 0; i < 9; ++i) {
+    Fbar_[i] = (i % 4 == 0) ? 1.0 : 0.0;
+    Pbar_[i] = 0.0;
+    dFlast_[i] = 0.0;
+    dFbar_prev_[i] = 0.0;
+  }
+}
+
+Engine::~Engine() {
+  if (graph_) hipGraphExecDestroy(graph_);
+  if (graph_def_) hipGraphDestroy(graph_def_);
+  if (st_) hipStreamSynchronize(st_);
+  free_all();
+  if (sc_host_) hipHostFree(sc_host_);
+  if (own_stream_) hipStreamDestroy(own_stream_);
+}
+
+void* Engine::alloc(size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  void* p = nullptr;
+  if (cfg_.dev_alloc) {
+    p = cfg_.dev_alloc(bytes, (void*)st_, cfg_.alloc_ctx);
+    if (!p) throw Error(RVE_ENOMEM, "device allocator returned NULL");
+  } else {
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error(RVE_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+  }
+  allocs_.push_back({p, bytes});
+  return p;
+}
+
+void Engine::free_all() {
+  for (auto& a : allocs_) {
+    if (cfg_.dev_free)
+      cfg_.dev_free(a.first, cfg_.alloc_ctx);
+    else
+      hipFree(a.first);
+  }
+  allocs_.clear();
+}
+
+void Engine::set_microstructure(const int32_t* phase, int32_t G,
+                                const double* quat, const int32_t* law,
+                                const double* params, int32_t nparams) {
+  if (!phase || !quat || !law || !params || G < 1)
+    throw Error(RVE_EINVAL, "null microstructure input or G < 1");
+  if (nparams < RVE_NPARAMS) throw Error(RVE_EINVAL, "nparams < RVE_NPARAMS");
+  for (int64_t v = 0; v < N_; ++v)
+    if (phase[v] < 0 || phase[v] >= G)
+      throw Error(RVE_EINVAL, "phase label out of [0, G)");
+  for (int g = 0; g < G; ++g) {
+    if (law[g] != 0 && law[g] != 1) throw Error(RVE_EINVAL, "unknown law id");
+    const double q2 = quat[4 * g] * quat[4 * g] + quat[4 * g + 1] * quat[4 * g + 1] +
+                      quat[4 * g + 2] * quat[4 * g + 2] +
+                      quat[4 * g + 3] * quat[4 * g + 3];
+    if (!(std::fabs(q2 - 1.0) < 1e-6)) throw Error(RVE_EINVAL, "quaternion not unit");
+  }
+  for (int i = 0; i < RVE_NPARAMS; ++i) {
+    if (!std::isfinite(params[i])) throw Error(RVE_EINVAL, "non-finite parameter");
+    params_[i] = params[i];
+  }
+  if (!(params_[3] > 0 && params_[4] > 0 && params_[5] >= 1 && params_[7] >= 0))
+    throw Error(RVE_EINVAL, "bad flow-rule parameters");
+  std::vector<double> tab = label_table(G, quat, law, params_);
+  if (G > labels_) {
+    table_ = (double*)alloc(tab.size() * sizeof(double));
+    labels_ = G;
+  }
+  RVE_HIP(hipMemcpyAsync(table_, tab.data(), tab.size() * sizeof(double),
+                         hipMemcpyHostToDevice, st_));
+  RVE_HIP(hipMemcpyAsync(phase_, phase, N_ * sizeof(int32_t),
+                         hipMemcpyHostToDevice, st_));
+  // reset to F = I, Fp^-1 = I, chi = 0, indicators = 0
+  std::vector<double> eye(9 * N_, 0.0);
+  for (int c = 0; c < 9; c += 4)
+    for (int64_t v = 0; v < N_; ++v) eye[c * N_ + v] = 1.0;
+  RVE_HIP(hipMemcpyAsync(Fprev_, eye.data(), 9 * N_ * sizeof(double),
+                         hipMemcpyHostToDevice, st_));
+  RVE_HIP(hipMemcpyAsync(Fpi_c_, eye.data(), 9 * N_ * sizeof(double),
+                         hipMemcpyHostToDevice, st_));
+  launch_fill_f64(Pc_, 0.0, 9 * N_, st_);
+  launch_fill_f64(chi_c_, 0.0, 12 * N_, st_);
+  launch_fill_f64(dg_c_, 0.0, 12 * N_, st_);
+  launch_fill_f64(pcyc_, 0.0, N_, st_);
+  launch_fill_f64(pcyc_lit_, 0.0, N_, st_);
+  launch_fill_f64(wcyc_, 0.0, 12 * N_, st_);
+  launch_fill_f64(dFt_prev_, 0.0, 9 * N_, st_);
+  RVE_HIP(hipGetLastError());
+  RVE_HIP(hipStreamSynchronize(st_));
+  for (int i = 0; i < 9; ++i) {
+    Fbar_[i] = (i % 4 == 0) ? 1.0 : 0.0;
+    Pbar_[i] = 0.0;
+    dFlast_[i] = 0.0;
+    dFbar_prev_[i] = 0.0;
+  }
+  s_prev_ = 0.0;
+  t_ = 0.0;
+  increments_ = 0;
+  have_micro_ = true;
+}
+
+void Engine::read_scalars(Scalars& h) {
+  RVE_HIP(hipMemcpyAsync(sc_host_, sc_, sizeof(Scalars), hipMemcpyDeviceToHost,
+                         st_));
+  RVE_HIP(hipStreamSynchronize(st_));
+  h = *sc_host_;
+}
+
+LawParams Engine::law_params(double dt) const {
+  LawParams lp;
+  lp.gdot0 = params_[3];
+  lp.g = params_[4];
+  lp.nexp = params_[5];
+  lp.c_af = params_[6];
+  lp.d_af = params_[7];
+  lp.dt = dt;
+  return lp;
+}
+
+void Engine::residual_passes(const double* P) {
+  SpectralLaunch<double> L;
+  L.src = SRC_FIELD;
+  L.in_field = P;
+  L.spec = (cplx<double>*)spec64_;
+  L.tw = (const cplx<double>*)tw64_;
+  L.vt = (const double*)vt64_;
+  L.psum = psum_;
+  L.psq = psq_;
+  L.dst = DST_NORM;
+  L.out_d = r64_;
+  L.partial_inv = partial_inv_;
+  launch_G<double>(n_, L, st_);
+  launch_reduce(RED_RESID, partial_inv_, nslab64_, psum_, psq_, n_,
+                1.0 / (double)N_, sc_, sc_->pbar, st_);
+}
+
+// constitutive update at F_ with the committed state, then r64 = G(P)
+int Engine::evaluate(const double* dg_start, double dt, double& rel,
+                     double& res, double& pn) {
+  launch_fill_i32(&sc_->fails, 0, 1, st_);
+  ConstArgs a{};
+  a.F = F_;
+  a.Fpi0 = Fpi_c_;
+  a.chi0 = chi_c_;
+  a.dg0 = dg_start;
+  a.phase = phase_;
+  a.table = table_;
+  a.P = P_;
+  a.Fpi = Fpi_t_;
+  a.chi = chi_t_;
+  a.dg = dg_t_;
+  a.fails = &sc_->fails;
+  a.iters = nullptr;
+  a.lp = law_params(dt);
+  a.N = N_;
+  launch_return_map(a, st_);
+  residual_passes(P_);
+  RVE_HIP(hipGetLastError());
+  Scalars h;
+  read_scalars(h);
+  res = std::sqrt(h.res2);
+  pn = std::sqrt(h.P2);
+  rel = pn > 0 ? res / pn : 0.0;
+  for (int i = 0; i < 9; ++i) Pbar_new_[i] = h.pbar[i];
+  return h.fails;
+}
+
+template <typename T>
+void Engine::tangent(double dt) {
+  TangentArgs<T> a{};
+  a.F = F_;
+  a.Fpi0 = Fpi_c_;
+  a.chi0 = chi_c_;
+  a.dg = dg_t_;
+  a.phase = phase_;
+  a.table = table_;
+  a.K = (T*)K_;
+  a.lp = law_params(dt);
+  a.N = N_;
+  launch_tangent<T>(a, st_);
+}
+
+template <typename T>
+void Engine::cg_iteration(int parity) {
+  const bool dbl = sizeof(T) == sizeof(double);
+  SpectralLaunch<T> L;
+  L.src = SRC_KP;
+  L.K = (const T*)K_;
+  L.r = (const T*)r_;
+  L.p_old = (const T*)(parity ? p1_ : p0_);
+  L.p_new = (T*)(parity ? p0_ : p1_);
+  L.spec = (cplx<T>*)spec_;
+  L.tw = (const cplx<T>*)(dbl ? tw64_ : tw32_);
+  L.vt = (const T*)(dbl ? vt64_ : vt32_);
+  L.dst = DST_DOT;
+  L.out_T = (T*)Ap_;
+  L.partial_inv = partial_inv_;
+  L.sc = sc_;
+  launch_G<T>(n_, L, st_);
+  const int nslab = dbl ? nslab64_ : nslab32_;
+  launch_reduce(RED_ALPHA, partial_inv_, nslab, nullptr, nullptr, 0, 0.0, sc_,
+                nullptr, st_);
+  launch_cg_update<T>((T*)x_, (T*)r_, L.p_new, (const T*)Ap_, sc_,
+                      partial_red_, kRedBlocks, 9 * N_, st_);
+  launch_reduce(RED_BETA, partial_red_, kRedBlocks, nullptr, nullptr, 0, 0.0,
+                sc_, nullptr, st_);
+}
+
+template <typename T>
+void Engine::capture_graph() {
+  RVE_HIP(hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal));
+  for (int j = 0; j < cfg_.cg_chunk; ++j) cg_iteration<T>(j & 1);
+  RVE_HIP(hipStreamEndCapture(st_, &graph_def_));
+  RVE_HIP(hipGraphInstantiate(&graph_, graph_def_, nullptr, nullptr, 0));
+}
+
+// CG on G(K : x) = b with b = -r64 (text after Eq. 16), from x = 0
+template <typename T>
+void Engine::cg_solve(int& iters, bool& breakdown) {
+  launch_init_scalars(sc_, cfg_.cg_max_iter, cfg_.cg_tol, st_);
+  launch_cg_init<T>(r64_, (T*)r_, (T*)x_, partial_red_, kRedBlocks, 9 * N_, st_);
+  launch_reduce(RED_INIT, partial_red_, kRedBlocks, nullptr, nullptr, 0, 0.0,
+                sc_, nullptr, st_);
+  RVE_HIP(hipGetLastError());
+  Scalars h;
+  int parity = 0;
+  for (;;) {
+    if (cfg_.use_graph) {
+      if (!graph_) capture_graph<T>();
+      RVE_HIP(hipGraphLaunch(graph_, st_));
+    } else {
+      for (int j = 0; j < cfg_.cg_chunk; ++j) {
+        cg_iteration<T>(parity);
+        parity ^= 1;
+      }
+      RVE_HIP(hipGetLastError());
+    }
+    read_scalars(h);
+    if (h.done) break;
+  }
+  iters = h.iters;
+  breakdown = h.breakdown != 0;
+}
+
+void Engine::commit(double dt) {
+  nn_fluct_increment(F_, Fprev_, dFlast_, dFt_prev_, N_, st_);
+  CommitArgs c{};
+  c.F = F_;
+  c.Fpi_t = Fpi_t_;
+  c.dg_t = dg_t_;
+  c.phase = phase_;
+  c.table = table_;
+  c.pcyc = pcyc_;
+  c.pcyc_lit = pcyc_lit_;
+  c.wcyc = wcyc_;
+  c.dt = dt;
+  c.N = N_;
+  launch_commit(c, st_);
+  RVE_HIP(hipMemcpyAsync(Pc_, P_, 9 * N_ * sizeof(double),
+                         hipMemcpyDeviceToDevice, st_));
+  RVE_HIP(hipGetLastError());
+  std::swap(Fpi_c_, Fpi_t_);
+  std::swap(chi_c_, chi_t_);
+  std::swap(dg_c_, dg_t_);
+  std::swap(Fprev_, F_);
+  for (int i = 0; i < 9; ++i) Pbar_[i] = Pbar_new_[i];
+}
+
+int Engine::increment(const double Fbar_new[9], double dt,
+                      rve_increment_info* info) {
+  if (!have_micro_) throw Error(RVE_ESTATE, "no microstructure set");
+  if (!(dt > 0.0) || !std::isfinite(dt)) throw Error(RVE_EINVAL, "dt must be > 0");
+  for (int i = 0; i < 9; ++i)
+    if (!std::isfinite(Fbar_new[i])) throw Error(RVE_EINVAL, "non-finite F_bar");
+  if (!(det3(Fbar_new) > 0.0)) throw Error(RVE_EINVAL, "det(F_bar) must be > 0");
+  const auto t0 = std::chrono::steady_clock::now();
+  rve_increment_info loc;
+  std::memset(&loc, 0, sizeof(loc));
+  double dF[9];
+  for (int i = 0; i < 9; ++i) dF[i] = Fbar_new[i] - Fbar_[i];
+  launch_predict(F_, Fprev_, dF, N_, st_);
+  const double* dg_start = dg_c_;
+  double rel = 0, res = 0, pn = 0;
+  int status = RVE_ENOTCONV;
+  int pre_fails = -1;
+  if (net_ && cfg_.warm_start && learned_candidate(Fbar_new)) {
+    // learned candidate in F2_: evaluate it, stash it, evaluate the plain
+    // predictor, keep the one with the smaller FP64 residual
+    std::swap(F_, F2_);
+    double relL, resL, pnL;
+    const int failsL = evaluate(dg_start, dt, relL, resL, pnL);
+    swap_trial_sets();
+    std::swap(F_, F2_);
+    double pbarL[9];
+    for (int i = 0; i < 9; ++i) pbarL[i] = Pbar_new_[i];
+    pre_fails = evaluate(dg_start, dt, rel, res, pn);
+    loc.plain_predictor_residual = rel;
+    if (failsL == 0 && relL < rel) {
+      swap_trial_sets();
+      std::swap(F_, F2_);
+      rel = relL;
+      res = resL;
+      pn = pnL;
+      pre_fails = 0;
+      for (int i = 0; i < 9; ++i) Pbar_new_[i] = pbarL[i];
+      loc.used_learned = 1;
+    }
+  }
+  for (int i = 0; i < 9; ++i) dFlast_[i] = dF[i];
+  for (int it = 0; it <= cfg_.newton_max_iter; ++it) {
+    const int fails = (it == 0 && pre_fails >= 0)
+                          ? pre_fails
+                          : evaluate(dg_start, dt, rel, res, pn);
+    if (it < RVE_MAX_NEWTON_LOG) loc.residual_history[it] = rel;
+    if (it == 0) {
+      loc.predictor_residual = rel;
+      if (!loc.used_learned) loc.plain_predictor_residual = rel;
+    }
+    loc.residual_rel = rel;
+    if (fails > 0) {
+      loc.local_failures = fails;
+      status = RVE_ELOCAL;
+      break;
+    }
+    if (res <= cfg_.newton_tol * pn) {
+      commit(dt);
+      double s2 = 0.0, dot = 0.0;
+      for (int i = 0; i < 9; ++i) s2 += dF[i] * dF[i];
+      for (int i = 0; i < 9; ++i) {
+        Fbar_[i] = Fbar_new[i];
+        dFbar_prev_[i] = dF[i];
+        (void)dot;
+      }
+      s_prev_ = std::sqrt(s2);
+      t_ += dt;
+      ++increments_;
+      status = RVE_OK;
+      loc.newton_iters = it;
+      break;
+    }
+    if (it == cfg_.newton_max_iter) {
+      loc.newton_iters = it;
+      status = RVE_ENOTCONV;
+      break;
+    }
+    int iters = 0;
+    bool bd = false;
+    if (fp64_) {
+      tangent<double>(dt);
+      cg_solve<double>(iters, bd);
+      launch_add_to_F<double>(F_, (const double*)x_, 9 * N_, st_);
+    } else {
+      tangent<float>(dt);
+      cg_solve<float>(iters, bd);
+      launch_add_to_F<float>(F_, (const float*)x_, 9 * N_, st_);
+    }
+    RVE_HIP(hipGetLastError());
+    if (it < RVE_MAX_NEWTON_LOG) loc.cg_iters[it] = iters;
+    loc.cg_iters_total += iters;
+    loc.cg_breakdowns += bd ? 1 : 0;
+    dg_start = dg_t_;
+  }
+  for (int i = 0; i < 9; ++i) loc.P_bar[i] = (status == RVE_OK) ? Pbar_[i] : Pbar_new_[i];
+  const double J = det3(Fbar_new);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += loc.P_bar[3 * i + k] * Fbar_new[3 * j + k];
+      loc.sigma_bar[3 * i + j] = s / J;
+    }
+  loc.status = status;
+  loc.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (info) *info = loc;
+  return status;
+}
+
+void Engine::reset_fips() {
+  launch_fill_f64(pcyc_, 0.0, N_, st_);
+  launch_fill_f64(pcyc_lit_, 0.0, N_, st_);
+  launch_fill_f64(wcyc_, 0.0, 12 * N_, st_);
+  RVE_HIP(hipGetLastError());
+  RVE_HIP(hipStreamSynchronize(st_));
+}
+
+void Engine::get_field(int field, void* dst, size_t bytes, bool on_device) {
+  if (!dst) throw Error(RVE_EINVAL, "null destination");
+  const double* src = nullptr;
+  size_t need = 0;
+  switch (field) {
+    case RVE_FIELD_F: src = Fprev_; need = 9; break;
+    case RVE_FIELD_P: src = Pc_; need = 9; break;
+    case RVE_FIELD_SIGMA:
+      launch_cauchy(Fprev_, Pc_, r64_, N_, st_);
+      src = r64_;
+      need = 9;
+      break;
+    case RVE_FIELD_FPINV: src = Fpi_c_; need = 9; break;
+    case RVE_FIELD_CHI: src = chi_c_; need = 12; break;
+    case RVE_FIELD_DGAMMA: src = dg_c_; need = 12; break;
+    case RVE_FIELD_PCYC: src = pcyc_; need = 1; break;
+    case RVE_FIELD_PCYC_LIT: src = pcyc_lit_; need = 1; break;
+    case RVE_FIELD_WCYC: src = wcyc_; need = 12; break;
+    default: throw Error(RVE_EINVAL, "unknown field id");
+  }
+  need *= N_ * sizeof(double);
+  if (bytes < need) throw Error(RVE_EINVAL, "destination too small");
+  RVE_HIP(hipMemcpyAsync(dst, src, need,
+                         on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                         st_));
+  RVE_HIP(hipStreamSynchronize(st_));
+}
+
+void Engine::get_macro(double out[29]) {
+  for (int i = 0; i < 9; ++i) {
+    out[i] = Fbar_[i];
+    out[9 + i] = Pbar_[i];
+  }
+  const double J = det3(Fbar_);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += Pbar_[3 * i + k] * Fbar_[3 * j + k];
+      out[18 + 3 * i + j] = s / J;
+    }
+  out[27] = t_;
+  out[28] = (double)increments_;
+}
+
+size_t Engine::state_size() const {
+  return sizeof(StateHeader) + (size_t)65 * N_ * sizeof(double);
+}
+
+void Engine::get_state(void* dst, size_t bytes) {
+  if (!dst || bytes < state_size()) throw Error(RVE_EINVAL, "state buffer too small");
+  StateHeader h{};
+  h.magic = kStateMagic;
+  h.n = n_;
+  h.increments = increments_;
+  h.t = t_;
+  for (int i = 0; i < 9; ++i) {
+    h.Fbar[i] = Fbar_[i];
+    h.Pbar[i] = Pbar_[i];
+  }
+  char* p = (char*)dst;
+  std::memcpy(p, &h, sizeof(h));
+  p += sizeof(h);
+  const double* arrs[8] = {Fprev_, Pc_, Fpi_c_, chi_c_, dg_c_, pcyc_, pcyc_lit_, wcyc_};
+  const int comps[8] = {9, 9, 9, 12, 12, 1, 1, 12};
+  for (int k = 0; k < 8; ++k) {
+    const size_t b = comps[k] * N_ * sizeof(double);
+    RVE_HIP(hipMemcpyAsync(p, arrs[k], b, hipMemcpyDeviceToHost, st_));
+    p += b;
+  }
+  RVE_HIP(hipStreamSynchronize(st_));
+}
+
+void Engine::set_state(const void* src, size_t bytes) {
+  if (!have_micro_) throw Error(RVE_ESTATE, "set the microstructure first");
+  if (!src || bytes < state_size()) throw Error(RVE_EINVAL, "state blob too small");
+  StateHeader h;
+  std::memcpy(&h, src, sizeof(h));
+  if (h.magic != kStateMagic || h.n != n_)
+    throw Error(RVE_EINVAL, "state blob from another grid or format");
+  const char* p = (const char*)src + sizeof(h);
+  double* arrs[8] = {Fprev_, Pc_, Fpi_c_, chi_c_, dg_c_, pcyc_, pcyc_lit_, wcyc_};
+  const int comps[8] = {9, 9, 9, 12, 12, 1, 1, 12};
+  for (int k = 0; k < 8; ++k) {
+    const size_t b = comps[k] * N_ * sizeof(double);
+    RVE_HIP(hipMemcpyAsync(arrs[k], p, b, hipMemcpyHostToDevice, st_));
+    p += b;
+  }
+  RVE_HIP(hipStreamSynchronize(st_));
+  increments_ = h.increments;
+  t_ = h.t;
+  for (int i = 0; i < 9; ++i) {
+    Fbar_[i] = h.Fbar[i];
+    Pbar_[i] = h.Pbar[i];
+  }
+}
+
+void Engine::apply_G_fp64(const double* in, double* out) {
+  SpectralLaunch<double> L;
+  L.src = SRC_FIELD;
+  L.in_field = in;
+  L.spec = (cplx<double>*)spec64_;
+  L.tw = (const cplx<double>*)tw64_;
+  L.vt = (const double*)vt64_;
+  L.dst = DST_NORM;
+  L.out_d = out;
+  L.partial_inv = partial_inv_;
+  launch_G<double>(n_, L, st_);
+}
+
+void Engine::debug_apply_G(const double* in, double* out, int precision) {
+  if (!in || !out) throw Error(RVE_EINVAL, "null field");
+  RVE_HIP(hipMemcpyAsync(r64_, in, 9 * N_ * sizeof(double),
+                         hipMemcpyHostToDevice, st_));
+  if (precision == RVE_PREC_FP64) {
+    apply_G_fp64(r64_, P_);
+  } else if (precision == RVE_PREC_MIXED) {
+    if (!dbg32_) {
+      dbg32_ = alloc(9 * N_ * sizeof(float));
+      dbgspec32_ = alloc(9 * N_ / 2 * 2 * sizeof(float));
+    }
+    launch_convert<float>(r64_, (float*)dbg32_, 9 * N_, st_);
+    SpectralLaunch<float> L;
+    L.src = SRC_FIELD;
+    L.in_field = (const float*)dbg32_;
+    L.spec = (cplx<float>*)dbgspec32_;
+    L.tw = (const cplx<float>*)tw32_;
+    L.vt = (const float*)vt32_;
+    L.dst = DST_NORM;
+    L.out_d = P_;
+    L.partial_inv = partial_inv_;
+    launch_G<float>(n_, L, st_);
+  } else {
+    throw Error(RVE_EINVAL, "unknown precision");
+  }
+  RVE_HIP(hipGetLastError());
+  RVE_HIP(hipMemcpyAsync(out, P_, 9 * N_ * sizeof(double), hipMemcpyDeviceToHost,
+                         st_));
+  RVE_HIP(hipStreamSynchronize(st_));
+}
+
+void Engine::debug_constitutive(const double* F, double dt, double* P, double* K,
+                                double* dg, int32_t* fails) {
+  if (!have_micro_) throw Error(RVE_ESTATE, "no microstructure set");
+  if (!F || !(dt > 0)) throw Error(RVE_EINVAL, "null F or dt <= 0");
+  RVE_HIP(hipMemcpyAsync(F_, F, 9 * N_ * sizeof(double), hipMemcpyHostToDevice,
+                         st_));
+  launch_fill_i32(&sc_->fails, 0, 1, st_);
+  ConstArgs a{};
+  a.F = F_;
+  a.Fpi0 = Fpi_c_;
+  a.chi0 = chi_c_;
+  a.dg0 = nullptr;
+  a.phase = phase_;
+  a.table = table_;
+  a.P = P_;
+  a.Fpi = Fpi_t_;
+  a.chi = chi_t_;
+  a.dg = dg_t_;
+  a.fails = &sc_->fails;
+  a.lp = law_params(dt);
+  a.N = N_;
+  launch_return_map(a, st_);
+  if (K) {
+    if (!fp64_ && !dbgK64_) dbgK64_ = alloc(81 * N_ * sizeof(double));
+    TangentArgs<double> t{};
+    t.F = F_;
+    t.Fpi0 = Fpi_c_;
+    t.chi0 = chi_c_;
+    t.dg = dg_t_;
+    t.phase = phase_;
+    t.table = table_;
+    t.K = (double*)(fp64_ ? K_ : dbgK64_);
+    t.lp = law_params(dt);
+    t.N = N_;
+    launch_tangent<double>(t, st_);
+  }
+  RVE_HIP(hipGetLastError());
+  Scalars h;
+  read_scalars(h);
+  if (fails) *fails = h.fails;
+  if (P)
+    RVE_HIP(hipMemcpyAsync(P, P_, 9 * N_ * sizeof(double), hipMemcpyDeviceToHost, st_));
+  if (K)
+    RVE_HIP(hipMemcpyAsync(K, fp64_ ? K_ : dbgK64_, 81 * N_ * sizeof(double),
+                           hipMemcpyDeviceToHost, st_));
+  if (dg)
+    RVE_HIP(hipMemcpyAsync(dg, dg_t_, 12 * N_ * sizeof(double),
+                           hipMemcpyDeviceToHost, st_));
+  RVE_HIP(hipStreamSynchronize(st_));
+}
+
+void Engine::debug_set_field(int field, const double* src, size_t bytes) {
+  double* dst = nullptr;
+  size_t need = 0;
+  switch (field) {
+    case RVE_FIELD_F: dst = Fprev_; need = 9; break;
+    case RVE_FIELD_FPINV: dst = Fpi_c_; need = 9; break;
+    case RVE_FIELD_CHI: dst = chi_c_; need = 12; break;
+    default: throw Error(RVE_EINVAL, "field cannot be set");
+  }
+  need *= N_ * sizeof(double);
+  if (!src || bytes < need) throw Error(RVE_EINVAL, "source too small");
+  RVE_HIP(hipMemcpyAsync(dst, src, need, hipMemcpyHostToDevice, st_));
+  RVE_HIP(hipStreamSynchronize(st_));
+}
+
+// Average duration (ms) of each hot-path kernel, timed with HIP events on
+// the engine's stream over `reps` launches of the solver's own launch
+// configuration, on the buffers of the last increment:
+//   0 pass A (K:p, direction update, z/y FFT)   1 pass B (x FFT, projection)
+//   2 pass C (inverse y/z FFT, p.Ap)            3 CG vector update
+//   4 return mapping (FP64)                     5 tangent
+//   6 FP64 residual G(P) (three passes + reduction)
+void Engine::bench_kernels(int reps, double* ms, int count) {
+  if (!have_micro_ || increments_ < 1)
+    throw Error(RVE_ESTATE, "run at least one increment first");
+  if (reps < 1 || !ms) throw Error(RVE_EINVAL, "bad arguments");
+  hipEvent_t ev[2];
+  RVE_HIP(hipEventCreate(&ev[0]));
+  RVE_HIP(hipEventCreate(&ev[1]));
+  double out[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  auto timed = [&](int slot, auto&& launch) {
+    launch();  // untimed first launch
+    RVE_HIP(hipEventRecord(ev[0], st_));
+    for (int i = 0; i < reps; ++i) launch();
+    RVE_HIP(hipEventRecord(ev[1], st_));
+    RVE_HIP(hipEventSynchronize(ev[1]));
+    float t = 0.f;
+    RVE_HIP(hipEventElapsedTime(&t, ev[0], ev[1]));
+    out[slot] = (double)t / reps;
+  };
+  const double dt = 0.1;
+  timed(4, [&] {
+    ConstArgs a{};
+    a.F = F_;
+    a.Fpi0 = Fpi_c_;
+    a.chi0 = chi_c_;
+    a.dg0 = dg_c_;
+    a.phase = phase_;
+    a.table = table_;
+    a.P = P_;
+    a.Fpi = Fpi_t_;
+    a.chi = chi_t_;
+    a.dg = dg_t_;
+    a.fails = &sc_->fails;
+    a.lp = law_params(dt);
+    a.N = N_;
+    launch_return_map(a, st_);
+  });
+  timed(5, [&] {
+    if (fp64_) tangent<double>(dt); else tangent<float>(dt);
+  });
+  timed(6, [&] { residual_passes(P_); });
+  auto passes = [&](auto tag, int mask) {
+    using T = decltype(tag);
+    const bool dbl = sizeof(T) == sizeof(double);
+    SpectralLaunch<T> L;
+    L.src = SRC_KP;
+    L.K = (const T*)K_;
+    L.r = (const T*)r_;
+    L.p_old = (const T*)p0_;
+    L.p_new = (T*)p1_;
+    L.spec = (cplx<T>*)spec_;
+    L.tw = (const cplx<T>*)(dbl ? tw64_ : tw32_);
+    L.vt = (const T*)(dbl ? vt64_ : vt32_);
+    L.dst = DST_DOT;
+    L.out_T = (T*)Ap_;
+    L.partial_inv = partial_inv_;
+    L.sc = sc_;
+    L.passes = mask;
+    launch_G<T>(n_, L, st_);
+  };
+  launch_bench_scalars(sc_, st_);
+  for (int b = 0; b < 3; ++b) {
+    timed(b, [&] {
+      if (fp64_) passes(double{}, 1 << b); else passes(float{}, 1 << b);
+    });
+  }
+  timed(3, [&] {
+    if (fp64_)
+      launch_cg_update<double>((double*)x_, (double*)r_, (const double*)p1_,
+                               (const double*)Ap_, sc_, partial_red_,
+                               kRedBlocks, 9 * N_, st_);
+    else
+      launch_cg_update<float>((float*)x_, (float*)r_, (const float*)p1_,
+                              (const float*)Ap_, sc_, partial_red_, kRedBlocks,
+                              9 * N_, st_);
+  });
+  RVE_HIP(hipGetLastError());
+  RVE_HIP(hipEventDestroy(ev[0]));
+  RVE_HIP(hipEventDestroy(ev[1]));
+  for (int i = 0; i < count && i < 8; ++i) ms[i] = out[i];
+}
+
+void Engine::swap_trial_sets() {
+  std::swap(P_, P2_);
+  std::swap(Fpi_t_, Fpi_t2_);
+  std::swap(chi_t_, chi_t2_);
+  std::swap(dg_t_, dg_t2_);
+  std::swap(r64_, r64b_);
+}
+
+void Engine::attach_net(Net* net) {
+  if (net && n_ % 16) throw Error(RVE_EINVAL, "the network needs n divisible by 16");
+  if (net && !X0_) {
+    const size_t f9 = 9 * N_ * sizeof(double), f12 = 12 * N_ * sizeof(double);
+    X0_ = (uint16_t*)alloc(N_ * kFeat * sizeof(uint16_t));
+    Ynet_ = (float*)alloc(N_ * kOut * sizeof(float));
+    F2_ = (double*)alloc(f9);
+    P2_ = (double*)alloc(f9);
+    Fpi_t2_ = (double*)alloc(f9);
+    chi_t2_ = (double*)alloc(f12);
+    dg_t2_ = (double*)alloc(f12);
+    r64b_ = (double*)alloc(f9);
+  }
+  net_ = net;
+}
+
+void Engine::feature_args(const double Fbar_new[9], FeatArgs& a, double& s_k) {
+  double dF[9], s2 = 0.0, dot = 0.0;
+  for (int i = 0; i < 9; ++i) {
+    dF[i] = Fbar_new[i] - Fbar_[i];
+    s2 += dF[i] * dF[i];
+    dot += dF[i] * dFbar_prev_[i];
+  }
+  s_k = std::sqrt(s2);
+  a.Fprev = Fprev_;
+  a.dFt_prev = dFt_prev_;
+  a.dg_prev = dg_c_;
+  a.phase = phase_;
+  a.table = table_;
+  for (int i = 0; i < 9; ++i) {
+    a.fbar_prev[i] = Fbar_[i];
+    a.dfbar_n[i] = s_k > 0 ? dF[i] / s_k : 0.0;
+  }
+  a.inv_s_prev = s_prev_ > 0 ? 1.0 / s_prev_ : 0.0;
+  a.reversal = (s_k > 0 && s_prev_ > 0) ? dot / (s_k * s_prev_) : 0.0;
+  a.N = N_;
+}
+
+void Engine::features(const double Fbar_new[9], uint16_t* dst) {
+  if (!have_micro_) throw Error(RVE_ESTATE, "no microstructure set");
+  if (!dst) throw Error(RVE_EINVAL, "null destination");
+  FeatArgs a{};
+  double s_k;
+  feature_args(Fbar_new, a, s_k);
+  a.X = dst;
+  nn_features(a, st_);
+  RVE_HIP(hipGetLastError());
+  RVE_HIP(hipStreamSynchronize(st_));
+}
+
+void Engine::target(float* dst) {
+  if (increments_ < 1) throw Error(RVE_ESTATE, "no committed increment yet");
+  if (!dst) throw Error(RVE_EINVAL, "null destination");
+  nn_target(dFt_prev_, s_prev_ > 0 ? 1.0 / s_prev_ : 0.0, dst, N_, st_);
+  RVE_HIP(hipGetLastError());
+  RVE_HIP(hipStreamSynchronize(st_));
+}
+
+// F2_ = plain predictor + G(network prediction) (the prediction is projected
+// so that it is compatible, periodic and of zero mean)
+bool Engine::learned_candidate(const double Fbar_new[9]) {
+  if (increments_ < 1) return false;  // no history for the features yet
+  FeatArgs a{};
+  double s_k;
+  feature_args(Fbar_new, a, s_k);
+  if (!(s_k > 0)) return false;
+  a.X = X0_;
+  nn_features(a, st_);
+  net_->forward(X0_, n_, Ynet_, st_);
+  nn_output_to_field(Ynet_, s_k, P2_, N_, st_);
+  apply_G_fp64(P2_, r64b_);
+  RVE_HIP(hipMemcpyAsync(F2_, F_, 9 * N_ * sizeof(double),
+                         hipMemcpyDeviceToDevice, st_));
+  nn_axpy_field(F2_, r64b_, 9 * N_, st_);
+  RVE_HIP(hipGetLastError());
+  return true;
+}
+
+}  // namespace rve

@@ -1,0 +1,129 @@
+// The RVE engine: device state of one periodic cell and the increment
+// algorithm (Sec. 2.1 of Lucarini & Segurado): homogeneous predictor, Newton
+// iterations with an FP64 equilibrium check, CG linear solves of
+// G(K : dF) = -G(P), commit of the internal variables on convergence.
+#pragma once
+
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/rve.h"
+#include "kernels.hpp"
+#include "nn.hpp"
+
+namespace rve {
+
+class Engine {
+ public:
+  explicit Engine(const rve_config& cfg);
+  ~Engine();
+
+  void set_microstructure(const int32_t* phase, int32_t G, const double* quat,
+                          const int32_t* law, const double* params,
+                          int32_t nparams);
+  int increment(const double Fbar_new[9], double dt, rve_increment_info* info);
+  void reset_fips();
+  void get_field(int field, void* dst, size_t bytes, bool on_device);
+  void get_macro(double out[29]);
+  size_t state_size() const;
+  void get_state(void* dst, size_t bytes);
+  void set_state(const void* src, size_t bytes);
+  void debug_apply_G(const double* in, double* out, int precision);
+  void debug_constitutive(const double* F, double dt, double* P, double* K,
+                          double* dg, int32_t* fails);
+  void debug_set_field(int field, const double* src, size_t bytes);
+  void bench_kernels(int reps, double* ms, int count);
+
+  // pieces used by the learned warm start
+  hipStream_t stream() const { return st_; }
+  int n() const { return n_; }
+  int64_t voxels() const { return N_; }
+  double* dev_F() { return F_; }
+  double* dev_Fprev() { return Fprev_; }
+  const double* dF_last() const { return dFlast_; }
+  void apply_G_fp64(const double* in, double* out);
+  const rve_config& config() const { return cfg_; }
+  // learned warm start
+  void attach_net(Net* net);
+  void features(const double Fbar_new[9], uint16_t* dst_dev);
+  void target(float* dst_dev);
+
+  std::string err;
+  bool poisoned = false;
+
+ private:
+  void* alloc(size_t bytes);
+  void free_all();
+  template <typename T>
+  void cg_solve(int& iters, bool& breakdown);
+  template <typename T>
+  void cg_iteration(int parity);
+  template <typename T>
+  void capture_graph();
+  void read_scalars(Scalars& h);
+  LawParams law_params(double dt) const;
+  void residual_passes(const double* P);
+  int evaluate(const double* dg_start, double dt, double& rel,
+               double& res, double& pn);
+  void commit(double dt);
+  template <typename T>
+  void tangent(double dt);
+  void feature_args(const double Fbar_new[9], FeatArgs& a, double& s_k);
+  bool learned_candidate(const double Fbar_new[9]);
+  void swap_trial_sets();
+
+  rve_config cfg_;
+  int n_;
+  int64_t N_;
+  bool fp64_;
+  hipStream_t st_;
+  std::vector<std::pair<void*, size_t>> allocs_;
+
+  // committed state
+  double *Fprev_, *Pc_, *Fpi_c_, *chi_c_, *dg_c_;
+  double *pcyc_, *pcyc_lit_, *wcyc_;
+  // Newton scratch
+  double *F_, *P_, *Fpi_t_, *chi_t_, *dg_t_, *r64_;
+  void* K_;      // [81][N] float (mixed) or double (fp64)
+  // CG vectors (T) and spectra
+  void *x_, *r_, *p0_, *p1_, *Ap_;
+  void* spec_;        // complex T
+  void* spec64_;      // complex double (aliases spec_ in fp64 mode)
+  double *partial_inv_, *partial_red_, *psum_, *psq_, *pbar_;
+  Scalars* sc_;
+  Scalars* sc_host_ = nullptr;
+  int32_t* phase_;
+  double* table_;
+  void *tw32_, *tw64_, *vt32_, *vt64_;
+  int nslab32_, nslab64_;
+  int labels_ = 0;
+  bool have_micro_ = false;
+  double params_[RVE_NPARAMS];
+
+  // macro state
+  double Fbar_[9];
+  double Pbar_[9];
+  double Pbar_new_[9];
+  double dFlast_[9];
+  double t_ = 0.0;
+  int64_t increments_ = 0;
+
+  hipStream_t own_stream_ = nullptr;
+  void* dbg32_ = nullptr;
+  void* dbgspec32_ = nullptr;
+  void* dbgK64_ = nullptr;
+  hipGraphExec_t graph_ = nullptr;
+  hipGraph_t graph_def_ = nullptr;
+  Net* net_ = nullptr;
+  double* dFt_prev_ = nullptr;        // fluctuation increment of the last increment
+  double dFbar_prev_[9];
+  double s_prev_ = 0.0;
+  uint16_t* X0_ = nullptr;            // network input
+  float* Ynet_ = nullptr;             // network output
+  // second trial set for the learned-vs-plain predictor comparison
+  double *F2_ = nullptr, *P2_ = nullptr, *Fpi_t2_ = nullptr, *chi_t2_ = nullptr,
+         *dg_t2_ = nullptr, *r64b_ = nullptr;
+};
+
+}  // namespace rve

@@ -1,0 +1,646 @@
+// Point constitutive update (Sec. 2.1, Eq. 2) and material tangent
+// K = dP/dF (Eq. 13), one FP64 thread per voxel.
+//
+// Grains: FCC crystal plasticity with the power-law flow rule of Sec. 3.2,
+// Eq. 22 (constant critical stress g, rate exponent n) and an
+// Armstrong-Frederick back stress, integrated by backward Euler over dt at
+// the committed state (Fp^-1_0, chi_0):
+//   Fp^-1 = Fp^-1_0 (I - sum_a dg_a s_a (x) m_a),  Fe = F Fp^-1,
+//   S = C : (Fe^T Fe - I)/2,  tau_a = s_a . S m_a,
+//   chi_a = (chi_0a + c dg_a)/(1 + d |dg_a|),  x_a = (tau_a - chi_a)/g,
+//   P = Fe S Fp^-T.
+// The 12 slips solve R_a = asinh(dg_a/a) - asinh(|x_a|^n sign x_a) = 0
+// (a = dt gdot0), which has the roots of dg_a = a |x_a|^n sign x_a but stays
+// well scaled under large overstress.  Damped Newton with backtracking on
+// |R|^2/2; a failed warm-started solve is retried from zero slips.
+//
+// The 12x12 Jacobian is diag(D) + U W^T with rank-6 factors (the resolved
+// stresses depend on the slips only through the symmetric elastic strain),
+// so each Newton step and each tangent column costs one 6x6 solve
+// (Sherman-Morrison-Woodbury) instead of a 12x12 one.
+//
+// Particles: isotropic St-Venant-Kirchhoff, P = F S, S = lam tr(E) I + 2 mu E.
+#include "kernels.hpp"
+
+namespace rve {
+
+namespace {
+
+constexpr int LOCAL_MAXIT = 60;
+constexpr double LOCAL_RTOL = 1e-10;
+constexpr double LOCAL_ATOL = 1e-18;
+constexpr double LOCAL_RFLOOR = 1e-10;
+
+// Voigt order 11, 22, 33, 23, 13, 12
+__device__ constexpr int VI[3][3] = {{0, 5, 4}, {5, 1, 3}, {4, 3, 2}};
+__device__ constexpr double VW[6] = {1, 1, 1, 2, 2, 2};
+
+__device__ __forceinline__ double sgn(double x) {
+  return (x > 0.0) ? 1.0 : ((x < 0.0) ? -1.0 : 0.0);
+}
+
+// asinh(|x|^n sign x) and its derivative; for |x|^n > 1 the identity
+// asinh(y) = ln y + ln(1 + sqrt(1 + y^-2)) avoids forming the power.
+__device__ __forceinline__ void asinh_pow(double x, double n, double& val,
+                                          double& der) {
+  const double ax = fabs(x);
+  if (ax == 0.0) {
+    val = 0.0;
+    der = 0.0;
+    return;
+  }
+  const double lnx = log(ax);
+  if (n * lnx > 0.0) {
+    const double yinv = exp(-n * lnx);
+    const double q = sqrt(1.0 + yinv * yinv);
+    val = sgn(x) * (n * lnx + log1p(q));
+    der = (n / ax) / q;
+  } else {
+    const double y = exp(n * lnx);
+    val = sgn(x) * asinh(y);
+    der = n * y / ax / sqrt(1.0 + y * y);
+  }
+}
+
+__device__ __forceinline__ void mm3(const double* A, const double* B,
+                                    double* C) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      C[3 * i + j] = A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] +
+                     A[3 * i + 2] * B[6 + j];
+}
+
+// S (Voigt) = C : E (Voigt), C_IJ from the table
+__device__ __forceinline__ void cmul6(const double* __restrict__ Cv,
+                                      const double* E, double* S) {
+#pragma unroll
+  for (int I = 0; I < 6; ++I) {
+    double acc = 0.0;
+#pragma unroll
+    for (int J = 0; J < 6; ++J) acc += Cv[6 * I + J] * VW[J] * E[J];
+    S[I] = acc;
+  }
+}
+
+struct CpEval {
+  double Fe[9];
+  double S[6];
+  double chi[12];
+  double x[12];
+  double R[12];
+};
+
+// Return-mapping residual at slips dg.  Fes = F Fp^-1_0.
+__device__ __forceinline__ void cp_eval(const double* Fes,
+                                        const double* chi0, const double* dg,
+                                        const double* __restrict__ tb,
+                                        const LawParams& lp, double a,
+                                        CpEval& e) {
+#pragma unroll
+  for (int i = 0; i < 9; ++i) e.Fe[i] = Fes[i];
+#pragma unroll
+  for (int al = 0; al < 12; ++al) {
+    const double s0 = tb[kTabS + 3 * al], s1 = tb[kTabS + 3 * al + 1],
+                 s2 = tb[kTabS + 3 * al + 2];
+    const double m0 = tb[kTabM + 3 * al], m1 = tb[kTabM + 3 * al + 1],
+                 m2 = tb[kTabM + 3 * al + 2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double u = dg[al] * (Fes[3 * i] * s0 + Fes[3 * i + 1] * s1 +
+                                 Fes[3 * i + 2] * s2);
+      e.Fe[3 * i] -= u * m0;
+      e.Fe[3 * i + 1] -= u * m1;
+      e.Fe[3 * i + 2] -= u * m2;
+    }
+  }
+  double C[9];
+#pragma unroll
+  for (int p = 0; p < 3; ++p)
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      C[3 * p + q] = e.Fe[p] * e.Fe[q] + e.Fe[3 + p] * e.Fe[3 + q] +
+                     e.Fe[6 + p] * e.Fe[6 + q];
+  const double E[6] = {0.5 * (C[0] - 1.0), 0.5 * (C[4] - 1.0),
+                       0.5 * (C[8] - 1.0), 0.5 * C[5],
+                       0.5 * C[2],         0.5 * C[1]};
+  cmul6(tb + kTabC, E, e.S);
+  const double* S = e.S;
+#pragma unroll
+  for (int al = 0; al < 12; ++al) {
+    const double s0 = tb[kTabS + 3 * al], s1 = tb[kTabS + 3 * al + 1],
+                 s2 = tb[kTabS + 3 * al + 2];
+    const double m0 = tb[kTabM + 3 * al], m1 = tb[kTabM + 3 * al + 1],
+                 m2 = tb[kTabM + 3 * al + 2];
+    const double Sm0 = S[0] * m0 + S[5] * m1 + S[4] * m2;
+    const double Sm1 = S[5] * m0 + S[1] * m1 + S[3] * m2;
+    const double Sm2 = S[4] * m0 + S[3] * m1 + S[2] * m2;
+    const double tau = s0 * Sm0 + s1 * Sm1 + s2 * Sm2;
+    const double chi = (chi0[al] + lp.c_af * dg[al]) / (1.0 + lp.d_af * fabs(dg[al]));
+    const double x = (tau - chi) / lp.g;
+    double val, der;
+    asinh_pow(x, lp.nexp, val, der);
+    e.chi[al] = chi;
+    e.x[al] = x;
+    e.R[al] = asinh(dg[al] / a) - val;
+  }
+}
+
+// Q = Fe^T Fes
+__device__ __forceinline__ void make_Q(const double* Fe, const double* Fes,
+                                       double* Q) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      Q[3 * i + j] = Fe[i] * Fes[j] + Fe[3 + i] * Fes[3 + j] +
+                     Fe[6 + i] * Fes[6 + j];
+}
+
+// V_a = sym((Q s_a) (x) m_a) in Voigt order
+__device__ __forceinline__ void make_V(const double* Q,
+                                       const double* __restrict__ tb, int al,
+                                       double* V) {
+  const double s0 = tb[kTabS + 3 * al], s1 = tb[kTabS + 3 * al + 1],
+               s2 = tb[kTabS + 3 * al + 2];
+  const double m[3] = {tb[kTabM + 3 * al], tb[kTabM + 3 * al + 1],
+                       tb[kTabM + 3 * al + 2]};
+  double qs[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) qs[i] = Q[3 * i] * s0 + Q[3 * i + 1] * s1 + Q[3 * i + 2] * s2;
+  V[0] = qs[0] * m[0];
+  V[1] = qs[1] * m[1];
+  V[2] = qs[2] * m[2];
+  V[3] = 0.5 * (qs[1] * m[2] + qs[2] * m[1]);
+  V[4] = 0.5 * (qs[0] * m[2] + qs[2] * m[0]);
+  V[5] = 0.5 * (qs[0] * m[1] + qs[1] * m[0]);
+}
+
+// Gaussian elimination of the 6x6 capacitance matrix with partial pivoting
+// by compare-and-swap; the swap decisions are kept for later right-hand sides.
+struct LU6 {
+  double M[36];
+  uint32_t swaps;
+};
+
+__device__ __forceinline__ void lu6_factor(LU6& L) {
+  uint32_t sw = 0;
+  int bit = 0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+#pragma unroll
+    for (int r = k + 1; r < 6; ++r) {
+      const bool s = fabs(L.M[6 * r + k]) > fabs(L.M[6 * k + k]);
+      if (s) {
+        // columns < k hold the multipliers of earlier steps; they stay with
+        // the step that made them (the solve applies swap k, then step k)
+#pragma unroll
+        for (int j = k; j < 6; ++j) {
+          const double t = L.M[6 * k + j];
+          L.M[6 * k + j] = L.M[6 * r + j];
+          L.M[6 * r + j] = t;
+        }
+      }
+      sw |= (s ? 1u : 0u) << bit;
+      ++bit;
+    }
+    const double inv = 1.0 / L.M[6 * k + k];
+#pragma unroll
+    for (int r = k + 1; r < 6; ++r) {
+      const double f = L.M[6 * r + k] * inv;
+      L.M[6 * r + k] = f;
+#pragma unroll
+      for (int j = k + 1; j < 6; ++j) L.M[6 * r + j] -= f * L.M[6 * k + j];
+    }
+  }
+  L.swaps = sw;
+}
+
+__device__ __forceinline__ void lu6_solve(const LU6& L, double* z) {
+  int bit = 0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+#pragma unroll
+    for (int r = k + 1; r < 6; ++r) {
+      if ((L.swaps >> bit) & 1u) {
+        const double t = z[k];
+        z[k] = z[r];
+        z[r] = t;
+      }
+      ++bit;
+    }
+#pragma unroll
+    for (int r = k + 1; r < 6; ++r) z[r] -= L.M[6 * r + k] * z[k];
+  }
+#pragma unroll
+  for (int k = 5; k >= 0; --k) {
+    double acc = z[k];
+#pragma unroll
+    for (int j = k + 1; j < 6; ++j) acc -= L.M[6 * k + j] * z[j];
+    z[k] = acc / L.M[6 * k + k];
+  }
+}
+
+// Diagonal D, factor h and the factored capacitance matrix at the slips dg.
+__device__ __forceinline__ void cp_jacobian(const CpEval& e, const double* Fes,
+                                            const double* dg,
+                                            const double* __restrict__ tb,
+                                            const LawParams& lp, double a,
+                                            double* D, double* hg, double* Q,
+                                            LU6& L) {
+  make_Q(e.Fe, Fes, Q);
+#pragma unroll
+  for (int i = 0; i < 36; ++i) L.M[i] = (i % 7 == 0) ? 1.0 : 0.0;
+#pragma unroll
+  for (int al = 0; al < 12; ++al) {
+    double val, h;
+    asinh_pow(e.x[al], lp.nexp, val, h);
+    const double ad = fabs(dg[al]);
+    const double dchi = (lp.c_af - lp.d_af * sgn(dg[al]) * e.chi[al]) / (1.0 + lp.d_af * ad);
+    D[al] = 1.0 / sqrt(a * a + dg[al] * dg[al]) + h * dchi / lp.g;
+    hg[al] = h / lp.g;
+    double V[6];
+    make_V(Q, tb, al, V);
+    const double f = hg[al] / D[al];
+#pragma unroll
+    for (int I = 0; I < 6; ++I)
+#pragma unroll
+      for (int J = 0; J < 6; ++J)
+        L.M[6 * I + J] += V[I] * f * VW[J] * tb[kTabN + 6 * al + J];
+  }
+  lu6_factor(L);
+}
+
+// out = J^-1 rhs with J = diag(D) + U W^T, U_a = hg_a w N_a, W_a = V_a
+__device__ __forceinline__ void cp_jsolve(const double* rhs, const double* D,
+                                          const double* hg, const double* Q,
+                                          const double* __restrict__ tb,
+                                          const LU6& L, double* out) {
+  double z[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int al = 0; al < 12; ++al) {
+    out[al] = rhs[al] / D[al];
+    double V[6];
+    make_V(Q, tb, al, V);
+#pragma unroll
+    for (int I = 0; I < 6; ++I) z[I] += V[I] * out[al];
+  }
+  lu6_solve(L, z);
+#pragma unroll
+  for (int al = 0; al < 12; ++al) {
+    double u = 0.0;
+#pragma unroll
+    for (int J = 0; J < 6; ++J) u += VW[J] * tb[kTabN + 6 * al + J] * z[J];
+    out[al] -= hg[al] * u / D[al];
+  }
+}
+
+__device__ __forceinline__ double half_sq(const double* R) {
+  double m = 0.0;
+#pragma unroll
+  for (int i = 0; i < 12; ++i) m += R[i] * R[i];
+  return 0.5 * m;
+}
+
+// Damped Newton from the slips in dg; returns true on convergence and
+// leaves the evaluation at the final slips in e.
+__device__ bool cp_local_solve(const double* Fes, const double* chi0,
+                               double* dg, const double* __restrict__ tb,
+                               const LawParams& lp, double a, CpEval& e,
+                               int& iters) {
+  cp_eval(Fes, chi0, dg, tb, lp, a, e);
+  for (int it = 0; it < LOCAL_MAXIT; ++it) {
+    ++iters;
+    double D[12], hg[12], Q[9];
+    LU6 L;
+    cp_jacobian(e, Fes, dg, tb, lp, a, D, hg, Q, L);
+    double negR[12], step[12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) negR[i] = -e.R[i];
+    cp_jsolve(negR, D, hg, Q, tb, L, step);
+    double smax = 0.0, dmax = 0.0, rmax = 0.0;
+    bool finite = true;
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+      smax = fmax(smax, fabs(step[i]));
+      dmax = fmax(dmax, fabs(dg[i] + step[i]));
+      rmax = fmax(rmax, fabs(e.R[i]));
+      finite = finite && isfinite(step[i]);
+    }
+    if (finite && smax <= LOCAL_ATOL + LOCAL_RTOL * dmax) {
+#pragma unroll
+      for (int i = 0; i < 12; ++i) dg[i] += step[i];
+      cp_eval(Fes, chi0, dg, tb, lp, a, e);
+      return true;
+    }
+    const double merit0 = half_sq(e.R);
+    double lam = 1.0;
+    bool accepted = false;
+    double trial[12];
+    for (int ls = 0; ls < 40; ++ls) {
+#pragma unroll
+      for (int i = 0; i < 12; ++i) trial[i] = dg[i] + lam * step[i];
+      cp_eval(Fes, chi0, trial, tb, lp, a, e);
+      const double mt = half_sq(e.R);
+      if (isfinite(mt) && mt <= (1.0 - 1e-4 * lam) * merit0) {
+        accepted = true;
+        break;
+      }
+      lam *= 0.5;
+    }
+    bool okv = true;
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+      dg[i] = trial[i];
+      okv = okv && isfinite(dg[i]);
+    }
+    if (!okv) return false;
+    if (!accepted && rmax <= LOCAL_RFLOOR) return true;
+  }
+  return false;
+}
+
+__device__ __forceinline__ void load9(const double* __restrict__ p, int64_t v,
+                                      int64_t N, double* o) {
+#pragma unroll
+  for (int c = 0; c < 9; ++c) o[c] = p[c * N + v];
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(128) void return_map_kernel(ConstArgs A) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= A.N) return;
+  const int64_t N = A.N;
+  const double* __restrict__ tb = A.table + (int64_t)A.phase[v] * kTableStride;
+  double F[9];
+  load9(A.F, v, N, F);
+  if (tb[0] != 0.0) {  // isotropic SVK particle
+    const double lam = tb[kTabLam], mu = tb[kTabMu];
+    double C[9];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        C[3 * p + q] = F[p] * F[q] + F[3 + p] * F[3 + q] + F[6 + p] * F[6 + q];
+    const double tr = 0.5 * (C[0] + C[4] + C[8] - 3.0);
+    double S[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) S[i] = mu * (C[i] - ((i % 4 == 0) ? 1.0 : 0.0));
+    S[0] += lam * tr;
+    S[4] += lam * tr;
+    S[8] += lam * tr;
+    double P[9];
+    mm3(F, S, P);
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+      A.P[c * N + v] = P[c];
+      A.Fpi[c * N + v] = A.Fpi0[c * N + v];
+    }
+#pragma unroll
+    for (int al = 0; al < 12; ++al) {
+      A.chi[al * N + v] = A.chi0[al * N + v];
+      A.dg[al * N + v] = 0.0;
+    }
+    if (A.iters) A.iters[v] = 0;
+    return;
+  }
+  double Fpi0[9], chi0[12], dg[12];
+  load9(A.Fpi0, v, N, Fpi0);
+  bool warm = false;
+#pragma unroll
+  for (int al = 0; al < 12; ++al) {
+    chi0[al] = A.chi0[al * N + v];
+    dg[al] = A.dg0 ? A.dg0[al * N + v] : 0.0;
+    warm = warm || (dg[al] != 0.0);
+  }
+  double Fes[9];
+  mm3(F, Fpi0, Fes);
+  const double a = A.lp.dt * A.lp.gdot0;
+  CpEval e;
+  int iters = 0;
+  bool ok = cp_local_solve(Fes, chi0, dg, tb, A.lp, a, e, iters);
+  if (!ok && warm) {
+#pragma unroll
+    for (int al = 0; al < 12; ++al) dg[al] = 0.0;
+    ok = cp_local_solve(Fes, chi0, dg, tb, A.lp, a, e, iters);
+  }
+  if (!ok) atomicAdd(A.fails, 1);
+  // Fp^-1 = Fp^-1_0 (I - sum dg s (x) m);  P = Fe S Fp^-T
+  double Fpi[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Fpi[i] = Fpi0[i];
+#pragma unroll
+  for (int al = 0; al < 12; ++al) {
+    const double s0 = tb[kTabS + 3 * al], s1 = tb[kTabS + 3 * al + 1],
+                 s2 = tb[kTabS + 3 * al + 2];
+    const double m0 = tb[kTabM + 3 * al], m1 = tb[kTabM + 3 * al + 1],
+                 m2 = tb[kTabM + 3 * al + 2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double u = dg[al] * (Fpi0[3 * i] * s0 + Fpi0[3 * i + 1] * s1 +
+                                 Fpi0[3 * i + 2] * s2);
+      Fpi[3 * i] -= u * m0;
+      Fpi[3 * i + 1] -= u * m1;
+      Fpi[3 * i + 2] -= u * m2;
+    }
+  }
+  double Sf[9] = {e.S[0], e.S[5], e.S[4], e.S[5], e.S[1],
+                  e.S[3], e.S[4], e.S[3], e.S[2]};
+  double FeS[9], P[9];
+  mm3(e.Fe, Sf, FeS);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      P[3 * i + j] = FeS[3 * i] * Fpi[3 * j] + FeS[3 * i + 1] * Fpi[3 * j + 1] +
+                     FeS[3 * i + 2] * Fpi[3 * j + 2];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) {
+    A.P[c * N + v] = P[c];
+    A.Fpi[c * N + v] = Fpi[c];
+  }
+#pragma unroll
+  for (int al = 0; al < 12; ++al) {
+    A.chi[al * N + v] = e.chi[al];
+    A.dg[al * N + v] = dg[al];
+  }
+  if (A.iters) A.iters[v] = iters;
+}
+
+template <typename TK>
+__global__ __launch_bounds__(128) void tangent_kernel(TangentArgs<TK> A) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= A.N) return;
+  const int64_t N = A.N;
+  const double* __restrict__ tb = A.table + (int64_t)A.phase[v] * kTableStride;
+  double F[9];
+  load9(A.F, v, N, F);
+  if (tb[0] != 0.0) {
+    // K_ijkl = d_ik S_lj + lam F_ij F_kl + mu F_il F_kj + mu (F F^T)_ik d_jl
+    const double lam = tb[kTabLam], mu = tb[kTabMu];
+    double C[9], B[9];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        C[3 * p + q] = F[p] * F[q] + F[3 + p] * F[3 + q] + F[6 + p] * F[6 + q];
+        B[3 * p + q] = F[3 * p] * F[3 * q] + F[3 * p + 1] * F[3 * q + 1] +
+                       F[3 * p + 2] * F[3 * q + 2];
+      }
+    const double tr = 0.5 * (C[0] + C[4] + C[8] - 3.0);
+    double S[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) S[i] = mu * (C[i] - ((i % 4 == 0) ? 1.0 : 0.0));
+    S[0] += lam * tr;
+    S[4] += lam * tr;
+    S[8] += lam * tr;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+          for (int l = 0; l < 3; ++l) {
+            double K = lam * F[3 * i + j] * F[3 * k + l] + mu * F[3 * i + l] * F[3 * k + j];
+            if (i == k) K += S[3 * l + j];
+            if (j == l) K += mu * B[3 * i + k];
+            A.K[(int64_t)(9 * (3 * i + j) + 3 * k + l) * N + v] = TK(K);
+          }
+    return;
+  }
+  double Fpi0[9], chi0[12], dg[12];
+  load9(A.Fpi0, v, N, Fpi0);
+#pragma unroll
+  for (int al = 0; al < 12; ++al) {
+    chi0[al] = A.chi0[al * N + v];
+    dg[al] = A.dg[al * N + v];
+  }
+  double Fes[9];
+  mm3(F, Fpi0, Fes);
+  const double a = A.lp.dt * A.lp.gdot0;
+  CpEval e;
+  cp_eval(Fes, chi0, dg, tb, A.lp, a, e);
+  double D[12], hg[12], Q[9];
+  LU6 L;
+  cp_jacobian(e, Fes, dg, tb, A.lp, a, D, hg, Q, L);
+  double Fpi[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Fpi[i] = Fpi0[i];
+#pragma unroll
+  for (int al = 0; al < 12; ++al) {
+    const double s0 = tb[kTabS + 3 * al], s1 = tb[kTabS + 3 * al + 1],
+                 s2 = tb[kTabS + 3 * al + 2];
+    const double m0 = tb[kTabM + 3 * al], m1 = tb[kTabM + 3 * al + 1],
+                 m2 = tb[kTabM + 3 * al + 2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double u = dg[al] * (Fpi0[3 * i] * s0 + Fpi0[3 * i + 1] * s1 +
+                                 Fpi0[3 * i + 2] * s2);
+      Fpi[3 * i] -= u * m0;
+      Fpi[3 * i + 1] -= u * m1;
+      Fpi[3 * i + 2] -= u * m2;
+    }
+  }
+  const double Sf[9] = {e.S[0], e.S[5], e.S[4], e.S[5], e.S[1],
+                        e.S[3], e.S[4], e.S[3], e.S[2]};
+  double PS[9], FeS[9], B[9];
+  mm3(Fpi, Sf, PS);   // Fp^-1 S
+  mm3(e.Fe, Sf, FeS);  // Fe S
+#pragma unroll
+  for (int l = 0; l < 3; ++l)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      B[3 * l + j] = PS[3 * l] * Fpi[3 * j] + PS[3 * l + 1] * Fpi[3 * j + 1] +
+                     PS[3 * l + 2] * Fpi[3 * j + 2];  // Fp^-1 S Fp^-T
+  const double* Cv = tb + kTabC;
+#pragma unroll 1
+  for (int kl = 0; kl < 9; ++kl) {
+    const int k = kl / 3, l = kl - 3 * (kl / 3);
+    const double fk[3] = {e.Fe[3 * k], e.Fe[3 * k + 1], e.Fe[3 * k + 2]};
+    const double pl[3] = {Fpi[3 * l], Fpi[3 * l + 1], Fpi[3 * l + 2]};
+    // dR/dF_kl: b_a = (h_a/g) fk . N_a pl  (dtau_a/dF = Fe N_a Fp^-T)
+    double b[12], gcol[12];
+#pragma unroll
+    for (int al = 0; al < 12; ++al) {
+      const double* Na = tb + kTabN + 6 * al;
+      const double Np0 = Na[0] * pl[0] + Na[5] * pl[1] + Na[4] * pl[2];
+      const double Np1 = Na[5] * pl[0] + Na[1] * pl[1] + Na[3] * pl[2];
+      const double Np2 = Na[4] * pl[0] + Na[3] * pl[1] + Na[2] * pl[2];
+      b[al] = hg[al] * (fk[0] * Np0 + fk[1] * Np1 + fk[2] * Np2);
+    }
+    cp_jsolve(b, D, hg, Q, tb, L, gcol);  // d dg / d F_kl
+    // sigma = C : sym(fk (x) pl) - C : sum_a g_a V_a
+    double E[6], acc6[6] = {0, 0, 0, 0, 0, 0}, acc9[9];
+    E[0] = fk[0] * pl[0];
+    E[1] = fk[1] * pl[1];
+    E[2] = fk[2] * pl[2];
+    E[3] = 0.5 * (fk[1] * pl[2] + fk[2] * pl[1]);
+    E[4] = 0.5 * (fk[0] * pl[2] + fk[2] * pl[0]);
+    E[5] = 0.5 * (fk[0] * pl[1] + fk[1] * pl[0]);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) acc9[i] = 0.0;
+#pragma unroll
+    for (int al = 0; al < 12; ++al) {
+      double V[6];
+      make_V(Q, tb, al, V);
+#pragma unroll
+      for (int I = 0; I < 6; ++I) acc6[I] += gcol[al] * V[I];
+      const double s[3] = {tb[kTabS + 3 * al], tb[kTabS + 3 * al + 1],
+                           tb[kTabS + 3 * al + 2]};
+      const double m[3] = {tb[kTabM + 3 * al], tb[kTabM + 3 * al + 1],
+                           tb[kTabM + 3 * al + 2]};
+      double u[3], vv[3], w[3], y[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        u[i] = Fes[3 * i] * s[0] + Fes[3 * i + 1] * s[1] + Fes[3 * i + 2] * s[2];
+        vv[i] = PS[3 * i] * m[0] + PS[3 * i + 1] * m[1] + PS[3 * i + 2] * m[2];
+        w[i] = FeS[3 * i] * m[0] + FeS[3 * i + 1] * m[1] + FeS[3 * i + 2] * m[2];
+        y[i] = Fpi0[3 * i] * s[0] + Fpi0[3 * i + 1] * s[1] + Fpi0[3 * i + 2] * s[2];
+      }
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+          acc9[3 * i + j] += gcol[al] * (u[i] * vv[j] + w[i] * y[j]);
+    }
+#pragma unroll
+    for (int I = 0; I < 6; ++I) E[I] -= acc6[I];
+    double sg[6];
+    cmul6(Cv, E, sg);
+    const double sf[9] = {sg[0], sg[5], sg[4], sg[5], sg[1],
+                          sg[3], sg[4], sg[3], sg[2]};
+    double Fs[9];
+    mm3(e.Fe, sf, Fs);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        double K = Fs[3 * i] * Fpi[3 * j] + Fs[3 * i + 1] * Fpi[3 * j + 1] +
+                   Fs[3 * i + 2] * Fpi[3 * j + 2] - acc9[3 * i + j];
+        if (i == k) K += B[3 * l + j];
+        A.K[(int64_t)(9 * (3 * i + j) + kl) * N + v] = TK(K);
+      }
+  }
+}
+
+void launch_return_map(const ConstArgs& a, hipStream_t s) {
+  const int blk = 128;
+  const int64_t grid = (a.N + blk - 1) / blk;
+  hipLaunchKernelGGL(return_map_kernel, dim3((unsigned)grid), dim3(blk), 0, s, a);
+}
+
+template <typename TK>
+void launch_tangent(const TangentArgs<TK>& a, hipStream_t s) {
+  const int blk = 128;
+  const int64_t grid = (a.N + blk - 1) / blk;
+  hipLaunchKernelGGL((tangent_kernel<TK>), dim3((unsigned)grid), dim3(blk), 0,
+                     s, a);
+}
+
+template void launch_tangent<float>(const TangentArgs<float>&, hipStream_t);
+template void launch_tangent<double>(const TangentArgs<double>&, hipStream_t);
+
+}  // namespace rve

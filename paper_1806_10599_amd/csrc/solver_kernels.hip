@@ -1,0 +1,371 @@
+// Elementwise and reduction kernels of the Newton-CG increment:
+//   predictor F = F_prev + dFbar (Sec. 2.1, Eq. 12 with the homogeneous
+//   first guess), CG vector updates with FP64-accumulated dot products and
+//   fixed-order (deterministic) reductions (text after Eq. 16), the Newton
+//   update F += dF, the commit of the increment with the fatigue indicators
+//   of Sec. 3.3, Eqs. 23-24.
+#include "kernels.hpp"
+
+namespace rve {
+
+namespace {
+
+__device__ __forceinline__ double block_reduce(double v, double* red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (t < s) red[t] += red[t + s];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+}  // namespace
+
+__global__ void predict_kernel(double* __restrict__ F,
+                               const double* __restrict__ Fp, int64_t N,
+                               double d0, double d1, double d2, double d3,
+                               double d4, double d5, double d6, double d7,
+                               double d8) {
+  const double d[9] = {d0, d1, d2, d3, d4, d5, d6, d7, d8};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 9 * N;
+       i += (int64_t)gridDim.x * blockDim.x)
+    F[i] = Fp[i] + d[i / N];
+}
+
+void launch_predict(double* F, const double* Fprev, const double dFbar[9],
+                    int64_t N, hipStream_t s) {
+  hipLaunchKernelGGL(predict_kernel, dim3(2048), dim3(kBlock), 0, s, F, Fprev,
+                     N, dFbar[0], dFbar[1], dFbar[2], dFbar[3], dFbar[4],
+                     dFbar[5], dFbar[6], dFbar[7], dFbar[8]);
+}
+
+// r = -r64 (rounded to T), x = 0, partial sums of r.r
+template <typename T>
+__global__ __launch_bounds__(kBlock) void cg_init_kernel(
+    const double* __restrict__ r64, T* __restrict__ r, T* __restrict__ x,
+    double* __restrict__ partial, int64_t n9) {
+  __shared__ double red[kBlock];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n9;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const T b = T(-r64[i]);
+    r[i] = b;
+    x[i] = T(0);
+    acc += double(b) * double(b);
+  }
+  const double t = block_reduce(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+template <typename T>
+void launch_cg_init(const double* r64, T* r, T* x, double* partial, int nblk,
+                    int64_t n9, hipStream_t s) {
+  hipLaunchKernelGGL((cg_init_kernel<T>), dim3(nblk), dim3(kBlock), 0, s, r64,
+                     r, x, partial, n9);
+}
+
+// x += alpha p, r -= alpha Ap, partial sums of the new r.r
+template <typename T>
+__global__ __launch_bounds__(kBlock) void cg_update_kernel(
+    T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
+    const T* __restrict__ Ap, const Scalars* __restrict__ sc,
+    double* __restrict__ partial, int64_t n9) {
+  __shared__ double red[kBlock];
+  if (sc->done) return;
+  const T alpha = T(sc->alpha);
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n9;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    x[i] += alpha * p[i];
+    const T rn = r[i] - alpha * Ap[i];
+    r[i] = rn;
+    acc += double(rn) * double(rn);
+  }
+  const double t = block_reduce(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+template <typename T>
+void launch_cg_update(T* x, T* r, const T* p, const T* Ap, const Scalars* sc,
+                      double* partial, int nblk, int64_t n9, hipStream_t s) {
+  hipLaunchKernelGGL((cg_update_kernel<T>), dim3(nblk), dim3(kBlock), 0, s, x,
+                     r, p, Ap, sc, partial, n9);
+}
+
+template <typename T>
+__global__ void add_to_F_kernel(double* __restrict__ F,
+                                const T* __restrict__ x, int64_t n9) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n9;
+       i += (int64_t)gridDim.x * blockDim.x)
+    F[i] += double(x[i]);
+}
+
+template <typename T>
+void launch_add_to_F(double* F, const T* x, int64_t n9, hipStream_t s) {
+  hipLaunchKernelGGL((add_to_F_kernel<T>), dim3(2048), dim3(kBlock), 0, s, F,
+                     x, n9);
+}
+
+template <typename T>
+__global__ void convert_kernel(const double* __restrict__ in,
+                               T* __restrict__ out, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = T(in[i]);
+}
+
+template <typename T>
+void launch_convert(const double* in, T* out, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL((convert_kernel<T>), dim3(2048), dim3(kBlock), 0, s, in,
+                     out, n);
+}
+
+// Single-block fixed-order reductions that also advance the CG scalars.
+__global__ __launch_bounds__(kBlock) void reduce_kernel(
+    int op, const double* __restrict__ partial, int count,
+    const double* __restrict__ psum, const double* __restrict__ psq, int nss,
+    double invN3, Scalars* __restrict__ sc, double* __restrict__ pbar) {
+  __shared__ double red[kBlock];
+  if ((op == RED_ALPHA || op == RED_BETA) && sc->done) return;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < count; i += blockDim.x) acc += partial[i];
+  const double tot = block_reduce(acc, red);
+  if (op == RED_RESID) {
+    double a2 = 0.0;
+    for (int i = threadIdx.x; i < 9 * nss; i += blockDim.x) a2 += psq[i];
+    const double P2 = block_reduce(a2, red);
+    for (int c = 0; c < 9; ++c) {
+      double a1 = 0.0;
+      for (int i = threadIdx.x; i < nss; i += blockDim.x) a1 += psum[c * nss + i];
+      const double m = block_reduce(a1, red);
+      if (threadIdx.x == 0) pbar[c] = m * invN3;
+    }
+    if (threadIdx.x == 0) {
+      sc->res2 = tot;
+      sc->P2 = P2;
+    }
+    return;
+  }
+  if (threadIdx.x != 0) return;
+  if (op == RED_INIT) {
+    sc->bb = tot;
+    sc->rr = tot;
+    sc->eta2bb = sc->eta2bb * tot;  // eta^2 was stored by the init kernel
+    sc->iters = 0;
+    sc->first = 1;
+    sc->breakdown = 0;
+    sc->converged = (tot == 0.0) ? 1 : 0;
+    sc->done = sc->converged;
+    sc->alpha = 0.0;
+    sc->beta = 0.0;
+  } else if (op == RED_ALPHA) {
+    sc->pAp = tot;
+    if (!(tot > 0.0) || !isfinite(tot)) {
+      sc->breakdown = 1;
+      sc->done = 1;
+      sc->iters += 1;
+    } else {
+      sc->alpha = sc->rr / tot;
+    }
+  } else if (op == RED_BETA) {
+    sc->iters += 1;
+    sc->rr_new = tot;
+    sc->first = 0;
+    if (tot <= sc->eta2bb) {
+      sc->converged = 1;
+      sc->done = 1;
+    } else if (sc->iters >= sc->max_iters || !isfinite(tot)) {
+      sc->done = 1;
+    } else {
+      sc->beta = tot / sc->rr;
+      sc->rr = tot;
+    }
+  }
+}
+
+void launch_reduce(int op, const double* partial, int count,
+                   const double* psum, const double* psq, int nss,
+                   double invN3, Scalars* sc, double* pbar, hipStream_t s) {
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kBlock), 0, s, op, partial,
+                     count, psum, psq, nss, invN3, sc, pbar);
+}
+
+__global__ void init_scalars_kernel(Scalars* sc, int max_iters, double eta) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    sc->max_iters = max_iters;
+    sc->eta2bb = eta * eta;
+    sc->done = 0;
+    sc->fails = 0;
+  }
+}
+
+__global__ void bench_scalars_kernel(Scalars* sc) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    // a matvec on p = r that leaves the vectors unchanged (alpha = 0)
+    sc->done = 0;
+    sc->first = 1;
+    sc->alpha = 0.0;
+    sc->beta = 0.0;
+  }
+}
+
+void launch_bench_scalars(Scalars* sc, hipStream_t s) {
+  hipLaunchKernelGGL(bench_scalars_kernel, dim3(1), dim3(64), 0, s, sc);
+}
+
+void launch_init_scalars(Scalars* sc, int max_iters, double eta,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(init_scalars_kernel, dim3(1), dim3(64), 0, s, sc,
+                     max_iters, eta);
+}
+
+// Commit: accumulate the indicator fields from the converged trial state.
+//   dLp = sum_a dg_a s_a (x) m_a;  Pcyc += sqrt(2/3 dLp:dLp);
+//   Pcyc_lit += dLp:dLp / dt;  W_a += tau_a dg_a.
+__global__ __launch_bounds__(kBlock) void commit_kernel(CommitArgs A) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= A.N) return;
+  const int64_t N = A.N;
+  const double* __restrict__ tb = A.table + (int64_t)A.phase[v] * kTableStride;
+  if (tb[0] != 0.0) return;  // elastic particles accumulate nothing
+  double dLp[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double dg[12];
+#pragma unroll
+  for (int al = 0; al < 12; ++al) {
+    dg[al] = A.dg_t[al * N + v];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        dLp[3 * i + j] += dg[al] * tb[kTabS + 3 * al + i] * tb[kTabM + 3 * al + j];
+  }
+  double dd = 0.0;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) dd += dLp[i] * dLp[i];
+  A.pcyc[v] += sqrt(2.0 / 3.0 * dd);
+  A.pcyc_lit[v] += dd / A.dt;
+  // resolved shear stresses at the converged state
+  double F[9], Fpi[9], Fe[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) {
+    F[c] = A.F[c * N + v];
+    Fpi[c] = A.Fpi_t[c * N + v];
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      Fe[3 * i + j] = F[3 * i] * Fpi[j] + F[3 * i + 1] * Fpi[3 + j] +
+                      F[3 * i + 2] * Fpi[6 + j];
+  double C[9];
+#pragma unroll
+  for (int p = 0; p < 3; ++p)
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      C[3 * p + q] = Fe[p] * Fe[q] + Fe[3 + p] * Fe[3 + q] + Fe[6 + p] * Fe[6 + q];
+  const double E[6] = {0.5 * (C[0] - 1.0), 0.5 * (C[4] - 1.0),
+                       0.5 * (C[8] - 1.0), 0.5 * C[5],
+                       0.5 * C[2],         0.5 * C[1]};
+  const double w[6] = {1, 1, 1, 2, 2, 2};
+  double S[6];
+#pragma unroll
+  for (int I = 0; I < 6; ++I) {
+    double acc = 0.0;
+#pragma unroll
+    for (int J = 0; J < 6; ++J) acc += tb[kTabC + 6 * I + J] * w[J] * E[J];
+    S[I] = acc;
+  }
+#pragma unroll
+  for (int al = 0; al < 12; ++al) {
+    const double* s = tb + kTabS + 3 * al;
+    const double* m = tb + kTabM + 3 * al;
+    const double Sm0 = S[0] * m[0] + S[5] * m[1] + S[4] * m[2];
+    const double Sm1 = S[5] * m[0] + S[1] * m[1] + S[3] * m[2];
+    const double Sm2 = S[4] * m[0] + S[3] * m[1] + S[2] * m[2];
+    const double tau = s[0] * Sm0 + s[1] * Sm1 + s[2] * Sm2;
+    A.wcyc[al * N + v] += tau * dg[al];
+  }
+}
+
+void launch_commit(const CommitArgs& a, hipStream_t s) {
+  const int64_t grid = (a.N + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(commit_kernel, dim3((unsigned)grid), dim3(kBlock), 0, s, a);
+}
+
+__global__ void fill_i32_kernel(int32_t* p, int32_t v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void fill_f64_kernel(double* p, double v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
+  const int64_t g = (n + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)(g < 2048 ? (g > 0 ? g : 1) : 2048)),
+                     dim3(kBlock), 0, s, p, v, n);
+}
+void launch_fill_f64(double* p, double v, int64_t n, hipStream_t s) {
+  const int64_t g = (n + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(fill_f64_kernel, dim3((unsigned)(g < 2048 ? (g > 0 ? g : 1) : 2048)),
+                     dim3(kBlock), 0, s, p, v, n);
+}
+
+// sigma = P F^T / det F
+__global__ void cauchy_kernel(const double* __restrict__ F,
+                              const double* __restrict__ P,
+                              double* __restrict__ sig, int64_t N) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  double f[9], p[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) {
+    f[c] = F[c * N + v];
+    p[c] = P[c * N + v];
+  }
+  const double J = f[0] * (f[4] * f[8] - f[5] * f[7]) -
+                   f[1] * (f[3] * f[8] - f[5] * f[6]) +
+                   f[2] * (f[3] * f[7] - f[4] * f[6]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      sig[(3 * i + j) * N + v] =
+          (p[3 * i] * f[3 * j] + p[3 * i + 1] * f[3 * j + 1] +
+           p[3 * i + 2] * f[3 * j + 2]) / J;
+}
+
+void launch_cauchy(const double* F, const double* P, double* sig, int64_t N,
+                   hipStream_t s) {
+  const int64_t g = (N + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(cauchy_kernel, dim3((unsigned)g), dim3(kBlock), 0, s, F, P,
+                     sig, N);
+}
+
+template void launch_cg_init<float>(const double*, float*, float*, double*,
+                                    int, int64_t, hipStream_t);
+template void launch_cg_init<double>(const double*, double*, double*, double*,
+                                     int, int64_t, hipStream_t);
+template void launch_cg_update<float>(float*, float*, const float*,
+                                      const float*, const Scalars*, double*,
+                                      int, int64_t, hipStream_t);
+template void launch_cg_update<double>(double*, double*, const double*,
+                                       const double*, const Scalars*, double*,
+                                       int, int64_t, hipStream_t);
+template void launch_add_to_F<float>(double*, const float*, int64_t,
+                                     hipStream_t);
+template void launch_add_to_F<double>(double*, const double*, int64_t,
+                                      hipStream_t);
+template void launch_convert<float>(const double*, float*, int64_t,
+                                    hipStream_t);
+template void launch_convert<double>(const double*, double*, int64_t,
+                                     hipStream_t);
+
+}  // namespace rve

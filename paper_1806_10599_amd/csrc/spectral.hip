@@ -1,0 +1,455 @@
+// The linear map G(A) = F^-1{ Ghat : F(A) } of Sec. 2.1, Eqs. 10-11, and the
+// CG matvec G(K : p) of Eqs. 15-16, as three passes over a cubic grid of N^3
+// voxels:
+//
+//   pass A (one block per x-slab and component group): build the real plane
+//     (the field itself, or K:p with the CG direction update fused in), pack
+//     rows y and y + N/2 as one complex line, FFT along z, unpack the two
+//     half spectra in place (kz < N/2; the kz = N/2 Nyquist plane is zeroed
+//     by the operator, so its slots hold the kz = 0 column's second half),
+//     FFT along y, store the spectrum [c][x][ky][kz] (kz < N/2).
+//   pass B (one block per ky and a tile of kz, for one tensor row i): FFT
+//     along x of the three components of row i, apply the projection
+//     Bhat_ij = v_j (sum_l Ahat_il v_l) / |v|^2 (zero at the null frequency
+//     and wherever a component is Nyquist; Sec. 2.2, Eqs. 18-21), fold in
+//     the 1/N^3 of the inverse transform, inverse FFT along x.
+//   pass C (one block per x-slab and component group): inverse of pass A,
+//     writing the real field and a per-block FP64 partial (||out||^2, or the
+//     CG dot p . Ap).
+//
+// Only the delta_ik structure of the operator is used: row i of the output
+// depends on row i of the input, so pass B never needs all nine components.
+#include "common.hpp"
+#include "fft.hpp"
+#include "kernels.hpp"
+
+namespace rve {
+
+template <int N>
+struct SlabGeom {
+  static constexpr int H = N / 2;
+  static constexpr int PITCH = N + 1;                 // LDS row pitch (complex)
+  static constexpr int PLANE = H * PITCH;             // one packed plane
+};
+
+// rows of the packed plane: line = q*H + y', element = z
+template <int N>
+struct RowMap {
+  __device__ __forceinline__ int operator()(int line, int e) const {
+    const int q = line / SlabGeom<N>::H;
+    const int yp = line - q * SlabGeom<N>::H;
+    return q * SlabGeom<N>::PLANE + yp * SlabGeom<N>::PITCH + e;
+  }
+};
+
+// spectral columns: line = q*H + kz, element = ky
+template <int N>
+struct ColMap {
+  __device__ __forceinline__ int operator()(int line, int y) const {
+    constexpr int H = SlabGeom<N>::H;
+    const int q = line / H;
+    const int kz = line - q * H;
+    int row, col;
+    if (y < H) {
+      row = y;
+      col = kz;
+    } else {
+      row = y - H;
+      col = (kz == 0) ? H : N - kz;
+    }
+    return q * SlabGeom<N>::PLANE + row * SlabGeom<N>::PITCH + col;
+  }
+};
+
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  // consecutive workgroups land on different XCDs (round robin over 8);
+  // give neighbouring logical tiles the same XCD so they share its L2
+  if (nb % 8) return b;
+  return (b % 8) * (nb / 8) + b / 8;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  // fixed-order tree reduction over the block (deterministic)
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (t < s) red[t] += red[t + s];
+    __syncthreads();
+  }
+  double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void load_twiddles(cplx<T>* tw,
+                                              const cplx<T>* __restrict__ g) {
+  for (int i = threadIdx.x; i < N; i += blockDim.x) tw[i] = g[i];
+}
+
+// ------------------------------------------------------------------ pass A
+template <typename T, int N, int CPB, int SRC>
+__global__ __launch_bounds__(kBlock) void slab_fwd_kernel(SlabFwdArgs<T> a) {
+  constexpr int H = N / 2;
+  constexpr int N3 = N * N * N;
+  constexpr int NG = 9 / CPB;
+  __shared__ cplx<T> lds[CPB * SlabGeom<N>::PLANE];
+  __shared__ cplx<T> tw[N];
+  __shared__ double red[kBlock];
+  if (SRC == SRC_KP && a.sc->done) return;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int x = lb / NG;
+  const int grp = lb - x * NG;
+  load_twiddles<T, N>(tw, a.tw);
+  double ss[CPB], s1[CPB];
+#pragma unroll
+  for (int q = 0; q < CPB; ++q) ss[q] = s1[q] = 0.0;
+
+  // build the real plane(s), packed: row y' holds y' (re) and y'+H (im)
+  const bool first = (SRC == SRC_KP) ? (a.sc->first != 0) : true;
+  const T beta = (SRC == SRC_KP) ? T(a.sc->beta) : T(0);
+  for (int t = threadIdx.x; t < N * N; t += blockDim.x) {
+    const int y = t / N, z = t - (t / N) * N;
+    const int v = (x * N + y) * N + z;
+    T out[CPB];
+    if constexpr (SRC == SRC_FIELD) {
+#pragma unroll
+      for (int q = 0; q < CPB; ++q) out[q] = a.field[(grp * CPB + q) * N3 + v];
+    } else {
+      T pd[9];
+#pragma unroll
+      for (int d = 0; d < 9; ++d) {
+        T val = a.r[d * N3 + v];
+        if (!first) val += beta * a.p_old[d * N3 + v];
+        pd[d] = val;
+      }
+#pragma unroll
+      for (int q = 0; q < CPB; ++q) {
+        const int c = grp * CPB + q;
+        a.p_new[c * N3 + v] = pd[c];
+        T acc = T(0);
+#pragma unroll
+        for (int d = 0; d < 9; ++d) acc += a.K[(9 * c + d) * N3 + v] * pd[d];
+        out[q] = acc;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < CPB; ++q) {
+      ss[q] += double(out[q]) * double(out[q]);
+      s1[q] += double(out[q]);
+      const int yp = (y < H) ? y : y - H;
+      T* slot = reinterpret_cast<T*>(&lds[q * SlabGeom<N>::PLANE +
+                                          yp * SlabGeom<N>::PITCH + z]);
+      slot[y < H ? 0 : 1] = out[q];
+    }
+  }
+  __syncthreads();
+
+  // FFT along z of the packed rows
+  fft_lines<N, -1>(lds, tw, CPB * H, RowMap<N>());
+
+  // unpack the two real-row spectra in place
+  for (int t = threadIdx.x; t < CPB * H * H; t += blockDim.x) {
+    const int q = t / (H * H);
+    const int rem = t - q * H * H;
+    const int yp = rem / H, k = rem - (rem / H) * H;
+    cplx<T>* row = &lds[q * SlabGeom<N>::PLANE + yp * SlabGeom<N>::PITCH];
+    if (k == 0) {
+      const cplx<T> z0 = row[0];
+      row[0] = {z0.x, T(0)};  // A_0 (real)
+      row[H] = {z0.y, T(0)};  // B_0 (real), kept in the Nyquist slot
+    } else {
+      const cplx<T> zk = row[k], zm = row[N - k];
+      const cplx<T> A = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
+      const cplx<T> B = {T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x)};
+      row[k] = A;
+      row[N - k] = B;
+    }
+  }
+  __syncthreads();
+
+  // FFT along y of every kz column
+  fft_lines<N, -1>(lds, tw, CPB * H, ColMap<N>());
+
+  // store the spectrum [c][x][ky][kz]
+  const ColMap<N> cm;
+  for (int t = threadIdx.x; t < CPB * N * H; t += blockDim.x) {
+    const int q = t / (N * H);
+    const int rem = t - q * N * H;
+    const int ky = rem / H, kz = rem - (rem / H) * H;
+    const int c = grp * CPB + q;
+    a.spec[((size_t)(c * N + x) * N + ky) * H + kz] = lds[cm(q * H + kz, ky)];
+  }
+  if (a.psum) {
+    // per-slab, per-component sum and sum of squares: [9][N]
+#pragma unroll
+    for (int q = 0; q < CPB; ++q) {
+      const double t1 = block_sum(s1[q], red);
+      const double t2 = block_sum(ss[q], red);
+      if (threadIdx.x == 0) {
+        const int c = grp * CPB + q;
+        a.psum[c * N + x] = t1;
+        a.psq[c * N + x] = t2;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ pass B
+template <typename T, int N, int TT>
+__global__ __launch_bounds__(kBlock) void pencil_proj_kernel(PencilArgs<T> a) {
+  constexpr int H = N / 2;
+  constexpr int TP = TT + 1;  // LDS pitch of a kx row (complex)
+  constexpr int NTILE = (H + TT - 1) / TT;
+  __shared__ cplx<T> lds[3 * N * TP];
+  __shared__ cplx<T> tw[N];
+  if (a.sc && a.sc->done) return;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int i = lb % 3;
+  const int rest = lb / 3;
+  const int tile = rest % NTILE;
+  const int ky = rest / NTILE;
+  const int kz0 = tile * TT;
+  const int ncol = (H - kz0) < TT ? (H - kz0) : TT;
+
+  if (ky == H) {  // Nyquist ky: the projection is zero there
+    for (int t = threadIdx.x; t < 3 * N * TT; t += blockDim.x) {
+      const int j = t / (N * TT);
+      const int rem = t - j * N * TT;
+      const int kx = rem / TT, tt = rem - (rem / TT) * TT;
+      if (tt < ncol)
+        a.spec[((size_t)((3 * i + j) * N + kx) * N + ky) * H + kz0 + tt] = {T(0), T(0)};
+    }
+    return;
+  }
+  load_twiddles<T, N>(tw, a.tw);
+  for (int t = threadIdx.x; t < 3 * N * TT; t += blockDim.x) {
+    const int j = t / (N * TT);
+    const int rem = t - j * N * TT;
+    const int kx = rem / TT, tt = rem - (rem / TT) * TT;
+    cplx<T> val = {T(0), T(0)};
+    if (tt < ncol)
+      val = a.spec[((size_t)((3 * i + j) * N + kx) * N + ky) * H + kz0 + tt];
+    lds[(j * N + kx) * TP + tt] = val;
+  }
+  __syncthreads();
+  auto pm = [](int line, int kx) {
+    const int j = line / TT;
+    const int tt = line - j * TT;
+    return (j * N + kx) * TP + tt;
+  };
+  fft_lines<N, -1>(lds, tw, 3 * TT, pm);
+
+  // projection, one (kx, kz) point per thread
+  const T v2 = a.vt[N + ky];
+  for (int t = threadIdx.x; t < N * TT; t += blockDim.x) {
+    const int kx = t / TT, tt = t - (t / TT) * TT;
+    const int kz = kz0 + tt;
+    const T v1 = a.vt[kx];
+    const T v3 = a.vt[2 * N + (kz < H ? kz : 0)];
+    const bool zero = (kx == H) || (tt >= ncol) || (kx == 0 && ky == 0 && kz == 0);
+    const T nrm = v1 * v1 + v2 * v2 + v3 * v3;
+    const T inv = zero ? T(0) : a.invN3 / nrm;
+    cplx<T> A0 = lds[(0 * N + kx) * TP + tt];
+    cplx<T> A1 = lds[(1 * N + kx) * TP + tt];
+    cplx<T> A2 = lds[(2 * N + kx) * TP + tt];
+    cplx<T> s = {(A0.x * v1 + A1.x * v2 + A2.x * v3) * inv,
+                 (A0.y * v1 + A1.y * v2 + A2.y * v3) * inv};
+    lds[(0 * N + kx) * TP + tt] = {v1 * s.x, v1 * s.y};
+    lds[(1 * N + kx) * TP + tt] = {v2 * s.x, v2 * s.y};
+    lds[(2 * N + kx) * TP + tt] = {v3 * s.x, v3 * s.y};
+  }
+  __syncthreads();
+  fft_lines<N, +1>(lds, tw, 3 * TT, pm);
+  for (int t = threadIdx.x; t < 3 * N * TT; t += blockDim.x) {
+    const int j = t / (N * TT);
+    const int rem = t - j * N * TT;
+    const int kx = rem / TT, tt = rem - (rem / TT) * TT;
+    if (tt < ncol)
+      a.spec[((size_t)((3 * i + j) * N + kx) * N + ky) * H + kz0 + tt] =
+          lds[(j * N + kx) * TP + tt];
+  }
+}
+
+// ------------------------------------------------------------------ pass C
+template <typename T, typename TO, int N, int CPB, int DST>
+__global__ __launch_bounds__(kBlock) void slab_inv_kernel(SlabInvArgs<T, TO> a) {
+  constexpr int H = N / 2;
+  constexpr int N3 = N * N * N;
+  constexpr int NG = 9 / CPB;
+  __shared__ cplx<T> lds[CPB * SlabGeom<N>::PLANE];
+  __shared__ cplx<T> tw[N];
+  __shared__ double red[kBlock];
+  if (a.sc && a.sc->done) return;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int x = lb / NG;
+  const int grp = lb - x * NG;
+  load_twiddles<T, N>(tw, a.tw);
+  const ColMap<N> cm;
+  for (int t = threadIdx.x; t < CPB * N * H; t += blockDim.x) {
+    const int q = t / (N * H);
+    const int rem = t - q * N * H;
+    const int ky = rem / H, kz = rem - (rem / H) * H;
+    const int c = grp * CPB + q;
+    lds[cm(q * H + kz, ky)] = a.spec[((size_t)(c * N + x) * N + ky) * H + kz];
+  }
+  __syncthreads();
+  fft_lines<N, +1>(lds, tw, CPB * H, ColMap<N>());
+
+  // pack the two half spectra of rows y' and y'+H into one complex line
+  for (int t = threadIdx.x; t < CPB * H * H; t += blockDim.x) {
+    const int q = t / (H * H);
+    const int rem = t - q * H * H;
+    const int yp = rem / H, k = rem - (rem / H) * H;
+    cplx<T>* row = &lds[q * SlabGeom<N>::PLANE + yp * SlabGeom<N>::PITCH];
+    if (k == 0) {
+      const T a0 = row[0].x, b0 = row[H].x;
+      row[0] = {a0, b0};
+      row[H] = {T(0), T(0)};
+    } else {
+      const cplx<T> A = row[k], B = row[N - k];
+      row[k] = {A.x - B.y, A.y + B.x};        // A + i B
+      row[N - k] = {A.x + B.y, B.x - A.y};    // conj(A) + i conj(B)
+    }
+  }
+  __syncthreads();
+  fft_lines<N, +1>(lds, tw, CPB * H, RowMap<N>());
+
+  double acc = 0.0;
+  for (int t = threadIdx.x; t < N * N; t += blockDim.x) {
+    const int y = t / N, z = t - (t / N) * N;
+    const int v = (x * N + y) * N + z;
+    const int yp = (y < H) ? y : y - H;
+#pragma unroll
+    for (int q = 0; q < CPB; ++q) {
+      const int c = grp * CPB + q;
+      const cplx<T> zz = lds[q * SlabGeom<N>::PLANE + yp * SlabGeom<N>::PITCH + z];
+      const T val = (y < H) ? zz.x : zz.y;
+      a.out[c * N3 + v] = TO(val);
+      if constexpr (DST == DST_DOT) {
+        acc += double(a.pdot[c * N3 + v]) * double(val);
+      } else {
+        acc += double(val) * double(val);
+      }
+    }
+  }
+  if (a.partial) {
+    double tot = block_sum(acc, red);
+    if (threadIdx.x == 0) a.partial[blockIdx.x] = tot;
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+template <typename T, int N>
+struct SpectralTraits {
+  // components per slab block: three (one tensor row) when the planes fit
+  static constexpr int CPB =
+      (3 * SlabGeom<N>::PLANE * (int)sizeof(cplx<T>) <= 64 * 1024) ? 3 : 1;
+  static constexpr int TT = (sizeof(T) == 4) ? 16 : 8;
+};
+
+template <typename T, int N>
+void launch_G_passes(const SpectralLaunch<T>& L, hipStream_t s) {
+  constexpr int CPB = SpectralTraits<T, N>::CPB;
+  constexpr int TT = SpectralTraits<T, N>::TT;
+  constexpr int H = N / 2;
+  constexpr int NTILE = (H + TT - 1) / TT;
+  const int nslab = N * (9 / CPB);
+  if (!(L.passes & 1)) {
+  } else if (L.src == SRC_FIELD) {
+    SlabFwdArgs<T> fa{};
+    fa.field = L.in_field;
+    fa.spec = L.spec;
+    fa.tw = L.tw;
+    fa.psum = L.psum;
+    fa.psq = L.psq;
+    fa.sc = L.sc;
+    hipLaunchKernelGGL((slab_fwd_kernel<T, N, CPB, SRC_FIELD>), dim3(nslab),
+                       dim3(kBlock), 0, s, fa);
+  } else {
+    SlabFwdArgs<T> fa{};
+    fa.K = L.K;
+    fa.r = L.r;
+    fa.p_old = L.p_old;
+    fa.p_new = L.p_new;
+    fa.spec = L.spec;
+    fa.tw = L.tw;
+    fa.psum = nullptr;
+    fa.psq = nullptr;
+    fa.sc = L.sc;
+    hipLaunchKernelGGL((slab_fwd_kernel<T, N, CPB, SRC_KP>), dim3(nslab),
+                       dim3(kBlock), 0, s, fa);
+  }
+  if (L.passes & 2) {
+  PencilArgs<T> pa{};
+  pa.spec = L.spec;
+  pa.tw = L.tw;
+  pa.vt = L.vt;
+  pa.invN3 = T(1.0 / (double(N) * N * N));
+  pa.sc = (L.src == SRC_KP) ? L.sc : nullptr;
+  hipLaunchKernelGGL((pencil_proj_kernel<T, N, TT>), dim3(N * NTILE * 3),
+                     dim3(kBlock), 0, s, pa);
+  }
+  if (!(L.passes & 4)) {
+  } else if (L.dst == DST_DOT) {
+    SlabInvArgs<T, T> ia{};
+    ia.spec = L.spec;
+    ia.tw = L.tw;
+    ia.out = L.out_T;
+    ia.pdot = L.p_new;
+    ia.partial = L.partial_inv;
+    ia.sc = L.sc;
+    hipLaunchKernelGGL((slab_inv_kernel<T, T, N, CPB, DST_DOT>), dim3(nslab),
+                       dim3(kBlock), 0, s, ia);
+  } else {
+    SlabInvArgs<T, double> ia{};
+    ia.spec = L.spec;
+    ia.tw = L.tw;
+    ia.out = L.out_d;
+    ia.pdot = nullptr;
+    ia.partial = L.partial_inv;
+    ia.sc = nullptr;
+    hipLaunchKernelGGL((slab_inv_kernel<T, double, N, CPB, DST_NORM>),
+                       dim3(nslab), dim3(kBlock), 0, s, ia);
+  }
+}
+
+template <typename T>
+void launch_G(int n, const SpectralLaunch<T>& L, hipStream_t s) {
+  switch (n) {
+    case 16: launch_G_passes<T, 16>(L, s); break;
+    case 24: launch_G_passes<T, 24>(L, s); break;
+    case 32: launch_G_passes<T, 32>(L, s); break;
+    case 40: launch_G_passes<T, 40>(L, s); break;
+    case 48: launch_G_passes<T, 48>(L, s); break;
+    case 64: launch_G_passes<T, 64>(L, s); break;
+    case 96: launch_G_passes<T, 96>(L, s); break;
+    case 128: launch_G_passes<T, 128>(L, s); break;
+    default: throw Error(-1, "unsupported grid size for the FFT passes");
+  }
+}
+
+int slab_blocks(int n, bool fp64) {
+  auto cpb = [&](auto tag, int nn) -> int {
+    using T = decltype(tag);
+    switch (nn) {
+      case 16: return SpectralTraits<T, 16>::CPB;
+      case 24: return SpectralTraits<T, 24>::CPB;
+      case 32: return SpectralTraits<T, 32>::CPB;
+      case 40: return SpectralTraits<T, 40>::CPB;
+      case 48: return SpectralTraits<T, 48>::CPB;
+      case 64: return SpectralTraits<T, 64>::CPB;
+      case 96: return SpectralTraits<T, 96>::CPB;
+      case 128: return SpectralTraits<T, 128>::CPB;
+    }
+    return 1;
+  };
+  const int c = fp64 ? cpb(double{}, n) : cpb(float{}, n);
+  return n * (9 / c);
+}
+
+template void launch_G<float>(int, const SpectralLaunch<float>&, hipStream_t);
+template void launch_G<double>(int, const SpectralLaunch<double>&, hipStream_t);
+
+}  // namespace rve

@@ -1,0 +1,161 @@
+"""Solver-level parity of the HIP path with the CPU oracle (Sec. 2.1).
+
+FP64 mode at a tight equilibrium tolerance (1e-12, CG 1e-10) reproduces
+the oracle's fields to 1e-10 relative (max norm) at every increment; mixed
+mode at 1e-6 matches the FP64 oracle's macroscopic loop to 1e-4 (Eq. 29)
+and its fatigue indicator fields to 1e-3 (Eq. 30).  Also: homogeneous
+medium, rollback of failed increments, bitwise checkpoint/resume, bitwise
+determinism, graph-captured CG equal to direct launches.
+"""
+
+import numpy as np
+import pytest
+
+from gpu_util import make_rve, oracle_for, rel_maxnorm, to_soa
+from synthetic import (config_by_name, macro_F, make_microstructure,
+                       material_params)
+
+pytestmark = pytest.mark.gpu
+
+TIGHT = dict(newton_tol=1e-12, cg_tol=1e-10, newton_max_iter=40,
+             cg_max_iter=5000)
+ORACLE_TIGHT = dict(tol=1e-12, eta=1e-10, newton_max=40, cg_max=5000)
+
+
+def _compare_state(r, o, tol=1e-10):
+    assert rel_maxnorm(r.field("F"), to_soa(o.F)) < tol
+    assert rel_maxnorm(r.field("P"), to_soa(o.P)) < tol
+    if np.max(o.pcyc) > 0:
+        assert rel_maxnorm(r.field("pcyc"), o.pcyc) < tol
+        assert rel_maxnorm(r.field("wcyc"), o.wcyc.T) < tol
+        assert rel_maxnorm(r.field("chi"), o.chi.T) < tol
+
+
+def test_homogeneous_medium_single_evaluation():
+    micro = make_microstructure(16, 1, 5)
+    r = make_rve(micro, "continuous", **TIGHT)
+    try:
+        for eps in (0.002, 0.004):
+            info = r.increment(macro_F(eps), 0.1)
+            assert info["status"] == 0 and info["newton_iters"] == 0
+            assert info["residuals"][0] < 1e-13
+            F = r.field("F")
+            assert np.max(np.abs(F - macro_F(eps).reshape(9, 1))) == 0.0
+    finally:
+        r.close()
+
+
+@pytest.mark.parametrize("cfg,ninc", [("C1", 7), ("C2", 2)])
+def test_fp64_increments_match_oracle(cfg, ninc):
+    c = config_by_name(cfg)
+    micro = c.microstructure()
+    hist = c.history()[:ninc]
+    r = make_rve(micro, c.operator, "fp64", **TIGHT)
+    o = oracle_for(micro, c.operator)
+    try:
+        for inc in hist:
+            print(f"{cfg} increment {inc['k']} eps={inc['eps']:+.4f}", flush=True)
+            info = r.increment(inc["F_bar"], inc["dt"])
+            oi = o.increment(inc["F_bar"], inc["dt"], **ORACLE_TIGHT)
+            assert info["status"] == 0 and oi.status == 0
+            _compare_state(r, o)
+            assert rel_maxnorm(info["P_bar"], oi.P_bar) < 1e-10
+    finally:
+        r.close()
+
+
+def test_mixed_precision_macro_loop_and_fips():
+    # C1 microstructure and first half cycle, mixed mode at tol 1e-6 against
+    # the FP64 oracle at 1e-12: Eq. 29 on sigma_11, Eq. 30 on P_cyc, W
+    c = config_by_name("C1")
+    micro = c.microstructure()
+    hist = c.history()[:10]
+    r = make_rve(micro, c.operator, "mixed", newton_tol=1e-6)
+    o = oracle_for(micro, c.operator)
+    s_gpu, s_ref = [], []
+    try:
+        for inc in hist:
+            info = r.increment(inc["F_bar"], inc["dt"])
+            oi = o.increment(inc["F_bar"], inc["dt"], **ORACLE_TIGHT)
+            assert info["status"] == 0
+            s_gpu.append(info["sigma_bar"][0, 0])
+            s_ref.append(oi.sigma_bar[0, 0])
+        s_gpu, s_ref = np.array(s_gpu), np.array(s_ref)
+        err = np.max(np.abs(s_gpu - s_ref)) / np.max(np.abs(s_ref))
+        assert err < 1e-4, err
+        pc = r.field("pcyc")
+        assert np.linalg.norm(pc - o.pcyc) / np.linalg.norm(o.pcyc) < 1e-3
+        w = r.field("wcyc")
+        for a in range(12):
+            ref = o.wcyc[:, a]
+            if np.linalg.norm(ref) > 0:
+                assert np.linalg.norm(w[a] - ref) / np.linalg.norm(ref) < 1e-3
+    finally:
+        r.close()
+
+
+def test_failed_increment_rolls_back_and_nan_is_local_failure():
+    micro = config_by_name("C1").microstructure()
+    r = make_rve(micro, "continuous", newton_max_iter=1)
+    try:
+        assert r.increment(macro_F(0.001), 0.2)["status"] in (0, -4)
+        blob = r.get_state()
+        fields = {k: r.field(k) for k in ("F", "P", "Fpinv", "chi", "pcyc")}
+        info = r.increment(macro_F(0.03), 0.2)
+        assert info["status"] == -4
+        for k, v in fields.items():
+            assert np.array_equal(r.field(k), v)
+        assert r.get_state() == blob
+        F = r.field("F")
+        F[0, 17] = np.nan
+        r.debug_set_field("F", F)
+        info = r.increment(macro_F(0.002), 0.2)
+        assert info["status"] == -5 and info["local_failures"] >= 1
+        assert np.array_equal(r.field("Fpinv"), fields["Fpinv"])
+    finally:
+        r.close()
+
+
+def test_checkpoint_resume_and_determinism_bitwise():
+    c = config_by_name("C1")
+    micro = c.microstructure()
+    hist = c.history()[:6]
+    a = make_rve(micro, c.operator)
+    b = make_rve(micro, c.operator)
+    try:
+        for inc in hist[:3]:
+            a.increment(inc["F_bar"], inc["dt"])
+            b.increment(inc["F_bar"], inc["dt"])
+        blob = a.get_state()
+        assert blob == b.get_state()             # two runs, bitwise equal
+        for inc in hist[3:]:
+            a.increment(inc["F_bar"], inc["dt"])
+        b.close()
+        b = make_rve(micro, c.operator)
+        b.set_state(blob)
+        for inc in hist[3:]:
+            b.increment(inc["F_bar"], inc["dt"])
+        assert a.get_state() == b.get_state()   # resume is bitwise
+    finally:
+        a.close()
+        b.close()
+
+
+def test_graph_capture_equals_direct_launches():
+    import torch
+    c = config_by_name("C1")
+    micro = c.microstructure()
+    hist = c.history()[:3]
+    s = torch.cuda.Stream()
+    a = make_rve(micro, c.operator, "mixed", use_graph=False)
+    b = make_rve(micro, c.operator, "mixed", use_graph=True, stream=s)
+    try:
+        for inc in hist:
+            ia = a.increment(inc["F_bar"], inc["dt"])
+            ib = b.increment(inc["F_bar"], inc["dt"])
+            assert ia["status"] == ib["status"] == 0
+            assert ia["residuals"] == ib["residuals"]
+        assert a.get_state() == b.get_state()
+    finally:
+        a.close()
+        b.close()
