@@ -256,6 +256,46 @@ rve_status rve_attach_warm_start(rve_t h, rve_ws_t w);
 rve_status rve_ws_features(rve_t h, const double F_bar_new[9], uint16_t* X);
 rve_status rve_ws_target(rve_t h, float* T);
 
+/* ---- batches of RVEs ------------------------------------------------------
+   count independent RVEs (1 <= count <= 255), each with its own cubic grid
+   n[b] in {16, 24, 32, 40, 48, 64}, microstructure and committed state,
+   solved together: each pass of the Newton-CG iteration (Sec. 2.1,
+   Eqs. 11-16) runs as one kernel launch over the whole batch, and each RVE
+   keeps its own Newton and CG stopping tests, so an RVE that has converged
+   does no further work in that increment.  Results per RVE are those of a
+   single handle with the same configuration up to the summation order of
+   the reductions.
+   cfg: projection, precision, tolerances, use_graph, stream and allocator
+   as for rve_create; cfg.n is ignored (grids come from n[count]); cfg.L is
+   each RVE's cell; warm_start must be 0.  All RVEs share the material
+   constants: rve_batch_set_microstructure rejects params that differ from
+   those of an earlier call.  Voxel layouts, fields and info records are those
+   of the single-RVE calls, per RVE b.
+   rve_batch_apply_macro_strain_increment: F_bar_new[count][9] (RVE b's
+   macro gradient at F_bar_new + 9 b), one dt; info[count] (nullable)
+   receives each RVE's record.  Every RVE that converges commits, the others
+   keep their committed state; returns RVE_OK when all converged, else the
+   status of the first RVE that did not.  Errors as for the single-RVE
+   calls; RVE_EINVAL for b out of range. */
+typedef struct rve_batch_s* rve_batch_t;
+rve_status rve_batch_create(const rve_config* cfg, int32_t count,
+                            const int32_t* n, rve_batch_t* out);
+rve_status rve_batch_destroy(rve_batch_t h);
+rve_status rve_batch_set_microstructure(rve_batch_t h, int32_t b,
+                                        const int32_t* phase, int32_t G,
+                                        const double* quat, const int32_t* law,
+                                        const double* params, int32_t nparams);
+rve_status rve_batch_apply_macro_strain_increment(rve_batch_t h,
+                                                  const double* F_bar_new,
+                                                  double dt,
+                                                  rve_increment_info* info);
+rve_status rve_batch_reset_fips(rve_batch_t h);
+rve_status rve_batch_get_fields(rve_batch_t h, int32_t b, int32_t field,
+                                void* dst, size_t dst_bytes,
+                                int32_t dst_on_device);
+rve_status rve_batch_get_macro(rve_batch_t h, int32_t b, double out[29]);
+const char* rve_batch_last_error(rve_batch_t h);
+
 #ifdef __cplusplus
 }
 #endif

@@ -115,6 +115,21 @@ def _load():
         "rve_attach_warm_start": (C.c_int, [C.c_void_p, C.c_void_p]),
         "rve_ws_features": (C.c_int, [C.c_void_p, P(C.c_double), C.c_void_p]),
         "rve_ws_target": (C.c_int, [C.c_void_p, C.c_void_p]),
+        "rve_batch_create": (C.c_int, [P(RveConfig), C.c_int32, P(C.c_int32),
+                                       P(C.c_void_p)]),
+        "rve_batch_destroy": (C.c_int, [C.c_void_p]),
+        "rve_batch_set_microstructure": (
+            C.c_int, [C.c_void_p, C.c_int32, P(C.c_int32), C.c_int32,
+                      P(C.c_double), P(C.c_int32), P(C.c_double), C.c_int32]),
+        "rve_batch_apply_macro_strain_increment": (
+            C.c_int, [C.c_void_p, P(C.c_double), C.c_double,
+                      P(RveIncrementInfo)]),
+        "rve_batch_reset_fips": (C.c_int, [C.c_void_p]),
+        "rve_batch_get_fields": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32,
+                                           C.c_void_p, C.c_size_t, C.c_int32]),
+        "rve_batch_get_macro": (C.c_int, [C.c_void_p, C.c_int32,
+                                          P(C.c_double)]),
+        "rve_batch_last_error": (C.c_char_p, [C.c_void_p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -138,6 +153,50 @@ def _dptr(a):
 
 def _iptr(a):
     return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _info_dict(info, rc):
+    k = info.newton_iters
+    nlog = min(k + 1, MAX_NEWTON_LOG)
+    return dict(status=rc, newton_iters=k,
+                cg_iters_total=info.cg_iters_total,
+                cg_iters=list(info.cg_iters[:min(k, MAX_NEWTON_LOG)]),
+                residuals=list(info.residual_history[:nlog]),
+                local_failures=info.local_failures,
+                used_learned=info.used_learned,
+                cg_breakdowns=info.cg_breakdowns,
+                residual_rel=info.residual_rel,
+                predictor_residual=info.predictor_residual,
+                plain_predictor_residual=info.plain_predictor_residual,
+                P_bar=np.array(info.P_bar).reshape(3, 3),
+                sigma_bar=np.array(info.sigma_bar).reshape(3, 3),
+                seconds=info.seconds)
+
+
+def _make_config(L, projection, precision, newton_tol, newton_max_iter, cg_tol,
+                 cg_max_iter, cg_chunk, use_graph, warm_start, stream, device,
+                 torch_allocator):
+    cfg = RveConfig()
+    LIB.rve_config_default(C.byref(cfg))
+    cfg.L[:] = tuple(float(x) for x in L)
+    cfg.projection = PROJ[projection]
+    cfg.precision = PREC[precision]
+    cfg.newton_tol = newton_tol
+    cfg.newton_max_iter = newton_max_iter
+    cfg.cg_tol = cg_tol
+    cfg.cg_max_iter = cg_max_iter
+    cfg.cg_chunk = cg_chunk
+    cfg.use_graph = 1 if use_graph else 0
+    cfg.warm_start = 1 if warm_start else 0
+    torch.cuda.set_device(device)
+    stream = stream if stream is not None else torch.cuda.current_stream()
+    cfg.stream = C.c_void_p(stream.cuda_stream or None)
+    alloc = None
+    if torch_allocator:
+        alloc = _TorchAllocator(device)
+        cfg.dev_alloc = alloc.alloc_fn
+        cfg.dev_free = alloc.free_fn
+    return cfg, stream, alloc
 
 
 class _TorchAllocator:
@@ -172,28 +231,12 @@ class Rve:
             raise RuntimeError("no GPU visible: the library runs on the GPU only")
         self._lib = LIB
         self._h = None
-        cfg = RveConfig()
-        LIB.rve_config_default(C.byref(cfg))
+        cfg, self.stream, self._alloc = _make_config(
+            L, projection, precision, newton_tol, newton_max_iter, cg_tol,
+            cg_max_iter, cg_chunk, use_graph, warm_start, stream, device,
+            torch_allocator)
         nn = (n, n, n) if np.isscalar(n) else tuple(n)
         cfg.n[:] = nn
-        cfg.L[:] = tuple(float(x) for x in L)
-        cfg.projection = PROJ[projection]
-        cfg.precision = PREC[precision]
-        cfg.newton_tol = newton_tol
-        cfg.newton_max_iter = newton_max_iter
-        cfg.cg_tol = cg_tol
-        cfg.cg_max_iter = cg_max_iter
-        cfg.cg_chunk = cg_chunk
-        cfg.use_graph = 1 if use_graph else 0
-        cfg.warm_start = 1 if warm_start else 0
-        torch.cuda.set_device(device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream()
-        cfg.stream = C.c_void_p(self.stream.cuda_stream or None)
-        self._alloc = None
-        if torch_allocator:
-            self._alloc = _TorchAllocator(device)
-            cfg.dev_alloc = self._alloc.alloc_fn
-            cfg.dev_free = self._alloc.free_fn
         self.cfg = cfg
         self.n = nn[0]
         self.N = nn[0] * nn[1] * nn[2]
@@ -246,21 +289,7 @@ class Rve:
         rc = LIB.rve_apply_macro_strain_increment(self._h, _dptr(Fb),
                                                   float(dt), C.byref(info))
         self._check(rc, ok=(RVE_OK, RVE_ENOTCONV, RVE_ELOCAL))
-        k = info.newton_iters
-        nlog = min(k + 1, MAX_NEWTON_LOG)
-        return dict(status=rc, newton_iters=k,
-                    cg_iters_total=info.cg_iters_total,
-                    cg_iters=list(info.cg_iters[:min(k, MAX_NEWTON_LOG)]),
-                    residuals=list(info.residual_history[:nlog]),
-                    local_failures=info.local_failures,
-                    used_learned=info.used_learned,
-                    cg_breakdowns=info.cg_breakdowns,
-                    residual_rel=info.residual_rel,
-                    predictor_residual=info.predictor_residual,
-                    plain_predictor_residual=info.plain_predictor_residual,
-                    P_bar=np.array(info.P_bar).reshape(3, 3),
-                    sigma_bar=np.array(info.sigma_bar).reshape(3, 3),
-                    seconds=info.seconds)
+        return _info_dict(info, rc)
 
     def reset_fips(self):
         self._check(LIB.rve_reset_fips(self._h))
@@ -357,6 +386,98 @@ class Rve:
 
 WS_FEAT = 48
 WS_OUT = 16
+
+
+class BatchRve:
+    """A batch of independent RVEs of mixed grid edges solved together (one
+    handle of the batch C ABI); one macro gradient per RVE."""
+
+    def __init__(self, ns, L=(1.0, 1.0, 1.0), projection="discrete",
+                 precision="fp64", newton_tol=1e-6, newton_max_iter=25,
+                 cg_tol=1e-4, cg_max_iter=2000, cg_chunk=8, use_graph=False,
+                 stream=None, device=0, torch_allocator=True):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the library runs on the GPU only")
+        self._lib = LIB
+        self._h = None
+        cfg, self.stream, self._alloc = _make_config(
+            L, projection, precision, newton_tol, newton_max_iter, cg_tol,
+            cg_max_iter, cg_chunk, use_graph, False, stream, device,
+            torch_allocator)
+        self.cfg = cfg
+        self.ns = [int(x) for x in ns]
+        arr = np.ascontiguousarray(self.ns, dtype=np.int32)
+        h = C.c_void_p()
+        rc = LIB.rve_batch_create(C.byref(cfg), len(self.ns), _iptr(arr),
+                                  C.byref(h))
+        if rc != RVE_OK:
+            raise RveError(rc, LIB.rve_batch_last_error(None).decode())
+        self._h = h
+
+    def __len__(self):
+        return len(self.ns)
+
+    def close(self):
+        if self._h is not None:
+            self._lib.rve_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, rc, ok=(RVE_OK,)):
+        if rc not in ok:
+            raise RveError(rc, self._lib.rve_batch_last_error(self._h).decode())
+        return rc
+
+    def set_microstructure(self, b, phase, quat, law, params):
+        phase = np.ascontiguousarray(phase, dtype=np.int32).reshape(-1)
+        quat = np.ascontiguousarray(quat, dtype=np.float64).reshape(-1, 4)
+        law = np.ascontiguousarray(law, dtype=np.int32).reshape(-1)
+        params = np.ascontiguousarray(params, dtype=np.float64).reshape(-1)
+        if phase.size != self.ns[b] ** 3:
+            raise ValueError("phase must have n^3 entries")
+        self._check(LIB.rve_batch_set_microstructure(
+            self._h, b, _iptr(phase), quat.shape[0], _dptr(quat), _iptr(law),
+            _dptr(params), params.size))
+
+    def increment(self, F_bar, dt):
+        """One increment of every RVE; F_bar is (3, 3) for all or (B, 3, 3).
+        Returns one dict per RVE (status included)."""
+        B = len(self.ns)
+        Fb = np.asarray(F_bar, dtype=np.float64)
+        Fb = np.ascontiguousarray(np.broadcast_to(Fb.reshape(-1, 9), (B, 9)))
+        info = (RveIncrementInfo * B)()
+        rc = LIB.rve_batch_apply_macro_strain_increment(self._h, _dptr(Fb),
+                                                        float(dt), info)
+        self._check(rc, ok=(RVE_OK, RVE_ENOTCONV, RVE_ELOCAL))
+        return [_info_dict(info[b], info[b].status) for b in range(B)]
+
+    def reset_fips(self):
+        self._check(LIB.rve_batch_reset_fips(self._h))
+
+    def field(self, b, name):
+        fid, comps = FIELDS[name]
+        out = np.empty((comps, self.ns[b] ** 3), dtype=np.float64)
+        self._check(LIB.rve_batch_get_fields(self._h, b, fid, out.ctypes.data_as(
+            C.c_void_p), out.nbytes, 0))
+        return out if comps > 1 else out[0]
+
+    def macro(self, b):
+        out = np.empty(29)
+        self._check(LIB.rve_batch_get_macro(self._h, b, _dptr(out)))
+        return dict(F_bar=out[:9].reshape(3, 3), P_bar=out[9:18].reshape(3, 3),
+                    sigma_bar=out[18:27].reshape(3, 3), t=out[27],
+                    increments=int(out[28]))
 
 
 class WarmStartNet:

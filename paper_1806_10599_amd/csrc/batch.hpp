@@ -1,0 +1,85 @@
+// A batch of independent RVEs of mixed grid edges solved together: one
+// voxel arena for all of them, one launch per pass for the whole batch,
+// per-RVE Newton/CG control (converged RVEs drop out of the work).
+#pragma once
+
+#include <array>
+#include <string>
+#include <vector>
+
+#include "../../include/rve.h"
+#include "kernels.hpp"
+
+namespace rve {
+
+class BatchEngine {
+ public:
+  BatchEngine(const rve_config& cfg, int count, const int32_t* n);
+  ~BatchEngine();
+  void set_microstructure(int b, const int32_t* phase, int32_t G,
+                          const double* quat, const int32_t* law,
+                          const double* params, int32_t nparams);
+  int increment(const double* Fbar_all, double dt, rve_increment_info* info);
+  void reset_fips();
+  void get_field(int b, int field, void* dst, size_t bytes, bool on_device);
+  void get_macro(int b, double out[29]);
+  int count() const { return B_; }
+
+ private:
+  void* alloc(size_t bytes);
+  void upload_scalars();
+  void read_scalars();
+  template <typename T>
+  void cg_iteration(int parity);
+  template <typename T>
+  void cg_solve(std::vector<int>& iters);
+  template <typename T>
+  BatchSpec<T> spec(bool cg, int parity) const;
+
+  rve_config cfg_;
+  int B_;
+  bool fp64_;
+  hipStream_t st_;
+  hipStream_t own_stream_ = nullptr;
+  std::vector<std::pair<void*, size_t>> allocs_;
+  std::vector<int> n_;
+  std::vector<int64_t> off_, soff_;
+  int64_t Nt_ = 0, St_ = 0;
+  // arena fields
+  double *Fprev_, *Pc_, *Fpi_c_, *chi_c_, *dg_c_, *pcyc_, *pcyc_lit_, *wcyc_;
+  double *F_, *P_, *Fpi_t_, *chi_t_, *dg_t_, *r64_, *dFt_;
+  void *K_, *x_, *r_, *p0_, *p1_, *Ap_, *spec_, *spec64_;
+  int32_t* phase_;
+  uint8_t* vrve_;
+  double* table_ = nullptr;
+  int table_labels_ = 0;
+  std::vector<std::vector<double>> host_tables_;
+  std::vector<int> label_count_;
+  std::vector<int> label_off_;
+  std::vector<std::vector<int32_t>> host_phase_;
+  std::vector<bool> have_micro_;
+  double params_[RVE_NPARAMS];
+  bool have_params_ = false;
+  // per-RVE control
+  Scalars* sc_;
+  Scalars* sc_host_ = nullptr;
+  double* dF_dev_;
+  // spectral descriptors (device) and grid sizes
+  void *items32_, *items64_;
+  int blocksA32_, blocksB32_, blocksA64_, blocksB64_;
+  size_t ldsA32_, ldsB32_, ldsA64_, ldsB64_;
+  double* partials_;
+  SegItem* seg_;
+  int seg_blocks_;
+  RedItem *red_inv32_, *red_inv64_, *red_seg_;
+  void *tw32_, *tw64_, *vt32_, *vt64_;  // per distinct edge, concatenated
+  double *psum_, *psq_;
+  // host macro state per RVE
+  std::vector<std::array<double, 9>> Fbar_, Pbar_;
+  std::vector<double> t_;
+  std::vector<int64_t> increments_;
+  hipGraphExec_t graph_ = nullptr;
+  hipGraph_t graph_def_ = nullptr;
+};
+
+}  // namespace rve

@@ -5,10 +5,17 @@
 #include <string>
 
 #include "../../include/rve.h"
+#include "batch.hpp"
 #include "engine.hpp"
 
 struct rve_s {
   rve::Engine* eng = nullptr;
+  std::string err;
+  bool poisoned = false;
+};
+
+struct rve_batch_s {
+  rve::BatchEngine* eng = nullptr;
   std::string err;
   bool poisoned = false;
 };
@@ -291,6 +298,83 @@ rve_status rve_ws_target(rve_t h, float* T) {
     h->eng->target(T);
     return RVE_OK;
   });
+}
+
+rve_status rve_batch_create(const rve_config* cfg, int32_t count,
+                            const int32_t* n, rve_batch_t* out) {
+  if (!cfg || !out || !n) return RVE_EINVAL;
+  *out = nullptr;
+  rve_batch_s* h = new (std::nothrow) rve_batch_s();
+  if (!h) return RVE_ENOMEM;
+  try {
+    h->eng = new rve::BatchEngine(*cfg, count, n);
+  } catch (const rve::Error& e) {
+    g_create_error = e.what();
+    delete h;
+    return (rve_status)e.code;
+  } catch (const std::bad_alloc&) {
+    g_create_error = "host allocation failed";
+    delete h;
+    return RVE_ENOMEM;
+  }
+  *out = h;
+  return RVE_OK;
+}
+
+rve_status rve_batch_destroy(rve_batch_t h) {
+  if (!h) return RVE_OK;
+  delete h->eng;
+  delete h;
+  return RVE_OK;
+}
+
+rve_status rve_batch_set_microstructure(rve_batch_t h, int32_t b,
+                                        const int32_t* phase, int32_t G,
+                                        const double* quat, const int32_t* law,
+                                        const double* params, int32_t nparams) {
+  return guarded(h, [&] {
+    h->eng->set_microstructure(b, phase, G, quat, law, params, nparams);
+    return RVE_OK;
+  });
+}
+
+rve_status rve_batch_apply_macro_strain_increment(rve_batch_t h,
+                                                  const double* F_bar_new,
+                                                  double dt,
+                                                  rve_increment_info* info) {
+  return guarded(h, [&] {
+    if (!F_bar_new) throw rve::Error(RVE_EINVAL, "null F_bar_new");
+    return h->eng->increment(F_bar_new, dt, info);
+  });
+}
+
+rve_status rve_batch_reset_fips(rve_batch_t h) {
+  return guarded(h, [&] {
+    h->eng->reset_fips();
+    return RVE_OK;
+  });
+}
+
+rve_status rve_batch_get_fields(rve_batch_t h, int32_t b, int32_t field,
+                                void* dst, size_t dst_bytes,
+                                int32_t dst_on_device) {
+  return guarded(h, [&] {
+    h->eng->get_field(b, field, dst, dst_bytes, dst_on_device != 0);
+    return RVE_OK;
+  });
+}
+
+rve_status rve_batch_get_macro(rve_batch_t h, int32_t b, double out[29]) {
+  return guarded(h, [&] {
+    if (!out) throw rve::Error(RVE_EINVAL, "null output");
+    h->eng->get_macro(b, out);
+    return RVE_OK;
+  });
+}
+
+const char* rve_batch_last_error(rve_batch_t h) {
+  if (!h) return g_create_error.c_str();
+  return h->err.c_str();
 }
 
 }  // extern "C"

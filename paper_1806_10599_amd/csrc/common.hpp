@@ -68,6 +68,8 @@ struct Scalars {
   int32_t max_iters;
   int32_t first;    // next pass-A call starts a new direction p = r
   int32_t fails;    // return-mapping failures of the last evaluation
+  int32_t inactive;  // batch: this RVE takes no part in the current work
+  int32_t commit;    // batch: commit this RVE's trial state
   int32_t pad;
   double pbar[9];   // <P> of the last residual evaluation
 };

@@ -20,6 +20,8 @@ struct SlabFwdArgs {
   double* psum;        // optional [9][N] per-slab sums
   double* psq;         // optional [9][N] per-slab sums of squares
   const Scalars* sc;
+  int64_t cs;          // component stride of the real fields (N^3, or the
+                       // voxel count of a batch arena)
 };
 
 template <typename T>
@@ -39,6 +41,7 @@ struct SlabInvArgs {
   const T* pdot;       // DST_DOT: direction for p . Ap
   double* partial;     // per block
   const Scalars* sc;   // optional early exit
+  int64_t cs;          // component stride of out / pdot
 };
 
 template <typename T>
@@ -64,6 +67,49 @@ struct SpectralLaunch {
 template <typename T>
 void launch_G(int n, const SpectralLaunch<T>& L, hipStream_t s);
 int slab_blocks(int n, bool fp64);
+int pencil_blocks(int n, bool fp64);
+
+// One RVE of a batch: where its voxels, spectrum and scalars live and where
+// its blocks start in the pass-A/C (blk[0]) and pass-B (blk[1]) grids.
+template <typename T>
+struct SpecItem {
+  int n;
+  int blk[2];
+  int pad;
+  int64_t off;          // voxel offset in the arena
+  int64_t soff;         // complex offset of the spectrum
+  const cplx<T>* tw;
+  const T* vt;
+  Scalars* sc;          // this RVE's scalars
+  double* partial;      // pass-C partials (slab_blocks entries)
+  double* psum;         // residual pass sums [9][n]
+  double* psq;
+};
+
+template <typename T>
+struct BatchSpec {
+  const SpecItem<T>* items;
+  int nitems;
+  int64_t cs;           // voxels in the arena (component stride)
+  const T* field;       // SRC_FIELD input
+  const T* K;
+  const T* r;
+  const T* p_old;
+  T* p_new;
+  cplx<T>* spec;
+};
+
+// passes of a batch: src SRC_FIELD (residual: out_d, norms) or SRC_KP (CG:
+// out_T = Ap, p.Ap partials); block counts of the three grids
+template <typename T>
+void launch_G_batch(const BatchSpec<T>& b, int src, T* out_T, double* out_d,
+                    int blocksA, int blocksB, size_t ldsA, size_t ldsB,
+                    hipStream_t s);
+template <typename T>
+void batch_lds(int n, size_t& slab, size_t& pencil);
+bool batch_supported(int n);
+template <typename T>
+void batch_allow_lds(size_t slab, size_t pencil);
 
 // ---------------------------------------------------------- constitutive
 // Per-label table, kTableStride doubles per label:
@@ -95,6 +141,9 @@ struct ConstArgs {
   int32_t* iters;        // optional per-voxel local iterations
   LawParams lp;
   int64_t N;
+  const uint8_t* vrve;   // batch: RVE of each voxel (null for one RVE)
+  Scalars* scs;          // batch: per-RVE flags (skip when inactive) and
+                         // per-RVE failure counts (fails unused)
 };
 
 template <typename TK>
@@ -108,6 +157,8 @@ struct TangentArgs {
   TK* K;                 // [81][N]
   LawParams lp;
   int64_t N;
+  const uint8_t* vrve;
+  const Scalars* scs;
 };
 
 void launch_return_map(const ConstArgs& a, hipStream_t s);
@@ -154,5 +205,62 @@ void launch_init_scalars(Scalars* sc, int max_iters, double eta, hipStream_t s);
 void launch_bench_scalars(Scalars* sc, hipStream_t s);
 
 constexpr int kRedBlocks = 1024;  // grid of the elementwise reductions
+
+// ---------------------------------------------------------- batch helpers
+// Elementwise batch kernels give each RVE its own run of blocks so that
+// every block's partial sum belongs to one RVE.
+struct SegItem {
+  int64_t off;      // voxel offset in the arena
+  int64_t n9;       // 9 * voxels of this RVE
+  int blk0;         // first block of this RVE
+  int nblk;
+  double* partial;  // per-block partials of this RVE (nblk entries)
+  Scalars* sc;
+};
+struct RedItem {
+  const double* partial;
+  int count;
+  const double* psum;
+  const double* psq;
+  int nss;
+  double invN3;
+};
+template <typename T>
+void launch_cg_init_batch(const SegItem* items, int nitems, int blocks,
+                          int64_t cs, const double* r64, T* r, T* x,
+                          hipStream_t s);
+template <typename T>
+void launch_cg_update_batch(const SegItem* items, int nitems, int blocks,
+                            int64_t cs, T* x, T* r, const T* p, const T* Ap,
+                            hipStream_t s);
+void launch_reduce_batch(int op, const RedItem* items, int nitems,
+                         Scalars* scs, hipStream_t s);
+void launch_predict_batch(double* F, const double* Fprev, const uint8_t* vrve,
+                          const double* dF /*[B][9]*/, int64_t N,
+                          hipStream_t s);
+struct CommitBatchArgs {
+  const uint8_t* vrve;
+  const Scalars* scs;
+  const double* dF;   // [B][9] macro increments
+  const double* F;    // Newton iterate (converged)
+  const double* P;
+  const double* Fpi_t;
+  const double* chi_t;
+  const double* dg_t;
+  double* Fprev;
+  double* Pc;
+  double* Fpi_c;
+  double* chi_c;
+  double* dg_c;
+  double* dFt;
+  const int32_t* phase;
+  const double* table;
+  double* pcyc;
+  double* pcyc_lit;
+  double* wcyc;
+  double dt;
+  int64_t N;
+};
+void launch_commit_batch(const CommitBatchArgs& a, hipStream_t s);
 
 }  // namespace rve

@@ -32,8 +32,17 @@ constexpr double LOCAL_ATOL = 1e-18;
 constexpr double LOCAL_RFLOOR = 1e-10;
 
 // Voigt order 11, 22, 33, 23, 13, 12
-__device__ constexpr int VI[3][3] = {{0, 5, 4}, {5, 1, 3}, {4, 3, 2}};
 __device__ constexpr double VW[6] = {1, 1, 1, 2, 2, 2};
+
+// Hides the table pointer's value from the optimizer so that table entries
+// are re-read (from cache) at each use instead of being hoisted out of the
+// local Newton loop into registers, which would exhaust the register file.
+// The asm is empty: no instruction is emitted and no memory is accessed.
+__device__ __forceinline__ const double* opaque(const double* p) {
+  uint64_t u = (uint64_t)p;
+  asm volatile("" : "+v"(u));
+  return (const double*)u;
+}
 
 __device__ __forceinline__ double sgn(double x) {
   return (x > 0.0) ? 1.0 : ((x < 0.0) ? -1.0 : 0.0);
@@ -88,8 +97,8 @@ struct CpEval {
   double Fe[9];
   double S[6];
   double chi[12];
-  double x[12];
   double R[12];
+  double h[12];   // d asinh(|x|^n sign x) / dx, x = (tau - chi)/g
 };
 
 // Return-mapping residual at slips dg.  Fes = F Fp^-1_0.
@@ -98,6 +107,7 @@ __device__ __forceinline__ void cp_eval(const double* Fes,
                                         const double* __restrict__ tb,
                                         const LawParams& lp, double a,
                                         CpEval& e) {
+  tb = opaque(tb);
 #pragma unroll
   for (int i = 0; i < 9; ++i) e.Fe[i] = Fes[i];
 #pragma unroll
@@ -142,7 +152,7 @@ __device__ __forceinline__ void cp_eval(const double* Fes,
     double val, der;
     asinh_pow(x, lp.nexp, val, der);
     e.chi[al] = chi;
-    e.x[al] = x;
+    e.h[al] = der;
     e.R[al] = asinh(dg[al] / a) - val;
   }
 }
@@ -249,13 +259,13 @@ __device__ __forceinline__ void cp_jacobian(const CpEval& e, const double* Fes,
                                             const LawParams& lp, double a,
                                             double* D, double* hg, double* Q,
                                             LU6& L) {
+  tb = opaque(tb);
   make_Q(e.Fe, Fes, Q);
 #pragma unroll
   for (int i = 0; i < 36; ++i) L.M[i] = (i % 7 == 0) ? 1.0 : 0.0;
 #pragma unroll
   for (int al = 0; al < 12; ++al) {
-    double val, h;
-    asinh_pow(e.x[al], lp.nexp, val, h);
+    const double h = e.h[al];
     const double ad = fabs(dg[al]);
     const double dchi = (lp.c_af - lp.d_af * sgn(dg[al]) * e.chi[al]) / (1.0 + lp.d_af * ad);
     D[al] = 1.0 / sqrt(a * a + dg[al] * dg[al]) + h * dchi / lp.g;
@@ -277,6 +287,7 @@ __device__ __forceinline__ void cp_jsolve(const double* rhs, const double* D,
                                           const double* hg, const double* Q,
                                           const double* __restrict__ tb,
                                           const LU6& L, double* out) {
+  tb = opaque(tb);
   double z[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
   for (int al = 0; al < 12; ++al) {
@@ -305,7 +316,7 @@ __device__ __forceinline__ double half_sq(const double* R) {
 
 // Damped Newton from the slips in dg; returns true on convergence and
 // leaves the evaluation at the final slips in e.
-__device__ bool cp_local_solve(const double* Fes, const double* chi0,
+__device__ __forceinline__ bool cp_local_solve(const double* Fes, const double* chi0,
                                double* dg, const double* __restrict__ tb,
                                const LawParams& lp, double a, CpEval& e,
                                int& iters) {
@@ -372,6 +383,7 @@ __device__ __forceinline__ void load9(const double* __restrict__ p, int64_t v,
 __global__ __launch_bounds__(128) void return_map_kernel(ConstArgs A) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= A.N) return;
+  if (A.vrve && A.scs[A.vrve[v]].inactive) return;
   const int64_t N = A.N;
   const double* __restrict__ tb = A.table + (int64_t)A.phase[v] * kTableStride;
   double F[9];
@@ -420,13 +432,16 @@ __global__ __launch_bounds__(128) void return_map_kernel(ConstArgs A) {
   const double a = A.lp.dt * A.lp.gdot0;
   CpEval e;
   int iters = 0;
-  bool ok = cp_local_solve(Fes, chi0, dg, tb, A.lp, a, e, iters);
-  if (!ok && warm) {
+  bool ok = false;
+  for (int attempt = 0; attempt < 2 && !ok; ++attempt) {
+    if (attempt == 1) {
+      if (!warm) break;
 #pragma unroll
-    for (int al = 0; al < 12; ++al) dg[al] = 0.0;
+      for (int al = 0; al < 12; ++al) dg[al] = 0.0;  // retry from zero slips
+    }
     ok = cp_local_solve(Fes, chi0, dg, tb, A.lp, a, e, iters);
   }
-  if (!ok) atomicAdd(A.fails, 1);
+  if (!ok) atomicAdd(A.vrve ? &A.scs[A.vrve[v]].fails : A.fails, 1);
   // Fp^-1 = Fp^-1_0 (I - sum dg s (x) m);  P = Fe S Fp^-T
   double Fpi[9];
 #pragma unroll
@@ -473,6 +488,7 @@ template <typename TK>
 __global__ __launch_bounds__(128) void tangent_kernel(TangentArgs<TK> A) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= A.N) return;
+  if (A.vrve && A.scs[A.vrve[v]].inactive) return;
   const int64_t N = A.N;
   const double* __restrict__ tb = A.table + (int64_t)A.phase[v] * kTableStride;
   double F[9];
@@ -559,8 +575,14 @@ __global__ __launch_bounds__(128) void tangent_kernel(TangentArgs<TK> A) {
 #pragma unroll 1
   for (int kl = 0; kl < 9; ++kl) {
     const int k = kl / 3, l = kl - 3 * (kl / 3);
-    const double fk[3] = {e.Fe[3 * k], e.Fe[3 * k + 1], e.Fe[3 * k + 2]};
-    const double pl[3] = {Fpi[3 * l], Fpi[3 * l + 1], Fpi[3 * l + 2]};
+    // rows k of Fe and l of Fp^-1, B row l: selects keep them in registers
+    double fk[3], pl[3], Bl[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      fk[c] = (k == 0) ? e.Fe[c] : ((k == 1) ? e.Fe[3 + c] : e.Fe[6 + c]);
+      pl[c] = (l == 0) ? Fpi[c] : ((l == 1) ? Fpi[3 + c] : Fpi[6 + c]);
+      Bl[c] = (l == 0) ? B[c] : ((l == 1) ? B[3 + c] : B[6 + c]);
+    }
     // dR/dF_kl: b_a = (h_a/g) fk . N_a pl  (dtau_a/dF = Fe N_a Fp^-T)
     double b[12], gcol[12];
 #pragma unroll
@@ -620,7 +642,7 @@ __global__ __launch_bounds__(128) void tangent_kernel(TangentArgs<TK> A) {
       for (int j = 0; j < 3; ++j) {
         double K = Fs[3 * i] * Fpi[3 * j] + Fs[3 * i + 1] * Fpi[3 * j + 1] +
                    Fs[3 * i + 2] * Fpi[3 * j + 2] - acc9[3 * i + j];
-        if (i == k) K += B[3 * l + j];
+        if (i == k) K += Bl[j];
         A.K[(int64_t)(9 * (3 * i + j) + kl) * N + v] = TK(K);
       }
   }

@@ -126,10 +126,10 @@ void Net::forward(const uint16_t* X, int n, float* Y, hipStream_t s) {
   hipStream_t st = s ? s : st_;
   const float* b[4];
   for (int k = 0; k < 4; ++k) b[k] = w_ + layer_off(k) + (int64_t)27 * kCin[k] * kCout[k];
-  nn_conv(kFeat, kWidth, 0, X, wf_[0], b[0], a1_, nullptr, nullptr, n, N, st);
-  nn_conv(kWidth, kWidth, 0, a1_, wf_[1], b[1], a2_, nullptr, nullptr, n, N, st);
-  nn_conv(kWidth, kWidth, 0, a2_, wf_[2], b[2], a3_, nullptr, nullptr, n, N, st);
-  nn_conv(kWidth, kOut, 1, a3_, wf_[3], b[3], nullptr, Y, nullptr, n, N, st);
+  nn_conv(kFeat, kWidth, 0, X, wf_[0], b[0], a1_, nullptr, nullptr, n, N, kWidth, st);
+  nn_conv(kWidth, kWidth, 0, a1_, wf_[1], b[1], a2_, nullptr, nullptr, n, N, kWidth, st);
+  nn_conv(kWidth, kWidth, 0, a2_, wf_[2], b[2], a3_, nullptr, nullptr, n, N, kWidth, st);
+  nn_conv(kWidth, kOut, 1, a3_, wf_[3], b[3], nullptr, Y, nullptr, n, N, kOutReal, st);
   RVE_HIP(hipGetLastError());
 }
 
@@ -160,7 +160,7 @@ double Net::train_step(const uint16_t* X, const float* T, int n, float lr,
       // gradient at the output of layer k-1, through its ReLU
       uint16_t* out = dbuf[k % 2];
       nn_conv(COUT, CIN, 2, dz, wb_[k], nullptr, out, nullptr, acts[k], n, N,
-              st_);
+              CIN, st_);
       dz = out;
     }
   }

@@ -41,7 +41,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(
     const uint16_t* __restrict__ X, const uint16_t* __restrict__ Wf,
     const float* __restrict__ bias, uint16_t* __restrict__ Yb,
     float* __restrict__ Yf, const uint16_t* __restrict__ mask_act, int n,
-    int64_t N) {
+    int64_t N, int cout_real) {
   constexpr int KC = CIN / 16, NT = COUT / 16;
   const int lane = threadIdx.x & 63;
   const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -75,7 +75,8 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) {
     const int co = nt * 16 + row;
-    const float bv = (EPI == 2) ? 0.f : bias[co];
+    // the bias has only the real output channels
+    const float bv = (EPI == 2 || co >= cout_real) ? 0.f : bias[co];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int64_t v = v0 + 4 * grp + i;
@@ -274,22 +275,25 @@ __global__ void pack_kernel(const float* __restrict__ W, int cin, int cout,
 namespace {
 template <int CIN, int COUT, int EPI>
 void conv_t(const uint16_t* X, const uint16_t* Wf, const float* b, uint16_t* Yb,
-            float* Yf, const uint16_t* mask, int n, int64_t N, hipStream_t s) {
+            float* Yf, const uint16_t* mask, int n, int64_t N, int creal,
+            hipStream_t s) {
   const int64_t tiles = N / 16;
   hipLaunchKernelGGL((conv_mfma_kernel<CIN, COUT, EPI>),
                      dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, s, X, Wf,
-                     b, Yb, Yf, mask, n, N);
+                     b, Yb, Yf, mask, n, N, creal);
 }
 }  // namespace
 
 void nn_conv(int cin, int cout, int epi, const uint16_t* X, const uint16_t* Wf,
              const float* b, uint16_t* Yb, float* Yf, const uint16_t* mask,
-             int n, int64_t N, hipStream_t s) {
+             int n, int64_t N, int cout_real, hipStream_t s) {
+  if (n % 16 || N != (int64_t)n * n * n)
+    throw Error(-1, "convolution grid must be n^3 with n % 16 == 0");
 #define RVE_CONV(CI, CO)                                                      \
   if (cin == CI && cout == CO) {                                              \
-    if (epi == 0) conv_t<CI, CO, 0>(X, Wf, b, Yb, Yf, mask, n, N, s);         \
-    else if (epi == 1) conv_t<CI, CO, 1>(X, Wf, b, Yb, Yf, mask, n, N, s);    \
-    else conv_t<CI, CO, 2>(X, Wf, b, Yb, Yf, mask, n, N, s);                  \
+    if (epi == 0) conv_t<CI, CO, 0>(X, Wf, b, Yb, Yf, mask, n, N, cout_real, s);      \
+    else if (epi == 1) conv_t<CI, CO, 1>(X, Wf, b, Yb, Yf, mask, n, N, cout_real, s); \
+    else conv_t<CI, CO, 2>(X, Wf, b, Yb, Yf, mask, n, N, cout_real, s);               \
     return;                                                                   \
   }
   RVE_CONV(48, 32)

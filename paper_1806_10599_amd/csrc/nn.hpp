@@ -15,7 +15,7 @@ constexpr int kOutReal = 9, kOut = 16;
 
 void nn_conv(int cin, int cout, int epi, const uint16_t* X, const uint16_t* Wf,
              const float* b, uint16_t* Yb, float* Yf, const uint16_t* mask,
-             int n, int64_t N, hipStream_t s);
+             int n, int64_t N, int cout_real, hipStream_t s);
 void nn_wgrad(int cin, int cout, const uint16_t* X, const uint16_t* dZ,
               float* part, int nchunks, int64_t chunk, int n, int64_t N,
               hipStream_t s);

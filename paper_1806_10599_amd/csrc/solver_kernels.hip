@@ -368,4 +368,257 @@ template void launch_convert<float>(const double*, float*, int64_t,
 template void launch_convert<double>(const double*, double*, int64_t,
                                      hipStream_t);
 
+
+// ------------------------------------------------------------------ batch
+__device__ __forceinline__ int seg_item(const SegItem* items, int nitems) {
+  int r = 0;
+  while (r + 1 < nitems && items[r + 1].blk0 <= (int)blockIdx.x) ++r;
+  return r;
+}
+
+// per RVE: r = -r64 (active) or 0 (inactive), x = 0, partial sums of r.r
+template <typename T>
+__global__ __launch_bounds__(kBlock) void cg_init_batch_kernel(
+    const SegItem* __restrict__ items, int nitems, int64_t cs,
+    const double* __restrict__ r64, T* __restrict__ r, T* __restrict__ x) {
+  __shared__ double red[kBlock];
+  const SegItem& it = items[seg_item(items, nitems)];
+  const bool act = !it.sc->inactive;
+  const int lb = blockIdx.x - it.blk0;
+  const int64_t nv = it.n9 / 9;
+  double acc = 0.0;
+  for (int64_t e = (int64_t)lb * blockDim.x + threadIdx.x; e < it.n9;
+       e += (int64_t)it.nblk * blockDim.x) {
+    const int64_t i = (e / nv) * cs + it.off + (e % nv);
+    const T b = act ? T(-r64[i]) : T(0);
+    r[i] = b;
+    x[i] = T(0);
+    acc += double(b) * double(b);
+  }
+  const double t = block_reduce(acc, red);
+  if (threadIdx.x == 0) it.partial[lb] = t;
+}
+
+template <typename T>
+void launch_cg_init_batch(const SegItem* items, int nitems, int blocks,
+                          int64_t cs, const double* r64, T* r, T* x,
+                          hipStream_t s) {
+  hipLaunchKernelGGL((cg_init_batch_kernel<T>), dim3(blocks), dim3(kBlock), 0,
+                     s, items, nitems, cs, r64, r, x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void cg_update_batch_kernel(
+    const SegItem* __restrict__ items, int nitems, int64_t cs,
+    T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
+    const T* __restrict__ Ap) {
+  __shared__ double red[kBlock];
+  const SegItem& it = items[seg_item(items, nitems)];
+  if (it.sc->done) return;
+  const T alpha = T(it.sc->alpha);
+  const int lb = blockIdx.x - it.blk0;
+  const int64_t nv = it.n9 / 9;
+  double acc = 0.0;
+  for (int64_t e = (int64_t)lb * blockDim.x + threadIdx.x; e < it.n9;
+       e += (int64_t)it.nblk * blockDim.x) {
+    const int64_t i = (e / nv) * cs + it.off + (e % nv);
+    x[i] += alpha * p[i];
+    const T rn = r[i] - alpha * Ap[i];
+    r[i] = rn;
+    acc += double(rn) * double(rn);
+  }
+  const double t = block_reduce(acc, red);
+  if (threadIdx.x == 0) it.partial[lb] = t;
+}
+
+template <typename T>
+void launch_cg_update_batch(const SegItem* items, int nitems, int blocks,
+                            int64_t cs, T* x, T* r, const T* p, const T* Ap,
+                            hipStream_t s) {
+  hipLaunchKernelGGL((cg_update_batch_kernel<T>), dim3(blocks), dim3(kBlock),
+                     0, s, items, nitems, cs, x, r, p, Ap);
+}
+
+// one block per RVE, same scalar logic as the single-RVE reduction
+__global__ __launch_bounds__(kBlock) void reduce_batch_kernel(
+    int op, const RedItem* __restrict__ items, Scalars* __restrict__ scs) {
+  __shared__ double red[kBlock];
+  const RedItem& it = items[blockIdx.x];
+  Scalars* sc = scs + blockIdx.x;
+  if (op == RED_RESID && sc->inactive) return;
+  if ((op == RED_ALPHA || op == RED_BETA) && sc->done) return;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < it.count; i += blockDim.x) acc += it.partial[i];
+  const double tot = block_reduce(acc, red);
+  if (op == RED_RESID) {
+    double a2 = 0.0;
+    for (int i = threadIdx.x; i < 9 * it.nss; i += blockDim.x) a2 += it.psq[i];
+    const double P2 = block_reduce(a2, red);
+    for (int c = 0; c < 9; ++c) {
+      double a1 = 0.0;
+      for (int i = threadIdx.x; i < it.nss; i += blockDim.x)
+        a1 += it.psum[c * it.nss + i];
+      const double m = block_reduce(a1, red);
+      if (threadIdx.x == 0) sc->pbar[c] = m * it.invN3;
+    }
+    if (threadIdx.x == 0) {
+      sc->res2 = tot;
+      sc->P2 = P2;
+    }
+    return;
+  }
+  if (threadIdx.x != 0) return;
+  if (op == RED_INIT) {
+    sc->bb = tot;
+    sc->rr = tot;
+    sc->eta2bb = sc->eta2bb * tot;
+    sc->iters = 0;
+    sc->first = 1;
+    sc->breakdown = 0;
+    sc->converged = (tot == 0.0) ? 1 : 0;
+    sc->done = (sc->converged || sc->inactive) ? 1 : 0;
+    sc->alpha = 0.0;
+    sc->beta = 0.0;
+  } else if (op == RED_ALPHA) {
+    sc->pAp = tot;
+    if (!(tot > 0.0) || !isfinite(tot)) {
+      sc->breakdown = 1;
+      sc->done = 1;
+      sc->iters += 1;
+    } else {
+      sc->alpha = sc->rr / tot;
+    }
+  } else if (op == RED_BETA) {
+    sc->iters += 1;
+    sc->rr_new = tot;
+    sc->first = 0;
+    if (tot <= sc->eta2bb) {
+      sc->converged = 1;
+      sc->done = 1;
+    } else if (sc->iters >= sc->max_iters || !isfinite(tot)) {
+      sc->done = 1;
+    } else {
+      sc->beta = tot / sc->rr;
+      sc->rr = tot;
+    }
+  }
+}
+
+void launch_reduce_batch(int op, const RedItem* items, int nitems,
+                         Scalars* scs, hipStream_t s) {
+  hipLaunchKernelGGL(reduce_batch_kernel, dim3(nitems), dim3(kBlock), 0, s, op,
+                     items, scs);
+}
+
+__global__ void predict_batch_kernel(double* __restrict__ F,
+                                     const double* __restrict__ Fp,
+                                     const uint8_t* __restrict__ vrve,
+                                     const double* __restrict__ dF, int64_t N) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 9 * N;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = i / N;
+    F[i] = Fp[i] + dF[9 * vrve[i - c * N] + c];
+  }
+}
+
+void launch_predict_batch(double* F, const double* Fprev, const uint8_t* vrve,
+                          const double* dF, int64_t N, hipStream_t s) {
+  hipLaunchKernelGGL(predict_batch_kernel, dim3(2048), dim3(kBlock), 0, s, F,
+                     Fprev, vrve, dF, N);
+}
+
+// commit of the RVEs flagged in their scalars: committed state <- trial,
+// F_prev <- F, the fluctuation increment, and the indicator fields
+__global__ __launch_bounds__(kBlock) void commit_batch_kernel(CommitBatchArgs A) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= A.N) return;
+  const int b = A.vrve[v];
+  if (!A.scs[b].commit) return;
+  const int64_t N = A.N;
+  double F[9], Fpi[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) {
+    F[c] = A.F[c * N + v];
+    Fpi[c] = A.Fpi_t[c * N + v];
+    A.dFt[c * N + v] = F[c] - A.Fprev[c * N + v] - A.dF[9 * b + c];
+    A.Fprev[c * N + v] = F[c];
+    A.Pc[c * N + v] = A.P[c * N + v];
+    A.Fpi_c[c * N + v] = Fpi[c];
+  }
+  double dg[12];
+#pragma unroll
+  for (int al = 0; al < 12; ++al) {
+    dg[al] = A.dg_t[al * N + v];
+    A.dg_c[al * N + v] = dg[al];
+    A.chi_c[al * N + v] = A.chi_t[al * N + v];
+  }
+  const double* __restrict__ tb = A.table + (int64_t)A.phase[v] * kTableStride;
+  if (tb[0] != 0.0) return;
+  double dLp[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int al = 0; al < 12; ++al)
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        dLp[3 * i + j] += dg[al] * tb[kTabS + 3 * al + i] * tb[kTabM + 3 * al + j];
+  double dd = 0.0;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) dd += dLp[i] * dLp[i];
+  A.pcyc[v] += sqrt(2.0 / 3.0 * dd);
+  A.pcyc_lit[v] += dd / A.dt;
+  double Fe[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      Fe[3 * i + j] = F[3 * i] * Fpi[j] + F[3 * i + 1] * Fpi[3 + j] +
+                      F[3 * i + 2] * Fpi[6 + j];
+  double C[9];
+#pragma unroll
+  for (int p = 0; p < 3; ++p)
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      C[3 * p + q] = Fe[p] * Fe[q] + Fe[3 + p] * Fe[3 + q] + Fe[6 + p] * Fe[6 + q];
+  const double E[6] = {0.5 * (C[0] - 1.0), 0.5 * (C[4] - 1.0),
+                       0.5 * (C[8] - 1.0), 0.5 * C[5],
+                       0.5 * C[2],         0.5 * C[1]};
+  const double w[6] = {1, 1, 1, 2, 2, 2};
+  double S[6];
+#pragma unroll
+  for (int I = 0; I < 6; ++I) {
+    double acc = 0.0;
+#pragma unroll
+    for (int J = 0; J < 6; ++J) acc += tb[kTabC + 6 * I + J] * w[J] * E[J];
+    S[I] = acc;
+  }
+#pragma unroll
+  for (int al = 0; al < 12; ++al) {
+    const double* s = tb + kTabS + 3 * al;
+    const double* m = tb + kTabM + 3 * al;
+    const double Sm0 = S[0] * m[0] + S[5] * m[1] + S[4] * m[2];
+    const double Sm1 = S[5] * m[0] + S[1] * m[1] + S[3] * m[2];
+    const double Sm2 = S[4] * m[0] + S[3] * m[1] + S[2] * m[2];
+    A.wcyc[al * N + v] += (s[0] * Sm0 + s[1] * Sm1 + s[2] * Sm2) * dg[al];
+  }
+}
+
+void launch_commit_batch(const CommitBatchArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(commit_batch_kernel, dim3((unsigned)((a.N + kBlock - 1) / kBlock)),
+                     dim3(kBlock), 0, s, a);
+}
+
+template void launch_cg_init_batch<float>(const SegItem*, int, int, int64_t,
+                                          const double*, float*, float*,
+                                          hipStream_t);
+template void launch_cg_init_batch<double>(const SegItem*, int, int, int64_t,
+                                           const double*, double*, double*,
+                                           hipStream_t);
+template void launch_cg_update_batch<float>(const SegItem*, int, int, int64_t,
+                                            float*, float*, const float*,
+                                            const float*, hipStream_t);
+template void launch_cg_update_batch<double>(const SegItem*, int, int, int64_t,
+                                             double*, double*, const double*,
+                                             const double*, hipStream_t);
+
 }  // namespace rve

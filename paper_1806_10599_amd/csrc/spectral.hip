@@ -89,16 +89,14 @@ __device__ __forceinline__ void load_twiddles(cplx<T>* tw,
 }
 
 // ------------------------------------------------------------------ pass A
+// lb: logical block within this RVE's pass-A grid
 template <typename T, int N, int CPB, int SRC>
-__global__ __launch_bounds__(kBlock) void slab_fwd_kernel(SlabFwdArgs<T> a) {
+__device__ __forceinline__ void slab_fwd_body(const SlabFwdArgs<T>& a, int lb,
+                                              cplx<T>* lds, cplx<T>* tw,
+                                              double* red) {
   constexpr int H = N / 2;
-  constexpr int N3 = N * N * N;
   constexpr int NG = 9 / CPB;
-  __shared__ cplx<T> lds[CPB * SlabGeom<N>::PLANE];
-  __shared__ cplx<T> tw[N];
-  __shared__ double red[kBlock];
-  if (SRC == SRC_KP && a.sc->done) return;
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t cs = a.cs;
   const int x = lb / NG;
   const int grp = lb - x * NG;
   load_twiddles<T, N>(tw, a.tw);
@@ -111,26 +109,26 @@ __global__ __launch_bounds__(kBlock) void slab_fwd_kernel(SlabFwdArgs<T> a) {
   const T beta = (SRC == SRC_KP) ? T(a.sc->beta) : T(0);
   for (int t = threadIdx.x; t < N * N; t += blockDim.x) {
     const int y = t / N, z = t - (t / N) * N;
-    const int v = (x * N + y) * N + z;
+    const int64_t v = (x * N + y) * N + z;
     T out[CPB];
     if constexpr (SRC == SRC_FIELD) {
 #pragma unroll
-      for (int q = 0; q < CPB; ++q) out[q] = a.field[(grp * CPB + q) * N3 + v];
+      for (int q = 0; q < CPB; ++q) out[q] = a.field[(grp * CPB + q) * cs + v];
     } else {
       T pd[9];
 #pragma unroll
       for (int d = 0; d < 9; ++d) {
-        T val = a.r[d * N3 + v];
-        if (!first) val += beta * a.p_old[d * N3 + v];
+        T val = a.r[d * cs + v];
+        if (!first) val += beta * a.p_old[d * cs + v];
         pd[d] = val;
       }
 #pragma unroll
       for (int q = 0; q < CPB; ++q) {
         const int c = grp * CPB + q;
-        a.p_new[c * N3 + v] = pd[c];
+        a.p_new[c * cs + v] = pd[c];
         T acc = T(0);
 #pragma unroll
-        for (int d = 0; d < 9; ++d) acc += a.K[(9 * c + d) * N3 + v] * pd[d];
+        for (int d = 0; d < 9; ++d) acc += a.K[(9 * c + d) * cs + v] * pd[d];
         out[q] = acc;
       }
     }
@@ -198,14 +196,11 @@ __global__ __launch_bounds__(kBlock) void slab_fwd_kernel(SlabFwdArgs<T> a) {
 
 // ------------------------------------------------------------------ pass B
 template <typename T, int N, int TT>
-__global__ __launch_bounds__(kBlock) void pencil_proj_kernel(PencilArgs<T> a) {
+__device__ __forceinline__ void pencil_body(const PencilArgs<T>& a, int lb,
+                                            cplx<T>* lds, cplx<T>* tw) {
   constexpr int H = N / 2;
   constexpr int TP = TT + 1;  // LDS pitch of a kx row (complex)
   constexpr int NTILE = (H + TT - 1) / TT;
-  __shared__ cplx<T> lds[3 * N * TP];
-  __shared__ cplx<T> tw[N];
-  if (a.sc && a.sc->done) return;
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int i = lb % 3;
   const int rest = lb / 3;
   const int tile = rest % NTILE;
@@ -274,15 +269,12 @@ __global__ __launch_bounds__(kBlock) void pencil_proj_kernel(PencilArgs<T> a) {
 
 // ------------------------------------------------------------------ pass C
 template <typename T, typename TO, int N, int CPB, int DST>
-__global__ __launch_bounds__(kBlock) void slab_inv_kernel(SlabInvArgs<T, TO> a) {
+__device__ __forceinline__ void slab_inv_body(const SlabInvArgs<T, TO>& a,
+                                              int lb, cplx<T>* lds,
+                                              cplx<T>* tw, double* red) {
   constexpr int H = N / 2;
-  constexpr int N3 = N * N * N;
   constexpr int NG = 9 / CPB;
-  __shared__ cplx<T> lds[CPB * SlabGeom<N>::PLANE];
-  __shared__ cplx<T> tw[N];
-  __shared__ double red[kBlock];
-  if (a.sc && a.sc->done) return;
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t cs = a.cs;
   const int x = lb / NG;
   const int grp = lb - x * NG;
   load_twiddles<T, N>(tw, a.tw);
@@ -319,16 +311,16 @@ __global__ __launch_bounds__(kBlock) void slab_inv_kernel(SlabInvArgs<T, TO> a) 
   double acc = 0.0;
   for (int t = threadIdx.x; t < N * N; t += blockDim.x) {
     const int y = t / N, z = t - (t / N) * N;
-    const int v = (x * N + y) * N + z;
+    const int64_t v = (x * N + y) * N + z;
     const int yp = (y < H) ? y : y - H;
 #pragma unroll
     for (int q = 0; q < CPB; ++q) {
       const int c = grp * CPB + q;
       const cplx<T> zz = lds[q * SlabGeom<N>::PLANE + yp * SlabGeom<N>::PITCH + z];
       const T val = (y < H) ? zz.x : zz.y;
-      a.out[c * N3 + v] = TO(val);
+      a.out[c * cs + v] = TO(val);
       if constexpr (DST == DST_DOT) {
-        acc += double(a.pdot[c * N3 + v]) * double(val);
+        acc += double(a.pdot[c * cs + v]) * double(val);
       } else {
         acc += double(val) * double(val);
       }
@@ -336,19 +328,155 @@ __global__ __launch_bounds__(kBlock) void slab_inv_kernel(SlabInvArgs<T, TO> a) 
   }
   if (a.partial) {
     double tot = block_sum(acc, red);
-    if (threadIdx.x == 0) a.partial[blockIdx.x] = tot;
+    if (threadIdx.x == 0) a.partial[lb] = tot;
   }
 }
 
-// ---------------------------------------------------------------- launchers
 template <typename T, int N>
 struct SpectralTraits {
   // components per slab block: three (one tensor row) when the planes fit
   static constexpr int CPB =
       (3 * SlabGeom<N>::PLANE * (int)sizeof(cplx<T>) <= 64 * 1024) ? 3 : 1;
   static constexpr int TT = (sizeof(T) == 4) ? 16 : 8;
+  static constexpr size_t SLAB_LDS =
+      (CPB * SlabGeom<N>::PLANE + N) * sizeof(cplx<T>) + kBlock * sizeof(double);
+  static constexpr size_t PENCIL_LDS =
+      (3 * N * (TT + 1) + N) * sizeof(cplx<T>);
 };
 
+// ---------------------------------------------------- single-RVE kernels
+template <typename T, int N, int CPB, int SRC>
+__global__ __launch_bounds__(kBlock) void slab_fwd_kernel(SlabFwdArgs<T> a) {
+  __shared__ cplx<T> lds[CPB * SlabGeom<N>::PLANE];
+  __shared__ cplx<T> tw[N];
+  __shared__ double red[kBlock];
+  if (SRC == SRC_KP && a.sc->done) return;
+  slab_fwd_body<T, N, CPB, SRC>(a, xcd_remap(blockIdx.x, gridDim.x), lds, tw, red);
+}
+
+template <typename T, int N, int TT>
+__global__ __launch_bounds__(kBlock) void pencil_proj_kernel(PencilArgs<T> a) {
+  __shared__ cplx<T> lds[3 * N * (TT + 1)];
+  __shared__ cplx<T> tw[N];
+  if (a.sc && a.sc->done) return;
+  pencil_body<T, N, TT>(a, xcd_remap(blockIdx.x, gridDim.x), lds, tw);
+}
+
+template <typename T, typename TO, int N, int CPB, int DST>
+__global__ __launch_bounds__(kBlock) void slab_inv_kernel(SlabInvArgs<T, TO> a) {
+  __shared__ cplx<T> lds[CPB * SlabGeom<N>::PLANE];
+  __shared__ cplx<T> tw[N];
+  __shared__ double red[kBlock];
+  if (a.sc && a.sc->done) return;
+  slab_inv_body<T, TO, N, CPB, DST>(a, xcd_remap(blockIdx.x, gridDim.x), lds,
+                                    tw, red);
+}
+
+// ------------------------------------------------------- batched kernels
+// Every RVE of a batch in one launch: block -> (RVE, local block) through
+// the descriptor table; the RVE's edge selects the compiled FFT plan.
+// Converged or retired RVEs (Scalars::done for CG work, ::inactive for the
+// residual) return at once.
+#define RVE_BATCH_SIZES(X) X(16) X(24) X(32) X(40) X(48) X(64)
+
+template <typename T>
+__device__ __forceinline__ int batch_item(const BatchSpec<T>& b, int pass) {
+  const int blk = blockIdx.x;
+  int r = 0;
+  while (r + 1 < b.nitems && b.items[r + 1].blk[pass] <= blk) ++r;
+  return r;
+}
+
+template <typename T, int SRC>
+__global__ __launch_bounds__(kBlock) void slab_fwd_batch_kernel(BatchSpec<T> b) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int r = batch_item(b, 0);
+  const SpecItem<T>& it = b.items[r];
+  if (SRC == SRC_KP ? it.sc->done : it.sc->inactive) return;
+  const int lb = blockIdx.x - it.blk[0];
+  SlabFwdArgs<T> a{};
+  a.cs = b.cs;
+  a.field = b.field ? b.field + it.off : nullptr;
+  a.K = b.K ? b.K + it.off : nullptr;
+  a.r = b.r ? b.r + it.off : nullptr;
+  a.p_old = b.p_old ? b.p_old + it.off : nullptr;
+  a.p_new = b.p_new ? b.p_new + it.off : nullptr;
+  a.spec = b.spec + it.soff;
+  a.tw = it.tw;
+  a.psum = it.psum;
+  a.psq = it.psq;
+  a.sc = it.sc;
+  switch (it.n) {
+#define RVE_CASE(NN)                                                         \
+  case NN: {                                                                 \
+    constexpr int CPB = SpectralTraits<T, NN>::CPB;                          \
+    cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem);                         \
+    cplx<T>* tw = lds + CPB * SlabGeom<NN>::PLANE;                           \
+    double* red = reinterpret_cast<double*>(tw + NN);                        \
+    slab_fwd_body<T, NN, CPB, SRC>(a, lb, lds, tw, red);                     \
+  } break;
+    RVE_BATCH_SIZES(RVE_CASE)
+#undef RVE_CASE
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void pencil_batch_kernel(BatchSpec<T> b,
+                                                              int cg) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int r = batch_item(b, 1);
+  const SpecItem<T>& it = b.items[r];
+  if (cg ? it.sc->done : it.sc->inactive) return;
+  const int lb = blockIdx.x - it.blk[1];
+  PencilArgs<T> a{};
+  a.spec = b.spec + it.soff;
+  a.tw = it.tw;
+  a.vt = it.vt;
+  a.sc = nullptr;
+  switch (it.n) {
+#define RVE_CASE(NN)                                                         \
+  case NN: {                                                                 \
+    constexpr int TT = SpectralTraits<T, NN>::TT;                            \
+    a.invN3 = T(1.0 / (double(NN) * NN * NN));                               \
+    cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem);                         \
+    pencil_body<T, NN, TT>(a, lb, lds, lds + 3 * NN * (TT + 1));             \
+  } break;
+    RVE_BATCH_SIZES(RVE_CASE)
+#undef RVE_CASE
+  }
+}
+
+template <typename T, typename TO, int DST>
+__global__ __launch_bounds__(kBlock) void slab_inv_batch_kernel(BatchSpec<T> b,
+                                                                TO* out) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int r = batch_item(b, 0);
+  const SpecItem<T>& it = b.items[r];
+  if (DST == DST_DOT ? it.sc->done : it.sc->inactive) return;
+  const int lb = blockIdx.x - it.blk[0];
+  SlabInvArgs<T, TO> a{};
+  a.cs = b.cs;
+  a.spec = b.spec + it.soff;
+  a.tw = it.tw;
+  a.out = out + it.off;
+  a.pdot = b.p_new ? b.p_new + it.off : nullptr;
+  a.partial = it.partial;
+  a.sc = nullptr;
+  switch (it.n) {
+#define RVE_CASE(NN)                                                         \
+  case NN: {                                                                 \
+    constexpr int CPB = SpectralTraits<T, NN>::CPB;                          \
+    cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem);                         \
+    cplx<T>* tw = lds + CPB * SlabGeom<NN>::PLANE;                           \
+    double* red = reinterpret_cast<double*>(tw + NN);                        \
+    slab_inv_body<T, TO, NN, CPB, DST>(a, lb, lds, tw, red);                 \
+  } break;
+    RVE_BATCH_SIZES(RVE_CASE)
+#undef RVE_CASE
+  }
+}
+
+// ---------------------------------------------------------------- launchers
 template <typename T, int N>
 void launch_G_passes(const SpectralLaunch<T>& L, hipStream_t s) {
   constexpr int CPB = SpectralTraits<T, N>::CPB;
@@ -359,6 +487,7 @@ void launch_G_passes(const SpectralLaunch<T>& L, hipStream_t s) {
   if (!(L.passes & 1)) {
   } else if (L.src == SRC_FIELD) {
     SlabFwdArgs<T> fa{};
+    fa.cs = (int64_t)N * N * N;
     fa.field = L.in_field;
     fa.spec = L.spec;
     fa.tw = L.tw;
@@ -369,6 +498,7 @@ void launch_G_passes(const SpectralLaunch<T>& L, hipStream_t s) {
                        dim3(kBlock), 0, s, fa);
   } else {
     SlabFwdArgs<T> fa{};
+    fa.cs = (int64_t)N * N * N;
     fa.K = L.K;
     fa.r = L.r;
     fa.p_old = L.p_old;
@@ -394,6 +524,7 @@ void launch_G_passes(const SpectralLaunch<T>& L, hipStream_t s) {
   if (!(L.passes & 4)) {
   } else if (L.dst == DST_DOT) {
     SlabInvArgs<T, T> ia{};
+    ia.cs = (int64_t)N * N * N;
     ia.spec = L.spec;
     ia.tw = L.tw;
     ia.out = L.out_T;
@@ -404,6 +535,7 @@ void launch_G_passes(const SpectralLaunch<T>& L, hipStream_t s) {
                        dim3(kBlock), 0, s, ia);
   } else {
     SlabInvArgs<T, double> ia{};
+    ia.cs = (int64_t)N * N * N;
     ia.spec = L.spec;
     ia.tw = L.tw;
     ia.out = L.out_d;
@@ -449,6 +581,83 @@ int slab_blocks(int n, bool fp64) {
   return n * (9 / c);
 }
 
+int pencil_blocks(int n, bool fp64) {
+  const int tt = fp64 ? 8 : 16;
+  return n * ((n / 2 + tt - 1) / tt) * 3;
+}
+
+bool batch_supported(int n) {
+  switch (n) {
+#define RVE_CASE(NN) case NN:
+    RVE_BATCH_SIZES(RVE_CASE)
+#undef RVE_CASE
+    return true;
+  }
+  return false;
+}
+
+template <typename T>
+void batch_lds(int n, size_t& slab, size_t& pencil) {
+  switch (n) {
+#define RVE_CASE(NN)                                   \
+  case NN:                                             \
+    slab = SpectralTraits<T, NN>::SLAB_LDS;            \
+    pencil = SpectralTraits<T, NN>::PENCIL_LDS;        \
+    return;
+    RVE_BATCH_SIZES(RVE_CASE)
+#undef RVE_CASE
+  }
+  throw Error(-1, "grid edge not supported in a batch");
+}
+
+template <typename T>
+void launch_G_batch(const BatchSpec<T>& b, int src, T* out_T, double* out_d,
+                    int blocksA, int blocksB, size_t ldsA, size_t ldsB,
+                    hipStream_t s) {
+  if (src == SRC_FIELD) {
+    hipLaunchKernelGGL((slab_fwd_batch_kernel<T, SRC_FIELD>), dim3(blocksA),
+                       dim3(kBlock), ldsA, s, b);
+    hipLaunchKernelGGL((pencil_batch_kernel<T>), dim3(blocksB), dim3(kBlock),
+                       ldsB, s, b, 0);
+    hipLaunchKernelGGL((slab_inv_batch_kernel<T, double, DST_NORM>),
+                       dim3(blocksA), dim3(kBlock), ldsA, s, b, out_d);
+  } else {
+    hipLaunchKernelGGL((slab_fwd_batch_kernel<T, SRC_KP>), dim3(blocksA),
+                       dim3(kBlock), ldsA, s, b);
+    hipLaunchKernelGGL((pencil_batch_kernel<T>), dim3(blocksB), dim3(kBlock),
+                       ldsB, s, b, 1);
+    hipLaunchKernelGGL((slab_inv_batch_kernel<T, T, DST_DOT>), dim3(blocksA),
+                       dim3(kBlock), ldsA, s, b, out_T);
+  }
+}
+
+// Dynamic LDS above the default 64 KiB (FP64 slabs of edge 64) must be
+// allowed per kernel before the first launch.
+template <typename T>
+void batch_allow_lds(size_t slab, size_t pencil) {
+  const void* slabs[] = {
+      reinterpret_cast<const void*>(&slab_fwd_batch_kernel<T, SRC_FIELD>),
+      reinterpret_cast<const void*>(&slab_fwd_batch_kernel<T, SRC_KP>),
+      reinterpret_cast<const void*>(&slab_inv_batch_kernel<T, double, DST_NORM>),
+      reinterpret_cast<const void*>(&slab_inv_batch_kernel<T, T, DST_DOT>)};
+  for (const void* f : slabs)
+    RVE_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)slab));
+  RVE_HIP(hipFuncSetAttribute(
+      reinterpret_cast<const void*>(&pencil_batch_kernel<T>),
+      hipFuncAttributeMaxDynamicSharedMemorySize, (int)pencil));
+}
+
+template void batch_allow_lds<float>(size_t, size_t);
+template void batch_allow_lds<double>(size_t, size_t);
+template void launch_G_batch<float>(const BatchSpec<float>&, int, float*,
+                                    double*, int, int, size_t, size_t,
+                                    hipStream_t);
+template void launch_G_batch<double>(const BatchSpec<double>&, int, double*,
+                                     double*, int, int, size_t, size_t,
+                                     hipStream_t);
+template void batch_lds<float>(int, size_t&, size_t&);
+template void batch_lds<double>(int, size_t&, size_t&);
 template void launch_G<float>(int, const SpectralLaunch<float>&, hipStream_t);
 template void launch_G<double>(int, const SpectralLaunch<double>&, hipStream_t);
 
