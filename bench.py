@@ -7,13 +7,17 @@ increment of that RVE solved to equilibrium tolerance 1e-6 (FP64 residual):
 predictor, return mapping, residual, Newton-CG, commit.
 
 * chosen: FP32 FFT/projection/CG, FP64 return mapping/residual/averages,
-  CG chunks replayed from a captured hipGraph.
+  FFT schedule tuned on the live buffers.  Direct launches: replaying the
+  CG chunks from captured graphs (--graph) measures the same rate here, and
+  direct launches let each timed kernel record its own start and end.
 * plain:  FP64 everywhere, direct launches, same kernels, same inputs.
 
-``value`` is the chosen path's voxel-increments/s.  The JSON line also
-carries the plain path, per-kernel durations measured with HIP events on
-the solver's stream, the roofline of the dominant kernel, and the CPU
-oracle timed on a bounded sample of the same workload.
+``value`` is the chosen path's voxel-increments/s.  Inside its timed region
+every launch of the hot-path kernels is bracketed by HIP events on the
+solver's stream (CG graphs included), so the JSON line carries each
+kernel's live average duration, the roofline of the dominant kernel (by
+total time), the plain path, and the CPU oracle timed on a bounded sample
+of the same workload.
 """
 
 from __future__ import annotations
@@ -34,16 +38,26 @@ METRIC = ("Newton-converged voxel-increments/s at 64^3 (chosen vs plain, "
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
-# algorithmic HBM bytes per voxel of each FFT/projection pass (FP32 chosen
-# path; FP64 doubles every float): see the design notes
+# algorithmic HBM bytes per voxel of each CG-matvec pass on the FP32 path
+# (each datum read or written once; the packed half spectrum of nine
+# components is 9 x n^3/2 complex = 36 B per voxel)
 PASS_BYTES_F32 = {
-    # K (81) + r, p_old (18) in, p_new (9) out, half spectrum (9 complex
-    # halves = 9 floats equivalent x 2 / 2) out
+    # K (81 floats) + r + p_old in, p_new out, half spectrum out
     "matvec_pass_a": 4 * (81 + 9 + 9 + 9) + 36,
     "matvec_pass_b": 36 + 36,                       # spectrum in and out
     "matvec_pass_c": 36 + 4 * 9 + 4 * 9,            # spectrum, p in; Ap out
     "cg_update": 4 * 9 * 6,                         # x, r, p, Ap in; x, r out
 }
+# algorithmic FP64 flops of the return mapping (add, mul, div, sqrt and each
+# elementary function count 1; a fused multiply-add counts 2): per residual
+# evaluation, per local Newton step (Jacobian, 6x6 capacitance factor and
+# Woodbury solve), per crystal voxel (set-up and final stress) and per
+# particle voxel
+RM_FLOPS = {"eval": 1124, "step": 2600, "crystal": 570, "particle": 110}
+# kernel classes timed live in the timed region: the two candidates for the
+# dominant kernel and the once-per-Newton-step kernels (timing a launch costs
+# a little throughput, so the other CG kernels are left to the profiler)
+LIVE_CLASSES = ("matvec_pass_a", "return_map", "tangent", "residual_fp64")
 
 
 def parse():
@@ -55,22 +69,48 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-live", action="store_true",
+                    help="no live kernel timing (no events in the timed region)")
+    ap.add_argument("--graph", action="store_true",
+                    help="chosen path replays CG chunks from captured graphs "
+                         "(live timing then uses event-record nodes)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain elementwise copy of 256 MiB "
+                         "(read + write), the reference kernel that scales "
+                         "hardware byte counters")
     return ap.parse_args()
 
 
-def run_path(micro, hist, precision, use_graph, steps, warmup, stream):
+def copy_calibration(stream):
+    """A plain copy kernel of known size: reads and writes 2^26 floats."""
+    import torch
+    with torch.cuda.stream(stream):
+        x = torch.ones(1 << 26, device="cuda", dtype=torch.float32)
+        y = torch.empty_like(x)
+        torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    return {"kernel": "elementwise mul by 1 (torch)", "bytes_read": 1 << 28,
+            "bytes_written": 1 << 28}
+
+
+def run_path(micro, hist, precision, use_graph, steps, warmup, stream,
+             live=True):
     import torch
     from paper_1806_10599_amd.binding import Rve
     from synthetic import material_params
     r = Rve(micro.n, projection="discrete", precision=precision,
             newton_tol=1e-6, cg_tol=1e-4, use_graph=use_graph, stream=stream)
     r.set_microstructure(micro.phase, micro.quat, micro.law, material_params())
+    if live:
+        r.set_kernel_timing(LIVE_CLASSES)
     infos = []
     for inc in hist[:warmup]:
         if inc["cycle_start"]:
             r.reset_fips()
         infos.append(r.increment(inc["F_bar"], inc["dt"]))
     torch.cuda.synchronize()
+    r.kernel_timing(reset=True)
+    r.return_map_counts(reset=True)
     t0 = time.perf_counter()
     timed = []
     for inc in hist[warmup:warmup + steps]:
@@ -82,10 +122,13 @@ def run_path(micro, hist, precision, use_graph, steps, warmup, stream):
         timed.append(info)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    kern = r.bench_kernels(reps=10)
+    live_t = r.kernel_timing() if live else None
+    counts = r.return_map_counts() if live else None
+    sched = r.fft_schedule()
     sig = [i["sigma_bar"][0, 0] for i in infos + timed]
     r.close()
-    return dict(elapsed=elapsed, infos=timed, kernels=kern, sigma11=sig)
+    return dict(elapsed=elapsed, infos=timed, live=live_t, rm_counts=counts,
+                sigma11=sig, schedule=sched)
 
 
 def oracle_sample(micro, hist, gpu_infos, budget_s):
@@ -136,6 +179,61 @@ def oracle_sample(micro, hist, gpu_infos, budget_s):
                 seconds_per_increment=sec_per_inc)
 
 
+def live_report(live, rmc, N, cg_total):
+    """Per-kernel live durations, FFT bandwidth and the dominant kernel's
+    roofline from the event timings of the timed region."""
+    avg_ms = {k: (ms / n if n else None) for k, (ms, n) in live.items()}
+    total_ms = {k: ms for k, (ms, n) in live.items()}
+    launches = {k: n for k, (ms, n) in live.items()}
+    # matvec passes: bytes actually streamed = per-voxel bytes x voxels x
+    # CG iterations done (launches past convergence in a replayed chunk
+    # return at once and move nothing)
+    mv = ("matvec_pass_a", "matvec_pass_b", "matvec_pass_c")
+    mv_ms = sum(total_ms[k] for k in mv)
+    fft_gbs = (N * cg_total * sum(PASS_BYTES_F32[k] for k in mv)
+               / (mv_ms * 1e-3) / 1e9) if all(launches[k] for k in mv) else None
+    rm_flops = (RM_FLOPS["eval"] * rmc["evals"] + RM_FLOPS["step"] * rmc["steps"]
+                + RM_FLOPS["crystal"] * rmc["crystal"]
+                + RM_FLOPS["particle"] * rmc["particle"])
+
+    def hbm(k):
+        per_launch = N * PASS_BYTES_F32[k] * cg_total / launches[k]
+        ach = per_launch / (avg_ms[k] * 1e-3) / 1e9
+        return dict(kernel=k, bound="hbm", achieved=round(ach, 1),
+                    peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(ach / HBM_PEAK_GBS, 4), traffic=None,
+                    bytes_per_launch=round(per_launch), avg_ms=round(avg_ms[k], 5),
+                    launches=launches[k])
+
+    def alu():
+        per_launch = rm_flops / launches["return_map"]
+        ach = per_launch / (avg_ms["return_map"] * 1e-3) / 1e12
+        return dict(kernel="return_map", bound="alu", achieved=round(ach, 3),
+                    peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=round(ach / FP64_PEAK_TFLOPS, 4), traffic=None,
+                    flops_per_launch=round(per_launch),
+                    avg_ms=round(avg_ms["return_map"], 4),
+                    launches=launches["return_map"])
+
+    timed = {k: v for k, v in total_ms.items() if launches[k]}
+    dom = max(timed, key=lambda k: timed[k])
+    roof = hbm(dom) if dom in PASS_BYTES_F32 else (alu() if dom == "return_map" else None)
+    rep = {
+        "fft_gbps": round(fft_gbs, 1) if fft_gbs else None,
+        "kernel_avg_ms_live": {k: (round(v, 5) if v else v)
+                               for k, v in avg_ms.items()},
+        "kernel_total_ms_live": {k: round(v, 3) for k, v in total_ms.items()},
+        "kernel_launches_live": launches,
+        "return_map_work": dict(rmc, flops=rm_flops),
+        "roofline": roof,
+    }
+    if launches["matvec_pass_a"] and dom != "matvec_pass_a":
+        rep["matvec_pass_a_roofline"] = hbm("matvec_pass_a")
+    if launches["return_map"] and dom != "return_map":
+        rep["return_map_roofline"] = alu()
+    return rep
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -153,39 +251,20 @@ def main():
     while len(hist) < need:
         hist = hist + cfg.history(cycles=cfg.cycles)
     stream = torch.cuda.Stream()
+    calib = copy_calibration(stream) if args.copy_calibration else None
     with torch.cuda.stream(stream):
-        chosen = run_path(micro, hist, "mixed", True, args.steps, args.warmup,
-                          stream)
+        chosen = run_path(micro, hist, "mixed", args.graph, args.steps,
+                          args.warmup, stream, live=not args.no_live)
         plain = None
         if not args.no_plain:
             plain = run_path(micro, hist, "fp64", False, args.steps,
-                             args.warmup, stream)
+                             args.warmup, stream, live=False)
     N = micro.n ** 3
     value = N * args.steps / chosen["elapsed"]
-    kern = chosen["kernels"]
-    mv_ms = kern["matvec_pass_a"] + kern["matvec_pass_b"] + kern["matvec_pass_c"]
-    mv_bytes = N * sum(PASS_BYTES_F32[k] for k in
-                       ("matvec_pass_a", "matvec_pass_b", "matvec_pass_c"))
-    fft_gbs = mv_bytes / (mv_ms * 1e-3) / 1e9
     infos = chosen["infos"]
     cg_per_inc = float(np.mean([i["cg_iters_total"] for i in infos]))
     newton_per_inc = float(np.mean([i["newton_iters"] for i in infos]))
-    # time share per increment of each kernel class
-    share = {
-        "matvec": cg_per_inc * mv_ms,
-        "cg_update": cg_per_inc * kern["cg_update"],
-        "return_map": (newton_per_inc + 1) * kern["return_map"],
-        "tangent": newton_per_inc * kern["tangent"],
-        "residual_fp64": (newton_per_inc + 1) * kern["residual_fp64"],
-    }
-    dom = max(("matvec_pass_a", "matvec_pass_b", "matvec_pass_c"),
-              key=lambda k: kern[k])
-    dom_bytes = N * PASS_BYTES_F32[dom]
-    achieved = dom_bytes / (kern[dom] * 1e-3) / 1e9
-    roof = dict(kernel=dom, bound="hbm", achieved=round(achieved, 1),
-                peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                bytes_per_launch=dom_bytes, avg_ms=kern[dom])
+    cg_total = sum(i["cg_iters_total"] for i in infos)
     out = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -205,14 +284,14 @@ def main():
                                 f"+-{cfg.eps_a:.1%} cycles, "
                                 f"{cfg.inc_per_cycle} inc/cycle, tol 1e-6"),
                    "voxels": N, "precision": "mixed FP32 FFT/CG + FP64",
-                   "graph": True},
-        "fft_gbps": round(fft_gbs, 1),
+                   "graph": args.graph,
+                   "fft_schedule": chosen["schedule"]},
         "newton_per_increment": newton_per_inc,
         "cg_per_increment": cg_per_inc,
-        "kernel_ms": {k: round(v, 4) for k, v in kern.items()},
-        "ms_share_per_increment": {k: round(v, 3) for k, v in share.items()},
-        "roofline": roof,
     }
+    live = chosen["live"]
+    if live is not None:
+        out.update(live_report(live, chosen["rm_counts"], N, cg_total))
     if plain is not None:
         pv = N * args.steps / plain["elapsed"]
         out["plain"] = {"value": round(pv, 1), "unit": "voxel-increments/s",
@@ -220,12 +299,15 @@ def main():
                         "dtype": "f64",
                         "cg_per_increment": float(np.mean(
                             [i["cg_iters_total"] for i in plain["infos"]])),
-                        "kernel_ms": {k: round(v, 4) for k, v in plain["kernels"].items()}}
+                        "newton_per_increment": float(np.mean(
+                            [i["newton_iters"] for i in plain["infos"]]))}
         out["chosen_over_plain"] = round(value / pv, 3)
         s_c = np.array(chosen["sigma11"])
         s_p = np.array(plain["sigma11"])
         out["sigma11_max_rel_diff_vs_plain"] = float(
             np.max(np.abs(s_c - s_p)) / np.max(np.abs(s_p)))
+    if calib:
+        out["copy_calibration"] = calib
     if not args.no_cpu:
         out["cpu_baseline"] = oracle_sample(micro, hist, infos,
                                             args.cpu_seconds)

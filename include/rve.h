@@ -208,6 +208,37 @@ rve_status rve_debug_set_field(rve_t h, int32_t field, const double* src,
 rve_status rve_bench_kernels(rve_t h, int32_t reps, double* ms_out,
                              int32_t count);
 
+/* Live kernel timing.  With bit k of mask set, every launch of kernel class
+   k made by the solver's own iteration (classes as for rve_bench_kernels;
+   CG launches inside captured graphs included) is bracketed by a pair of
+   HIP events on the handle's stream; the elapsed times are summed after
+   each synchronisation of that stream.  Changing the mask re-captures the
+   CG graph.  rve_get_kernel_timing copies the summed milliseconds and the
+   launch counts of classes [0, count) (count <= 8; either pointer may be
+   NULL) and zeroes them when reset != 0.  Launches whose RVE has already
+   converged (the tail of a CG chunk) are counted like any other. */
+rve_status rve_set_kernel_timing(rve_t h, uint32_t mask);
+rve_status rve_get_kernel_timing(rve_t h, double* ms_total, int64_t* launches,
+                                 int32_t count, int32_t reset);
+/* Work of the return mappings timed while bit 4 (return mapping) is set:
+   out[0] local Newton steps and out[1] residual evaluations summed over
+   crystal voxels and launches, out[2] crystal and out[3] particle voxel
+   visits (Sec. 3.2, Eq. 22 integrated per voxel).  Zeroed when reset != 0
+   and whenever bit 4 is switched on. */
+rve_status rve_get_return_map_counts(rve_t h, int64_t out[4], int32_t reset);
+
+/* FFT schedule of the CG matvec (Sec. 2.1, Eq. 16): cpb components of the
+   tensor field per slab block in the z/y-transform passes (1 or 3) and tt
+   kz columns per block in the x-transform and projection pass (8 or 16).
+   By default (0, 0) the handle times every valid schedule once on its own
+   buffers at the first CG solve and keeps the fastest.  rve_set_fft_schedule
+   forces one (or (0, 0) to tune again); RVE_EINVAL when the schedule does
+   not exist for the grid and precision.  rve_get_fft_schedule returns the
+   schedule in use (zeros before the first solve) and, in *ms (nullable),
+   the tuned matvec time in milliseconds (0 when forced). */
+rve_status rve_set_fft_schedule(rve_t h, int32_t cpb, int32_t tt);
+rve_status rve_get_fft_schedule(rve_t h, int32_t out[2], double* ms);
+
 /* ---- learned warm start -------------------------------------------------
    A small network predicts the fluctuation increment of the next load
    increment from the committed state, so that the Newton iteration of

@@ -31,6 +31,8 @@ FIELDS = {"F": (0, 9), "P": (1, 9), "sigma": (2, 9), "Fpinv": (3, 9),
           "pcyc_lit": (7, 1), "wcyc": (8, 12)}
 NPARAMS = 10
 MAX_NEWTON_LOG = 64
+KERNEL_CLASSES = ("matvec_pass_a", "matvec_pass_b", "matvec_pass_c",
+                  "cg_update", "return_map", "tangent", "residual_fp64")
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -101,6 +103,15 @@ def _load():
                                           P(C.c_double), C.c_size_t]),
         "rve_bench_kernels": (C.c_int, [C.c_void_p, C.c_int32,
                                         P(C.c_double), C.c_int32]),
+        "rve_set_kernel_timing": (C.c_int, [C.c_void_p, C.c_uint32]),
+        "rve_get_kernel_timing": (C.c_int, [C.c_void_p, P(C.c_double),
+                                            P(C.c_int64), C.c_int32,
+                                            C.c_int32]),
+        "rve_get_return_map_counts": (C.c_int, [C.c_void_p, P(C.c_int64),
+                                                C.c_int32]),
+        "rve_set_fft_schedule": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+        "rve_get_fft_schedule": (C.c_int, [C.c_void_p, P(C.c_int32),
+                                           P(C.c_double)]),
         "rve_ws_create": (C.c_int, [P(RveWsConfig), P(C.c_void_p)]),
         "rve_ws_destroy": (C.c_int, [C.c_void_p]),
         "rve_ws_param_count": (C.c_int, [C.c_void_p, P(C.c_int64)]),
@@ -355,11 +366,44 @@ class Rve:
         """Average ms per launch of the hot-path kernels (see rve.h)."""
         out = np.zeros(7)
         self._check(LIB.rve_bench_kernels(self._h, int(reps), _dptr(out), 7))
-        keys = ("matvec_pass_a", "matvec_pass_b", "matvec_pass_c",
-                "cg_update", "return_map", "tangent", "residual_fp64")
-        return dict(zip(keys, out.tolist()))
+        return dict(zip(KERNEL_CLASSES, out.tolist()))
 
     # --------------------------------------------------- learned warm start
+    def set_kernel_timing(self, classes):
+        """Time the given kernel classes live (names of KERNEL_CLASSES)."""
+        mask = 0
+        for c in classes:
+            mask |= 1 << KERNEL_CLASSES.index(c)
+        self._check(LIB.rve_set_kernel_timing(self._h, mask))
+
+    def kernel_timing(self, reset=False):
+        """{class: (total ms, launches)} since the last reset."""
+        n = len(KERNEL_CLASSES)
+        ms = (C.c_double * n)()
+        cnt = (C.c_int64 * n)()
+        self._check(LIB.rve_get_kernel_timing(self._h, ms, cnt, n,
+                                              1 if reset else 0))
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(KERNEL_CLASSES)}
+
+    def return_map_counts(self, reset=False):
+        """Local Newton steps, residual evaluations, crystal and particle
+        voxel visits of the return mappings timed live."""
+        out = (C.c_int64 * 4)()
+        self._check(LIB.rve_get_return_map_counts(self._h, out,
+                                                  1 if reset else 0))
+        return dict(steps=out[0], evals=out[1], crystal=out[2],
+                    particle=out[3])
+
+    def set_fft_schedule(self, cpb=0, tt=0):
+        """Force the CG-matvec FFT schedule; (0, 0) tunes it again."""
+        self._check(LIB.rve_set_fft_schedule(self._h, int(cpb), int(tt)))
+
+    def fft_schedule(self):
+        out = (C.c_int32 * 2)()
+        ms = C.c_double()
+        self._check(LIB.rve_get_fft_schedule(self._h, out, C.byref(ms)))
+        return dict(cpb=out[0], tt=out[1], tuned_ms=ms.value)
+
     def attach_warm_start(self, net):
         self._check(LIB.rve_attach_warm_start(self._h, net._h if net else None))
         self._net = net

@@ -300,6 +300,48 @@ rve_status rve_ws_target(rve_t h, float* T) {
   });
 }
 
+rve_status rve_set_kernel_timing(rve_t h, uint32_t mask) {
+  return guarded(h, [&] {
+    h->eng->set_timing(mask);
+    return RVE_OK;
+  });
+}
+
+rve_status rve_get_kernel_timing(rve_t h, double* ms_total, int64_t* launches,
+                                 int32_t count, int32_t reset) {
+  return guarded(h, [&] {
+    if (count > 8) throw rve::Error(RVE_EINVAL, "count > 8");
+    h->eng->get_timing(ms_total, launches, count, reset != 0);
+    return RVE_OK;
+  });
+}
+
+rve_status rve_get_return_map_counts(rve_t h, int64_t out[4], int32_t reset) {
+  return guarded(h, [&] {
+    if (!out) throw rve::Error(RVE_EINVAL, "null output");
+    h->eng->get_rm_counts(out, reset != 0);
+    return RVE_OK;
+  });
+}
+
+rve_status rve_set_fft_schedule(rve_t h, int32_t cpb, int32_t tt) {
+  return guarded(h, [&] {
+    h->eng->set_schedule(cpb, tt);
+    return RVE_OK;
+  });
+}
+
+rve_status rve_get_fft_schedule(rve_t h, int32_t out[2], double* ms) {
+  return guarded(h, [&] {
+    if (!out) throw rve::Error(RVE_EINVAL, "null output");
+    int o[2];
+    h->eng->get_schedule(o, ms);
+    out[0] = o[0];
+    out[1] = o[1];
+    return RVE_OK;
+  });
+}
+
 rve_status rve_batch_create(const rve_config* cfg, int32_t count,
                             const int32_t* n, rve_batch_t* out) {
   if (!cfg || !out || !n) return RVE_EINVAL;

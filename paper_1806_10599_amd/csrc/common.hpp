@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cstdint>
 #include <cstdio>
@@ -49,6 +50,29 @@ struct Error : std::runtime_error {
       throw ::rve::Error(-3, std::string(#expr) + ": " +                    \
                                  hipGetErrorString(e_));                    \
   } while (0)
+
+// Events for the next kernel launch made through rve::launch.  The live
+// kernel timer sets them just before a timed launch; the launch then records
+// them at the start and at the end of that kernel's own execution (AMD's
+// extended launch), so the timing holds the kernel alone.
+struct NextLaunchEvents {
+  hipEvent_t start = nullptr;
+  hipEvent_t stop = nullptr;
+};
+inline thread_local NextLaunchEvents g_next_launch_events;
+
+template <typename F, typename... Args>
+inline void launch(F kernel, dim3 grid, dim3 block, uint32_t lds,
+                   hipStream_t s, Args... args) {
+  NextLaunchEvents& ev = g_next_launch_events;
+  if (ev.start) {
+    hipEvent_t a = ev.start, b = ev.stop;
+    ev = NextLaunchEvents{};
+    hipExtLaunchKernelGGL(kernel, grid, block, lds, s, a, b, 0, args...);
+  } else {
+    hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+  }
+}
 
 // Device-side scalars of one CG solve (and the residual norms).
 struct Scalars {

@@ -93,8 +93,8 @@ Engine::Engine(const rve_config& cfg) : cfg_(cfg) {
   spec64_ = fp64_ ? spec_ : alloc(9 * N_ / 2 * 2 * sizeof(double));
   nslab32_ = slab_blocks(n_, false);
   nslab64_ = slab_blocks(n_, true);
-  const int nslab_max = nslab32_ > nslab64_ ? nslab32_ : nslab64_;
-  partial_inv_ = (double*)alloc(nslab_max * sizeof(double));
+  // room for the partials of any schedule (one component per slab block)
+  partial_inv_ = (double*)alloc(9 * n_ * sizeof(double));
   partial_red_ = (double*)alloc(kRedBlocks * sizeof(double));
   psum_ = (double*)alloc(9 * n_ * sizeof(double));
   psq_ = (double*)alloc(9 * n_ * sizeof(double));
@@ -275,14 +275,21 @@ int Engine::evaluate(const double* dg_start, double dt, double& rel,
   a.chi = chi_t_;
   a.dg = dg_t_;
   a.fails = &sc_->fails;
-  a.iters = nullptr;
+  a.iters = timer_.on(4) ? rm_iters_ : nullptr;
+  a.evals = timer_.on(4) ? rm_evals_ : nullptr;
   a.lp = law_params(dt);
   a.N = N_;
+  timer_.begin(4, st_);
   launch_return_map(a, st_);
+  timer_.end(4, st_);
+  if (a.iters) launch_rm_count(rm_iters_, rm_evals_, N_, rm_stats_, st_);
+  timer_.begin_span(6, st_);
   residual_passes(P_);
+  timer_.end_span(6, st_);
   RVE_HIP(hipGetLastError());
   Scalars h;
   read_scalars(h);
+  timer_.flush();
   res = std::sqrt(h.res2);
   pn = std::sqrt(h.P2);
   rel = pn > 0 ? res / pn : 0.0;
@@ -302,11 +309,15 @@ void Engine::tangent(double dt) {
   a.K = (T*)K_;
   a.lp = law_params(dt);
   a.N = N_;
+  timer_.begin(5, st_);
   launch_tangent<T>(a, st_);
+  timer_.end(5, st_);
 }
 
-template <typename T>
-void Engine::cg_iteration(int parity) {
+// One CG iteration as a sequence of launch steps; run(cls, launch) issues a
+// step (cls: kernel class for live timing, -1 untimed).
+template <typename T, typename Run>
+void Engine::cg_iteration_steps(int parity, Run&& run) {
   const bool dbl = sizeof(T) == sizeof(double);
   SpectralLaunch<T> L;
   L.src = SRC_KP;
@@ -321,27 +332,164 @@ void Engine::cg_iteration(int parity) {
   L.out_T = (T*)Ap_;
   L.partial_inv = partial_inv_;
   L.sc = sc_;
-  launch_G<T>(n_, L, st_);
-  const int nslab = dbl ? nslab64_ : nslab32_;
-  launch_reduce(RED_ALPHA, partial_inv_, nslab, nullptr, nullptr, 0, 0.0, sc_,
-                nullptr, st_);
-  launch_cg_update<T>((T*)x_, (T*)r_, L.p_new, (const T*)Ap_, sc_,
-                      partial_red_, kRedBlocks, 9 * N_, st_);
-  launch_reduce(RED_BETA, partial_red_, kRedBlocks, nullptr, nullptr, 0, 0.0,
-                sc_, nullptr, st_);
+  L.cpb = sched_cpb_;
+  L.tt = sched_tt_;
+  if (timer_.mask() & 7u) {
+    for (int pass = 0; pass < 3; ++pass)  // passes A, B, C one by one
+      run(pass, [&, pass] {
+        SpectralLaunch<T> Lp = L;
+        Lp.passes = 1 << pass;
+        launch_G<T>(n_, Lp, st_);
+      });
+  } else {
+    run(-1, [&] { launch_G<T>(n_, L, st_); });
+  }
+  const int nslab = slab_blocks(n_, dbl, sched_cpb_);
+  run(-1, [&] {
+    launch_reduce(RED_ALPHA, partial_inv_, nslab, nullptr, nullptr, 0, 0.0,
+                  sc_, nullptr, st_);
+  });
+  run(3, [&] {
+    launch_cg_update<T>((T*)x_, (T*)r_, L.p_new, (const T*)Ap_, sc_,
+                        partial_red_, kRedBlocks, 9 * N_, st_);
+  });
+  run(-1, [&] {
+    launch_reduce(RED_BETA, partial_red_, kRedBlocks, nullptr, nullptr, 0,
+                  0.0, sc_, nullptr, st_);
+  });
 }
 
 template <typename T>
+void Engine::cg_iteration(int parity) {
+  cg_iteration_steps<T>(parity, [&](int cls, auto&& launch) {
+    if (cls >= 0) timer_.begin(cls, st_);
+    launch();
+    if (cls >= 0) timer_.end(cls, st_);
+  });
+}
+
+// The CG chunk as one graph.  Without live timing the chunk is captured in
+// one piece; with it, each step is captured as a child graph and the timed
+// steps are bracketed by event-record nodes, linked in launch order.
+template <typename T>
 void Engine::capture_graph() {
-  RVE_HIP(hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal));
-  for (int j = 0; j < cfg_.cg_chunk; ++j) cg_iteration<T>(j & 1);
-  RVE_HIP(hipStreamEndCapture(st_, &graph_def_));
+  if (!(timer_.mask() & 0xFu)) {
+    RVE_HIP(hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal));
+    for (int j = 0; j < cfg_.cg_chunk; ++j) cg_iteration<T>(j & 1);
+    RVE_HIP(hipStreamEndCapture(st_, &graph_def_));
+  } else {
+    RVE_HIP(hipGraphCreate(&graph_def_, 0));
+    hipGraphNode_t last = nullptr;
+    auto add = [&](auto&& make) {
+      hipGraphNode_t node;
+      make(&node, last ? &last : nullptr, last ? 1 : 0);
+      last = node;
+    };
+    for (int j = 0; j < cfg_.cg_chunk; ++j)
+      cg_iteration_steps<T>(j & 1, [&](int cls, auto&& launch) {
+        hipGraph_t child;
+        RVE_HIP(hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal));
+        launch();
+        RVE_HIP(hipStreamEndCapture(st_, &child));
+        const bool timed = cls >= 0 && timer_.on(cls);
+        KernelTimer::Pair pr{};
+        if (timed) {
+          pr = timer_.graph_pair(cls);
+          add([&](hipGraphNode_t* n, const hipGraphNode_t* d, size_t nd) {
+            RVE_HIP(hipGraphAddEventRecordNode(n, graph_def_, d, nd, pr.second.first));
+          });
+        }
+        add([&](hipGraphNode_t* n, const hipGraphNode_t* d, size_t nd) {
+          RVE_HIP(hipGraphAddChildGraphNode(n, graph_def_, d, nd, child));
+        });
+        RVE_HIP(hipGraphDestroy(child));
+        if (timed) {
+          add([&](hipGraphNode_t* n, const hipGraphNode_t* d, size_t nd) {
+            RVE_HIP(hipGraphAddEventRecordNode(n, graph_def_, d, nd, pr.second.second));
+          });
+          graph_pairs_.push_back(pr);
+        }
+      });
+  }
   RVE_HIP(hipGraphInstantiate(&graph_, graph_def_, nullptr, nullptr, 0));
+}
+
+// Picks the fastest FFT schedule (components per slab block in passes A
+// and C, kz columns per pass-B block) for this grid and precision by timing
+// one CG matvec G(K : p) of each valid candidate on the live buffers (the
+// CG vectors are re-initialised afterwards).
+template <typename T>
+void Engine::autotune() {
+  const bool dbl = sizeof(T) == sizeof(double);
+  hipEvent_t ev[2];
+  RVE_HIP(hipEventCreate(&ev[0]));
+  RVE_HIP(hipEventCreate(&ev[1]));
+  float best = 0.f;
+  int bc = 0, bt = 0;
+  launch_bench_scalars(sc_, st_);
+  for (int cpb : {1, 3})
+    for (int tt : {8, 16}) {
+      if (!schedule_valid(n_, dbl, cpb, tt)) continue;
+      SpectralLaunch<T> L;
+      L.src = SRC_KP;
+      L.K = (const T*)K_;
+      L.r = (const T*)r_;
+      L.p_old = (const T*)p0_;
+      L.p_new = (T*)p1_;
+      L.spec = (cplx<T>*)spec_;
+      L.tw = (const cplx<T>*)(dbl ? tw64_ : tw32_);
+      L.vt = (const T*)(dbl ? vt64_ : vt32_);
+      L.dst = DST_DOT;
+      L.out_T = (T*)Ap_;
+      L.partial_inv = partial_inv_;
+      L.sc = sc_;
+      L.cpb = cpb;
+      L.tt = tt;
+      constexpr int reps = 4;
+      launch_G<T>(n_, L, st_);  // untimed first launch
+      RVE_HIP(hipEventRecord(ev[0], st_));
+      for (int i = 0; i < reps; ++i) launch_G<T>(n_, L, st_);
+      RVE_HIP(hipEventRecord(ev[1], st_));
+      RVE_HIP(hipEventSynchronize(ev[1]));
+      float t = 0.f;
+      RVE_HIP(hipEventElapsedTime(&t, ev[0], ev[1]));
+      if (bc == 0 || t < best) {
+        best = t;
+        bc = cpb;
+        bt = tt;
+      }
+    }
+  hipEventDestroy(ev[0]);
+  hipEventDestroy(ev[1]);
+  if (bc == 0) throw Error(RVE_EINVAL, "no FFT schedule for this grid");
+  sched_cpb_ = bc;
+  sched_tt_ = bt;
+  sched_ms_ = best / 4.0;
+}
+
+void Engine::set_schedule(int cpb, int tt) {
+  if (cpb || tt) {
+    if (!schedule_valid(n_, fp64_, cpb, tt))
+      throw Error(RVE_EINVAL, "no such FFT schedule for this grid and precision");
+  }
+  RVE_HIP(hipStreamSynchronize(st_));
+  if (graph_) {
+    RVE_HIP(hipGraphExecDestroy(graph_));
+    graph_ = nullptr;
+  }
+  if (graph_def_) {
+    RVE_HIP(hipGraphDestroy(graph_def_));
+    graph_def_ = nullptr;
+  }
+  timer_.recycle(graph_pairs_);
+  sched_cpb_ = cpb;
+  sched_tt_ = tt;
 }
 
 // CG on G(K : x) = b with b = -r64 (text after Eq. 16), from x = 0
 template <typename T>
 void Engine::cg_solve(int& iters, bool& breakdown) {
+  if (!sched_cpb_) autotune<T>();
   launch_init_scalars(sc_, cfg_.cg_max_iter, cfg_.cg_tol, st_);
   launch_cg_init<T>(r64_, (T*)r_, (T*)x_, partial_red_, kRedBlocks, 9 * N_, st_);
   launch_reduce(RED_INIT, partial_red_, kRedBlocks, nullptr, nullptr, 0, 0.0,
@@ -353,6 +501,7 @@ void Engine::cg_solve(int& iters, bool& breakdown) {
     if (cfg_.use_graph) {
       if (!graph_) capture_graph<T>();
       RVE_HIP(hipGraphLaunch(graph_, st_));
+      timer_.replayed(graph_pairs_);
     } else {
       for (int j = 0; j < cfg_.cg_chunk; ++j) {
         cg_iteration<T>(parity);
@@ -361,6 +510,7 @@ void Engine::cg_solve(int& iters, bool& breakdown) {
       RVE_HIP(hipGetLastError());
     }
     read_scalars(h);
+    timer_.flush();
     if (h.done) break;
   }
   iters = h.iters;
@@ -720,10 +870,61 @@ void Engine::debug_set_field(int field, const double* src, size_t bytes) {
 //   2 pass C (inverse y/z FFT, p.Ap)            3 CG vector update
 //   4 return mapping (FP64)                     5 tangent
 //   6 FP64 residual G(P) (three passes + reduction)
+void Engine::set_timing(uint32_t mask) {
+  if (mask == timer_.mask()) return;
+  // captured CG graphs hold (or lack) the timing events: capture again
+  RVE_HIP(hipStreamSynchronize(st_));
+  if (graph_) {
+    RVE_HIP(hipGraphExecDestroy(graph_));
+    graph_ = nullptr;
+  }
+  if (graph_def_) {
+    RVE_HIP(hipGraphDestroy(graph_def_));
+    graph_def_ = nullptr;
+  }
+  timer_.recycle(graph_pairs_);
+  if ((mask >> 4) & 1u) {
+    if (!rm_iters_) {
+      rm_iters_ = (int32_t*)alloc(N_ * sizeof(int32_t));
+      rm_evals_ = (int32_t*)alloc(N_ * sizeof(int32_t));
+      rm_stats_ = (unsigned long long*)alloc(4 * sizeof(unsigned long long));
+    }
+    RVE_HIP(hipMemsetAsync(rm_stats_, 0, 4 * sizeof(unsigned long long), st_));
+    RVE_HIP(hipStreamSynchronize(st_));
+  }
+  timer_.set_mask(mask);
+}
+
+void Engine::get_rm_counts(int64_t out[4], bool reset) {
+  unsigned long long h[4] = {0, 0, 0, 0};
+  if (rm_stats_) {
+    RVE_HIP(hipMemcpyAsync(h, rm_stats_, sizeof(h), hipMemcpyDeviceToHost, st_));
+    RVE_HIP(hipStreamSynchronize(st_));
+    if (reset) {
+      RVE_HIP(hipMemsetAsync(rm_stats_, 0, sizeof(h), st_));
+      RVE_HIP(hipStreamSynchronize(st_));
+    }
+  }
+  for (int k = 0; k < 4; ++k) out[k] = (int64_t)h[k];
+}
+
+void Engine::get_timing(double* ms, int64_t* launches, int count, bool reset) {
+  if (count < 0) throw Error(RVE_EINVAL, "negative count");
+  timer_.read(ms, launches, count, reset);
+}
+
 void Engine::bench_kernels(int reps, double* ms, int count) {
   if (!have_micro_ || increments_ < 1)
     throw Error(RVE_ESTATE, "run at least one increment first");
   if (reps < 1 || !ms) throw Error(RVE_EINVAL, "bad arguments");
+  // these launches are not part of the solver's iteration: keep them out of
+  // the live timing
+  struct MaskGuard {
+    KernelTimer& t;
+    uint32_t saved;
+    ~MaskGuard() { t.set_mask(saved); }
+  } guard{timer_, timer_.mask()};
+  timer_.set_mask(0);
   hipEvent_t ev[2];
   RVE_HIP(hipEventCreate(&ev[0]));
   RVE_HIP(hipEventCreate(&ev[1]));
@@ -777,6 +978,8 @@ void Engine::bench_kernels(int reps, double* ms, int count) {
     L.partial_inv = partial_inv_;
     L.sc = sc_;
     L.passes = mask;
+    L.cpb = sched_cpb_;
+    L.tt = sched_tt_;
     launch_G<T>(n_, L, st_);
   };
   launch_bench_scalars(sc_, st_);

@@ -10,6 +10,7 @@
 
 #include "../../include/rve.h"
 #include "kernels.hpp"
+#include "ktimer.hpp"
 #include "nn.hpp"
 
 namespace rve {
@@ -34,6 +35,16 @@ class Engine {
                           double* dg, int32_t* fails);
   void debug_set_field(int field, const double* src, size_t bytes);
   void bench_kernels(int reps, double* ms, int count);
+  void set_timing(uint32_t mask);
+  void get_timing(double* ms, int64_t* launches, int count, bool reset);
+  void get_rm_counts(int64_t out[4], bool reset);
+  // FFT schedule of the CG matvec: (0, 0) = autotune at the next solve
+  void set_schedule(int cpb, int tt);
+  void get_schedule(int out[2], double* ms) const {
+    out[0] = sched_cpb_;
+    out[1] = sched_tt_;
+    if (ms) *ms = sched_ms_;
+  }
 
   // pieces used by the learned warm start
   hipStream_t stream() const { return st_; }
@@ -59,8 +70,12 @@ class Engine {
   void cg_solve(int& iters, bool& breakdown);
   template <typename T>
   void cg_iteration(int parity);
+  template <typename T, typename Run>
+  void cg_iteration_steps(int parity, Run&& run);
   template <typename T>
   void capture_graph();
+  template <typename T>
+  void autotune();
   void read_scalars(Scalars& h);
   LawParams law_params(double dt) const;
   void residual_passes(const double* P);
@@ -97,6 +112,8 @@ class Engine {
   double* table_;
   void *tw32_, *tw64_, *vt32_, *vt64_;
   int nslab32_, nslab64_;
+  int sched_cpb_ = 0, sched_tt_ = 0;   // 0: not tuned yet
+  double sched_ms_ = 0.0;
   int labels_ = 0;
   bool have_micro_ = false;
   double params_[RVE_NPARAMS];
@@ -115,6 +132,11 @@ class Engine {
   void* dbgK64_ = nullptr;
   hipGraphExec_t graph_ = nullptr;
   hipGraph_t graph_def_ = nullptr;
+  KernelTimer timer_;
+  std::vector<KernelTimer::Pair> graph_pairs_;   // timing events inside graph_
+  int32_t* rm_iters_ = nullptr;                  // per-voxel work of the
+  int32_t* rm_evals_ = nullptr;                  // return mapping (timed runs)
+  unsigned long long* rm_stats_ = nullptr;
   Net* net_ = nullptr;
   double* dFt_prev_ = nullptr;        // fluctuation increment of the last increment
   double dFbar_prev_[9];

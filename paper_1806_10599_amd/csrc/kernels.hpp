@@ -62,12 +62,18 @@ struct SpectralLaunch {
   double* partial_inv = nullptr;
   Scalars* sc = nullptr;
   int passes = 7;   // bit 0: pass A, bit 1: pass B, bit 2: pass C
+  int cpb = 0;      // components per slab block in passes A and C (1 or 3;
+                    // 0: the default of the grid edge and precision)
+  int tt = 0;       // kz columns per pass-B block (8 or 16; 0: default)
 };
 
 template <typename T>
 void launch_G(int n, const SpectralLaunch<T>& L, hipStream_t s);
-int slab_blocks(int n, bool fp64);
-int pencil_blocks(int n, bool fp64);
+// block counts of the slab (A, C) and pencil (B) grids; 0 = default schedule
+int slab_blocks(int n, bool fp64, int cpb = 0);
+int pencil_blocks(int n, bool fp64, int tt = 0);
+// whether a (cpb, tt) schedule exists for the grid edge and precision
+bool schedule_valid(int n, bool fp64, int cpb, int tt);
 
 // One RVE of a batch: where its voxels, spectrum and scalars live and where
 // its blocks start in the pass-A/C (blk[0]) and pass-B (blk[1]) grids.
@@ -138,7 +144,8 @@ struct ConstArgs {
   double* chi;           // trial [12][N]
   double* dg;            // trial [12][N]
   int32_t* fails;        // counter
-  int32_t* iters;        // optional per-voxel local iterations
+  int32_t* iters;        // optional per-voxel local Newton steps (-1: particle)
+  int32_t* evals;        // with iters: per-voxel residual evaluations
   LawParams lp;
   int64_t N;
   const uint8_t* vrve;   // batch: RVE of each voxel (null for one RVE)
@@ -162,6 +169,8 @@ struct TangentArgs {
 };
 
 void launch_return_map(const ConstArgs& a, hipStream_t s);
+void launch_rm_count(const int32_t* iters, const int32_t* evals, int64_t N,
+                     unsigned long long* stats, hipStream_t s);
 template <typename TK>
 void launch_tangent(const TangentArgs<TK>& a, hipStream_t s);
 

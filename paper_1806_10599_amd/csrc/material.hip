@@ -319,8 +319,9 @@ __device__ __forceinline__ double half_sq(const double* R) {
 __device__ __forceinline__ bool cp_local_solve(const double* Fes, const double* chi0,
                                double* dg, const double* __restrict__ tb,
                                const LawParams& lp, double a, CpEval& e,
-                               int& iters) {
+                               int& iters, int& evals) {
   cp_eval(Fes, chi0, dg, tb, lp, a, e);
+  ++evals;
   for (int it = 0; it < LOCAL_MAXIT; ++it) {
     ++iters;
     double D[12], hg[12], Q[9];
@@ -343,6 +344,7 @@ __device__ __forceinline__ bool cp_local_solve(const double* Fes, const double* 
 #pragma unroll
       for (int i = 0; i < 12; ++i) dg[i] += step[i];
       cp_eval(Fes, chi0, dg, tb, lp, a, e);
+      ++evals;
       return true;
     }
     const double merit0 = half_sq(e.R);
@@ -353,6 +355,7 @@ __device__ __forceinline__ bool cp_local_solve(const double* Fes, const double* 
 #pragma unroll
       for (int i = 0; i < 12; ++i) trial[i] = dg[i] + lam * step[i];
       cp_eval(Fes, chi0, trial, tb, lp, a, e);
+      ++evals;
       const double mt = half_sq(e.R);
       if (isfinite(mt) && mt <= (1.0 - 1e-4 * lam) * merit0) {
         accepted = true;
@@ -415,7 +418,10 @@ __global__ __launch_bounds__(128) void return_map_kernel(ConstArgs A) {
       A.chi[al * N + v] = A.chi0[al * N + v];
       A.dg[al * N + v] = 0.0;
     }
-    if (A.iters) A.iters[v] = 0;
+    if (A.iters) {
+      A.iters[v] = -1;  // particle voxel
+      A.evals[v] = 0;
+    }
     return;
   }
   double Fpi0[9], chi0[12], dg[12];
@@ -431,7 +437,7 @@ __global__ __launch_bounds__(128) void return_map_kernel(ConstArgs A) {
   mm3(F, Fpi0, Fes);
   const double a = A.lp.dt * A.lp.gdot0;
   CpEval e;
-  int iters = 0;
+  int iters = 0, evals = 0;
   bool ok = false;
   for (int attempt = 0; attempt < 2 && !ok; ++attempt) {
     if (attempt == 1) {
@@ -439,7 +445,7 @@ __global__ __launch_bounds__(128) void return_map_kernel(ConstArgs A) {
 #pragma unroll
       for (int al = 0; al < 12; ++al) dg[al] = 0.0;  // retry from zero slips
     }
-    ok = cp_local_solve(Fes, chi0, dg, tb, A.lp, a, e, iters);
+    ok = cp_local_solve(Fes, chi0, dg, tb, A.lp, a, e, iters, evals);
   }
   if (!ok) atomicAdd(A.vrve ? &A.scs[A.vrve[v]].fails : A.fails, 1);
   // Fp^-1 = Fp^-1_0 (I - sum dg s (x) m);  P = Fe S Fp^-T
@@ -481,7 +487,38 @@ __global__ __launch_bounds__(128) void return_map_kernel(ConstArgs A) {
     A.chi[al * N + v] = e.chi[al];
     A.dg[al * N + v] = dg[al];
   }
-  if (A.iters) A.iters[v] = iters;
+  if (A.iters) {
+    A.iters[v] = iters;
+    A.evals[v] = evals;
+  }
+}
+
+// Work counts of the last return mapping: stats[0] += local Newton steps,
+// [1] += residual evaluations, [2] += crystal voxels, [3] += particle voxels
+__global__ __launch_bounds__(256) void rm_count_kernel(
+    const int32_t* __restrict__ iters, const int32_t* __restrict__ evals,
+    int64_t N, unsigned long long* __restrict__ stats) {
+  __shared__ unsigned long long red[4][256];
+  unsigned long long c[4] = {0, 0, 0, 0};
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < N;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    const int it = iters[v];
+    if (it < 0) {
+      c[3] += 1;
+    } else {
+      c[0] += (unsigned long long)it;
+      c[1] += (unsigned long long)evals[v];
+      c[2] += 1;
+    }
+  }
+  for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = c[k];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) atomicAdd(&stats[threadIdx.x], red[threadIdx.x][0]);
 }
 
 template <typename TK>
@@ -651,14 +688,20 @@ __global__ __launch_bounds__(128) void tangent_kernel(TangentArgs<TK> A) {
 void launch_return_map(const ConstArgs& a, hipStream_t s) {
   const int blk = 128;
   const int64_t grid = (a.N + blk - 1) / blk;
-  hipLaunchKernelGGL(return_map_kernel, dim3((unsigned)grid), dim3(blk), 0, s, a);
+  launch(return_map_kernel, dim3((unsigned)grid), dim3(blk), 0, s, a);
+}
+
+void launch_rm_count(const int32_t* iters, const int32_t* evals, int64_t N,
+                     unsigned long long* stats, hipStream_t s) {
+  hipLaunchKernelGGL(rm_count_kernel, dim3(64), dim3(256), 0, s, iters, evals,
+                     N, stats);
 }
 
 template <typename TK>
 void launch_tangent(const TangentArgs<TK>& a, hipStream_t s) {
   const int blk = 128;
   const int64_t grid = (a.N + blk - 1) / blk;
-  hipLaunchKernelGGL((tangent_kernel<TK>), dim3((unsigned)grid), dim3(blk), 0,
+  launch((tangent_kernel<TK>), dim3((unsigned)grid), dim3(blk), 0,
                      s, a);
 }
 

@@ -92,7 +92,7 @@ __global__ __launch_bounds__(kBlock) void cg_update_kernel(
 template <typename T>
 void launch_cg_update(T* x, T* r, const T* p, const T* Ap, const Scalars* sc,
                       double* partial, int nblk, int64_t n9, hipStream_t s) {
-  hipLaunchKernelGGL((cg_update_kernel<T>), dim3(nblk), dim3(kBlock), 0, s, x,
+  launch((cg_update_kernel<T>), dim3(nblk), dim3(kBlock), 0, s, x,
                      r, p, Ap, sc, partial, n9);
 }
 

@@ -477,10 +477,18 @@ __global__ __launch_bounds__(kBlock) void slab_inv_batch_kernel(BatchSpec<T> b,
 }
 
 // ---------------------------------------------------------------- launchers
+// three component planes per slab block fit the LDS budget of one block
 template <typename T, int N>
+constexpr bool cpb3_fits() {
+  return 3 * SlabGeom<N>::PLANE * (int)sizeof(cplx<T>) <= 64 * 1024;
+}
+template <typename T, int N, int TT>
+constexpr bool pencil_fits() {
+  return (3 * N * (TT + 1) + N) * (int)sizeof(cplx<T>) <= 64 * 1024;
+}
+
+template <typename T, int N, int CPB, int TT>
 void launch_G_passes(const SpectralLaunch<T>& L, hipStream_t s) {
-  constexpr int CPB = SpectralTraits<T, N>::CPB;
-  constexpr int TT = SpectralTraits<T, N>::TT;
   constexpr int H = N / 2;
   constexpr int NTILE = (H + TT - 1) / TT;
   const int nslab = N * (9 / CPB);
@@ -494,7 +502,7 @@ void launch_G_passes(const SpectralLaunch<T>& L, hipStream_t s) {
     fa.psum = L.psum;
     fa.psq = L.psq;
     fa.sc = L.sc;
-    hipLaunchKernelGGL((slab_fwd_kernel<T, N, CPB, SRC_FIELD>), dim3(nslab),
+    launch((slab_fwd_kernel<T, N, CPB, SRC_FIELD>), dim3(nslab),
                        dim3(kBlock), 0, s, fa);
   } else {
     SlabFwdArgs<T> fa{};
@@ -508,7 +516,7 @@ void launch_G_passes(const SpectralLaunch<T>& L, hipStream_t s) {
     fa.psum = nullptr;
     fa.psq = nullptr;
     fa.sc = L.sc;
-    hipLaunchKernelGGL((slab_fwd_kernel<T, N, CPB, SRC_KP>), dim3(nslab),
+    launch((slab_fwd_kernel<T, N, CPB, SRC_KP>), dim3(nslab),
                        dim3(kBlock), 0, s, fa);
   }
   if (L.passes & 2) {
@@ -518,7 +526,7 @@ void launch_G_passes(const SpectralLaunch<T>& L, hipStream_t s) {
   pa.vt = L.vt;
   pa.invN3 = T(1.0 / (double(N) * N * N));
   pa.sc = (L.src == SRC_KP) ? L.sc : nullptr;
-  hipLaunchKernelGGL((pencil_proj_kernel<T, N, TT>), dim3(N * NTILE * 3),
+  launch((pencil_proj_kernel<T, N, TT>), dim3(N * NTILE * 3),
                      dim3(kBlock), 0, s, pa);
   }
   if (!(L.passes & 4)) {
@@ -531,7 +539,7 @@ void launch_G_passes(const SpectralLaunch<T>& L, hipStream_t s) {
     ia.pdot = L.p_new;
     ia.partial = L.partial_inv;
     ia.sc = L.sc;
-    hipLaunchKernelGGL((slab_inv_kernel<T, T, N, CPB, DST_DOT>), dim3(nslab),
+    launch((slab_inv_kernel<T, T, N, CPB, DST_DOT>), dim3(nslab),
                        dim3(kBlock), 0, s, ia);
   } else {
     SlabInvArgs<T, double> ia{};
@@ -542,27 +550,47 @@ void launch_G_passes(const SpectralLaunch<T>& L, hipStream_t s) {
     ia.pdot = nullptr;
     ia.partial = L.partial_inv;
     ia.sc = nullptr;
-    hipLaunchKernelGGL((slab_inv_kernel<T, double, N, CPB, DST_NORM>),
+    launch((slab_inv_kernel<T, double, N, CPB, DST_NORM>),
                        dim3(nslab), dim3(kBlock), 0, s, ia);
   }
+}
+
+// the schedule (cpb, tt) of one launch; 0 picks the default of the traits
+template <typename T, int N>
+void launch_G_sched(const SpectralLaunch<T>& L, hipStream_t s) {
+  const int cpb = L.cpb ? L.cpb : SpectralTraits<T, N>::CPB;
+  const int tt = L.tt ? L.tt : SpectralTraits<T, N>::TT;
+  if (cpb == 3) {
+    if constexpr (cpb3_fits<T, N>()) {
+      if constexpr (pencil_fits<T, N, 16>())
+        if (tt == 16) return launch_G_passes<T, N, 3, 16>(L, s);
+      if (tt == 8) return launch_G_passes<T, N, 3, 8>(L, s);
+    }
+  } else if (cpb == 1) {
+    if constexpr (pencil_fits<T, N, 16>())
+      if (tt == 16) return launch_G_passes<T, N, 1, 16>(L, s);
+    if (tt == 8) return launch_G_passes<T, N, 1, 8>(L, s);
+  }
+  throw Error(-1, "unsupported FFT schedule");
 }
 
 template <typename T>
 void launch_G(int n, const SpectralLaunch<T>& L, hipStream_t s) {
   switch (n) {
-    case 16: launch_G_passes<T, 16>(L, s); break;
-    case 24: launch_G_passes<T, 24>(L, s); break;
-    case 32: launch_G_passes<T, 32>(L, s); break;
-    case 40: launch_G_passes<T, 40>(L, s); break;
-    case 48: launch_G_passes<T, 48>(L, s); break;
-    case 64: launch_G_passes<T, 64>(L, s); break;
-    case 96: launch_G_passes<T, 96>(L, s); break;
-    case 128: launch_G_passes<T, 128>(L, s); break;
+    case 16: launch_G_sched<T, 16>(L, s); break;
+    case 24: launch_G_sched<T, 24>(L, s); break;
+    case 32: launch_G_sched<T, 32>(L, s); break;
+    case 40: launch_G_sched<T, 40>(L, s); break;
+    case 48: launch_G_sched<T, 48>(L, s); break;
+    case 64: launch_G_sched<T, 64>(L, s); break;
+    case 96: launch_G_sched<T, 96>(L, s); break;
+    case 128: launch_G_sched<T, 128>(L, s); break;
     default: throw Error(-1, "unsupported grid size for the FFT passes");
   }
 }
 
-int slab_blocks(int n, bool fp64) {
+int slab_blocks(int n, bool fp64, int cpb_sel) {
+  if (cpb_sel) return n * (9 / cpb_sel);
   auto cpb = [&](auto tag, int nn) -> int {
     using T = decltype(tag);
     switch (nn) {
@@ -581,9 +609,28 @@ int slab_blocks(int n, bool fp64) {
   return n * (9 / c);
 }
 
-int pencil_blocks(int n, bool fp64) {
-  const int tt = fp64 ? 8 : 16;
+int pencil_blocks(int n, bool fp64, int tt_sel) {
+  const int tt = tt_sel ? tt_sel : (fp64 ? 8 : 16);
   return n * ((n / 2 + tt - 1) / tt) * 3;
+}
+
+bool schedule_valid(int n, bool fp64, int cpb, int tt) {
+  if (tt != 8 && tt != 16) return false;
+  if (cpb != 1 && cpb != 3) return false;
+  auto fits = [&](auto tag) -> bool {
+    using T = decltype(tag);
+    switch (n) {
+#define RVE_FITS(NN)                                                        \
+  case NN:                                                                  \
+    return (cpb == 1 || cpb3_fits<T, NN>()) &&                              \
+           (tt == 8 || pencil_fits<T, NN, 16>());
+      RVE_FITS(16) RVE_FITS(24) RVE_FITS(32) RVE_FITS(40) RVE_FITS(48)
+      RVE_FITS(64) RVE_FITS(96) RVE_FITS(128)
+#undef RVE_FITS
+    }
+    return false;
+  };
+  return fp64 ? fits(double{}) : fits(float{});
 }
 
 bool batch_supported(int n) {

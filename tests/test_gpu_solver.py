@@ -159,3 +159,86 @@ def test_graph_capture_equals_direct_launches():
     finally:
         a.close()
         b.close()
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_live_kernel_timing_counts_and_leaves_results_unchanged(graph):
+    """Live event timing brackets each launch of the chosen classes in the
+    solver's own iteration (CG graphs included) and changes no result."""
+    import torch
+    from paper_1806_10599_amd.binding import KERNEL_CLASSES
+    c = config_by_name("C1")
+    micro = c.microstructure()
+    hist = c.history()[:3]
+    s = torch.cuda.Stream()
+    a = make_rve(micro, c.operator, "mixed", use_graph=graph, stream=s)
+    b = make_rve(micro, c.operator, "mixed", use_graph=graph, stream=s)
+    try:
+        b.set_kernel_timing(KERNEL_CLASSES)
+        evals = cg = newton = 0
+        for inc in hist:
+            ia = a.increment(inc["F_bar"], inc["dt"])
+            ib = b.increment(inc["F_bar"], inc["dt"])
+            assert ia["status"] == ib["status"] == 0
+            assert ia["residuals"] == ib["residuals"]
+            evals += ib["newton_iters"] + 1
+            newton += ib["newton_iters"]
+            cg += ib["cg_iters_total"]
+        assert a.get_state() == b.get_state()
+        t = b.kernel_timing(reset=True)
+        assert t["return_map"][1] == evals and t["residual_fp64"][1] == evals
+        assert t["tangent"][1] == newton
+        chunk = 8
+        for k in ("matvec_pass_a", "matvec_pass_b", "matvec_pass_c", "cg_update"):
+            ms, n = t[k]
+            assert ms > 0.0
+            if graph:   # whole chunks are replayed
+                assert n % chunk == 0 and cg <= n < cg + chunk * newton
+            else:
+                assert cg <= n < cg + chunk * newton
+        assert all(v == (0.0, 0) for v in b.kernel_timing().values())
+        cnt = b.return_map_counts(reset=True)
+        assert cnt["crystal"] + cnt["particle"] == evals * micro.n ** 3
+        assert cnt["evals"] >= cnt["crystal"] and cnt["steps"] >= 0
+        b.set_kernel_timing(())
+        inc = c.history()[3]
+        ib = b.increment(inc["F_bar"], inc["dt"])
+        assert ib["status"] == 0
+        assert all(v == (0.0, 0) for v in b.kernel_timing().values())
+    finally:
+        a.close()
+        b.close()
+
+
+def test_fft_schedules_agree_and_autotune_picks_one():
+    """Every valid CG-matvec schedule gives the same increments (the
+    schedules regroup the same per-component transforms; only the order of
+    the p.Ap partial sums differs); the default tunes one."""
+    from paper_1806_10599_amd.binding import RveError
+    c = config_by_name("C1")
+    micro = c.microstructure()
+    hist = c.history()[:2]
+    ref = make_rve(micro, c.operator, "mixed")
+    try:
+        ri = [ref.increment(inc["F_bar"], inc["dt"]) for inc in hist]
+        sch = ref.fft_schedule()
+        assert sch["cpb"] in (1, 3) and sch["tt"] in (8, 16)
+        assert sch["tuned_ms"] > 0.0
+    finally:
+        ref.close()
+    for cpb in (1, 3):
+        for tt in (8, 16):
+            r = make_rve(micro, c.operator, "mixed")
+            try:
+                r.set_fft_schedule(cpb, tt)
+                for inc, a in zip(hist, ri):
+                    b = r.increment(inc["F_bar"], inc["dt"])
+                    assert b["status"] == 0
+                    assert b["newton_iters"] == a["newton_iters"]
+                    assert rel_maxnorm(b["sigma_bar"], a["sigma_bar"]) < 1e-6
+                assert r.fft_schedule()["cpb"] == cpb
+                assert r.fft_schedule()["tt"] == tt
+                with pytest.raises(RveError):
+                    r.set_fft_schedule(2, 8)
+            finally:
+                r.close()
