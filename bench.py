@@ -38,12 +38,13 @@ METRIC = ("Newton-converged voxel-increments/s at 64^3 (chosen vs plain, "
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
-# algorithmic HBM bytes per voxel of each CG-matvec pass on the FP32 path
-# (each datum read or written once; the packed half spectrum of nine
+# algorithmic HBM bytes per voxel of each CG-iteration kernel on the FP32
+# path (each datum read or written once; the packed half spectrum of nine
 # components is 9 x n^3/2 complex = 36 B per voxel)
 PASS_BYTES_F32 = {
-    # K (81 floats) + r + p_old in, p_new out, half spectrum out
-    "matvec_pass_a": 4 * (81 + 9 + 9 + 9) + 36,
+    # K (81 floats), r, p_old in; p, K:p out
+    "matvec_kp": 4 * (81 + 9 + 9 + 9 + 9),
+    "matvec_pass_a": 4 * 9 + 36,                    # K:p in, half spectrum out
     "matvec_pass_b": 36 + 36,                       # spectrum in and out
     "matvec_pass_c": 36 + 4 * 9 + 4 * 9,            # spectrum, p in; Ap out
     "cg_update": 4 * 9 * 6,                         # x, r, p, Ap in; x, r out
@@ -57,7 +58,7 @@ RM_FLOPS = {"eval": 1124, "step": 2600, "crystal": 570, "particle": 110}
 # kernel classes timed live in the timed region: the two candidates for the
 # dominant kernel and the once-per-Newton-step kernels (timing a launch costs
 # a little throughput, so the other CG kernels are left to the profiler)
-LIVE_CLASSES = ("matvec_pass_a", "return_map", "tangent", "residual_fp64")
+LIVE_CLASSES = ("matvec_kp", "return_map", "tangent", "residual_fp64")
 
 
 def parse():
@@ -188,7 +189,7 @@ def live_report(live, rmc, N, cg_total):
     # matvec passes: bytes actually streamed = per-voxel bytes x voxels x
     # CG iterations done (launches past convergence in a replayed chunk
     # return at once and move nothing)
-    mv = ("matvec_pass_a", "matvec_pass_b", "matvec_pass_c")
+    mv = ("matvec_pass_a", "matvec_pass_b", "matvec_pass_c")  # FFT passes
     mv_ms = sum(total_ms[k] for k in mv)
     fft_gbs = (N * cg_total * sum(PASS_BYTES_F32[k] for k in mv)
                / (mv_ms * 1e-3) / 1e9) if all(launches[k] for k in mv) else None
@@ -227,8 +228,9 @@ def live_report(live, rmc, N, cg_total):
         "return_map_work": dict(rmc, flops=rm_flops),
         "roofline": roof,
     }
-    if launches["matvec_pass_a"] and dom != "matvec_pass_a":
-        rep["matvec_pass_a_roofline"] = hbm("matvec_pass_a")
+    for k in PASS_BYTES_F32:
+        if launches[k] and k != dom:
+            rep[k + "_roofline"] = hbm(k)
     if launches["return_map"] and dom != "return_map":
         rep["return_map_roofline"] = alu()
     return rep

@@ -199,12 +199,17 @@ rve_status rve_debug_set_field(rve_t h, int32_t field, const double* src,
 /* rve_bench_kernels: average duration in milliseconds of each hot-path
    kernel over `reps` launches, timed with HIP events on the handle's
    stream, using the launch configuration and buffers of the last increment
-   (needs at least one committed increment).  ms_out[count], count <= 8:
-   0 matvec pass A (K:p and the forward z/y FFTs), 1 pass B (x FFTs and the
-   projection of Sec. 2.2), 2 pass C (inverse y/z FFTs and p.Ap), 3 CG vector
-   update, 4 FP64 return mapping (Sec. 3.2, Eq. 22), 5 tangent (Eq. 13),
-   6 FP64 residual G(P) (Eq. 11).  Only scratch buffers are written; the
-   committed state is untouched. */
+   (needs at least one committed increment).  ms_out[count], count <= 8,
+   indexed by kernel class:
+     0 matvec pass A (forward z/y FFTs of K:p),
+     1 pass B (x FFTs and the projection of Sec. 2.2),
+     2 pass C (inverse y/z FFTs and p.Ap),
+     3 CG vector update,
+     4 FP64 return mapping (Sec. 3.2, Eq. 22),
+     5 tangent (Eq. 13),
+     6 FP64 residual G(P) (Eq. 11; three kernels),
+     7 CG direction and K:p (Eqs. 15-16).
+   Only scratch buffers are written; the committed state is untouched. */
 rve_status rve_bench_kernels(rve_t h, int32_t reps, double* ms_out,
                              int32_t count);
 

@@ -32,7 +32,8 @@ FIELDS = {"F": (0, 9), "P": (1, 9), "sigma": (2, 9), "Fpinv": (3, 9),
 NPARAMS = 10
 MAX_NEWTON_LOG = 64
 KERNEL_CLASSES = ("matvec_pass_a", "matvec_pass_b", "matvec_pass_c",
-                  "cg_update", "return_map", "tangent", "residual_fp64")
+                  "cg_update", "return_map", "tangent", "residual_fp64",
+                  "matvec_kp")
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -364,8 +365,9 @@ class Rve:
 
     def bench_kernels(self, reps=20):
         """Average ms per launch of the hot-path kernels (see rve.h)."""
-        out = np.zeros(7)
-        self._check(LIB.rve_bench_kernels(self._h, int(reps), _dptr(out), 7))
+        out = np.zeros(len(KERNEL_CLASSES))
+        self._check(LIB.rve_bench_kernels(self._h, int(reps), _dptr(out),
+                                          len(KERNEL_CLASSES)))
         return dict(zip(KERNEL_CLASSES, out.tolist()))
 
     # --------------------------------------------------- learned warm start

@@ -89,6 +89,7 @@ Engine::Engine(const rve_config& cfg) : cfg_(cfg) {
   p0_ = alloc(9 * N_ * tsz);
   p1_ = alloc(9 * N_ * tsz);
   Ap_ = alloc(9 * N_ * tsz);
+  Kp_ = alloc(9 * N_ * tsz);
   spec_ = alloc(9 * N_ / 2 * 2 * tsz);
   spec64_ = fp64_ ? spec_ : alloc(9 * N_ / 2 * 2 * sizeof(double));
   nslab32_ = slab_blocks(n_, false);
@@ -319,12 +320,16 @@ void Engine::tangent(double dt) {
 template <typename T, typename Run>
 void Engine::cg_iteration_steps(int parity, Run&& run) {
   const bool dbl = sizeof(T) == sizeof(double);
+  T* p_new = (T*)(parity ? p0_ : p1_);
+  // p = r + beta p_old and y = K : p in one streaming pass, then G(y)
+  run(7, [&] {
+    launch_kp<T>((const T*)K_, (const T*)r_, (const T*)(parity ? p1_ : p0_),
+                 p_new, (T*)Kp_, sc_, N_, st_);
+  });
   SpectralLaunch<T> L;
-  L.src = SRC_KP;
-  L.K = (const T*)K_;
-  L.r = (const T*)r_;
-  L.p_old = (const T*)(parity ? p1_ : p0_);
-  L.p_new = (T*)(parity ? p0_ : p1_);
+  L.src = SRC_FIELD;
+  L.in_field = (const T*)Kp_;
+  L.p_new = p_new;
   L.spec = (cplx<T>*)spec_;
   L.tw = (const cplx<T>*)(dbl ? tw64_ : tw32_);
   L.vt = (const T*)(dbl ? vt64_ : vt32_);
@@ -368,12 +373,15 @@ void Engine::cg_iteration(int parity) {
   });
 }
 
+// kernel classes launched inside a CG iteration: passes A-C, update, K:p
+constexpr uint32_t kCgClasses = 0x8Fu;
+
 // The CG chunk as one graph.  Without live timing the chunk is captured in
 // one piece; with it, each step is captured as a child graph and the timed
 // steps are bracketed by event-record nodes, linked in launch order.
 template <typename T>
 void Engine::capture_graph() {
-  if (!(timer_.mask() & 0xFu)) {
+  if (!(timer_.mask() & kCgClasses)) {
     RVE_HIP(hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal));
     for (int j = 0; j < cfg_.cg_chunk; ++j) cg_iteration<T>(j & 1);
     RVE_HIP(hipStreamEndCapture(st_, &graph_def_));
@@ -416,8 +424,8 @@ void Engine::capture_graph() {
 
 // Picks the fastest FFT schedule (components per slab block in passes A
 // and C, kz columns per pass-B block) for this grid and precision by timing
-// one CG matvec G(K : p) of each valid candidate on the live buffers (the
-// CG vectors are re-initialised afterwards).
+// the three FFT passes of one CG matvec G(K : p) for each valid candidate,
+// on the live buffers (the CG vectors are re-initialised afterwards).
 template <typename T>
 void Engine::autotune() {
   const bool dbl = sizeof(T) == sizeof(double);
@@ -427,14 +435,14 @@ void Engine::autotune() {
   float best = 0.f;
   int bc = 0, bt = 0;
   launch_bench_scalars(sc_, st_);
+  launch_kp<T>((const T*)K_, (const T*)r_, (const T*)p0_, (T*)p1_, (T*)Kp_,
+               sc_, N_, st_);
   for (int cpb : {1, 3})
     for (int tt : {8, 16}) {
       if (!schedule_valid(n_, dbl, cpb, tt)) continue;
       SpectralLaunch<T> L;
-      L.src = SRC_KP;
-      L.K = (const T*)K_;
-      L.r = (const T*)r_;
-      L.p_old = (const T*)p0_;
+      L.src = SRC_FIELD;
+      L.in_field = (const T*)Kp_;
       L.p_new = (T*)p1_;
       L.spec = (cplx<T>*)spec_;
       L.tw = (const cplx<T>*)(dbl ? tw64_ : tw32_);
@@ -965,10 +973,8 @@ void Engine::bench_kernels(int reps, double* ms, int count) {
     using T = decltype(tag);
     const bool dbl = sizeof(T) == sizeof(double);
     SpectralLaunch<T> L;
-    L.src = SRC_KP;
-    L.K = (const T*)K_;
-    L.r = (const T*)r_;
-    L.p_old = (const T*)p0_;
+    L.src = SRC_FIELD;
+    L.in_field = (const T*)Kp_;
     L.p_new = (T*)p1_;
     L.spec = (cplx<T>*)spec_;
     L.tw = (const cplx<T>*)(dbl ? tw64_ : tw32_);
@@ -983,6 +989,15 @@ void Engine::bench_kernels(int reps, double* ms, int count) {
     launch_G<T>(n_, L, st_);
   };
   launch_bench_scalars(sc_, st_);
+  timed(7, [&] {
+    if (fp64_)
+      launch_kp<double>((const double*)K_, (const double*)r_,
+                        (const double*)p0_, (double*)p1_, (double*)Kp_, sc_,
+                        N_, st_);
+    else
+      launch_kp<float>((const float*)K_, (const float*)r_, (const float*)p0_,
+                       (float*)p1_, (float*)Kp_, sc_, N_, st_);
+  });
   for (int b = 0; b < 3; ++b) {
     timed(b, [&] {
       if (fp64_) passes(double{}, 1 << b); else passes(float{}, 1 << b);

@@ -103,6 +103,7 @@ class Engine {
   void* K_;      // [81][N] float (mixed) or double (fp64)
   // CG vectors (T) and spectra
   void *x_, *r_, *p0_, *p1_, *Ap_;
+  void* Kp_;     // K : p of the current CG direction
   void* spec_;        // complex T
   void* spec64_;      // complex double (aliases spec_ in fp64 mode)
   double *partial_inv_, *partial_red_, *psum_, *psq_, *pbar_;

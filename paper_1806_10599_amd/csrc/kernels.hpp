@@ -197,6 +197,9 @@ template <typename T>
 void launch_cg_update(T* x, T* r, const T* p, const T* Ap, const Scalars* sc,
                       double* partial, int nblk, int64_t n9, hipStream_t s);
 template <typename T>
+void launch_kp(const T* K, const T* r, const T* p_old, T* p_new, T* y,
+               const Scalars* sc, int64_t N, hipStream_t s);
+template <typename T>
 void launch_add_to_F(double* F, const T* x, int64_t n9, hipStream_t s);
 template <typename T>
 void launch_convert(const double* in, T* out, int64_t n, hipStream_t s);

@@ -96,6 +96,52 @@ void launch_cg_update(T* x, T* r, const T* p, const T* Ap, const Scalars* sc,
                      r, p, Ap, sc, partial, n9);
 }
 
+// CG direction and material product (Sec. 2.1, Eqs. 15-16): per voxel
+// p = r (first iteration) or r + beta p_old, then y = K : p
+// (y_c = sum_d K[9c + d] p_d); streams K once, coalesced per component
+template <typename T>
+__global__ __launch_bounds__(kBlock) void kp_kernel(
+    const T* __restrict__ K, const T* __restrict__ r,
+    const T* __restrict__ p_old, T* __restrict__ p_new, T* __restrict__ y,
+    const Scalars* __restrict__ sc, int64_t N) {
+  if (sc->done) return;
+  const bool first = sc->first != 0;
+  const T beta = T(sc->beta);
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < N;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    T pd[9];
+#pragma unroll
+    for (int d = 0; d < 9; ++d) {
+      T val = r[d * N + v];
+      if (!first) val += beta * p_old[d * N + v];
+      pd[d] = val;
+      p_new[d * N + v] = val;
+    }
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+      T acc = T(0);
+#pragma unroll
+      for (int d = 0; d < 9; ++d) acc += K[(9 * c + d) * N + v] * pd[d];
+      y[c * N + v] = acc;
+    }
+  }
+}
+
+template <typename T>
+void launch_kp(const T* K, const T* r, const T* p_old, T* p_new, T* y,
+               const Scalars* sc, int64_t N, hipStream_t s) {
+  const int64_t g = (N + kBlock - 1) / kBlock;
+  launch((kp_kernel<T>), dim3((unsigned)(g < 4096 ? g : 4096)), dim3(kBlock),
+         0, s, K, r, p_old, p_new, y, sc, N);
+}
+
+template void launch_kp<float>(const float*, const float*, const float*,
+                               float*, float*, const Scalars*, int64_t,
+                               hipStream_t);
+template void launch_kp<double>(const double*, const double*, const double*,
+                                double*, double*, const Scalars*, int64_t,
+                                hipStream_t);
+
 template <typename T>
 __global__ void add_to_F_kernel(double* __restrict__ F,
                                 const T* __restrict__ x, int64_t n9) {

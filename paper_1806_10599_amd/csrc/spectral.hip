@@ -350,7 +350,7 @@ __global__ __launch_bounds__(kBlock) void slab_fwd_kernel(SlabFwdArgs<T> a) {
   __shared__ cplx<T> lds[CPB * SlabGeom<N>::PLANE];
   __shared__ cplx<T> tw[N];
   __shared__ double red[kBlock];
-  if (SRC == SRC_KP && a.sc->done) return;
+  if (a.sc && a.sc->done) return;
   slab_fwd_body<T, N, CPB, SRC>(a, xcd_remap(blockIdx.x, gridDim.x), lds, tw, red);
 }
 
@@ -525,7 +525,7 @@ void launch_G_passes(const SpectralLaunch<T>& L, hipStream_t s) {
   pa.tw = L.tw;
   pa.vt = L.vt;
   pa.invN3 = T(1.0 / (double(N) * N * N));
-  pa.sc = (L.src == SRC_KP) ? L.sc : nullptr;
+  pa.sc = L.sc;
   launch((pencil_proj_kernel<T, N, TT>), dim3(N * NTILE * 3),
                      dim3(kBlock), 0, s, pa);
   }

@@ -189,7 +189,8 @@ def test_live_kernel_timing_counts_and_leaves_results_unchanged(graph):
         assert t["return_map"][1] == evals and t["residual_fp64"][1] == evals
         assert t["tangent"][1] == newton
         chunk = 8
-        for k in ("matvec_pass_a", "matvec_pass_b", "matvec_pass_c", "cg_update"):
+        for k in ("matvec_kp", "matvec_pass_a", "matvec_pass_b",
+                  "matvec_pass_c", "cg_update"):
             ms, n = t[k]
             assert ms > 0.0
             if graph:   # whole chunks are replayed
