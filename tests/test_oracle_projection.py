@@ -16,6 +16,8 @@ oracle's own formulas:
   the rank of the dense operator.
 """
 
+import os
+
 import numpy as np
 import pytest
 
@@ -51,12 +53,16 @@ def test_dft_round_trip_and_library_fft():
 
 # ------------------------------------------------------------ Eq. 18 values
 def test_paper_frequencies_even_and_odd():
-    # Eq. 18 for n = 4: 2 pi (2 - i)/4, i = 1..4
-    assert np.allclose(paper_frequencies(4),
-                       [np.pi / 2, 0.0, -np.pi / 2, -np.pi])
-    # Eq. 18 for n = 5: 2 pi (3 - i)/5
-    assert np.allclose(paper_frequencies(5),
-                       2 * np.pi * np.array([2, 1, 0, -1, -2]) / 5)
+    # Eq. 18, listed by hand for n = 4..8 (tests/golden/eq18_frequencies.txt)
+    path = os.path.join(os.path.dirname(__file__), "golden",
+                        "eq18_frequencies.txt")
+    rows = [list(map(int, l.split())) for l in open(path)
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) == 5
+    for n, *m in rows:
+        assert len(m) == n
+        assert np.allclose(paper_frequencies(n), 2 * np.pi * np.array(m) / n,
+                           rtol=0, atol=1e-15)
     q, nyq = frequencies_dft_order(4)
     assert np.allclose(q, [0.0, np.pi / 2, -np.pi, -np.pi / 2])
     assert list(nyq) == [False, False, True, False]
