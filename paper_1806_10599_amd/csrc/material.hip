@@ -1,5 +1,6 @@
 // Point constitutive update (Sec. 2.1, Eq. 2) and material tangent
-// K = dP/dF (Eq. 13), one FP64 thread per voxel.
+// K = dP/dF (Eq. 13) in FP64: the return mapping runs four lanes per voxel
+// (three slip systems per lane), the tangent one lane per voxel.
 //
 // Grains: FCC crystal plasticity with the power-law flow rule of Sec. 3.2,
 // Eq. 22 (constant critical stress g, rate exponent n) and an
@@ -307,85 +308,244 @@ __device__ __forceinline__ void cp_jsolve(const double* rhs, const double* D,
   }
 }
 
-__device__ __forceinline__ double half_sq(const double* R) {
-  double m = 0.0;
-#pragma unroll
-  for (int i = 0; i < 12; ++i) m += R[i] * R[i];
-  return 0.5 * m;
-}
-
-// Damped Newton from the slips in dg; returns true on convergence and
-// leaves the evaluation at the final slips in e.
-__device__ __forceinline__ bool cp_local_solve(const double* Fes, const double* chi0,
-                               double* dg, const double* __restrict__ tb,
-                               const LawParams& lp, double a, CpEval& e,
-                               int& iters, int& evals) {
-  cp_eval(Fes, chi0, dg, tb, lp, a, e);
-  ++evals;
-  for (int it = 0; it < LOCAL_MAXIT; ++it) {
-    ++iters;
-    double D[12], hg[12], Q[9];
-    LU6 L;
-    cp_jacobian(e, Fes, dg, tb, lp, a, D, hg, Q, L);
-    double negR[12], step[12];
-#pragma unroll
-    for (int i = 0; i < 12; ++i) negR[i] = -e.R[i];
-    cp_jsolve(negR, D, hg, Q, tb, L, step);
-    double smax = 0.0, dmax = 0.0, rmax = 0.0;
-    bool finite = true;
-#pragma unroll
-    for (int i = 0; i < 12; ++i) {
-      smax = fmax(smax, fabs(step[i]));
-      dmax = fmax(dmax, fabs(dg[i] + step[i]));
-      rmax = fmax(rmax, fabs(e.R[i]));
-      finite = finite && isfinite(step[i]);
-    }
-    if (finite && smax <= LOCAL_ATOL + LOCAL_RTOL * dmax) {
-#pragma unroll
-      for (int i = 0; i < 12; ++i) dg[i] += step[i];
-      cp_eval(Fes, chi0, dg, tb, lp, a, e);
-      ++evals;
-      return true;
-    }
-    const double merit0 = half_sq(e.R);
-    double lam = 1.0;
-    bool accepted = false;
-    double trial[12];
-    for (int ls = 0; ls < 40; ++ls) {
-#pragma unroll
-      for (int i = 0; i < 12; ++i) trial[i] = dg[i] + lam * step[i];
-      cp_eval(Fes, chi0, trial, tb, lp, a, e);
-      ++evals;
-      const double mt = half_sq(e.R);
-      if (isfinite(mt) && mt <= (1.0 - 1e-4 * lam) * merit0) {
-        accepted = true;
-        break;
-      }
-      lam *= 0.5;
-    }
-    bool okv = true;
-#pragma unroll
-    for (int i = 0; i < 12; ++i) {
-      dg[i] = trial[i];
-      okv = okv && isfinite(dg[i]);
-    }
-    if (!okv) return false;
-    if (!accepted && rmax <= LOCAL_RFLOOR) return true;
-  }
-  return false;
-}
-
 __device__ __forceinline__ void load9(const double* __restrict__ p, int64_t v,
                                       int64_t N, double* o) {
 #pragma unroll
   for (int c = 0; c < 9; ++c) o[c] = p[c * N + v];
 }
 
+// ---- return mapping with several lanes per voxel ----------------------------
+// LPV consecutive lanes (2 or 4, inside one quad) share a voxel; lane h of
+// the group owns the slips kOwn*h .. kOwn*h + kOwn - 1 (kOwn = 12 / LPV).
+// Sums over slips are formed per lane and completed across the group in a
+// butterfly (x + other at each level: the same value on every lane, since
+// floating-point addition commutes), so all lanes of a voxel take every
+// decision on identical numbers and run the same iterations.  Splitting the
+// per-slip state removes the register spills of the one-lane kernel.
+
+// the value of lane (this ^ X) within the quad, X in {1, 2}
+template <int X>
+__device__ __forceinline__ double quad_xor(double x) {
+  constexpr int ctrl = (X == 1) ? 0xB1 : 0x4E;  // quad_perm 1,0,3,2 / 2,3,0,1
+  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)(u & 0xffffffffull),
+                                          ctrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), ctrl, 0xF,
+                                          0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                          (unsigned long long)(unsigned)lo));
+}
+template <int LPV>
+__device__ __forceinline__ double grp_sum(double x) {
+  x = x + quad_xor<1>(x);
+  if constexpr (LPV == 4) x = x + quad_xor<2>(x);
+  return x;
+}
+template <int LPV>
+__device__ __forceinline__ double grp_max(double x) {
+  x = fmax(x, quad_xor<1>(x));
+  if constexpr (LPV == 4) x = fmax(x, quad_xor<2>(x));
+  return x;
+}
+
+// R, h of the own slips at t = dg + lam*step and Q = Fe^T Fes
+template <int LPV, int kOwn = 12 / LPV>
+__device__ __forceinline__ void pr_eval(const double* Fes,
+                                        const double* __restrict__ chi0p,
+                                        int64_t N, int h, const double* dg,
+                                        const double* step, double lam,
+                                        const double* __restrict__ tb0,
+                                        const LawParams& lp, double a,
+                                        double* R, double* hd, double* Q) {
+  double dFe[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) dFe[i] = 0.0;
+#pragma unroll
+  for (int j = 0; j < kOwn; ++j) {
+    const double* __restrict__ tb = opaque(tb0) + 3 * (kOwn * h + j);
+    const double t = dg[j] + lam * step[j];
+    const double s0 = tb[kTabS], s1 = tb[kTabS + 1], s2 = tb[kTabS + 2];
+    const double m0 = tb[kTabM], m1 = tb[kTabM + 1], m2 = tb[kTabM + 2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double u = t * (Fes[3 * i] * s0 + Fes[3 * i + 1] * s1 +
+                            Fes[3 * i + 2] * s2);
+      dFe[3 * i] += u * m0;
+      dFe[3 * i + 1] += u * m1;
+      dFe[3 * i + 2] += u * m2;
+    }
+  }
+  double Fe[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Fe[i] = Fes[i] - grp_sum<LPV>(dFe[i]);
+  double S[6];
+  {
+    double C[9];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        C[3 * p + q] = Fe[p] * Fe[q] + Fe[3 + p] * Fe[3 + q] + Fe[6 + p] * Fe[6 + q];
+    const double E[6] = {0.5 * (C[0] - 1.0), 0.5 * (C[4] - 1.0),
+                         0.5 * (C[8] - 1.0), 0.5 * C[5],
+                         0.5 * C[2],         0.5 * C[1]};
+    cmul6(opaque(tb0) + kTabC, E, S);
+  }
+#pragma unroll
+  for (int j = 0; j < kOwn; ++j) {
+    const double* __restrict__ tb = opaque(tb0) + 3 * (kOwn * h + j);
+    const double t = dg[j] + lam * step[j];
+    const double s0 = tb[kTabS], s1 = tb[kTabS + 1], s2 = tb[kTabS + 2];
+    const double m0 = tb[kTabM], m1 = tb[kTabM + 1], m2 = tb[kTabM + 2];
+    const double Sm0 = S[0] * m0 + S[5] * m1 + S[4] * m2;
+    const double Sm1 = S[5] * m0 + S[1] * m1 + S[3] * m2;
+    const double Sm2 = S[4] * m0 + S[3] * m1 + S[2] * m2;
+    const double tau = s0 * Sm0 + s1 * Sm1 + s2 * Sm2;
+    const double chi0 = opaque(chi0p)[(kOwn * h + j) * N];
+    const double chi = (chi0 + lp.c_af * t) / (1.0 + lp.d_af * fabs(t));
+    const double x = (tau - chi) / lp.g;
+    double val, der;
+    asinh_pow(x, lp.nexp, val, der);
+    hd[j] = der;
+    R[j] = asinh(t / a) - val;
+  }
+  make_Q(Fe, Fes, Q);
+}
+
+// Newton step of the own slips: step = -J^-1 R, J = diag(D) + U W^T
+template <int LPV, int kOwn = 12 / LPV>
+__device__ __forceinline__ void pr_step(const double* dg, const double* R,
+                                        const double* hd, const double* Q,
+                                        const double* __restrict__ chi0p,
+                                        int64_t N, int h,
+                                        const double* __restrict__ tb0,
+                                        const LawParams& lp, double a,
+                                        double* step) {
+  LU6 L;
+#pragma unroll
+  for (int i = 0; i < 36; ++i) L.M[i] = 0.0;
+  double D[kOwn];
+#pragma unroll
+  for (int j = 0; j < kOwn; ++j) {
+    const int al = kOwn * h + j;
+    const double* __restrict__ tb = opaque(tb0);
+    const double chi0 = opaque(chi0p)[al * N];
+    const double chi = (chi0 + lp.c_af * dg[j]) / (1.0 + lp.d_af * fabs(dg[j]));
+    const double dchi = (lp.c_af - lp.d_af * sgn(dg[j]) * chi) /
+                        (1.0 + lp.d_af * fabs(dg[j]));
+    D[j] = 1.0 / sqrt(a * a + dg[j] * dg[j]) + hd[j] * dchi / lp.g;
+    double V[6];
+    make_V(Q, tb, al, V);
+    const double f = (hd[j] / lp.g) / D[j];
+#pragma unroll
+    for (int I = 0; I < 6; ++I)
+#pragma unroll
+      for (int J = 0; J < 6; ++J)
+        L.M[6 * I + J] += V[I] * f * VW[J] * tb[kTabN + 6 * al + J];
+    step[j] = -R[j] / D[j];
+  }
+#pragma unroll
+  for (int i = 0; i < 36; ++i) L.M[i] = ((i % 7 == 0) ? 1.0 : 0.0) + grp_sum<LPV>(L.M[i]);
+  lu6_factor(L);
+  double z[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < kOwn; ++j) {
+    double V[6];
+    make_V(Q, opaque(tb0), kOwn * h + j, V);
+#pragma unroll
+    for (int I = 0; I < 6; ++I) z[I] += V[I] * step[j];
+  }
+#pragma unroll
+  for (int I = 0; I < 6; ++I) z[I] = grp_sum<LPV>(z[I]);
+  lu6_solve(L, z);
+#pragma unroll
+  for (int j = 0; j < kOwn; ++j) {
+    const double* __restrict__ tb = opaque(tb0) + kTabN + 6 * (kOwn * h + j);
+    double u = 0.0;
+#pragma unroll
+    for (int J = 0; J < 6; ++J) u += VW[J] * tb[J] * z[J];
+    step[j] -= (hd[j] / lp.g) * u / D[j];
+  }
+}
+
+template <int kOwn>
+__device__ __forceinline__ double own_half_sq(const double* R) {
+  double m = 0.0;
+#pragma unroll
+  for (int j = 0; j < kOwn; ++j) m += R[j] * R[j];
+  return 0.5 * m;
+}
+
+// damped Newton with Armijo backtracking on |R|^2/2 over the group (the
+// iteration of the one-lane formulation); dg holds the own slips
+template <int LPV, int kOwn = 12 / LPV>
+__device__ __forceinline__ bool pr_local_solve(const double* Fes,
+                                               const double* __restrict__ chi0p,
+                                               int64_t N, int h, double* dg,
+                                               const double* __restrict__ tb,
+                                               const LawParams& lp, double a,
+                                               int& iters, int& evals) {
+  double R[kOwn], hd[kOwn], Q[9], step[kOwn];
+#pragma unroll
+  for (int j = 0; j < kOwn; ++j) step[j] = 0.0;
+  pr_eval<LPV>(Fes, chi0p, N, h, dg, step, 0.0, tb, lp, a, R, hd, Q);
+  ++evals;
+  for (int it = 0; it < LOCAL_MAXIT; ++it) {
+    ++iters;
+    pr_step<LPV>(dg, R, hd, Q, chi0p, N, h, tb, lp, a, step);
+    double smax = 0.0, dmax = 0.0, rmax = 0.0, bad = 0.0;
+#pragma unroll
+    for (int j = 0; j < kOwn; ++j) {
+      smax = fmax(smax, fabs(step[j]));
+      dmax = fmax(dmax, fabs(dg[j] + step[j]));
+      rmax = fmax(rmax, fabs(R[j]));
+      bad = isfinite(step[j]) ? bad : 1.0;
+    }
+    smax = grp_max<LPV>(smax);
+    dmax = grp_max<LPV>(dmax);
+    rmax = grp_max<LPV>(rmax);
+    bad = grp_max<LPV>(bad);
+    if (bad == 0.0 && smax <= LOCAL_ATOL + LOCAL_RTOL * dmax) {
+#pragma unroll
+      for (int j = 0; j < kOwn; ++j) dg[j] += step[j];
+      return true;
+    }
+    const double merit0 = grp_sum<LPV>(own_half_sq<kOwn>(R));
+    double lam = 1.0, lam_used = 1.0;
+    bool accepted = false;
+    for (int ls = 0; ls < 40; ++ls) {
+      pr_eval<LPV>(Fes, chi0p, N, h, dg, step, lam, tb, lp, a, R, hd, Q);
+      ++evals;
+      lam_used = lam;
+      const double mt = grp_sum<LPV>(own_half_sq<kOwn>(R));
+      if (isfinite(mt) && mt <= (1.0 - 1e-4 * lam) * merit0) {
+        accepted = true;
+        break;
+      }
+      lam *= 0.5;
+    }
+    double nf = 0.0;
+#pragma unroll
+    for (int j = 0; j < kOwn; ++j) {
+      dg[j] = dg[j] + lam_used * step[j];
+      nf = isfinite(dg[j]) ? nf : 1.0;
+    }
+    if (grp_max<LPV>(nf) != 0.0) return false;
+    if (!accepted && rmax <= LOCAL_RFLOOR) return true;
+  }
+  return false;
+}
+
 }  // namespace
 
-__global__ __launch_bounds__(128) void return_map_kernel(ConstArgs A) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= A.N) return;
+// LPV lanes per voxel (see pr_eval); 256 threads per block
+template <int LPV, int MINB>
+__global__ __launch_bounds__(256, MINB) void return_map_group_kernel(ConstArgs A) {
+  constexpr int kOwn = 12 / LPV;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t v = t / LPV;
+  const int h = (int)(t % LPV);
+  if (v >= A.N) return;  // all lanes of a voxel leave together
   if (A.vrve && A.scs[A.vrve[v]].inactive) return;
   const int64_t N = A.N;
   const double* __restrict__ tb = A.table + (int64_t)A.phase[v] * kTableStride;
@@ -409,85 +569,110 @@ __global__ __launch_bounds__(128) void return_map_kernel(ConstArgs A) {
     double P[9];
     mm3(F, S, P);
 #pragma unroll
-    for (int c = 0; c < 9; ++c) {
-      A.P[c * N + v] = P[c];
-      A.Fpi[c * N + v] = A.Fpi0[c * N + v];
-    }
+    for (int c = 0; c < 9; ++c)
+      if (c % LPV == h) {
+        A.P[c * N + v] = P[c];
+        A.Fpi[c * N + v] = A.Fpi0[c * N + v];
+      }
 #pragma unroll
-    for (int al = 0; al < 12; ++al) {
+    for (int j = 0; j < kOwn; ++j) {
+      const int al = kOwn * h + j;
       A.chi[al * N + v] = A.chi0[al * N + v];
       A.dg[al * N + v] = 0.0;
     }
-    if (A.iters) {
+    if (A.iters && h == 0) {
       A.iters[v] = -1;  // particle voxel
       A.evals[v] = 0;
     }
     return;
   }
-  double Fpi0[9], chi0[12], dg[12];
+  double Fpi0[9], dg[kOwn];
   load9(A.Fpi0, v, N, Fpi0);
-  bool warm = false;
+  double warm = 0.0;
 #pragma unroll
-  for (int al = 0; al < 12; ++al) {
-    chi0[al] = A.chi0[al * N + v];
-    dg[al] = A.dg0 ? A.dg0[al * N + v] : 0.0;
-    warm = warm || (dg[al] != 0.0);
+  for (int j = 0; j < kOwn; ++j) {
+    dg[j] = A.dg0 ? A.dg0[(kOwn * h + j) * N + v] : 0.0;
+    warm = (dg[j] != 0.0) ? 1.0 : warm;
   }
+  warm = grp_max<LPV>(warm);
   double Fes[9];
   mm3(F, Fpi0, Fes);
   const double a = A.lp.dt * A.lp.gdot0;
-  CpEval e;
+  const double* chi0p = A.chi0 + v;
   int iters = 0, evals = 0;
   bool ok = false;
   for (int attempt = 0; attempt < 2 && !ok; ++attempt) {
     if (attempt == 1) {
-      if (!warm) break;
+      if (warm == 0.0) break;
 #pragma unroll
-      for (int al = 0; al < 12; ++al) dg[al] = 0.0;  // retry from zero slips
+      for (int j = 0; j < kOwn; ++j) dg[j] = 0.0;  // retry from zero slips
     }
-    ok = cp_local_solve(Fes, chi0, dg, tb, A.lp, a, e, iters, evals);
+    ok = pr_local_solve<LPV>(Fes, chi0p, N, h, dg, tb, A.lp, a, iters, evals);
   }
-  if (!ok) atomicAdd(A.vrve ? &A.scs[A.vrve[v]].fails : A.fails, 1);
-  // Fp^-1 = Fp^-1_0 (I - sum dg s (x) m);  P = Fe S Fp^-T
-  double Fpi[9];
+  if (!ok && h == 0) atomicAdd(A.vrve ? &A.scs[A.vrve[v]].fails : A.fails, 1);
+  // final state: Fp^-1 = Fp^-1_0 (I - sum dg s (x) m), Fe = F Fp^-1,
+  // S = C : Ee, P = Fe S Fp^-T
+  double dFpi[9], dFe[9];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) Fpi[i] = Fpi0[i];
+  for (int i = 0; i < 9; ++i) dFpi[i] = dFe[i] = 0.0;
 #pragma unroll
-  for (int al = 0; al < 12; ++al) {
-    const double s0 = tb[kTabS + 3 * al], s1 = tb[kTabS + 3 * al + 1],
-                 s2 = tb[kTabS + 3 * al + 2];
-    const double m0 = tb[kTabM + 3 * al], m1 = tb[kTabM + 3 * al + 1],
-                 m2 = tb[kTabM + 3 * al + 2];
+  for (int j = 0; j < kOwn; ++j) {
+    const double* __restrict__ tj = opaque(tb) + 3 * (kOwn * h + j);
+    const double s0 = tj[kTabS], s1 = tj[kTabS + 1], s2 = tj[kTabS + 2];
+    const double m0 = tj[kTabM], m1 = tj[kTabM + 1], m2 = tj[kTabM + 2];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      const double u = dg[al] * (Fpi0[3 * i] * s0 + Fpi0[3 * i + 1] * s1 +
-                                 Fpi0[3 * i + 2] * s2);
-      Fpi[3 * i] -= u * m0;
-      Fpi[3 * i + 1] -= u * m1;
-      Fpi[3 * i + 2] -= u * m2;
+      const double u = dg[j] * (Fpi0[3 * i] * s0 + Fpi0[3 * i + 1] * s1 +
+                                Fpi0[3 * i + 2] * s2);
+      dFpi[3 * i] += u * m0;
+      dFpi[3 * i + 1] += u * m1;
+      dFpi[3 * i + 2] += u * m2;
+      const double w = dg[j] * (Fes[3 * i] * s0 + Fes[3 * i + 1] * s1 +
+                                Fes[3 * i + 2] * s2);
+      dFe[3 * i] += w * m0;
+      dFe[3 * i + 1] += w * m1;
+      dFe[3 * i + 2] += w * m2;
     }
   }
-  double Sf[9] = {e.S[0], e.S[5], e.S[4], e.S[5], e.S[1],
-                  e.S[3], e.S[4], e.S[3], e.S[2]};
-  double FeS[9], P[9];
-  mm3(e.Fe, Sf, FeS);
+  double Fpi[9], Fe[9];
 #pragma unroll
-  for (int i = 0; i < 3; ++i)
+  for (int i = 0; i < 9; ++i) {
+    Fpi[i] = Fpi0[i] - grp_sum<LPV>(dFpi[i]);
+    Fe[i] = Fes[i] - grp_sum<LPV>(dFe[i]);
+  }
+  double S[6];
+  {
+    double C[9];
 #pragma unroll
-    for (int j = 0; j < 3; ++j)
-      P[3 * i + j] = FeS[3 * i] * Fpi[3 * j] + FeS[3 * i + 1] * Fpi[3 * j + 1] +
-                     FeS[3 * i + 2] * Fpi[3 * j + 2];
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        C[3 * p + q] = Fe[p] * Fe[q] + Fe[3 + p] * Fe[3 + q] + Fe[6 + p] * Fe[6 + q];
+    const double E[6] = {0.5 * (C[0] - 1.0), 0.5 * (C[4] - 1.0),
+                         0.5 * (C[8] - 1.0), 0.5 * C[5],
+                         0.5 * C[2],         0.5 * C[1]};
+    cmul6(opaque(tb) + kTabC, E, S);
+  }
+  const double Sf[9] = {S[0], S[5], S[4], S[5], S[1], S[3], S[4], S[3], S[2]};
+  double FeS[9];
+  mm3(Fe, Sf, FeS);
 #pragma unroll
   for (int c = 0; c < 9; ++c) {
-    A.P[c * N + v] = P[c];
+    if (c % LPV != h) continue;
+    const int i = c / 3, j = c - 3 * (c / 3);
+    const double P = FeS[3 * i] * Fpi[3 * j] + FeS[3 * i + 1] * Fpi[3 * j + 1] +
+                     FeS[3 * i + 2] * Fpi[3 * j + 2];
+    A.P[c * N + v] = P;
     A.Fpi[c * N + v] = Fpi[c];
   }
 #pragma unroll
-  for (int al = 0; al < 12; ++al) {
-    A.chi[al * N + v] = e.chi[al];
-    A.dg[al * N + v] = dg[al];
+  for (int j = 0; j < kOwn; ++j) {
+    const int al = kOwn * h + j;
+    const double chi0 = A.chi0[al * N + v];
+    A.chi[al * N + v] = (chi0 + A.lp.c_af * dg[j]) / (1.0 + A.lp.d_af * fabs(dg[j]));
+    A.dg[al * N + v] = dg[j];
   }
-  if (A.iters) {
+  if (A.iters && h == 0) {
     A.iters[v] = iters;
     A.evals[v] = evals;
   }
@@ -685,10 +870,13 @@ __global__ __launch_bounds__(128) void tangent_kernel(TangentArgs<TK> A) {
   }
 }
 
+// four lanes per voxel at two waves per SIMD: the fastest of the measured
+// shapes (2 or 4 lanes, 1 or 2 waves per SIMD) at 64^3
 void launch_return_map(const ConstArgs& a, hipStream_t s) {
-  const int blk = 128;
-  const int64_t grid = (a.N + blk - 1) / blk;
-  launch(return_map_kernel, dim3((unsigned)grid), dim3(blk), 0, s, a);
+  constexpr int kLanes = 4, kBlk = 256;
+  const int64_t grid = (kLanes * a.N + kBlk - 1) / kBlk;
+  launch(return_map_group_kernel<kLanes, 2>, dim3((unsigned)grid), dim3(kBlk),
+         0, s, a);
 }
 
 void launch_rm_count(const int32_t* iters, const int32_t* evals, int64_t N,
