@@ -1,13 +1,17 @@
 """Benchmark: Newton-converged voxel-increments/s at 64^3 (chosen vs plain).
 
-Workload: the 64^3 precision-form RVE (200 Voronoi grains plus 8 % stiff
-particles, discrete projection operator, fully reversed +-0.6 % cycles, 40
-increments per cycle), synthetic and seeded.  One "step" is one load
-increment of that RVE solved to equilibrium tolerance 1e-6 (FP64 residual):
-predictor, return mapping, residual, Newton-CG, commit.
+Workload: the 64^3 RVE (200 Voronoi grains plus 8 % stiff particles,
+discrete projection operator, five fully reversed +-0.6 % cycles of 40
+increments), synthetic and seeded.  One "step" is one load increment of
+that RVE solved to equilibrium tolerance 1e-6 (FP64 residual): predictor,
+return mapping, residual, Newton-CG, commit.  The timed steps are the last
+``--steps`` increments of the history (by default the fifth cycle, which the
+warm-start network never saw in training); the increments before them run
+untimed to reach that state.
 
 * chosen: FP32 FFT/projection/CG, FP64 return mapping/residual/averages,
-  FFT schedule tuned on the live buffers.  Direct launches: replaying the
+  learned warm start with the homogeneous predictor as fallback (the
+  shipped weights), FFT schedule tuned on the live buffers.  Direct launches: replaying the
   CG chunks from captured graphs (--graph) measures the same rate here, and
   direct launches let each timed kernel record its own start and end.
 * plain:  FP64 everywhere, direct launches, same kernels, same inputs.
@@ -72,6 +76,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-live", action="store_true",
                     help="no live kernel timing (no events in the timed region)")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="chosen path without the learned warm start")
     ap.add_argument("--graph", action="store_true",
                     help="chosen path replays CG chunks from captured graphs "
                          "(live timing then uses event-record nodes)")
@@ -95,26 +101,37 @@ def copy_calibration(stream):
 
 
 def run_path(micro, hist, precision, use_graph, steps, warmup, stream,
-             live=True):
+             live=True, learned=False):
+    """Solve the history; time its last ``steps`` increments (at least
+    ``warmup`` untimed increments come first)."""
     import torch
-    from paper_1806_10599_amd.binding import Rve
+    from paper_1806_10599_amd.binding import Rve, WarmStartNet
+    from paper_1806_10599_amd.warmstart import trained_params
     from synthetic import material_params
     r = Rve(micro.n, projection="discrete", precision=precision,
-            newton_tol=1e-6, cg_tol=1e-4, use_graph=use_graph, stream=stream)
+            newton_tol=1e-6, cg_tol=1e-4, use_graph=use_graph, stream=stream,
+            warm_start=learned)
     r.set_microstructure(micro.phase, micro.quat, micro.law, material_params())
+    net = None
+    if learned:
+        net = WarmStartNet(stream=stream)
+        net.set_params(trained_params())
+        r.attach_warm_start(net)
     if live:
         r.set_kernel_timing(LIVE_CLASSES)
-    infos = []
-    for inc in hist[:warmup]:
+    start = max(warmup, len(hist) - steps)
+    for inc in hist[:start]:
         if inc["cycle_start"]:
             r.reset_fips()
-        infos.append(r.increment(inc["F_bar"], inc["dt"]))
+        info = r.increment(inc["F_bar"], inc["dt"])
+        if info["status"] != 0:
+            raise RuntimeError(f"increment {inc['k']} failed: {info['status']}")
     torch.cuda.synchronize()
     r.kernel_timing(reset=True)
     r.return_map_counts(reset=True)
     t0 = time.perf_counter()
     timed = []
-    for inc in hist[warmup:warmup + steps]:
+    for inc in hist[start:start + steps]:
         if inc["cycle_start"]:
             r.reset_fips()
         info = r.increment(inc["F_bar"], inc["dt"])
@@ -126,10 +143,22 @@ def run_path(micro, hist, precision, use_graph, steps, warmup, stream,
     live_t = r.kernel_timing() if live else None
     counts = r.return_map_counts() if live else None
     sched = r.fft_schedule()
-    sig = [i["sigma_bar"][0, 0] for i in infos + timed]
+    sig = [i["sigma_bar"][0, 0] for i in timed]
+    if net is not None:
+        r.attach_warm_start(None)
+        net.close()
     r.close()
     return dict(elapsed=elapsed, infos=timed, live=live_t, rm_counts=counts,
-                sigma11=sig, schedule=sched)
+                sigma11=sig, schedule=sched, start=start)
+
+
+def predictor_stats(infos):
+    return dict(
+        newton_per_increment=float(np.mean([i["newton_iters"] for i in infos])),
+        cg_per_increment=float(np.mean([i["cg_iters_total"] for i in infos])),
+        median_predictor_residual=float(np.median(
+            [i["predictor_residual"] for i in infos])),
+        learned_start_used=float(np.mean([i["used_learned"] for i in infos])))
 
 
 def oracle_sample(micro, hist, gpu_infos, budget_s):
@@ -249,14 +278,15 @@ def main():
     cfg = config_by_name(args.config)
     micro = cfg.microstructure()
     hist = cfg.history()
-    need = args.warmup + args.steps
-    while len(hist) < need:
-        hist = hist + cfg.history(cycles=cfg.cycles)
+    if args.warmup + args.steps > len(hist):
+        raise SystemExit(f"the {cfg.name} history has {len(hist)} increments; "
+                         f"warmup + steps must not exceed it")
     stream = torch.cuda.Stream()
     calib = copy_calibration(stream) if args.copy_calibration else None
     with torch.cuda.stream(stream):
         chosen = run_path(micro, hist, "mixed", args.graph, args.steps,
-                          args.warmup, stream, live=not args.no_live)
+                          args.warmup, stream, live=not args.no_live,
+                          learned=not args.no_learned)
         plain = None
         if not args.no_plain:
             plain = run_path(micro, hist, "fp64", False, args.steps,
@@ -287,9 +317,19 @@ def main():
                                 f"{cfg.inc_per_cycle} inc/cycle, tol 1e-6"),
                    "voxels": N, "precision": "mixed FP32 FFT/CG + FP64",
                    "graph": args.graph,
+                   "warm_start": ("homogeneous" if args.no_learned else
+                                  "learned (weights/warmstart.npy), with "
+                                  "homogeneous fallback"),
+                   "timed_increments": [chosen["start"] + 1,
+                                        chosen["start"] + args.steps],
+                   "timed_window": ("last cycle of the history, held out from "
+                                    "the warm-start training"
+                                    if args.steps <= cfg.inc_per_cycle else
+                                    "last increments of the history"),
                    "fft_schedule": chosen["schedule"]},
         "newton_per_increment": newton_per_inc,
         "cg_per_increment": cg_per_inc,
+        "predictor": predictor_stats(infos),
     }
     live = chosen["live"]
     if live is not None:
@@ -302,7 +342,8 @@ def main():
                         "cg_per_increment": float(np.mean(
                             [i["cg_iters_total"] for i in plain["infos"]])),
                         "newton_per_increment": float(np.mean(
-                            [i["newton_iters"] for i in plain["infos"]]))}
+                            [i["newton_iters"] for i in plain["infos"]])),
+                        "predictor": predictor_stats(plain["infos"])}
         out["chosen_over_plain"] = round(value / pv, 3)
         s_c = np.array(chosen["sigma11"])
         s_p = np.array(plain["sigma11"])
@@ -311,8 +352,10 @@ def main():
     if calib:
         out["copy_calibration"] = calib
     if not args.no_cpu:
-        out["cpu_baseline"] = oracle_sample(micro, hist, infos,
-                                            args.cpu_seconds)
+        # the oracle implements the homogeneous-predictor method: scale its
+        # sample by the plain path's counts when they are there
+        ref = plain["infos"] if plain is not None else infos
+        out["cpu_baseline"] = oracle_sample(micro, hist, ref, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

@@ -287,6 +287,10 @@ rve_status rve_ws_forward(rve_ws_t w, const uint16_t* X, int32_t n, float* Y);
 rve_status rve_ws_train_step(rve_ws_t w, const uint16_t* X, const float* T,
                              int32_t n, float lr, double* loss,
                              float* grad_host);
+/* The loss of one sample without a training step (parameters and optimiser
+   state untouched). */
+rve_status rve_ws_loss(rve_ws_t w, const uint16_t* X, const float* T,
+                       int32_t n, double* loss);
 const char* rve_ws_last_error(rve_ws_t w);
 rve_status rve_attach_warm_start(rve_t h, rve_ws_t w);
 rve_status rve_ws_features(rve_t h, const double F_bar_new[9], uint16_t* X);

@@ -123,6 +123,8 @@ def _load():
         "rve_ws_train_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p,
                                         C.c_int32, C.c_float, P(C.c_double),
                                         P(C.c_float)]),
+        "rve_ws_loss": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_int32, P(C.c_double)]),
         "rve_ws_last_error": (C.c_char_p, [C.c_void_p]),
         "rve_attach_warm_start": (C.c_int, [C.c_void_p, C.c_void_p]),
         "rve_ws_features": (C.c_int, [C.c_void_p, P(C.c_double), C.c_void_p]),
@@ -588,3 +590,11 @@ class WarmStartNet:
             float(lr), C.byref(loss),
             g.ctypes.data_as(C.POINTER(C.c_float)) if want_grad else None))
         return (loss.value, g) if want_grad else loss.value
+
+    def loss(self, X, T, n):
+        """Loss of one sample; no training step."""
+        out = C.c_double()
+        self._check(LIB.rve_ws_loss(self._h, C.c_void_p(X.data_ptr()),
+                                    C.c_void_p(T.data_ptr()), n,
+                                    C.byref(out)))
+        return out.value

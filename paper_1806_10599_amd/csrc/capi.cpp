@@ -273,6 +273,15 @@ rve_status rve_ws_train_step(rve_ws_t w, const uint16_t* X, const float* T,
   });
 }
 
+rve_status rve_ws_loss(rve_ws_t w, const uint16_t* X, const float* T,
+                       int32_t n, double* loss) {
+  return guarded(w, [&] {
+    if (!X || !T || !loss) throw rve::Error(RVE_EINVAL, "null buffer");
+    *loss = w->net->loss(X, T, n);
+    return RVE_OK;
+  });
+}
+
 const char* rve_ws_last_error(rve_ws_t w) {
   if (!w) return g_create_error.c_str();
   return w->err.c_str();

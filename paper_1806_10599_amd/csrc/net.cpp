@@ -133,6 +133,21 @@ void Net::forward(const uint16_t* X, int n, float* Y, hipStream_t s) {
   RVE_HIP(hipGetLastError());
 }
 
+double Net::loss(const uint16_t* X, const float* T, int n) {
+  if (n % 16) throw Error(-1, "the network needs a grid edge divisible by 16");
+  const int64_t N = (int64_t)n * n * n;
+  ensure(N);
+  forward(X, n, yf_);
+  nn_mse(yf_, T, kOut, kOutReal, N, dy_, dyf_, lpart_, kLossBlocks, st_);
+  RVE_HIP(hipGetLastError());
+  RVE_HIP(hipMemcpyAsync(lhost_, lpart_, kLossBlocks * sizeof(double),
+                         hipMemcpyDeviceToHost, st_));
+  RVE_HIP(hipStreamSynchronize(st_));
+  double L = 0.0;
+  for (int i = 0; i < kLossBlocks; ++i) L += lhost_[i];
+  return L;
+}
+
 double Net::train_step(const uint16_t* X, const float* T, int n, float lr,
                        float* grad_host) {
   if (n % 16) throw Error(-1, "the network needs a grid edge divisible by 16");

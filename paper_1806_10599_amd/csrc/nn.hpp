@@ -68,6 +68,7 @@ class Net {
   // X [N][kFeat] bf16 -> Y [N][kOut] f32
   void forward(const uint16_t* X, int n, float* Y, hipStream_t s = nullptr);
   // one Adam step on one sample; returns the loss, optionally the gradient
+  double loss(const uint16_t* X, const float* T, int n);  // forward + MSE only
   double train_step(const uint16_t* X, const float* T, int n, float lr,
                     float* grad_host);
   hipStream_t stream() const { return st_; }

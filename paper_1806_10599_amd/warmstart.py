@@ -9,7 +9,13 @@ increments, and loops over them.  Samples stay on the GPU as torch tensors
 
 from __future__ import annotations
 
+import os
+
 import numpy as np
+
+# parameters written by paper_1806_10599_amd.train_warmstart (float32 .npy)
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights",
+                       "warmstart.npy")
 
 LAYERS = ((40, 32), (32, 32), (32, 32), (32, 9))
 
@@ -28,6 +34,14 @@ def init_params(seed: int = 0, out_scale: float = 0.1) -> np.ndarray:
             W *= out_scale
         parts += [W.ravel(), np.zeros(co)]
     return np.concatenate(parts).astype(np.float32)
+
+
+def trained_params(path: str = WEIGHTS) -> np.ndarray:
+    """The shipped trained parameters (no pickled objects are loaded)."""
+    p = np.load(path, allow_pickle=False)
+    if p.dtype != np.float32 or p.shape != (param_count(),):
+        raise ValueError(f"{path}: expected {param_count()} float32 parameters")
+    return p
 
 
 def unflatten(p):

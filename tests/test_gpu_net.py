@@ -195,3 +195,68 @@ def test_warm_start_keeps_the_equilibrium():
         a.close()
         b.close()
         net.close()
+
+
+def test_loss_entry_point_leaves_training_state_alone():
+    """rve_ws_loss returns the training step's loss and changes nothing."""
+    import torch
+    from paper_1806_10599_amd.warmstart import init_params
+    n = 16
+    p = init_params(2)
+    a, b = _net(p), _net(p)
+    Xt, Xref = _features(n, 4)
+    T = np.zeros((n ** 3, 16), dtype=np.float32)
+    T[:, :9] = 0.25 * Xref[9:18].reshape(9, -1).T
+    Tt = torch.from_numpy(T).cuda()
+    l0 = a.loss(Xt, Tt, n)
+    assert a.loss(Xt, Tt, n) == l0
+    for _ in range(3):
+        la = a.train_step(Xt, Tt, n, lr=1e-3)
+        b.loss(Xt, Tt, n)          # interleaved evaluations
+        lb = b.train_step(Xt, Tt, n, lr=1e-3)
+        assert la == lb
+    assert l0 == _net(p).train_step(Xt, Tt, n, lr=0.0)
+    assert np.array_equal(a.get_params(), b.get_params())
+    a.close()
+    b.close()
+
+
+def test_shipped_weights_beat_the_homogeneous_predictor_on_held_out_cycle():
+    """The trained parameters (never trained on the fifth 64^3 cycle) give a
+    smaller predictor residual there and the same equilibrium."""
+    from gpu_util import make_rve
+    from paper_1806_10599_amd.warmstart import trained_params
+    c = config_by_name("C3")
+    micro = c.microstructure()
+    hist = c.history()
+    first = next(j for j, inc in enumerate(hist) if inc["cycle"] == c.cycles - 1)
+    stop = first + 10
+    net = _net(trained_params())
+    a = make_rve(micro, c.operator, "mixed")
+    b = make_rve(micro, c.operator, "mixed", warm_start=True)
+    b.attach_warm_start(net)
+    try:
+        ra, rb = [], []
+        for j, inc in enumerate(hist[:stop]):
+            if inc["cycle_start"]:
+                a.reset_fips()
+                b.reset_fips()
+            ia = a.increment(inc["F_bar"], inc["dt"])
+            ib = b.increment(inc["F_bar"], inc["dt"])
+            assert ia["status"] == 0 and ib["status"] == 0
+            if j >= first:
+                ra.append(ia)
+                rb.append(ib)
+        used = np.mean([i["used_learned"] for i in rb])
+        pa = np.median([i["predictor_residual"] for i in ra])
+        pb = np.median([i["predictor_residual"] for i in rb])
+        assert used >= 0.8, used
+        assert pb < 0.5 * pa, (pa, pb)
+        for x, y in zip(ra, rb):
+            s_a, s_b = x["sigma_bar"][0, 0], y["sigma_bar"][0, 0]
+            assert abs(s_a - s_b) <= 1e-4 * abs(s_a) + 1e-3
+    finally:
+        b.attach_warm_start(None)
+        a.close()
+        b.close()
+        net.close()
