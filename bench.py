@@ -76,6 +76,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-live", action="store_true",
                     help="no live kernel timing (no events in the timed region)")
+    ap.add_argument("--start", type=int, default=None,
+                    help="first timed increment (0-based; default: the last "
+                         "--steps increments of the history are timed)")
     ap.add_argument("--no-learned", action="store_true",
                     help="chosen path without the learned warm start")
     ap.add_argument("--graph", action="store_true",
@@ -101,7 +104,7 @@ def copy_calibration(stream):
 
 
 def run_path(micro, hist, precision, use_graph, steps, warmup, stream,
-             live=True, learned=False):
+             live=True, learned=False, start=None):
     """Solve the history; time its last ``steps`` increments (at least
     ``warmup`` untimed increments come first)."""
     import torch
@@ -119,7 +122,7 @@ def run_path(micro, hist, precision, use_graph, steps, warmup, stream,
         r.attach_warm_start(net)
     if live:
         r.set_kernel_timing(LIVE_CLASSES)
-    start = max(warmup, len(hist) - steps)
+    start = max(warmup, len(hist) - steps) if start is None else max(warmup, start)
     for inc in hist[:start]:
         if inc["cycle_start"]:
             r.reset_fips()
@@ -209,6 +212,27 @@ def oracle_sample(micro, hist, gpu_infos, budget_s):
                 seconds_per_increment=sec_per_inc)
 
 
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_traffic_c3_64cubed.json")
+
+
+def pmc_traffic(kernel):
+    """HBM bytes per dispatch of a kernel class from the committed
+    FETCH_SIZE/WRITE_SIZE runs (scaled by the copy-kernel calibration), or
+    None when there is no such measurement or the kernel's source file has
+    changed since it was taken."""
+    import hashlib
+    try:
+        with open(PMC_SUMMARY) as f:
+            summ = json.load(f)
+        k = summ["kernels"][kernel]
+        with open(os.path.join(ROOT, k["source"]), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != k["source_sha256"]:
+                return None
+        return float(k["traffic_bytes_per_dispatch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def live_report(live, rmc, N, cg_total):
     """Per-kernel live durations, FFT bandwidth and the dominant kernel's
     roofline from the event timings of the timed region."""
@@ -231,7 +255,7 @@ def live_report(live, rmc, N, cg_total):
         ach = per_launch / (avg_ms[k] * 1e-3) / 1e9
         return dict(kernel=k, bound="hbm", achieved=round(ach, 1),
                     peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(ach / HBM_PEAK_GBS, 4), traffic=None,
+                    frac=round(ach / HBM_PEAK_GBS, 4), traffic=pmc_traffic(k),
                     bytes_per_launch=round(per_launch), avg_ms=round(avg_ms[k], 5),
                     launches=launches[k])
 
@@ -240,7 +264,8 @@ def live_report(live, rmc, N, cg_total):
         ach = per_launch / (avg_ms["return_map"] * 1e-3) / 1e12
         return dict(kernel="return_map", bound="alu", achieved=round(ach, 3),
                     peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=round(ach / FP64_PEAK_TFLOPS, 4), traffic=None,
+                    frac=round(ach / FP64_PEAK_TFLOPS, 4),
+                    traffic=pmc_traffic("return_map"),
                     flops_per_launch=round(per_launch),
                     avg_ms=round(avg_ms["return_map"], 4),
                     launches=launches["return_map"])
@@ -278,7 +303,7 @@ def main():
     cfg = config_by_name(args.config)
     micro = cfg.microstructure()
     hist = cfg.history()
-    if args.warmup + args.steps > len(hist):
+    if max(args.warmup, args.start or 0) + args.steps > len(hist):
         raise SystemExit(f"the {cfg.name} history has {len(hist)} increments; "
                          f"warmup + steps must not exceed it")
     stream = torch.cuda.Stream()
@@ -286,11 +311,11 @@ def main():
     with torch.cuda.stream(stream):
         chosen = run_path(micro, hist, "mixed", args.graph, args.steps,
                           args.warmup, stream, live=not args.no_live,
-                          learned=not args.no_learned)
+                          learned=not args.no_learned, start=args.start)
         plain = None
         if not args.no_plain:
             plain = run_path(micro, hist, "fp64", False, args.steps,
-                             args.warmup, stream, live=False)
+                             args.warmup, stream, live=False, start=args.start)
     N = micro.n ** 3
     value = N * args.steps / chosen["elapsed"]
     infos = chosen["infos"]
@@ -324,8 +349,9 @@ def main():
                                         chosen["start"] + args.steps],
                    "timed_window": ("last cycle of the history, held out from "
                                     "the warm-start training"
-                                    if args.steps <= cfg.inc_per_cycle else
-                                    "last increments of the history"),
+                                    if (args.start is None and
+                                        args.steps <= cfg.inc_per_cycle) else
+                                    "increments of the history"),
                    "fft_schedule": chosen["schedule"]},
         "newton_per_increment": newton_per_inc,
         "cg_per_increment": cg_per_inc,

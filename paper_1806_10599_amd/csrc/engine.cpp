@@ -100,6 +100,7 @@ Engine::Engine(const rve_config& cfg) : cfg_(cfg) {
   psum_ = (double*)alloc(9 * n_ * sizeof(double));
   psq_ = (double*)alloc(9 * n_ * sizeof(double));
   sc_ = (Scalars*)alloc(sizeof(Scalars));
+  RVE_HIP(hipMemsetAsync(sc_, 0, sizeof(Scalars), st_));
   phase_ = (int32_t*)alloc(N_ * sizeof(int32_t));
   table_ = nullptr;
   RVE_HIP(hipHostMalloc((void**)&sc_host_, sizeof(Scalars), hipHostMallocDefault));

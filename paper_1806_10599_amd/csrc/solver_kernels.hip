@@ -4,6 +4,7 @@
 //   fixed-order (deterministic) reductions (text after Eq. 16), the Newton
 //   update F += dF, the commit of the increment with the fatigue indicators
 //   of Sec. 3.3, Eqs. 23-24.
+#include "cg_scalars.hpp"
 #include "kernels.hpp"
 
 namespace rve {
@@ -92,8 +93,8 @@ __global__ __launch_bounds__(kBlock) void cg_update_kernel(
 template <typename T>
 void launch_cg_update(T* x, T* r, const T* p, const T* Ap, const Scalars* sc,
                       double* partial, int nblk, int64_t n9, hipStream_t s) {
-  launch((cg_update_kernel<T>), dim3(nblk), dim3(kBlock), 0, s, x,
-                     r, p, Ap, sc, partial, n9);
+  launch((cg_update_kernel<T>), dim3(nblk), dim3(kBlock), 0, s, x, r, p, Ap,
+         sc, partial, n9);
 }
 
 // CG direction and material product (Sec. 2.1, Eqs. 15-16): per voxel
@@ -177,9 +178,7 @@ __global__ __launch_bounds__(kBlock) void reduce_kernel(
     double invN3, Scalars* __restrict__ sc, double* __restrict__ pbar) {
   __shared__ double red[kBlock];
   if ((op == RED_ALPHA || op == RED_BETA) && sc->done) return;
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < count; i += blockDim.x) acc += partial[i];
-  const double tot = block_reduce(acc, red);
+  const double tot = cg_sum_partials(partial, count, red);
   if (op == RED_RESID) {
     double a2 = 0.0;
     for (int i = threadIdx.x; i < 9 * nss; i += blockDim.x) a2 += psq[i];
@@ -197,40 +196,7 @@ __global__ __launch_bounds__(kBlock) void reduce_kernel(
     return;
   }
   if (threadIdx.x != 0) return;
-  if (op == RED_INIT) {
-    sc->bb = tot;
-    sc->rr = tot;
-    sc->eta2bb = sc->eta2bb * tot;  // eta^2 was stored by the init kernel
-    sc->iters = 0;
-    sc->first = 1;
-    sc->breakdown = 0;
-    sc->converged = (tot == 0.0) ? 1 : 0;
-    sc->done = sc->converged;
-    sc->alpha = 0.0;
-    sc->beta = 0.0;
-  } else if (op == RED_ALPHA) {
-    sc->pAp = tot;
-    if (!(tot > 0.0) || !isfinite(tot)) {
-      sc->breakdown = 1;
-      sc->done = 1;
-      sc->iters += 1;
-    } else {
-      sc->alpha = sc->rr / tot;
-    }
-  } else if (op == RED_BETA) {
-    sc->iters += 1;
-    sc->rr_new = tot;
-    sc->first = 0;
-    if (tot <= sc->eta2bb) {
-      sc->converged = 1;
-      sc->done = 1;
-    } else if (sc->iters >= sc->max_iters || !isfinite(tot)) {
-      sc->done = 1;
-    } else {
-      sc->beta = tot / sc->rr;
-      sc->rr = tot;
-    }
-  }
+  cg_scalar_update(op, tot, sc);
 }
 
 void launch_reduce(int op, const double* partial, int count,
