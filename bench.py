@@ -84,6 +84,9 @@ def parse():
     ap.add_argument("--graph", action="store_true",
                     help="chosen path replays CG chunks from captured graphs "
                          "(live timing then uses event-record nodes)")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched-RVE measurement")
+    ap.add_argument("--batch-steps", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain elementwise copy of 256 MiB "
                          "(read + write), the reference kernel that scales "
@@ -153,6 +156,66 @@ def run_path(micro, hist, precision, use_graph, steps, warmup, stream,
     r.close()
     return dict(elapsed=elapsed, infos=timed, live=live_t, rm_counts=counts,
                 sigma11=sig, schedule=sched, start=start)
+
+
+def batch_run(steps, stream):
+    """The batch workload: 32 RVEs of edges 24-48 (20-150 grains each, about
+    1.8 M voxels), one launch per pass for the whole batch, CG chunks replayed
+    from a captured graph; then the same RVEs and increments solved one after
+    another with single-RVE handles (same precision, operator and
+    tolerances).  Both timed over the first ``steps`` increments."""
+    import torch
+    from paper_1806_10599_amd.binding import BatchRve, Rve
+    from synthetic import config_by_name, material_params
+    cfg = config_by_name("C4")
+    micros = cfg.batch_microstructures()
+    hist = cfg.history()[:steps]
+    vox = sum(m.n ** 3 for m in micros)
+    b = BatchRve([m.n for m in micros], projection=cfg.operator,
+                 precision=cfg.precision, newton_tol=1e-6, cg_tol=1e-4,
+                 use_graph=True, stream=stream)
+    for j, m in enumerate(micros):
+        b.set_microstructure(j, m.phase, m.quat, m.law, material_params())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    newton = []
+    for inc in hist:
+        infos = b.increment(inc["F_bar"], inc["dt"])
+        if any(i["status"] != 0 for i in infos):
+            raise RuntimeError("batched increment failed")
+        newton.append(max(i["newton_iters"] for i in infos))
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    sig_b = [b.macro(j)["sigma_bar"][0, 0] for j in range(len(micros))]
+    b.close()
+    t_single = 0.0
+    sig_s = []
+    for m in micros:
+        r = Rve(m.n, projection=cfg.operator, precision=cfg.precision,
+                newton_tol=1e-6, cg_tol=1e-4, stream=stream)
+        r.set_microstructure(m.phase, m.quat, m.law, material_params())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for inc in hist:
+            if r.increment(inc["F_bar"], inc["dt"])["status"] != 0:
+                raise RuntimeError("single-RVE increment failed")
+        torch.cuda.synchronize()
+        t_single += time.perf_counter() - t0
+        sig_s.append(r.macro()["sigma_bar"][0, 0])
+        r.close()
+    sig_b, sig_s = np.array(sig_b), np.array(sig_s)
+    return {"workload": (f"{len(micros)} RVEs, edges "
+                         f"{sorted(set(m.n for m in micros))}, {vox} voxels, "
+                         f"{cfg.operator} operator, {cfg.precision}, tol 1e-6, "
+                         f"first {steps} increments of +-{cfg.eps_a:.1%} cycles"),
+            "value": round(vox * steps / t_batch, 1),
+            "unit": "voxel-increments/s",
+            "ms_per_step": round(1e3 * t_batch / steps, 3),
+            "max_newton_per_increment": float(np.mean(newton)),
+            "one_by_one_value": round(vox * steps / t_single, 1),
+            "batched_over_one_by_one": round(t_single / t_batch, 3),
+            "sigma11_max_rel_diff_vs_one_by_one": float(
+                np.max(np.abs(sig_b - sig_s)) / np.max(np.abs(sig_s)))}
 
 
 def predictor_stats(infos):
@@ -375,6 +438,9 @@ def main():
         s_p = np.array(plain["sigma11"])
         out["sigma11_max_rel_diff_vs_plain"] = float(
             np.max(np.abs(s_c - s_p)) / np.max(np.abs(s_p)))
+    if not args.no_batch:
+        with torch.cuda.stream(stream):
+            out["batch"] = batch_run(args.batch_steps, stream)
     if calib:
         out["copy_calibration"] = calib
     if not args.no_cpu:
