@@ -164,9 +164,12 @@ __device__ __forceinline__ void stockham_pass(cplx<T>* lds, const cplx<T>* tw,
   constexpr int BPL = N / R;  // butterflies per line
   const int lpc = (int)blockDim.x / BPL;
   const int t = threadIdx.x;
-  const int lo = t / BPL;
-  const int j = t - lo * BPL;
-  const bool lane_ok = lo < lpc;
+  // lines vary fastest across threads: the 32 lanes of a half-wave touch 32
+  // different lines at the same element, which the odd LDS pitches (and the
+  // column and pencil maps) place in distinct banks
+  const int lo = t % lpc;
+  const int j = t / lpc;
+  const bool lane_ok = j < BPL;
   const int k = j % NS;
   for (int l0 = 0; l0 < nlines; l0 += lpc) {
     const int l = l0 + lo;
