@@ -104,42 +104,48 @@ __device__ __forceinline__ void slab_fwd_body(const SlabFwdArgs<T>& a, int lb,
 #pragma unroll
   for (int q = 0; q < CPB; ++q) ss[q] = s1[q] = 0.0;
 
-  // build the real plane(s), packed: row y' holds y' (re) and y'+H (im)
+  // build the real plane(s), packed: row y' holds y' (re) and y'+H (im);
+  // each thread builds both rows of a (y', z) slot and stores one complex
   const bool first = (SRC == SRC_KP) ? (a.sc->first != 0) : true;
   const T beta = (SRC == SRC_KP) ? T(a.sc->beta) : T(0);
-  for (int t = threadIdx.x; t < N * N; t += blockDim.x) {
-    const int y = t / N, z = t - (t / N) * N;
-    const int64_t v = (x * N + y) * N + z;
-    T out[CPB];
-    if constexpr (SRC == SRC_FIELD) {
+  for (int t = threadIdx.x; t < H * N; t += blockDim.x) {
+    const int yp = t / N, z = t - (t / N) * N;
+    T out[2][CPB];
 #pragma unroll
-      for (int q = 0; q < CPB; ++q) out[q] = a.field[(grp * CPB + q) * cs + v];
-    } else {
-      T pd[9];
+    for (int hh = 0; hh < 2; ++hh) {
+      const int64_t v = ((int64_t)x * N + yp + hh * H) * N + z;
+      if constexpr (SRC == SRC_FIELD) {
 #pragma unroll
-      for (int d = 0; d < 9; ++d) {
-        T val = a.r[d * cs + v];
-        if (!first) val += beta * a.p_old[d * cs + v];
-        pd[d] = val;
-      }
+        for (int q = 0; q < CPB; ++q)
+          out[hh][q] = a.field[(grp * CPB + q) * cs + v];
+      } else {
+        T pd[9];
 #pragma unroll
-      for (int q = 0; q < CPB; ++q) {
-        const int c = grp * CPB + q;
-        a.p_new[c * cs + v] = pd[c];
-        T acc = T(0);
+        for (int d = 0; d < 9; ++d) {
+          T val = a.r[d * cs + v];
+          if (!first) val += beta * a.p_old[d * cs + v];
+          pd[d] = val;
+        }
 #pragma unroll
-        for (int d = 0; d < 9; ++d) acc += a.K[(9 * c + d) * cs + v] * pd[d];
-        out[q] = acc;
+        for (int q = 0; q < CPB; ++q) {
+          const int c = grp * CPB + q;
+          a.p_new[c * cs + v] = pd[c];
+          T acc = T(0);
+#pragma unroll
+          for (int d = 0; d < 9; ++d) acc += a.K[(9 * c + d) * cs + v] * pd[d];
+          out[hh][q] = acc;
+        }
       }
     }
 #pragma unroll
     for (int q = 0; q < CPB; ++q) {
-      ss[q] += double(out[q]) * double(out[q]);
-      s1[q] += double(out[q]);
-      const int yp = (y < H) ? y : y - H;
-      T* slot = reinterpret_cast<T*>(&lds[q * SlabGeom<N>::PLANE +
-                                          yp * SlabGeom<N>::PITCH + z]);
-      slot[y < H ? 0 : 1] = out[q];
+#pragma unroll
+      for (int hh = 0; hh < 2; ++hh) {
+        ss[q] += double(out[hh][q]) * double(out[hh][q]);
+        s1[q] += double(out[hh][q]);
+      }
+      lds[q * SlabGeom<N>::PLANE + yp * SlabGeom<N>::PITCH + z] =
+          cplx<T>{out[0][q], out[1][q]};
     }
   }
   __syncthreads();
@@ -309,20 +315,22 @@ __device__ __forceinline__ void slab_inv_body(const SlabInvArgs<T, TO>& a,
   fft_lines<N, +1>(lds, tw, CPB * H, RowMap<N>());
 
   double acc = 0.0;
-  for (int t = threadIdx.x; t < N * N; t += blockDim.x) {
-    const int y = t / N, z = t - (t / N) * N;
-    const int64_t v = (x * N + y) * N + z;
-    const int yp = (y < H) ? y : y - H;
+  for (int t = threadIdx.x; t < H * N; t += blockDim.x) {
+    const int yp = t / N, z = t - (t / N) * N;
 #pragma unroll
     for (int q = 0; q < CPB; ++q) {
       const int c = grp * CPB + q;
       const cplx<T> zz = lds[q * SlabGeom<N>::PLANE + yp * SlabGeom<N>::PITCH + z];
-      const T val = (y < H) ? zz.x : zz.y;
-      a.out[c * cs + v] = TO(val);
-      if constexpr (DST == DST_DOT) {
-        acc += double(a.pdot[c * cs + v]) * double(val);
-      } else {
-        acc += double(val) * double(val);
+#pragma unroll
+      for (int hh = 0; hh < 2; ++hh) {
+        const int64_t v = ((int64_t)x * N + yp + hh * H) * N + z;
+        const T val = hh ? zz.y : zz.x;
+        a.out[c * cs + v] = TO(val);
+        if constexpr (DST == DST_DOT) {
+          acc += double(a.pdot[c * cs + v]) * double(val);
+        } else {
+          acc += double(val) * double(val);
+        }
       }
     }
   }
