@@ -87,6 +87,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched-RVE measurement")
     ap.add_argument("--batch-steps", type=int, default=8)
+    ap.add_argument("--large-steps", type=int, default=6,
+                    help="increments of the 128^3 RVE (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain elementwise copy of 256 MiB "
                          "(read + write), the reference kernel that scales "
@@ -216,6 +218,32 @@ def batch_run(steps, stream):
             "batched_over_one_by_one": round(t_single / t_batch, 3),
             "sigma11_max_rel_diff_vs_one_by_one": float(
                 np.max(np.abs(sig_b - sig_s)) / np.max(np.abs(sig_s)))}
+
+
+def large_run(steps, stream):
+    """The 128^3 RVE (1000 grains, 5 % particles, never seen by the
+    warm-start training): its first ``steps`` increments with the learned
+    start and, for comparison, with the homogeneous predictor; both mixed
+    precision.  The first increment has no history for the network and is
+    left out of the statistics."""
+    import torch
+    from synthetic import config_by_name
+    cfg = config_by_name("C5")
+    micro = cfg.microstructure()
+    hist = cfg.history()[:steps]
+    out = {"workload": (f"{cfg.n}^3 RVE, {cfg.grains} grains + "
+                        f"{cfg.particle_fraction:.0%} stiff particles, "
+                        f"{cfg.operator} operator, mixed, tol 1e-6, increments "
+                        f"2-{steps} of +-{cfg.eps_a:.1%} cycles")}
+    for mode in ("learned", "homogeneous"):
+        r = run_path(micro, hist, "mixed", False, steps - 1, 1, stream,
+                     live=False, learned=(mode == "learned"), start=1)
+        n3 = micro.n ** 3
+        out[mode] = dict(value=round(n3 * (steps - 1) / r["elapsed"], 1),
+                         ms_per_step=round(1e3 * r["elapsed"] / (steps - 1), 3),
+                         **predictor_stats(r["infos"]))
+    out["unit"] = "voxel-increments/s"
+    return out
 
 
 def predictor_stats(infos):
@@ -441,6 +469,9 @@ def main():
     if not args.no_batch:
         with torch.cuda.stream(stream):
             out["batch"] = batch_run(args.batch_steps, stream)
+    if args.large_steps > 1:
+        with torch.cuda.stream(stream):
+            out["large_rve"] = large_run(args.large_steps, stream)
     if calib:
         out["copy_calibration"] = calib
     if not args.no_cpu:
