@@ -35,6 +35,10 @@ __device__ __forceinline__ double cg_sum_partials(const double* partial,
 __device__ __forceinline__ void cg_scalar_update(int op, double tot,
                                                  Scalars* sc) {
   if (op == RED_INIT) {
+    sc->rrs[0] = tot;
+    sc->rrs[1] = 0.0;
+    sc->its[0] = 0;
+    sc->its[1] = -1;  // iteration 0 has no previous update
     sc->bb = tot;
     sc->rr = tot;
     sc->eta2bb = sc->eta2bb * tot;  // eta^2 was stored by the init kernel
@@ -68,6 +72,83 @@ __device__ __forceinline__ void cg_scalar_update(int op, double tot,
       sc->rr = tot;
     }
   }
+}
+
+// ---- reductions consumed by the next kernel ----------------------------------
+// Instead of a one-block reduction launch between two kernels, every block
+// of the consuming kernel sums the producer's partials itself (the same
+// fixed order as cg_sum_partials, so every block and the stand-alone
+// reduction get the same number) and takes the scalar decision locally;
+// block 0 alone publishes the result.  Iteration k (parity p = k & 1) reads
+// slot p ^ 1 and publishes slot p, so no block reads what another block of
+// the same launch writes.
+
+struct BetaStep {
+  bool first;   // iteration 0: the direction is r itself
+  bool stop;    // converged, capped or non-finite: no further work
+  double beta;
+};
+
+// In the direction kernel of parity p: reduce the r.r partials of the last
+// update (RED_BETA's decision), unless this is iteration 0.
+__device__ __forceinline__ BetaStep cg_beta_consume(const double* partial,
+                                                    int count, Scalars* sc,
+                                                    int p, double* red) {
+  BetaStep d{false, false, 0.0};
+  const int q = p ^ 1;
+  const int prev = sc->its[q];
+  if (prev < 0) {
+    d.first = true;
+    return d;
+  }
+  const int k = prev + 1;
+  const double rr = cg_sum_partials(partial, count, red);
+  const double rr_prev = sc->rrs[q];
+  const bool conv = rr <= sc->eta2bb;
+  d.stop = conv || k >= sc->max_iters || !isfinite(rr);
+  d.beta = d.stop ? 0.0 : rr / rr_prev;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->rrs[p] = rr;
+    sc->its[p] = k;
+    sc->iters = k;
+    sc->rr_new = rr;
+    sc->first = 0;
+    if (conv) sc->converged = 1;
+    if (d.stop) {
+      sc->done = 1;
+    } else {
+      sc->beta = d.beta;
+      sc->rr = rr;
+    }
+  }
+  return d;
+}
+
+struct AlphaStep {
+  bool stop;    // p.Ap <= 0 (or non-finite): breakdown
+  double alpha;
+};
+
+// In the update kernel of parity p: reduce the p.Ap partials of the inverse
+// pass (RED_ALPHA's decision).
+__device__ __forceinline__ AlphaStep cg_alpha_consume(const double* partial,
+                                                      int count, Scalars* sc,
+                                                      int p, double* red) {
+  const double pAp = cg_sum_partials(partial, count, red);
+  AlphaStep d;
+  d.stop = !(pAp > 0.0) || !isfinite(pAp);
+  d.alpha = d.stop ? 0.0 : sc->rrs[p] / pAp;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->pAp = pAp;
+    if (d.stop) {
+      sc->breakdown = 1;
+      sc->done = 1;
+      sc->iters = sc->its[p] + 1;
+    } else {
+      sc->alpha = d.alpha;
+    }
+  }
+  return d;
 }
 
 }  // namespace rve

@@ -96,6 +96,10 @@ struct Scalars {
   int32_t commit;    // batch: commit this RVE's trial state
   int32_t pad;
   double pbar[9];   // <P> of the last residual evaluation
+  // CG iteration k has parity k & 1; slot q holds r.r and the number of
+  // completed updates published by the direction kernel of parity q
+  double rrs[2];
+  int32_t its[2];
 };
 
 constexpr int kBlock = 256;

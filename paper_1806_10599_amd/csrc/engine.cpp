@@ -322,10 +322,13 @@ template <typename T, typename Run>
 void Engine::cg_iteration_steps(int parity, Run&& run) {
   const bool dbl = sizeof(T) == sizeof(double);
   T* p_new = (T*)(parity ? p0_ : p1_);
-  // p = r + beta p_old and y = K : p in one streaming pass, then G(y)
+  const int nslab = slab_blocks(n_, dbl, sched_cpb_);
+  // beta from the last update's r.r partials, p = r + beta p_old and
+  // y = K : p in one streaming pass, then G(y)
   run(7, [&] {
     launch_kp<T>((const T*)K_, (const T*)r_, (const T*)(parity ? p1_ : p0_),
-                 p_new, (T*)Kp_, sc_, N_, st_);
+                 p_new, (T*)Kp_, sc_, N_, st_, partial_red_, kRedBlocks,
+                 parity);
   });
   SpectralLaunch<T> L;
   L.src = SRC_FIELD;
@@ -350,18 +353,11 @@ void Engine::cg_iteration_steps(int parity, Run&& run) {
   } else {
     run(-1, [&] { launch_G<T>(n_, L, st_); });
   }
-  const int nslab = slab_blocks(n_, dbl, sched_cpb_);
-  run(-1, [&] {
-    launch_reduce(RED_ALPHA, partial_inv_, nslab, nullptr, nullptr, 0, 0.0,
-                  sc_, nullptr, st_);
-  });
+  // alpha from the p.Ap partials of pass C, then x += alpha p, r -= alpha Ap
   run(3, [&] {
     launch_cg_update<T>((T*)x_, (T*)r_, L.p_new, (const T*)Ap_, sc_,
-                        partial_red_, kRedBlocks, 9 * N_, st_);
-  });
-  run(-1, [&] {
-    launch_reduce(RED_BETA, partial_red_, kRedBlocks, nullptr, nullptr, 0,
-                  0.0, sc_, nullptr, st_);
+                        partial_red_, kRedBlocks, 9 * N_, st_, partial_inv_,
+                        nslab, parity);
   });
 }
 
@@ -385,6 +381,7 @@ void Engine::capture_graph() {
   if (!(timer_.mask() & kCgClasses)) {
     RVE_HIP(hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal));
     for (int j = 0; j < cfg_.cg_chunk; ++j) cg_iteration<T>(j & 1);
+    launch_cg_close(partial_red_, kRedBlocks, sc_, st_);
     RVE_HIP(hipStreamEndCapture(st_, &graph_def_));
   } else {
     RVE_HIP(hipGraphCreate(&graph_def_, 0));
@@ -394,31 +391,32 @@ void Engine::capture_graph() {
       make(&node, last ? &last : nullptr, last ? 1 : 0);
       last = node;
     };
-    for (int j = 0; j < cfg_.cg_chunk; ++j)
-      cg_iteration_steps<T>(j & 1, [&](int cls, auto&& launch) {
-        hipGraph_t child;
-        RVE_HIP(hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal));
-        launch();
-        RVE_HIP(hipStreamEndCapture(st_, &child));
-        const bool timed = cls >= 0 && timer_.on(cls);
-        KernelTimer::Pair pr{};
-        if (timed) {
-          pr = timer_.graph_pair(cls);
-          add([&](hipGraphNode_t* n, const hipGraphNode_t* d, size_t nd) {
-            RVE_HIP(hipGraphAddEventRecordNode(n, graph_def_, d, nd, pr.second.first));
-          });
-        }
+    auto step = [&](int cls, auto&& launch) {
+      hipGraph_t child;
+      RVE_HIP(hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal));
+      launch();
+      RVE_HIP(hipStreamEndCapture(st_, &child));
+      const bool timed = cls >= 0 && timer_.on(cls);
+      KernelTimer::Pair pr{};
+      if (timed) {
+        pr = timer_.graph_pair(cls);
         add([&](hipGraphNode_t* n, const hipGraphNode_t* d, size_t nd) {
-          RVE_HIP(hipGraphAddChildGraphNode(n, graph_def_, d, nd, child));
+          RVE_HIP(hipGraphAddEventRecordNode(n, graph_def_, d, nd, pr.second.first));
         });
-        RVE_HIP(hipGraphDestroy(child));
-        if (timed) {
-          add([&](hipGraphNode_t* n, const hipGraphNode_t* d, size_t nd) {
-            RVE_HIP(hipGraphAddEventRecordNode(n, graph_def_, d, nd, pr.second.second));
-          });
-          graph_pairs_.push_back(pr);
-        }
+      }
+      add([&](hipGraphNode_t* n, const hipGraphNode_t* d, size_t nd) {
+        RVE_HIP(hipGraphAddChildGraphNode(n, graph_def_, d, nd, child));
       });
+      RVE_HIP(hipGraphDestroy(child));
+      if (timed) {
+        add([&](hipGraphNode_t* n, const hipGraphNode_t* d, size_t nd) {
+          RVE_HIP(hipGraphAddEventRecordNode(n, graph_def_, d, nd, pr.second.second));
+        });
+        graph_pairs_.push_back(pr);
+      }
+    };
+    for (int j = 0; j < cfg_.cg_chunk; ++j) cg_iteration_steps<T>(j & 1, step);
+    step(-1, [&] { launch_cg_close(partial_red_, kRedBlocks, sc_, st_); });
   }
   RVE_HIP(hipGraphInstantiate(&graph_, graph_def_, nullptr, nullptr, 0));
 }
@@ -516,6 +514,7 @@ void Engine::cg_solve(int& iters, bool& breakdown) {
         cg_iteration<T>(parity);
         parity ^= 1;
       }
+      launch_cg_close(partial_red_, kRedBlocks, sc_, st_);
       RVE_HIP(hipGetLastError());
     }
     read_scalars(h);

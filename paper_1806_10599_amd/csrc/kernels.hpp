@@ -193,12 +193,20 @@ void launch_predict(double* F, const double* Fprev, const double dFbar[9],
 template <typename T>
 void launch_cg_init(const double* r64, T* r, T* x, double* partial, int nblk,
                     int64_t n9, hipStream_t s);
+// partial_in / partial: reduce the producer's partials in every block and
+// take the CG decision there (see cg_scalars.hpp); null: use the scalars
 template <typename T>
-void launch_cg_update(T* x, T* r, const T* p, const T* Ap, const Scalars* sc,
-                      double* partial, int nblk, int64_t n9, hipStream_t s);
+void launch_cg_update(T* x, T* r, const T* p, const T* Ap, Scalars* sc,
+                      double* partial, int nblk, int64_t n9, hipStream_t s,
+                      const double* partial_in = nullptr, int count_in = 0,
+                      int parity = 0);
 template <typename T>
 void launch_kp(const T* K, const T* r, const T* p_old, T* p_new, T* y,
-               const Scalars* sc, int64_t N, hipStream_t s);
+               Scalars* sc, int64_t N, hipStream_t s,
+               const double* partial = nullptr, int count = 0, int parity = 0);
+// the CG decision after the last update of a chunk (even chunk length)
+void launch_cg_close(const double* partial, int count, Scalars* sc,
+                     hipStream_t s);
 template <typename T>
 void launch_add_to_F(double* F, const T* x, int64_t n9, hipStream_t s);
 template <typename T>

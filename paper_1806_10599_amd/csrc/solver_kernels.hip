@@ -69,15 +69,26 @@ void launch_cg_init(const double* r64, T* r, T* x, double* partial, int nblk,
                      r, x, partial, n9);
 }
 
-// x += alpha p, r -= alpha Ap, partial sums of the new r.r
+// x += alpha p, r -= alpha Ap, partial sums of the new r.r.  With
+// partial_in != null the kernel first reduces the p.Ap partials of the
+// inverse pass itself (cg_alpha_consume); otherwise it takes alpha from the
+// scalars.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void cg_update_kernel(
     T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
-    const T* __restrict__ Ap, const Scalars* __restrict__ sc,
-    double* __restrict__ partial, int64_t n9) {
+    const T* __restrict__ Ap, Scalars* __restrict__ sc,
+    double* __restrict__ partial, int64_t n9,
+    const double* __restrict__ partial_in, int count_in, int parity) {
   __shared__ double red[kBlock];
   if (sc->done) return;
-  const T alpha = T(sc->alpha);
+  T alpha;
+  if (partial_in) {
+    const AlphaStep d = cg_alpha_consume(partial_in, count_in, sc, parity, red);
+    if (d.stop) return;
+    alpha = T(d.alpha);
+  } else {
+    alpha = T(sc->alpha);
+  }
   double acc = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n9;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -91,23 +102,38 @@ __global__ __launch_bounds__(kBlock) void cg_update_kernel(
 }
 
 template <typename T>
-void launch_cg_update(T* x, T* r, const T* p, const T* Ap, const Scalars* sc,
-                      double* partial, int nblk, int64_t n9, hipStream_t s) {
+void launch_cg_update(T* x, T* r, const T* p, const T* Ap, Scalars* sc,
+                      double* partial, int nblk, int64_t n9, hipStream_t s,
+                      const double* partial_in, int count_in, int parity) {
   launch((cg_update_kernel<T>), dim3(nblk), dim3(kBlock), 0, s, x, r, p, Ap,
-         sc, partial, n9);
+         sc, partial, n9, partial_in, count_in, parity);
 }
 
 // CG direction and material product (Sec. 2.1, Eqs. 15-16): per voxel
 // p = r (first iteration) or r + beta p_old, then y = K : p
-// (y_c = sum_d K[9c + d] p_d); streams K once, coalesced per component
+// (y_c = sum_d K[9c + d] p_d); streams K once, coalesced per component.
+// With partial != null the kernel first reduces the r.r partials of the last
+// update itself (cg_beta_consume); otherwise it takes first and beta from
+// the scalars.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void kp_kernel(
     const T* __restrict__ K, const T* __restrict__ r,
     const T* __restrict__ p_old, T* __restrict__ p_new, T* __restrict__ y,
-    const Scalars* __restrict__ sc, int64_t N) {
+    Scalars* __restrict__ sc, int64_t N, const double* __restrict__ partial,
+    int count, int parity) {
+  __shared__ double red[kBlock];
   if (sc->done) return;
-  const bool first = sc->first != 0;
-  const T beta = T(sc->beta);
+  bool first;
+  T beta;
+  if (partial) {
+    const BetaStep d = cg_beta_consume(partial, count, sc, parity, red);
+    if (d.stop) return;
+    first = d.first;
+    beta = T(d.beta);
+  } else {
+    first = sc->first != 0;
+    beta = T(sc->beta);
+  }
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < N;
        v += (int64_t)gridDim.x * blockDim.x) {
     T pd[9];
@@ -130,18 +156,19 @@ __global__ __launch_bounds__(kBlock) void kp_kernel(
 
 template <typename T>
 void launch_kp(const T* K, const T* r, const T* p_old, T* p_new, T* y,
-               const Scalars* sc, int64_t N, hipStream_t s) {
+               Scalars* sc, int64_t N, hipStream_t s, const double* partial,
+               int count, int parity) {
   const int64_t g = (N + kBlock - 1) / kBlock;
   launch((kp_kernel<T>), dim3((unsigned)(g < 4096 ? g : 4096)), dim3(kBlock),
-         0, s, K, r, p_old, p_new, y, sc, N);
+         0, s, K, r, p_old, p_new, y, sc, N, partial, count, parity);
 }
 
 template void launch_kp<float>(const float*, const float*, const float*,
-                               float*, float*, const Scalars*, int64_t,
-                               hipStream_t);
+                               float*, float*, Scalars*, int64_t, hipStream_t,
+                               const double*, int, int);
 template void launch_kp<double>(const double*, const double*, const double*,
-                                double*, double*, const Scalars*, int64_t,
-                                hipStream_t);
+                                double*, double*, Scalars*, int64_t,
+                                hipStream_t, const double*, int, int);
 
 template <typename T>
 __global__ void add_to_F_kernel(double* __restrict__ F,
@@ -197,6 +224,22 @@ __global__ __launch_bounds__(kBlock) void reduce_kernel(
   }
   if (threadIdx.x != 0) return;
   cg_scalar_update(op, tot, sc);
+}
+
+// End of a CG chunk: the decision the next direction kernel would take
+// (the chunk length is even, so the next iteration has parity 0), published
+// for the host.
+__global__ __launch_bounds__(kBlock) void cg_close_kernel(
+    const double* __restrict__ partial, int count, Scalars* __restrict__ sc) {
+  __shared__ double red[kBlock];
+  if (sc->done) return;
+  (void)cg_beta_consume(partial, count, sc, 0, red);
+}
+
+void launch_cg_close(const double* partial, int count, Scalars* sc,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(cg_close_kernel, dim3(1), dim3(kBlock), 0, s, partial,
+                     count, sc);
 }
 
 void launch_reduce(int op, const double* partial, int count,
@@ -366,11 +409,13 @@ template void launch_cg_init<float>(const double*, float*, float*, double*,
 template void launch_cg_init<double>(const double*, double*, double*, double*,
                                      int, int64_t, hipStream_t);
 template void launch_cg_update<float>(float*, float*, const float*,
-                                      const float*, const Scalars*, double*,
-                                      int, int64_t, hipStream_t);
+                                      const float*, Scalars*, double*, int,
+                                      int64_t, hipStream_t, const double*, int,
+                                      int);
 template void launch_cg_update<double>(double*, double*, const double*,
-                                       const double*, const Scalars*, double*,
-                                       int, int64_t, hipStream_t);
+                                       const double*, Scalars*, double*, int,
+                                       int64_t, hipStream_t, const double*,
+                                       int, int);
 template void launch_add_to_F<float>(double*, const float*, int64_t,
                                      hipStream_t);
 template void launch_add_to_F<double>(double*, const double*, int64_t,
