@@ -243,3 +243,66 @@ def test_fft_schedules_agree_and_autotune_picks_one():
                     r.set_fft_schedule(2, 8)
             finally:
                 r.close()
+
+
+def test_full_size_chosen_path_sampled_against_oracle():
+    """The 64^3 workload in the launch configuration bench.py times (mixed
+    precision, learned warm start, tuned FFT schedule): after each of the
+    first increments, sampled voxels are re-integrated by the oracle's point
+    law from the previous committed state at the GPU's converged F (FP64 on
+    both sides), and the whole-field invariants are checked with the
+    oracle's projection: ||G(P)|| <= tol ||P|| (Sec. 2.1, Eq. 11), F - F_bar
+    compatible (G(F - F_bar) = F - F_bar) and <F> = F_bar (to the FP32
+    rounding of the CG corrections)."""
+    import torch
+    from oracle import material
+    from oracle.solver import OracleRVE
+    from paper_1806_10599_amd.binding import Rve, WarmStartNet
+    from paper_1806_10599_amd.warmstart import trained_params
+    c = config_by_name("C3")
+    micro = c.microstructure()
+    hist = c.history()[:3]
+    N = micro.n ** 3
+    o = OracleRVE((micro.n,) * 3, micro.phase, micro.quat, micro.law,
+                  material_params(), c.operator)
+    net = WarmStartNet()
+    net.set_params(trained_params())
+    r = Rve(micro.n, projection=c.operator, precision="mixed", warm_start=True)
+    r.set_microstructure(micro.phase, micro.quat, micro.law, material_params())
+    r.attach_warm_start(net)
+    rng = np.random.default_rng(7)
+    try:
+        prev = {k: r.field(k) for k in ("Fpinv", "chi")}
+        for inc in hist:
+            info = r.increment(inc["F_bar"], inc["dt"])
+            assert info["status"] == 0
+            F = r.field("F").T.reshape(N, 3, 3)
+            P = r.field("P").T.reshape(N, 3, 3)
+            # point law at sampled crystal voxels
+            idx = rng.choice(o.cp_idx, size=256, replace=False)
+            g = o.phase[idx]
+            Fpi0 = prev["Fpinv"][:, idx].T.reshape(-1, 3, 3)
+            chi0 = prev["chi"][:, idx].T
+            ref = material.cp_update(F[idx], Fpi0, chi0, np.zeros((idx.size, 12)),
+                                     o.S0g[g], o.Cg[g], o.params, inc["dt"],
+                                     tangent=False)
+            assert ref["ok"].all()
+            err = np.max(np.abs(P[idx] - ref["P"])) / np.max(np.abs(ref["P"]))
+            assert err < 1e-9, err
+            dg = r.field("dgamma")[:, idx].T
+            assert np.max(np.abs(dg - ref["dg"])) <= 1e-9 * max(
+                1e-12, np.max(np.abs(ref["dg"]))) + 1e-15
+            # whole-field invariants with the oracle's projection
+            res = np.linalg.norm(o.G(P)) / np.linalg.norm(P)
+            assert res <= 1e-6 * (1 + 1e-6), res
+            Fb = np.asarray(inc["F_bar"]).reshape(3, 3)
+            fl = F - Fb[None]
+            comp = np.linalg.norm(o.G(fl) - fl) / np.linalg.norm(fl)
+            assert comp < 1e-5, comp
+            # the FP32 CG corrections have zero mean to FP32 rounding only
+            assert np.max(np.abs(F.mean(axis=0) - Fb)) < 1e-9
+            prev = {k: r.field(k) for k in ("Fpinv", "chi")}
+    finally:
+        r.attach_warm_start(None)
+        r.close()
+        net.close()
