@@ -234,7 +234,7 @@ rve_status rve_get_return_map_counts(rve_t h, int64_t out[4], int32_t reset);
 
 /* FFT schedule of the CG matvec (Sec. 2.1, Eq. 16): cpb components of the
    tensor field per slab block in the z/y-transform passes (1 or 3) and tt
-   kz columns per block in the x-transform and projection pass (8 or 16).
+   kz columns per block in the x-transform and projection pass (4, 8 or 16).
    By default (0, 0) the handle times every valid schedule once on its own
    buffers at the first CG solve and keeps the fastest.  rve_set_fft_schedule
    forces one (or (0, 0) to tune again); RVE_EINVAL when the schedule does

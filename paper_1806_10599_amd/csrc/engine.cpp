@@ -437,7 +437,7 @@ void Engine::autotune() {
   launch_kp<T>((const T*)K_, (const T*)r_, (const T*)p0_, (T*)p1_, (T*)Kp_,
                sc_, N_, st_);
   for (int cpb : {1, 3})
-    for (int tt : {8, 16}) {
+    for (int tt : {4, 8, 16}) {
       if (!schedule_valid(n_, dbl, cpb, tt)) continue;
       SpectralLaunch<T> L;
       L.src = SRC_FIELD;

@@ -64,7 +64,7 @@ struct SpectralLaunch {
   int passes = 7;   // bit 0: pass A, bit 1: pass B, bit 2: pass C
   int cpb = 0;      // components per slab block in passes A and C (1 or 3;
                     // 0: the default of the grid edge and precision)
-  int tt = 0;       // kz columns per pass-B block (8 or 16; 0: default)
+  int tt = 0;       // kz columns per pass-B block (4, 8 or 16; 0: default)
 };
 
 template <typename T>

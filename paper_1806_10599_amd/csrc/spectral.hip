@@ -573,11 +573,13 @@ void launch_G_sched(const SpectralLaunch<T>& L, hipStream_t s) {
       if constexpr (pencil_fits<T, N, 16>())
         if (tt == 16) return launch_G_passes<T, N, 3, 16>(L, s);
       if (tt == 8) return launch_G_passes<T, N, 3, 8>(L, s);
+      if (tt == 4) return launch_G_passes<T, N, 3, 4>(L, s);
     }
   } else if (cpb == 1) {
     if constexpr (pencil_fits<T, N, 16>())
       if (tt == 16) return launch_G_passes<T, N, 1, 16>(L, s);
     if (tt == 8) return launch_G_passes<T, N, 1, 8>(L, s);
+    if (tt == 4) return launch_G_passes<T, N, 1, 4>(L, s);
   }
   throw Error(-1, "unsupported FFT schedule");
 }
@@ -623,7 +625,7 @@ int pencil_blocks(int n, bool fp64, int tt_sel) {
 }
 
 bool schedule_valid(int n, bool fp64, int cpb, int tt) {
-  if (tt != 8 && tt != 16) return false;
+  if (tt != 4 && tt != 8 && tt != 16) return false;
   if (cpb != 1 && cpb != 3) return false;
   auto fits = [&](auto tag) -> bool {
     using T = decltype(tag);
@@ -631,7 +633,7 @@ bool schedule_valid(int n, bool fp64, int cpb, int tt) {
 #define RVE_FITS(NN)                                                        \
   case NN:                                                                  \
     return (cpb == 1 || cpb3_fits<T, NN>()) &&                              \
-           (tt == 8 || pencil_fits<T, NN, 16>());
+           (tt != 16 || pencil_fits<T, NN, 16>());
       RVE_FITS(16) RVE_FITS(24) RVE_FITS(32) RVE_FITS(40) RVE_FITS(48)
       RVE_FITS(64) RVE_FITS(96) RVE_FITS(128)
 #undef RVE_FITS
