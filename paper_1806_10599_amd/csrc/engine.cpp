@@ -431,14 +431,19 @@ void Engine::autotune() {
   hipEvent_t ev[2];
   RVE_HIP(hipEventCreate(&ev[0]));
   RVE_HIP(hipEventCreate(&ev[1]));
-  float best = 0.f;
-  int bc = 0, bt = 0;
+  std::vector<std::pair<int, int>> cand;
+  for (int cpb : {1, 3})
+    for (int tt : {4, 8, 16})
+      if (schedule_valid(n_, dbl, cpb, tt)) cand.push_back({cpb, tt});
   launch_bench_scalars(sc_, st_);
   launch_kp<T>((const T*)K_, (const T*)r_, (const T*)p0_, (T*)p1_, (T*)Kp_,
                sc_, N_, st_);
-  for (int cpb : {1, 3})
-    for (int tt : {4, 8, 16}) {
-      if (!schedule_valid(n_, dbl, cpb, tt)) continue;
+  // three interleaved rounds, the best of each candidate's timings: robust
+  // against clock and cache drift between candidates
+  std::vector<float> tbest(cand.size(), 0.f);
+  constexpr int reps = 4;
+  for (int round = 0; round < 3; ++round)
+    for (size_t c = 0; c < cand.size(); ++c) {
       SpectralLaunch<T> L;
       L.src = SRC_FIELD;
       L.in_field = (const T*)Kp_;
@@ -450,9 +455,8 @@ void Engine::autotune() {
       L.out_T = (T*)Ap_;
       L.partial_inv = partial_inv_;
       L.sc = sc_;
-      L.cpb = cpb;
-      L.tt = tt;
-      constexpr int reps = 4;
+      L.cpb = cand[c].first;
+      L.tt = cand[c].second;
       launch_G<T>(n_, L, st_);  // untimed first launch
       RVE_HIP(hipEventRecord(ev[0], st_));
       for (int i = 0; i < reps; ++i) launch_G<T>(n_, L, st_);
@@ -460,11 +464,15 @@ void Engine::autotune() {
       RVE_HIP(hipEventSynchronize(ev[1]));
       float t = 0.f;
       RVE_HIP(hipEventElapsedTime(&t, ev[0], ev[1]));
-      if (bc == 0 || t < best) {
-        best = t;
-        bc = cpb;
-        bt = tt;
-      }
+      if (round == 0 || t < tbest[c]) tbest[c] = t;
+    }
+  float best = 0.f;
+  int bc = 0, bt = 0;
+  for (size_t c = 0; c < cand.size(); ++c)
+    if (bc == 0 || tbest[c] < best) {
+      best = tbest[c];
+      bc = cand[c].first;
+      bt = cand[c].second;
     }
   hipEventDestroy(ev[0]);
   hipEventDestroy(ev[1]);

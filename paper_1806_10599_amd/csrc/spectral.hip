@@ -206,6 +206,9 @@ __device__ __forceinline__ void pencil_body(const PencilArgs<T>& a, int lb,
                                             cplx<T>* lds, cplx<T>* tw) {
   constexpr int H = N / 2;
   constexpr int TP = TT + 1;  // LDS pitch of a kx row (complex)
+  // component planes of the pencil start TT slots apart in the LDS banks, so
+  // that the lines of the three components do not share banks
+  constexpr int CPS = N * TP + TT;
   constexpr int NTILE = (H + TT - 1) / TT;
   const int i = lb % 3;
   const int rest = lb / 3;
@@ -232,13 +235,13 @@ __device__ __forceinline__ void pencil_body(const PencilArgs<T>& a, int lb,
     cplx<T> val = {T(0), T(0)};
     if (tt < ncol)
       val = a.spec[((size_t)((3 * i + j) * N + kx) * N + ky) * H + kz0 + tt];
-    lds[(j * N + kx) * TP + tt] = val;
+    lds[j * CPS + kx * TP + tt] = val;
   }
   __syncthreads();
   auto pm = [](int line, int kx) {
     const int j = line / TT;
     const int tt = line - j * TT;
-    return (j * N + kx) * TP + tt;
+    return j * CPS + kx * TP + tt;
   };
   fft_lines<N, -1>(lds, tw, 3 * TT, pm);
 
@@ -252,14 +255,14 @@ __device__ __forceinline__ void pencil_body(const PencilArgs<T>& a, int lb,
     const bool zero = (kx == H) || (tt >= ncol) || (kx == 0 && ky == 0 && kz == 0);
     const T nrm = v1 * v1 + v2 * v2 + v3 * v3;
     const T inv = zero ? T(0) : a.invN3 / nrm;
-    cplx<T> A0 = lds[(0 * N + kx) * TP + tt];
-    cplx<T> A1 = lds[(1 * N + kx) * TP + tt];
-    cplx<T> A2 = lds[(2 * N + kx) * TP + tt];
+    cplx<T> A0 = lds[0 * CPS + kx * TP + tt];
+    cplx<T> A1 = lds[1 * CPS + kx * TP + tt];
+    cplx<T> A2 = lds[2 * CPS + kx * TP + tt];
     cplx<T> s = {(A0.x * v1 + A1.x * v2 + A2.x * v3) * inv,
                  (A0.y * v1 + A1.y * v2 + A2.y * v3) * inv};
-    lds[(0 * N + kx) * TP + tt] = {v1 * s.x, v1 * s.y};
-    lds[(1 * N + kx) * TP + tt] = {v2 * s.x, v2 * s.y};
-    lds[(2 * N + kx) * TP + tt] = {v3 * s.x, v3 * s.y};
+    lds[0 * CPS + kx * TP + tt] = {v1 * s.x, v1 * s.y};
+    lds[1 * CPS + kx * TP + tt] = {v2 * s.x, v2 * s.y};
+    lds[2 * CPS + kx * TP + tt] = {v3 * s.x, v3 * s.y};
   }
   __syncthreads();
   fft_lines<N, +1>(lds, tw, 3 * TT, pm);
@@ -269,7 +272,7 @@ __device__ __forceinline__ void pencil_body(const PencilArgs<T>& a, int lb,
     const int kx = rem / TT, tt = rem - (rem / TT) * TT;
     if (tt < ncol)
       a.spec[((size_t)((3 * i + j) * N + kx) * N + ky) * H + kz0 + tt] =
-          lds[(j * N + kx) * TP + tt];
+          lds[j * CPS + kx * TP + tt];
   }
 }
 
@@ -349,7 +352,7 @@ struct SpectralTraits {
   static constexpr size_t SLAB_LDS =
       (CPB * SlabGeom<N>::PLANE + N) * sizeof(cplx<T>) + kBlock * sizeof(double);
   static constexpr size_t PENCIL_LDS =
-      (3 * N * (TT + 1) + N) * sizeof(cplx<T>);
+      (3 * (N * (TT + 1) + TT) + N) * sizeof(cplx<T>);
 };
 
 // ---------------------------------------------------- single-RVE kernels
@@ -364,7 +367,7 @@ __global__ __launch_bounds__(kBlock) void slab_fwd_kernel(SlabFwdArgs<T> a) {
 
 template <typename T, int N, int TT>
 __global__ __launch_bounds__(kBlock) void pencil_proj_kernel(PencilArgs<T> a) {
-  __shared__ cplx<T> lds[3 * N * (TT + 1)];
+  __shared__ cplx<T> lds[3 * (N * (TT + 1) + TT)];
   __shared__ cplx<T> tw[N];
   if (a.sc && a.sc->done) return;
   pencil_body<T, N, TT>(a, xcd_remap(blockIdx.x, gridDim.x), lds, tw);
@@ -447,7 +450,7 @@ __global__ __launch_bounds__(kBlock) void pencil_batch_kernel(BatchSpec<T> b,
     constexpr int TT = SpectralTraits<T, NN>::TT;                            \
     a.invN3 = T(1.0 / (double(NN) * NN * NN));                               \
     cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem);                         \
-    pencil_body<T, NN, TT>(a, lb, lds, lds + 3 * NN * (TT + 1));             \
+    pencil_body<T, NN, TT>(a, lb, lds, lds + 3 * (NN * (TT + 1) + TT));             \
   } break;
     RVE_BATCH_SIZES(RVE_CASE)
 #undef RVE_CASE
@@ -492,7 +495,7 @@ constexpr bool cpb3_fits() {
 }
 template <typename T, int N, int TT>
 constexpr bool pencil_fits() {
-  return (3 * N * (TT + 1) + N) * (int)sizeof(cplx<T>) <= 64 * 1024;
+  return (3 * (N * (TT + 1) + TT) + N) * (int)sizeof(cplx<T>) <= 64 * 1024;
 }
 
 template <typename T, int N, int CPB, int TT>
