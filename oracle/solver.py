@@ -35,7 +35,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import crystal, material
+from . import crystal, material, umat
 from .projection import apply_G
 
 OK, EINVAL, ENOTCONV, ELOCAL = 0, -1, -4, -5
@@ -255,6 +255,49 @@ class OracleRVE:
         """Voxel Cauchy stress sigma = P F^T / det F."""
         J = np.linalg.det(self.F)
         return self.P @ np.swapaxes(self.F, 1, 2) / J[:, None, None]
+
+
+class OracleUmatRVE(OracleRVE):
+    """The same increment algorithm with a user material in the form of a
+    commercial FE code's subroutine (Appendix A): the material returns the
+    Cauchy stress and the Jaumann-rate tangent from (F at t_k, F at t_k-1,
+    state variables at t_k-1, dt); P follows from Eq. A.1 and K from
+    Eq. A.16.  State variables are committed with the increment; the
+    fatigue indicators of the crystal law are not defined for such a
+    material and stay zero.
+
+    ``umat(F1, F0, statev, dt) -> (sigma6, ddsdde, statev_new, ok)``.
+    """
+
+    def __init__(self, shape, umat_fn, statev0, operator="continuous",
+                 L=(1.0, 1.0, 1.0)):
+        self.shape = tuple(int(s) for s in shape)
+        self.N = int(np.prod(self.shape))
+        self.umat = umat_fn
+        self.statev0 = np.array(statev0, dtype=np.float64).reshape(self.N, -1)
+        self.operator = operator
+        self.L = tuple(float(x) for x in L)
+        self.reset()
+
+    def reset(self):
+        super().reset()
+        self.statev = self.statev0.copy()
+
+    def constitutive(self, F, dt, dg_start):
+        s6, D, sv, ok = self.umat(F, self.F, self.statev, dt)
+        sig = umat.sym_from_voigt(s6)
+        P = umat.piola_from_cauchy(F, sig)
+        K = umat.tangent_from_jaumann(F, sig, umat.tensor_from_voigt(D))
+        trial = dict(statev=sv, dg=np.zeros((self.N, 12)))
+        return P, K, trial, int(np.count_nonzero(~ok))
+
+    def _commit(self, F, F_bar_new, P, trial, dt):
+        self.F = F
+        self.F_bar = F_bar_new.copy()
+        self.statev = trial["statev"]
+        self.P = P
+        self.t += dt
+        self.increments += 1
 
 
 def run_history(rve: OracleRVE, history, tol=1e-6, eta=1e-4, newton_max=25,
