@@ -94,6 +94,8 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=8)
     ap.add_argument("--large-steps", type=int, default=6,
                     help="increments of the 128^3 RVE (0: skip)")
+    ap.add_argument("--no-umat", action="store_true",
+                    help="skip the Appendix A bridge measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain elementwise copy of 256 MiB "
                          "(read + write), the reference kernel that scales "
@@ -249,6 +251,41 @@ def large_run(steps, stream):
                          **predictor_stats(r["infos"]))
     out["unit"] = "voxel-increments/s"
     return out
+
+
+# Appendix A bridge: FP64 reads F (9), sigma (6), ddsdde (36) and writes
+# P (9), K (81) per voxel
+UMAT_BYTES = 8 * (9 + 6 + 36 + 9 + 81)
+
+
+def umat_run(stream, n=128 ** 3, calls=20):
+    """The Appendix A bridge on n voxels of a user material's output (Cauchy
+    stress and Jaumann-rate tangent): mean duration of one call from HIP
+    events on the launch stream, against HBM bandwidth."""
+    import torch
+    from paper_1806_10599_amd.binding import umat_bridge
+    g = torch.Generator(device="cuda").manual_seed(0)
+    with torch.cuda.stream(stream):
+        F = torch.eye(3, dtype=torch.float64, device="cuda").reshape(9, 1) + \
+            0.15 * torch.randn((9, n), dtype=torch.float64, device="cuda",
+                               generator=g)
+        sig = torch.randn((6, n), dtype=torch.float64, device="cuda", generator=g)
+        D = torch.randn((36, n), dtype=torch.float64, device="cuda", generator=g)
+        umat_bridge(F, sig, D, stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(
+            enable_timing=True)
+        e0.record(stream)
+        for _ in range(calls):
+            umat_bridge(F, sig, D, stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    us = 1e3 * e0.elapsed_time(e1) / calls
+    gbs = UMAT_BYTES * n / (us * 1e-6) / 1e9
+    return {"workload": f"{n} voxels, FP64 (F, sigma, 6x6 tangent -> P, K)",
+            "us_per_call": round(us, 2), "bytes_per_voxel": UMAT_BYTES,
+            "voxels_per_s": round(n / (us * 1e-6), 1),
+            "achieved_GBps": round(gbs, 1), "peak_GBps": HBM_PEAK_GBS,
+            "frac": round(gbs / HBM_PEAK_GBS, 3)}
 
 
 def predictor_stats(infos):
@@ -480,6 +517,8 @@ def main():
     if args.large_steps > 1:
         with torch.cuda.stream(stream):
             out["large_rve"] = large_run(args.large_steps, stream)
+    if not args.no_umat:
+        out["umat_bridge"] = umat_run(stream)
     if calib:
         out["copy_calibration"] = calib
     if not args.no_cpu:

@@ -134,6 +134,57 @@ rve_status rve_set_microstructure(rve_t h, const int32_t* phase, int32_t G,
                                   const double* quat, const int32_t* law,
                                   const double* params, int32_t nparams);
 
+/* User material in the form of a commercial FE code's finite-strain user
+   subroutine (Appendix A; Sec. 2.3 of the paper describes plugging such
+   subroutines into the solver).  The solver calls fn at every constitutive
+   evaluation of the increment algorithm with device pointers, structure-of-
+   arrays over the n voxels (component c of voxel v at c*n + v), float64:
+     F1 [9][n]         deformation gradient at t_k (row-major 3x3)
+     F0 [9][n]         committed deformation gradient at t_k-1
+     statev_old [nstatev][n]  committed state variables (read only)
+     statev_new [nstatev][n]  trial state variables (write every entry)
+     sigma [6][n]      Cauchy stress at t_k, order 11, 22, 33, 12, 13, 23
+     ddsdde [36][n]    6x6 tangent of the Jaumann rate of the Kirchhoff stress
+                       divided by J (Eq. A.2), entry (I, J) at (6 I + J) n + v,
+                       engineering shear strains
+     fails             device int32 counter: add 1 per voxel whose update failed
+   dt is the time step; stream the hipStream_t on which fn must enqueue its
+   work (it must not synchronize the device or read the outputs back).  fn
+   returns 0 when the work was enqueued, anything else is an error
+   (RVE_EDEVICE from the increment).  The library then forms P (Eq. A.1) and,
+   before each linear solve, K (Eq. A.16).  The pointers are valid only
+   during the call; the library owns them.  State variables are committed
+   with the increment (rolled back on RVE_ENOTCONV / RVE_ELOCAL). */
+typedef int32_t (*rve_umat_fn)(void* user, const double* F1, const double* F0,
+                               const double* statev_old, double* statev_new,
+                               int32_t nstatev, double* sigma, double* ddsdde,
+                               int32_t* fails, int64_t n, double dt,
+                               void* stream);
+
+/* Uses fn for every voxel in place of the crystal-plasticity microstructure
+   (user is passed through to fn).  statev0: host [nstatev][N] initial state
+   variables (may be NULL when nstatev = 0), 0 <= nstatev <= 1024.  Resets
+   the state to F = I, P = 0, t = 0.  The fatigue indicator fields stay zero,
+   the learned warm start is not used, and the crystal-only entry points
+   (rve_debug_constitutive, rve_bench_kernels, rve_ws_features and the FPINV,
+   CHI and DGAMMA fields) return RVE_ESTATE until rve_set_microstructure is
+   called again.  Checkpoint blobs then also hold the state variables.
+   Errors: RVE_EINVAL (null fn, nstatev out of range, null statev0),
+   RVE_ENOMEM. */
+rve_status rve_set_user_material(rve_t h, rve_umat_fn fn, void* user,
+                                 int32_t nstatev, const double* statev0);
+
+/* The example user material shipped with the library, an rve_umat_fn: a
+   compressible neo-Hookean solid, tau = mu (B - I) + lambda ln J I, with its
+   exact Jaumann tangent.  State variables (nstatev >= 3): 0 mu, 1 lambda
+   (per voxel, MPa), 2 the sum over converged increments of |J - J_prev|.
+   user is ignored; returns 0, or -1 for nstatev < 3 or a launch failure.
+   A voxel with det F1 <= 0 counts as a failure. */
+int32_t rve_umat_neo_hooke(void* user, const double* F1, const double* F0,
+                           const double* statev_old, double* statev_new,
+                           int32_t nstatev, double* sigma, double* ddsdde,
+                           int32_t* fails, int64_t n, double dt, void* stream);
+
 /* One load increment to the macroscopic gradient F_bar_new[9] (row-major)
    over the time step dt (Sec. 2.1, Eqs. 12-16 and the end of Sec. 2.1).
    Predictor F = F_prev + (F_bar_new - F_bar_prev) (plus the projected
@@ -157,7 +208,8 @@ enum {
   RVE_FIELD_PCYC = 6,      /* [N] accumulated plastic slip, sum sqrt(2/3 dLp:dLp) */
   RVE_FIELD_PCYC_LIT = 7,  /* [N] sum dLp:dLp / dt (Eq. 23 integrand)         */
   RVE_FIELD_WCYC = 8,      /* [12][N] plastic work per system (Eq. 24), MPa   */
-  RVE_FIELD_COUNT = 9
+  RVE_FIELD_STATEV = 9,    /* [nstatev][N] committed user-material state      */
+  RVE_FIELD_COUNT = 10
 };
 
 /* Copies one committed field (float64, layout above) into dst (host, or
@@ -170,7 +222,8 @@ rve_status rve_get_fields(rve_t h, int32_t field, void* dst, size_t dst_bytes,
 rve_status rve_get_macro(rve_t h, double out[29]);
 
 /* Checkpoint: the committed state (F, Fp^-1, chi, dgamma, indicators, macro
-   state, counters) as an opaque little-endian blob.  rve_state_size gives
+   state, counters; user-material state variables) as an opaque
+   little-endian blob.  rve_state_size gives
    the byte count; rve_set_state restores a blob from the same grid. */
 rve_status rve_state_size(rve_t h, size_t* bytes);
 rve_status rve_get_state(rve_t h, void* dst, size_t bytes);
@@ -295,6 +348,25 @@ const char* rve_ws_last_error(rve_ws_t w);
 rve_status rve_attach_warm_start(rve_t h, rve_ws_t w);
 rve_status rve_ws_features(rve_t h, const double F_bar_new[9], uint16_t* X);
 rve_status rve_ws_target(rve_t h, float* T);
+
+/* ---- user materials of commercial FE codes (Appendix A) -----------------
+   rve_umat_bridge converts, voxel by voxel, the output of a finite-strain
+   user material written for a commercial FE code -- the Cauchy stress and
+   the tangent of the Jaumann rate of the Kirchhoff stress (Appendix A,
+   Eq. A.2), both in the component order 11, 22, 33, 12, 13, 23 with
+   engineering shear strains -- into the first Piola-Kirchhoff stress
+   P = J sigma F^-T (Eq. A.1) and the tangent K = dP/dF of the FFT solver
+   (Eq. A.16).  All arrays are caller-owned device memory, float64,
+   structure-of-arrays over n voxels: F [9][n] (row-major 3x3 per voxel),
+   sigma [6][n], ddsdde [36][n] (6x6 row-major per voxel: entry (I, J) at
+   (6 I + J) n + v), outputs P [9][n] and K [81][n] (component
+   9 (3i+j) + (3k+l) = dP_ij/dF_kl).  The work is enqueued on stream
+   (hipStream_t, NULL = default stream); the call returns after enqueueing.
+   n = 0 does nothing.  Errors: RVE_EINVAL (null pointer, n < 0),
+   RVE_EDEVICE (launch failure); rve_last_error(NULL) describes them. */
+rve_status rve_umat_bridge(const double* F, const double* sigma,
+                           const double* ddsdde, int64_t n, double* P,
+                           double* K, void* stream);
 
 /* ---- batches of RVEs ------------------------------------------------------
    count independent RVEs (1 <= count <= 255), each with its own cubic grid

@@ -28,7 +28,7 @@ PROJ = {"continuous": 0, "discrete": 1}
 PREC = {"fp64": 0, "mixed": 1}
 FIELDS = {"F": (0, 9), "P": (1, 9), "sigma": (2, 9), "Fpinv": (3, 9),
           "chi": (4, 12), "dgamma": (5, 12), "pcyc": (6, 1),
-          "pcyc_lit": (7, 1), "wcyc": (8, 12)}
+          "pcyc_lit": (7, 1), "wcyc": (8, 12), "statev": (9, None)}
 NPARAMS = 10
 MAX_NEWTON_LOG = 64
 KERNEL_CLASSES = ("matvec_pass_a", "matvec_pass_b", "matvec_pass_c",
@@ -36,6 +36,12 @@ KERNEL_CLASSES = ("matvec_pass_a", "matvec_pass_b", "matvec_pass_c",
                   "matvec_kp")
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+# user material (Appendix A form): (user, F1, F0, statev_old, statev_new,
+# nstatev, sigma, ddsdde, fails, n, dt, stream) -> 0 when enqueued
+UMAT_FN = C.CFUNCTYPE(C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                      C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                      C.c_void_p, C.c_void_p, C.c_int64, C.c_double,
+                      C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 
@@ -129,6 +135,17 @@ def _load():
         "rve_attach_warm_start": (C.c_int, [C.c_void_p, C.c_void_p]),
         "rve_ws_features": (C.c_int, [C.c_void_p, P(C.c_double), C.c_void_p]),
         "rve_ws_target": (C.c_int, [C.c_void_p, C.c_void_p]),
+        "rve_set_user_material": (C.c_int, [C.c_void_p, UMAT_FN, C.c_void_p,
+                                            C.c_int32, P(C.c_double)]),
+        "rve_umat_neo_hooke": (C.c_int32, [C.c_void_p, C.c_void_p,
+                                           C.c_void_p, C.c_void_p,
+                                           C.c_void_p, C.c_int32,
+                                           C.c_void_p, C.c_void_p,
+                                           C.c_void_p, C.c_int64,
+                                           C.c_double, C.c_void_p]),
+        "rve_umat_bridge": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_int64, C.c_void_p, C.c_void_p,
+                                      C.c_void_p]),
         "rve_batch_create": (C.c_int, [P(RveConfig), C.c_int32, P(C.c_int32),
                                        P(C.c_void_p)]),
         "rve_batch_destroy": (C.c_int, [C.c_void_p]),
@@ -153,6 +170,8 @@ def _load():
 
 
 LIB = _load()
+# the example user material of the library, as a function pointer
+NEO_HOOKE_UMAT = UMAT_FN(("rve_umat_neo_hooke", LIB))
 
 
 class RveError(RuntimeError):
@@ -294,6 +313,38 @@ class Rve:
         self._check(LIB.rve_set_microstructure(
             self._h, _iptr(phase), quat.shape[0], _dptr(quat), _iptr(law),
             _dptr(params), params.size))
+        self._nsv = 0
+
+    def set_user_material(self, material, statev0=None, user=None):
+        """Use a user material of the Appendix A form for every voxel.
+
+        ``material``: "neo_hooke" (the library's example material, whose
+        state variables are mu, lambda and the accumulated |dJ|), a
+        ``UMAT_FN`` function pointer, or a Python callable with the
+        ``UMAT_FN`` arguments (device pointers as integers) that enqueues its
+        work on the given stream.  ``statev0``: (nstatev, N) initial state
+        variables."""
+        if isinstance(material, str):
+            if material != "neo_hooke":
+                raise ValueError(f"unknown built-in user material {material!r}")
+            fn = NEO_HOOKE_UMAT
+        elif isinstance(material, UMAT_FN):
+            fn = material
+        elif callable(material):
+            fn = UMAT_FN(material)
+        else:
+            raise TypeError("material must be a name, a UMAT_FN or a callable")
+        if statev0 is None:
+            sv = np.zeros((0, self.N))
+        else:
+            sv = np.ascontiguousarray(statev0, dtype=np.float64)
+            if sv.ndim != 2 or sv.shape[1] != self.N:
+                raise ValueError("statev0 must have shape (nstatev, N)")
+        self._check(LIB.rve_set_user_material(
+            self._h, fn, C.c_void_p(user), sv.shape[0],
+            _dptr(sv) if sv.size else None))
+        self._umat = fn          # keep the callback alive
+        self._nsv = sv.shape[0]
 
     def increment(self, F_bar, dt):
         """One load increment; returns a dict (status included, no raise on
@@ -310,6 +361,12 @@ class Rve:
 
     def field(self, name):
         fid, comps = FIELDS[name]
+        if comps is None:
+            comps = getattr(self, "_nsv", 0)
+            out = np.empty((comps, self.N), dtype=np.float64)
+            self._check(LIB.rve_get_fields(self._h, fid, out.ctypes.data_as(
+                C.c_void_p), out.nbytes, 0))
+            return out
         out = np.empty((comps, self.N), dtype=np.float64)
         self._check(LIB.rve_get_fields(self._h, fid, out.ctypes.data_as(
             C.c_void_p), out.nbytes, 0))
@@ -434,6 +491,31 @@ class Rve:
 
 WS_FEAT = 48
 WS_OUT = 16
+
+
+def umat_bridge(F, sigma, ddsdde, stream=None):
+    """Appendix A: P and K from the Cauchy stress and the Jaumann-rate tangent
+    of a commercial-FE-style user material.  Inputs: float64 CUDA tensors of
+    shapes (9, n), (6, n), (36, n); returns P (9, n) and K (81, n)."""
+    for t, rows in ((F, 9), (sigma, 6), (ddsdde, 36)):
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+                and t.dim() == 2 and t.shape[0] == rows):
+            raise ValueError("expected contiguous float64 CUDA tensors of "
+                             "shapes (9, n), (6, n), (36, n)")
+    n = F.shape[1]
+    if sigma.shape[1] != n or ddsdde.shape[1] != n:
+        raise ValueError("inconsistent voxel counts")
+    P = torch.empty((9, n), dtype=torch.float64, device=F.device)
+    K = torch.empty((81, n), dtype=torch.float64, device=F.device)
+    st = stream if stream is not None else torch.cuda.current_stream()
+    rc = LIB.rve_umat_bridge(C.c_void_p(F.data_ptr()),
+                             C.c_void_p(sigma.data_ptr()),
+                             C.c_void_p(ddsdde.data_ptr()), n,
+                             C.c_void_p(P.data_ptr()), C.c_void_p(K.data_ptr()),
+                             C.c_void_p(st.cuda_stream or None))
+    if rc != RVE_OK:
+        raise RveError(rc, LIB.rve_last_error(None).decode())
+    return P, K
 
 
 class BatchRve:

@@ -110,6 +110,26 @@ rve_status rve_set_microstructure(rve_t h, const int32_t* phase, int32_t G,
   });
 }
 
+rve_status rve_set_user_material(rve_t h, rve_umat_fn fn, void* user,
+                                 int32_t nstatev, const double* statev0) {
+  return guarded(h, [&] {
+    h->eng->set_user_material(fn, user, nstatev, statev0);
+    return RVE_OK;
+  });
+}
+
+int32_t rve_umat_neo_hooke(void* user, const double* F1, const double* F0,
+                           const double* statev_old, double* statev_new,
+                           int32_t nstatev, double* sigma, double* ddsdde,
+                           int32_t* fails, int64_t n, double dt, void* stream) {
+  (void)user;
+  (void)dt;
+  if (nstatev < 3 || n < 0) return -1;
+  rve::launch_neo_hooke_umat(F1, F0, statev_old, statev_new, nstatev, sigma,
+                             ddsdde, fails, n, (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 rve_status rve_apply_macro_strain_increment(rve_t h, const double F_bar_new[9],
                                             double dt,
                                             rve_increment_info* info) {
@@ -349,6 +369,22 @@ rve_status rve_get_fft_schedule(rve_t h, int32_t out[2], double* ms) {
     out[1] = o[1];
     return RVE_OK;
   });
+}
+
+rve_status rve_umat_bridge(const double* F, const double* sigma,
+                           const double* ddsdde, int64_t n, double* P,
+                           double* K, void* stream) {
+  if (n < 0 || (n > 0 && (!F || !sigma || !ddsdde || !P || !K))) {
+    g_create_error = "rve_umat_bridge: null pointer or n < 0";
+    return RVE_EINVAL;
+  }
+  rve::launch_umat_bridge(F, sigma, ddsdde, n, P, K, (hipStream_t)stream);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    g_create_error = std::string("rve_umat_bridge: ") + hipGetErrorString(e);
+    return RVE_EDEVICE;
+  }
+  return RVE_OK;
 }
 
 rve_status rve_batch_create(const rve_config* cfg, int32_t count,

@@ -214,6 +214,14 @@ void Engine::set_microstructure(const int32_t* phase, int32_t G,
   launch_fill_f64(dFt_prev_, 0.0, 9 * N_, st_);
   RVE_HIP(hipGetLastError());
   RVE_HIP(hipStreamSynchronize(st_));
+  reset_macro_state();
+  umat_fn_ = nullptr;
+  umat_user_ = nullptr;
+  nsv_ = 0;
+  have_micro_ = true;
+}
+
+void Engine::reset_macro_state() {
   for (int i = 0; i < 9; ++i) {
     Fbar_[i] = (i % 4 == 0) ? 1.0 : 0.0;
     Pbar_[i] = 0.0;
@@ -223,6 +231,46 @@ void Engine::set_microstructure(const int32_t* phase, int32_t G,
   s_prev_ = 0.0;
   t_ = 0.0;
   increments_ = 0;
+}
+
+void Engine::require_crystal(const char* what) const {
+  if (umat_fn_)
+    throw Error(RVE_ESTATE, std::string(what) +
+                                " needs the crystal-plasticity microstructure, "
+                                "not a user material");
+}
+
+void Engine::set_user_material(rve_umat_fn fn, void* user, int32_t nstatev,
+                               const double* statev0) {
+  if (!fn) throw Error(RVE_EINVAL, "null user material");
+  if (nstatev < 0 || nstatev > 1024) throw Error(RVE_EINVAL, "nstatev out of [0, 1024]");
+  if (nstatev > 0 && !statev0) throw Error(RVE_EINVAL, "null initial state variables");
+  if (!usig_) {
+    usig_ = (double*)alloc(6 * N_ * sizeof(double));
+    udds_ = (double*)alloc(36 * N_ * sizeof(double));
+  }
+  if (nstatev > nsv_cap_) {
+    sv_c_ = (double*)alloc(nstatev * N_ * sizeof(double));
+    sv_t_ = (double*)alloc(nstatev * N_ * sizeof(double));
+    nsv_cap_ = nstatev;
+  }
+  if (nstatev > 0)
+    RVE_HIP(hipMemcpyAsync(sv_c_, statev0, nstatev * N_ * sizeof(double),
+                           hipMemcpyHostToDevice, st_));
+  // F = I, P = 0, indicators 0 (not defined for a user material)
+  launch_fill_f64(Fprev_, 0.0, 9 * N_, st_);
+  for (int c = 0; c < 9; c += 4) launch_fill_f64(Fprev_ + c * N_, 1.0, N_, st_);
+  launch_fill_f64(Pc_, 0.0, 9 * N_, st_);
+  launch_fill_f64(pcyc_, 0.0, N_, st_);
+  launch_fill_f64(pcyc_lit_, 0.0, N_, st_);
+  launch_fill_f64(wcyc_, 0.0, 12 * N_, st_);
+  launch_fill_f64(dFt_prev_, 0.0, 9 * N_, st_);
+  RVE_HIP(hipGetLastError());
+  RVE_HIP(hipStreamSynchronize(st_));
+  reset_macro_state();
+  umat_fn_ = fn;
+  umat_user_ = user;
+  nsv_ = nstatev;
   have_micro_ = true;
 }
 
@@ -281,10 +329,19 @@ int Engine::evaluate(const double* dg_start, double dt, double& rel,
   a.evals = timer_.on(4) ? rm_evals_ : nullptr;
   a.lp = law_params(dt);
   a.N = N_;
-  timer_.begin(4, st_);
-  launch_return_map(a, st_);
-  timer_.end(4, st_);
-  if (a.iters) launch_rm_count(rm_iters_, rm_evals_, N_, rm_stats_, st_);
+  if (umat_fn_) {
+    // user material: sigma and its Jaumann tangent, then P (Eq. A.1)
+    const int32_t rc = umat_fn_(umat_user_, F_, Fprev_, sv_c_, sv_t_, nsv_,
+                                usig_, udds_, &sc_->fails, N_, dt, (void*)st_);
+    if (rc != 0)
+      throw Error(RVE_EDEVICE, "user material returned " + std::to_string(rc));
+    launch_umat_piola(F_, usig_, N_, P_, st_);
+  } else {
+    timer_.begin(4, st_);
+    launch_return_map(a, st_);
+    timer_.end(4, st_);
+    if (a.iters) launch_rm_count(rm_iters_, rm_evals_, N_, rm_stats_, st_);
+  }
   timer_.begin_span(6, st_);
   residual_passes(P_);
   timer_.end_span(6, st_);
@@ -311,6 +368,11 @@ void Engine::tangent(double dt) {
   a.K = (T*)K_;
   a.lp = law_params(dt);
   a.N = N_;
+  if (umat_fn_) {
+    // user material: K from the last evaluation's sigma and tangent (Eq. A.16)
+    launch_umat_tangent<T>(F_, usig_, udds_, N_, (T*)K_, st_);
+    return;
+  }
   timer_.begin(5, st_);
   launch_tangent<T>(a, st_);
   timer_.end(5, st_);
@@ -546,7 +608,10 @@ void Engine::commit(double dt) {
   c.wcyc = wcyc_;
   c.dt = dt;
   c.N = N_;
-  launch_commit(c, st_);
+  if (umat_fn_)
+    std::swap(sv_c_, sv_t_);
+  else
+    launch_commit(c, st_);
   RVE_HIP(hipMemcpyAsync(Pc_, P_, 9 * N_ * sizeof(double),
                          hipMemcpyDeviceToDevice, st_));
   RVE_HIP(hipGetLastError());
@@ -574,7 +639,7 @@ int Engine::increment(const double Fbar_new[9], double dt,
   double rel = 0, res = 0, pn = 0;
   int status = RVE_ENOTCONV;
   int pre_fails = -1;
-  if (net_ && cfg_.warm_start && learned_candidate(Fbar_new)) {
+  if (net_ && cfg_.warm_start && !umat_fn_ && learned_candidate(Fbar_new)) {
     // learned candidate in F2_: evaluate it, stash it, evaluate the plain
     // predictor, keep the one with the smaller FP64 residual
     std::swap(F_, F2_);
@@ -688,13 +753,22 @@ void Engine::get_field(int field, void* dst, size_t bytes, bool on_device) {
     case RVE_FIELD_FPINV: src = Fpi_c_; need = 9; break;
     case RVE_FIELD_CHI: src = chi_c_; need = 12; break;
     case RVE_FIELD_DGAMMA: src = dg_c_; need = 12; break;
+    case RVE_FIELD_STATEV:
+      if (!umat_fn_) throw Error(RVE_ESTATE, "no user material set");
+      src = sv_c_;
+      need = (size_t)nsv_;
+      break;
     case RVE_FIELD_PCYC: src = pcyc_; need = 1; break;
     case RVE_FIELD_PCYC_LIT: src = pcyc_lit_; need = 1; break;
     case RVE_FIELD_WCYC: src = wcyc_; need = 12; break;
     default: throw Error(RVE_EINVAL, "unknown field id");
   }
+  if (umat_fn_ && (field == RVE_FIELD_FPINV || field == RVE_FIELD_CHI ||
+                   field == RVE_FIELD_DGAMMA))
+    throw Error(RVE_ESTATE, "crystal-plasticity field requested with a user material");
   need *= N_ * sizeof(double);
   if (bytes < need) throw Error(RVE_EINVAL, "destination too small");
+  if (need == 0) return;
   RVE_HIP(hipMemcpyAsync(dst, src, need,
                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                          st_));
@@ -718,7 +792,7 @@ void Engine::get_macro(double out[29]) {
 }
 
 size_t Engine::state_size() const {
-  return sizeof(StateHeader) + (size_t)65 * N_ * sizeof(double);
+  return sizeof(StateHeader) + (size_t)(65 + nsv_) * N_ * sizeof(double);
 }
 
 void Engine::get_state(void* dst, size_t bytes) {
@@ -742,6 +816,9 @@ void Engine::get_state(void* dst, size_t bytes) {
     RVE_HIP(hipMemcpyAsync(p, arrs[k], b, hipMemcpyDeviceToHost, st_));
     p += b;
   }
+  if (nsv_ > 0)
+    RVE_HIP(hipMemcpyAsync(p, sv_c_, nsv_ * N_ * sizeof(double),
+                           hipMemcpyDeviceToHost, st_));
   RVE_HIP(hipStreamSynchronize(st_));
 }
 
@@ -760,6 +837,9 @@ void Engine::set_state(const void* src, size_t bytes) {
     RVE_HIP(hipMemcpyAsync(arrs[k], p, b, hipMemcpyHostToDevice, st_));
     p += b;
   }
+  if (nsv_ > 0)
+    RVE_HIP(hipMemcpyAsync(sv_c_, p, nsv_ * N_ * sizeof(double),
+                           hipMemcpyHostToDevice, st_));
   RVE_HIP(hipStreamSynchronize(st_));
   increments_ = h.increments;
   t_ = h.t;
@@ -816,6 +896,7 @@ void Engine::debug_apply_G(const double* in, double* out, int precision) {
 void Engine::debug_constitutive(const double* F, double dt, double* P, double* K,
                                 double* dg, int32_t* fails) {
   if (!have_micro_) throw Error(RVE_ESTATE, "no microstructure set");
+  require_crystal("the constitutive test hook");
   if (!F || !(dt > 0)) throw Error(RVE_EINVAL, "null F or dt <= 0");
   RVE_HIP(hipMemcpyAsync(F_, F, 9 * N_ * sizeof(double), hipMemcpyHostToDevice,
                          st_));
@@ -932,6 +1013,7 @@ void Engine::get_timing(double* ms, int64_t* launches, int count, bool reset) {
 void Engine::bench_kernels(int reps, double* ms, int count) {
   if (!have_micro_ || increments_ < 1)
     throw Error(RVE_ESTATE, "run at least one increment first");
+  require_crystal("kernel benchmarking");
   if (reps < 1 || !ms) throw Error(RVE_EINVAL, "bad arguments");
   // these launches are not part of the solver's iteration: keep them out of
   // the live timing
@@ -1075,6 +1157,7 @@ void Engine::feature_args(const double Fbar_new[9], FeatArgs& a, double& s_k) {
 
 void Engine::features(const double Fbar_new[9], uint16_t* dst) {
   if (!have_micro_) throw Error(RVE_ESTATE, "no microstructure set");
+  require_crystal("the warm-start features");
   if (!dst) throw Error(RVE_EINVAL, "null destination");
   FeatArgs a{};
   double s_k;

@@ -23,6 +23,10 @@ class Engine {
   void set_microstructure(const int32_t* phase, int32_t G, const double* quat,
                           const int32_t* law, const double* params,
                           int32_t nparams);
+  // a user material in the Cauchy-stress / Jaumann-tangent form (Appendix A)
+  // in place of the crystal-plasticity microstructure
+  void set_user_material(rve_umat_fn fn, void* user, int32_t nstatev,
+                         const double* statev0);
   int increment(const double Fbar_new[9], double dt, rve_increment_info* info);
   void reset_fips();
   void get_field(int field, void* dst, size_t bytes, bool on_device);
@@ -87,6 +91,8 @@ class Engine {
   void feature_args(const double Fbar_new[9], FeatArgs& a, double& s_k);
   bool learned_candidate(const double Fbar_new[9]);
   void swap_trial_sets();
+  void reset_macro_state();
+  void require_crystal(const char* what) const;
 
   rve_config cfg_;
   int n_;
@@ -144,6 +150,13 @@ class Engine {
   double s_prev_ = 0.0;
   uint16_t* X0_ = nullptr;            // network input
   float* Ynet_ = nullptr;             // network output
+  // user material (Appendix A): callback, state variables [nsv][N]
+  // (committed and trial), Cauchy stress [6][N] and 6x6 tangent [36][N] of
+  // the last evaluation
+  rve_umat_fn umat_fn_ = nullptr;
+  void* umat_user_ = nullptr;
+  int32_t nsv_ = 0, nsv_cap_ = 0;
+  double *sv_c_ = nullptr, *sv_t_ = nullptr, *usig_ = nullptr, *udds_ = nullptr;
   // second trial set for the learned-vs-plain predictor comparison
   double *F2_ = nullptr, *P2_ = nullptr, *Fpi_t2_ = nullptr, *chi_t2_ = nullptr,
          *dg_t2_ = nullptr, *r64b_ = nullptr;

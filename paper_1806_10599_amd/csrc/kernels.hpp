@@ -169,6 +169,21 @@ struct TangentArgs {
 };
 
 void launch_return_map(const ConstArgs& a, hipStream_t s);
+// Appendix A bridge: F [9][N], sigma [6][N], ddsdde [36][N] -> P [9][N]
+// (Eq. A.1), K [81][N] (Eq. A.16); fused, P only, K only (in T)
+void launch_umat_bridge(const double* F, const double* sigma,
+                        const double* ddsdde, int64_t N, double* P, double* K,
+                        hipStream_t s);
+void launch_umat_piola(const double* F, const double* sigma, int64_t N,
+                       double* P, hipStream_t s);
+template <typename T>
+void launch_umat_tangent(const double* F, const double* sigma,
+                         const double* ddsdde, int64_t N, T* K, hipStream_t s);
+// example user material (compressible neo-Hookean) in the same form
+void launch_neo_hooke_umat(const double* F1, const double* F0,
+                           const double* sv0, double* sv1, int nsv,
+                           double* sigma, double* ddsdde, int32_t* fails,
+                           int64_t N, hipStream_t s);
 void launch_rm_count(const int32_t* iters, const int32_t* evals, int64_t N,
                      unsigned long long* stats, hipStream_t s);
 template <typename TK>
