@@ -116,7 +116,8 @@ def copy_calibration(stream):
 
 
 def run_path(micro, hist, precision, use_graph, steps, warmup, stream,
-             live=True, learned=False, start=None, cg_chunk=8):
+             live=True, learned=False, start=None, cg_chunk=8,
+             with_fips=False):
     """Solve the history; time its last ``steps`` increments (at least
     ``warmup`` untimed increments come first)."""
     import torch
@@ -158,13 +159,36 @@ def run_path(micro, hist, precision, use_graph, steps, warmup, stream,
     live_t = r.kernel_timing() if live else None
     counts = r.return_map_counts() if live else None
     sched = r.fft_schedule()
+    nonlocal_ = nonlocal_fips_report(r, micro.n) if with_fips else None
     sig = [i["sigma_bar"][0, 0] for i in timed]
     if net is not None:
         r.attach_warm_start(None)
         net.close()
     r.close()
     return dict(elapsed=elapsed, infos=timed, live=live_t, rm_counts=counts,
-                sigma11=sig, schedule=sched, start=start)
+                sigma11=sig, schedule=sched, start=start, nonlocal_=nonlocal_)
+
+
+def nonlocal_fips_report(r, n, width_voxels=2.0):
+    """Eqs. 25-26 on the committed indicator fields (after the timed
+    window): the first call builds the band lists on the host, later calls
+    only run the device reductions."""
+    import torch
+    w = width_voxels / n
+    t0 = time.perf_counter()
+    first = r.nonlocal_fips(w, arrays=False)
+    t1 = time.perf_counter()
+    reps = 20
+    for _ in range(reps):
+        res = r.nonlocal_fips(w, arrays=False)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    assert res["wcyc_b"] == first["wcyc_b"]
+    return {"band_width_voxels": width_voxels, "grains": res["grains"],
+            "bands": res["bands"], "pcyc_g": res["pcyc_g"],
+            "pcyc_lit_g": res["pcyc_lit_g"], "wcyc_b": res["wcyc_b"],
+            "first_call_ms": round(1e3 * (t1 - t0), 3),
+            "call_ms": round(1e3 * (t2 - t1) / reps, 3)}
 
 
 def batch_run(steps, stream):
@@ -196,6 +220,14 @@ def batch_run(steps, stream):
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
     sig_b = [b.macro(j)["sigma_bar"][0, 0] for j in range(len(micros))]
+    # statistical volume element: Eqs. 25-26 per RVE, mean and standard
+    # deviation over the RVEs (bands two voxel edges wide)
+    fb = [b.nonlocal_fips(j, arrays=False) for j in range(len(micros))]
+    pg = np.array([f["pcyc_g"] for f in fb])
+    wb = np.array([f["wcyc_b"] for f in fb])
+    sve = {"rves": len(fb), "band_width_voxels": 2.0,
+           "pcyc_g_mean": float(pg.mean()), "pcyc_g_std": float(pg.std(ddof=1)),
+           "wcyc_b_mean": float(wb.mean()), "wcyc_b_std": float(wb.std(ddof=1))}
     b.close()
     t_single = 0.0
     sig_s = []
@@ -224,7 +256,8 @@ def batch_run(steps, stream):
             "one_by_one_value": round(vox * steps / t_single, 1),
             "batched_over_one_by_one": round(t_single / t_batch, 3),
             "sigma11_max_rel_diff_vs_one_by_one": float(
-                np.max(np.abs(sig_b - sig_s)) / np.max(np.abs(sig_s)))}
+                np.max(np.abs(sig_b - sig_s)) / np.max(np.abs(sig_s))),
+            "sve_nonlocal_fips": sve}
 
 
 def large_run(steps, stream):
@@ -445,7 +478,7 @@ def main():
         chosen = run_path(micro, hist, "mixed", args.graph, args.steps,
                           args.warmup, stream, live=not args.no_live,
                           learned=not args.no_learned, start=args.start,
-                          cg_chunk=args.cg_chunk)
+                          cg_chunk=args.cg_chunk, with_fips=True)
         plain = None
         if not args.no_plain:
             plain = run_path(micro, hist, "fp64", False, args.steps,
@@ -492,6 +525,7 @@ def main():
         "newton_per_increment": newton_per_inc,
         "cg_per_increment": cg_per_inc,
         "predictor": predictor_stats(infos),
+        "nonlocal_fips": chosen["nonlocal_"],
     }
     live = chosen["live"]
     if live is not None:

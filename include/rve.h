@@ -221,6 +221,59 @@ rve_status rve_get_fields(rve_t h, int32_t field, void* dst, size_t dst_bytes,
 /* Macro state: F_bar (9), P_bar (9), sigma_bar (9), t, increments. */
 rve_status rve_get_macro(rve_t h, double out[29]);
 
+/* ---- non-local fatigue indicators (Sec. 3.3, Eqs. 25-26) ----------------
+   Averages of the committed indicator fields over integration volumes and
+   their maxima over the RVE:
+   * Eq. 25: the grain average of P_cyc over every crystal grain (a label of
+     law 0 with at least one voxel); its maximum P_cyc^g.  Both P_cyc
+     fields (RVE_FIELD_PCYC and the literal RVE_FIELD_PCYC_LIT) are
+     averaged.
+   * Eq. 26: every crystal grain is cut, for each of its four {111} slip
+     planes, into bands of width band_width (length units of the cell
+     lengths L) parallel to the plane; a band's value is the largest, over
+     the plane's three slip systems a, of the band average of W_cyc^a; the
+     maximum over all bands is W_cyc^b.
+   Band geometry: voxel centres at ((i + 1/2) L_d / n); the grain's
+   reference point is the centre of its voxel of lowest index; a voxel's
+   offset d from it is the periodic minimal image (grains are taken to span
+   less than half the cell per axis); band index j = floor(d.n / w + 1/2)
+   with n the sample-frame unit normal of the plane (slip systems 3p..3p+2
+   lie on plane p).  The band lists are built on the host when a width is
+   first used and kept until the width or the microstructure changes; the
+   averages and maxima run on the device in a fixed order (bitwise
+   reproducible).  The first index wins among equal maxima. */
+typedef struct {
+  double band_width;       /* the width used                                */
+  int32_t grains;          /* crystal grains with at least one voxel        */
+  int32_t pcyc_label;      /* label of P_cyc^g (-1: no crystal grain)       */
+  double pcyc_g;           /* Eq. 25 on RVE_FIELD_PCYC                      */
+  double pcyc_lit_g;       /* Eq. 25 on RVE_FIELD_PCYC_LIT                  */
+  int32_t pcyc_lit_label;  /* label of pcyc_lit_g                           */
+  int32_t wcyc_label;      /* grain of the band of W_cyc^b (-1: no band)    */
+  int64_t bands;           /* bands with at least one voxel                 */
+  double wcyc_b;           /* Eq. 26                                        */
+  int64_t wcyc_band;       /* index of that band in the band list           */
+  int32_t wcyc_plane;      /* its slip plane, 0..3                          */
+  int32_t wcyc_j;          /* its band index j                              */
+  int32_t wcyc_system;     /* slip system of its value, 0..11               */
+  int32_t wcyc_voxels;     /* voxels in that band                           */
+} rve_nonlocal_fips;
+
+/* Fills *out for the committed indicator fields.  Optional host outputs
+   (NULL to skip): grain_pcyc[labels], grain_pcyc_lit[labels] per label
+   (0 for labels that are not crystal grains; labels must equal the G of
+   rve_set_microstructure); band_wcyc[band_cap] band values and
+   band_desc[band_cap][5] (label, plane, j, system of the value, voxels),
+   bands in (label, plane, j) order.  Call with NULL arrays first to learn
+   out->bands.  Errors: RVE_EINVAL (band_width not finite or <= 0, labels
+   mismatch, band_cap < bands: *out is filled first), RVE_ESTATE (no
+   crystal microstructure). */
+rve_status rve_get_nonlocal_fips(rve_t h, double band_width,
+                                 rve_nonlocal_fips* out, double* grain_pcyc,
+                                 double* grain_pcyc_lit, int32_t labels,
+                                 double* band_wcyc, int32_t* band_desc,
+                                 int64_t band_cap);
+
 /* Checkpoint: the committed state (F, Fp^-1, chi, dgamma, indicators, macro
    state, counters; user-material state variables) as an opaque
    little-endian blob.  rve_state_size gives
@@ -239,8 +292,9 @@ const char* rve_last_error(rve_t h);
    tangent) at F[9][N] with the committed internal variables and time step dt,
    writing P[9][N], K[81][N] (component 9*(3i+j) + (3k+l) = dP_ij/dF_kl) and
    the trial slips dg[12][N]; returns the failed-voxel count in *fails.
-   rve_debug_set_field: overwrites one committed field (F, FPINV or CHI) from
-   host memory, e.g. to inject a failure. */
+   rve_debug_set_field: overwrites one committed field (F, FPINV, CHI, PCYC,
+   PCYC_LIT or WCYC) from host memory, e.g. to inject a failure or given
+   indicator fields. */
 rve_status rve_debug_apply_G(rve_t h, const double* in, double* out,
                              int32_t precision);
 rve_status rve_debug_constitutive(rve_t h, const double* F, double dt,
@@ -406,6 +460,16 @@ rve_status rve_batch_get_fields(rve_batch_t h, int32_t b, int32_t field,
                                 void* dst, size_t dst_bytes,
                                 int32_t dst_on_device);
 rve_status rve_batch_get_macro(rve_batch_t h, int32_t b, double out[29]);
+
+/* rve_get_nonlocal_fips for RVE b of a batch (same arguments and rules;
+   labels is that RVE's G). */
+rve_status rve_batch_get_nonlocal_fips(rve_batch_t h, int32_t b,
+                                       double band_width,
+                                       rve_nonlocal_fips* out,
+                                       double* grain_pcyc,
+                                       double* grain_pcyc_lit, int32_t labels,
+                                       double* band_wcyc, int32_t* band_desc,
+                                       int64_t band_cap);
 const char* rve_batch_last_error(rve_batch_t h);
 
 #ifdef __cplusplus

@@ -69,6 +69,16 @@ class RveIncrementInfo(C.Structure):
                 ("seconds", C.c_double)]
 
 
+class RveNonlocalFips(C.Structure):
+    _fields_ = [("band_width", C.c_double), ("grains", C.c_int32),
+                ("pcyc_label", C.c_int32), ("pcyc_g", C.c_double),
+                ("pcyc_lit_g", C.c_double), ("pcyc_lit_label", C.c_int32),
+                ("wcyc_label", C.c_int32), ("bands", C.c_int64),
+                ("wcyc_b", C.c_double), ("wcyc_band", C.c_int64),
+                ("wcyc_plane", C.c_int32), ("wcyc_j", C.c_int32),
+                ("wcyc_system", C.c_int32), ("wcyc_voxels", C.c_int32)]
+
+
 class RveWsConfig(C.Structure):
     _fields_ = [("stream", C.c_void_p), ("dev_alloc", ALLOC_FN),
                 ("dev_free", FREE_FN), ("alloc_ctx", C.c_void_p)]
@@ -96,6 +106,17 @@ def _load():
         "rve_get_fields": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p,
                                      C.c_size_t, C.c_int32]),
         "rve_get_macro": (C.c_int, [C.c_void_p, P(C.c_double)]),
+        "rve_get_nonlocal_fips": (C.c_int, [C.c_void_p, C.c_double,
+                                            P(RveNonlocalFips), C.c_void_p,
+                                            C.c_void_p, C.c_int32,
+                                            C.c_void_p, C.c_void_p,
+                                            C.c_int64]),
+        "rve_batch_get_nonlocal_fips": (C.c_int, [C.c_void_p, C.c_int32,
+                                                  C.c_double,
+                                                  P(RveNonlocalFips),
+                                                  C.c_void_p, C.c_void_p,
+                                                  C.c_int32, C.c_void_p,
+                                                  C.c_void_p, C.c_int64]),
         "rve_state_size": (C.c_int, [C.c_void_p, P(C.c_size_t)]),
         "rve_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
         "rve_set_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
@@ -206,6 +227,25 @@ def _info_dict(info, rc):
                 seconds=info.seconds)
 
 
+def _nonlocal_fips(call, labels, band_width, arrays):
+    """Runs a get_nonlocal_fips entry point (``call(width, out, gp, gpl,
+    labels, bw, bd, cap)`` returning a status) and converts the result."""
+    out = RveNonlocalFips()
+    call(band_width, C.byref(out), None, None, 0, None, None, 0)
+    res = {k: getattr(out, k) for k, _ in RveNonlocalFips._fields_}
+    if arrays:
+        gp = np.zeros(labels)
+        gpl = np.zeros(labels)
+        nb = out.bands
+        bw = np.zeros(max(nb, 1))
+        bd = np.zeros((max(nb, 1), 5), dtype=np.int32)
+        call(band_width, C.byref(out), _dptr(gp), _dptr(gpl), labels,
+             _dptr(bw), bd.ctypes.data_as(C.c_void_p), nb)
+        res.update(grain_pcyc=gp, grain_pcyc_lit=gpl, band_wcyc=bw[:nb],
+                   band_desc=bd[:nb])
+    return res
+
+
 def _make_config(L, projection, precision, newton_tol, newton_max_iter, cg_tol,
                  cg_max_iter, cg_chunk, use_graph, warm_start, stream, device,
                  torch_allocator):
@@ -314,6 +354,7 @@ class Rve:
             self._h, _iptr(phase), quat.shape[0], _dptr(quat), _iptr(law),
             _dptr(params), params.size))
         self._nsv = 0
+        self._labels = quat.shape[0]
 
     def set_user_material(self, material, statev0=None, user=None):
         """Use a user material of the Appendix A form for every voxel.
@@ -386,6 +427,15 @@ class Rve:
         return dict(F_bar=out[:9].reshape(3, 3), P_bar=out[9:18].reshape(3, 3),
                     sigma_bar=out[18:27].reshape(3, 3), t=out[27],
                     increments=int(out[28]))
+
+    def nonlocal_fips(self, band_width=None, arrays=True):
+        """Eqs. 25-26 on the committed indicator fields; band_width defaults
+        to two voxel edges (along the first axis)."""
+        w = 2.0 * self.cfg.L[0] / self.n if band_width is None else band_width
+
+        def call(*a):
+            self._check(LIB.rve_get_nonlocal_fips(self._h, *a))
+        return _nonlocal_fips(call, getattr(self, "_labels", 0), float(w), arrays)
 
     def get_state(self) -> bytes:
         sz = C.c_size_t()
@@ -579,6 +629,9 @@ class BatchRve:
         self._check(LIB.rve_batch_set_microstructure(
             self._h, b, _iptr(phase), quat.shape[0], _dptr(quat), _iptr(law),
             _dptr(params), params.size))
+        if not hasattr(self, "_labels"):
+            self._labels = [0] * len(self.ns)
+        self._labels[b] = quat.shape[0]
 
     def increment(self, F_bar, dt):
         """One increment of every RVE; F_bar is (3, 3) for all or (B, 3, 3).
@@ -608,6 +661,16 @@ class BatchRve:
         return dict(F_bar=out[:9].reshape(3, 3), P_bar=out[9:18].reshape(3, 3),
                     sigma_bar=out[18:27].reshape(3, 3), t=out[27],
                     increments=int(out[28]))
+
+    def nonlocal_fips(self, b, band_width=None, arrays=True):
+        """Eqs. 25-26 for RVE b; band_width defaults to two voxel edges."""
+        w = (2.0 * self.cfg.L[0] / self.ns[b] if band_width is None
+             else band_width)
+
+        def call(*a):
+            self._check(LIB.rve_batch_get_nonlocal_fips(self._h, b, *a))
+        labels = getattr(self, "_labels", [0] * len(self.ns))[b]
+        return _nonlocal_fips(call, labels, float(w), arrays)
 
 
 class WarmStartNet:

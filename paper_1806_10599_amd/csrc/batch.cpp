@@ -252,6 +252,36 @@ void* BatchEngine::alloc(size_t bytes) {
   return p;
 }
 
+void BatchEngine::release(void* p) {
+  for (size_t i = 0; i < allocs_.size(); ++i) {
+    if (allocs_[i].first != p) continue;
+    if (cfg_.dev_free)
+      cfg_.dev_free(p, cfg_.alloc_ctx);
+    else
+      hipFree(p);
+    allocs_.erase(allocs_.begin() + i);
+    return;
+  }
+}
+
+void BatchEngine::nonlocal_fips(int b, double width, rve_nonlocal_fips* out,
+                                double* grain_pcyc, double* grain_pcyc_lit,
+                                int32_t labels, double* band_wcyc,
+                                int32_t* band_desc, int64_t band_cap) {
+  if (b < 0 || b >= B_) throw Error(RVE_EINVAL, "RVE index out of range");
+  if (!have_micro_[b]) throw Error(RVE_ESTATE, "no microstructure set");
+  if ((int)fips_.size() != B_) fips_.resize(B_);
+  if (!fips_[b].built_for(width)) {
+    RVE_HIP(hipStreamSynchronize(st_));
+    fips_[b].build(n_[b], cfg_.L, host_phase_[b].data(),
+                   host_tables_[b].data(), label_count_[b], width,
+                   [this](size_t s) { return alloc(s); },
+                   [this](void* p) { release(p); });
+  }
+  fips_[b].evaluate(pcyc_, pcyc_lit_, wcyc_, Nt_, off_[b], st_, out, grain_pcyc,
+                    grain_pcyc_lit, labels, band_wcyc, band_desc, band_cap);
+}
+
 void BatchEngine::set_microstructure(int b, const int32_t* phase, int32_t G,
                                      const double* quat, const int32_t* law,
                                      const double* params, int32_t nparams) {
@@ -295,6 +325,8 @@ void BatchEngine::set_microstructure(int b, const int32_t* phase, int32_t G,
                          hipMemcpyHostToDevice, st_));
   host_phase_[b].assign(phase, phase + Nb);
   have_micro_[b] = true;
+  if ((int)fips_.size() != B_) fips_.resize(B_);
+  fips_[b].invalidate();
   // phases of every RVE with its label offset
   std::vector<int32_t> ph(Nt_, 0);
   for (int k = 0; k < B_; ++k) {

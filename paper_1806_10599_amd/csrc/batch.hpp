@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/rve.h"
+#include "fips.hpp"
 #include "kernels.hpp"
 
 namespace rve {
@@ -23,10 +24,14 @@ class BatchEngine {
   void reset_fips();
   void get_field(int b, int field, void* dst, size_t bytes, bool on_device);
   void get_macro(int b, double out[29]);
+  void nonlocal_fips(int b, double width, rve_nonlocal_fips* out,
+                     double* grain_pcyc, double* grain_pcyc_lit, int32_t labels,
+                     double* band_wcyc, int32_t* band_desc, int64_t band_cap);
   int count() const { return B_; }
 
  private:
   void* alloc(size_t bytes);
+  void release(void* p);
   void upload_scalars();
   void read_scalars();
   template <typename T>
@@ -58,6 +63,7 @@ class BatchEngine {
   std::vector<int> label_off_;
   std::vector<std::vector<int32_t>> host_phase_;
   std::vector<bool> have_micro_;
+  std::vector<FipIndex> fips_;
   double params_[RVE_NPARAMS];
   bool have_params_ = false;
   // per-RVE control

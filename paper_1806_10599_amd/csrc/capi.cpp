@@ -154,6 +154,18 @@ rve_status rve_get_fields(rve_t h, int32_t field, void* dst, size_t dst_bytes,
   });
 }
 
+rve_status rve_get_nonlocal_fips(rve_t h, double band_width,
+                                 rve_nonlocal_fips* out, double* grain_pcyc,
+                                 double* grain_pcyc_lit, int32_t labels,
+                                 double* band_wcyc, int32_t* band_desc,
+                                 int64_t band_cap) {
+  return guarded(h, [&] {
+    h->eng->nonlocal_fips(band_width, out, grain_pcyc, grain_pcyc_lit, labels,
+                          band_wcyc, band_desc, band_cap);
+    return RVE_OK;
+  });
+}
+
 rve_status rve_get_macro(rve_t h, double out[29]) {
   return guarded(h, [&] {
     if (!out) throw rve::Error(RVE_EINVAL, "null output");
@@ -447,6 +459,20 @@ rve_status rve_batch_get_fields(rve_batch_t h, int32_t b, int32_t field,
                                 int32_t dst_on_device) {
   return guarded(h, [&] {
     h->eng->get_field(b, field, dst, dst_bytes, dst_on_device != 0);
+    return RVE_OK;
+  });
+}
+
+rve_status rve_batch_get_nonlocal_fips(rve_batch_t h, int32_t b,
+                                       double band_width,
+                                       rve_nonlocal_fips* out,
+                                       double* grain_pcyc,
+                                       double* grain_pcyc_lit, int32_t labels,
+                                       double* band_wcyc, int32_t* band_desc,
+                                       int64_t band_cap) {
+  return guarded(h, [&] {
+    h->eng->nonlocal_fips(b, band_width, out, grain_pcyc, grain_pcyc_lit,
+                          labels, band_wcyc, band_desc, band_cap);
     return RVE_OK;
   });
 }

@@ -156,6 +156,18 @@ void* Engine::alloc(size_t bytes) {
   return p;
 }
 
+void Engine::release(void* p) {
+  for (size_t i = 0; i < allocs_.size(); ++i) {
+    if (allocs_[i].first != p) continue;
+    if (cfg_.dev_free)
+      cfg_.dev_free(p, cfg_.alloc_ctx);
+    else
+      hipFree(p);
+    allocs_.erase(allocs_.begin() + i);
+    return;
+  }
+}
+
 void Engine::free_all() {
   for (auto& a : allocs_) {
     if (cfg_.dev_free)
@@ -197,6 +209,10 @@ void Engine::set_microstructure(const int32_t* phase, int32_t G,
                          hipMemcpyHostToDevice, st_));
   RVE_HIP(hipMemcpyAsync(phase_, phase, N_ * sizeof(int32_t),
                          hipMemcpyHostToDevice, st_));
+  phase_host_.assign(phase, phase + N_);
+  table_host_ = tab;
+  G_ = G;
+  fips_.invalidate();
   // reset to F = I, Fp^-1 = I, chi = 0, indicators = 0
   std::vector<double> eye(9 * N_, 0.0);
   for (int c = 0; c < 9; c += 4)
@@ -791,6 +807,22 @@ void Engine::get_macro(double out[29]) {
   out[28] = (double)increments_;
 }
 
+void Engine::nonlocal_fips(double width, rve_nonlocal_fips* out,
+                           double* grain_pcyc, double* grain_pcyc_lit,
+                           int32_t labels, double* band_wcyc,
+                           int32_t* band_desc, int64_t band_cap) {
+  if (!have_micro_) throw Error(RVE_ESTATE, "no microstructure set");
+  require_crystal("the non-local indicators");
+  if (!fips_.built_for(width)) {
+    RVE_HIP(hipStreamSynchronize(st_));
+    fips_.build(n_, cfg_.L, phase_host_.data(), table_host_.data(), G_, width,
+                [this](size_t b) { return alloc(b); },
+                [this](void* p) { release(p); });
+  }
+  fips_.evaluate(pcyc_, pcyc_lit_, wcyc_, N_, 0, st_, out, grain_pcyc,
+                 grain_pcyc_lit, labels, band_wcyc, band_desc, band_cap);
+}
+
 size_t Engine::state_size() const {
   return sizeof(StateHeader) + (size_t)(65 + nsv_) * N_ * sizeof(double);
 }
@@ -952,6 +984,9 @@ void Engine::debug_set_field(int field, const double* src, size_t bytes) {
     case RVE_FIELD_F: dst = Fprev_; need = 9; break;
     case RVE_FIELD_FPINV: dst = Fpi_c_; need = 9; break;
     case RVE_FIELD_CHI: dst = chi_c_; need = 12; break;
+    case RVE_FIELD_PCYC: dst = pcyc_; need = 1; break;
+    case RVE_FIELD_PCYC_LIT: dst = pcyc_lit_; need = 1; break;
+    case RVE_FIELD_WCYC: dst = wcyc_; need = 12; break;
     default: throw Error(RVE_EINVAL, "field cannot be set");
   }
   need *= N_ * sizeof(double);

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/rve.h"
+#include "fips.hpp"
 #include "kernels.hpp"
 #include "ktimer.hpp"
 #include "nn.hpp"
@@ -31,6 +32,9 @@ class Engine {
   void reset_fips();
   void get_field(int field, void* dst, size_t bytes, bool on_device);
   void get_macro(double out[29]);
+  void nonlocal_fips(double width, rve_nonlocal_fips* out, double* grain_pcyc,
+                     double* grain_pcyc_lit, int32_t labels, double* band_wcyc,
+                     int32_t* band_desc, int64_t band_cap);
   size_t state_size() const;
   void get_state(void* dst, size_t bytes);
   void set_state(const void* src, size_t bytes);
@@ -69,6 +73,7 @@ class Engine {
 
  private:
   void* alloc(size_t bytes);
+  void release(void* p);
   void free_all();
   template <typename T>
   void cg_solve(int& iters, bool& breakdown);
@@ -123,6 +128,11 @@ class Engine {
   double sched_ms_ = 0.0;
   int labels_ = 0;
   bool have_micro_ = false;
+  // host copies for the non-local indicators' band lists
+  std::vector<int32_t> phase_host_;
+  std::vector<double> table_host_;
+  int G_ = 0;
+  FipIndex fips_;
   double params_[RVE_NPARAMS];
 
   // macro state
