@@ -243,6 +243,48 @@ class OracleRVE:
         self.t += dt
         self.increments += 1
 
+    # ------------------------------------------------- time incrementation
+    def increment_adaptive(self, F_bar_new, dt, max_cutbacks=6, grow_after=2,
+                           **kw):
+        """Automatic time incrementation (named in Sec. 2.3, no algorithm
+        given; reading of this implementation): try the whole step; after a
+        failed attempt (nothing committed) halve the sub-step, after
+        ``grow_after`` converged sub-steps in a row double it (never past
+        the rest of the step).  Sub-step targets lie on the straight path
+        F_bar_0 + f (F_bar_new - F_bar_0) with time f dt; the last one is
+        F_bar_new itself.  Fails when the sub-step would fall below
+        2^-max_cutbacks of the step; the RVE then returns to its state
+        before the call.  Returns (status, substeps, cutbacks, list of the
+        sub-steps' (fraction, IncrementInfo))."""
+        import copy
+        F_bar_new = np.asarray(F_bar_new, dtype=np.float64).reshape(3, 3)
+        F0 = self.F_bar.copy()
+        done, h, streak, cutbacks = 0.0, 1.0, 0, 0
+        snapshot = None
+        steps = []
+        while done < 1.0:
+            h = min(h, 1.0 - done)
+            f = done + h
+            target = F_bar_new if f == 1.0 else F0 + f * (F_bar_new - F0)
+            info = self.increment(target, h * dt, **kw)
+            if info.status == OK:
+                steps.append((h, info))
+                done = f
+                streak += 1
+                if streak >= grow_after:
+                    h *= 2.0
+                    streak = 0
+                continue
+            cutbacks += 1
+            streak = 0
+            if snapshot is None:
+                snapshot = copy.deepcopy(self.__dict__)
+            h *= 0.5
+            if h < 2.0 ** (-max_cutbacks):
+                self.__dict__.update(snapshot)
+                return info.status, len(steps), cutbacks, steps
+        return OK, len(steps), cutbacks, steps
+
     # -------------------------------------------------------------- outputs
     def P_bar(self):
         return self.P.mean(axis=0)
