@@ -195,6 +195,34 @@ rve_status rve_apply_macro_strain_increment(rve_t h, const double F_bar_new[9],
                                             double dt,
                                             rve_increment_info* info);
 
+/* Automatic time incrementation (named among the solver's capabilities in
+   Sec. 2.3, without an algorithm; this is the library's reading): the
+   step to F_bar_new over dt is first tried whole; after a failed attempt
+   (RVE_ENOTCONV or RVE_ELOCAL, nothing committed) the sub-step is halved,
+   after grow_after converged sub-steps in a row it is doubled (never past
+   the rest of the step).  Sub-step targets lie on the straight path
+   F_bar_0 + f (F_bar_new - F_bar_0) with time step f dt; the last one is
+   F_bar_new itself.  When the sub-step would fall below 2^-max_cutbacks of
+   the step the call fails with the last attempt's status and the RVE is
+   returned to its state before the call (also when a sub-step target is
+   rejected with RVE_EINVAL).  0 <= max_cutbacks <= 30, grow_after >= 1.
+   info (may be NULL) sums the converged sub-steps. */
+typedef struct {
+  int32_t status;             /* rve_status of the call                      */
+  int32_t substeps;           /* converged sub-steps                          */
+  int32_t cutbacks;           /* failed attempts                              */
+  int32_t newton_iters_total; /* Newton corrections of converged sub-steps   */
+  int32_t cg_iters_total;     /* CG matvecs of converged sub-steps            */
+  int32_t pad;
+  double min_fraction;        /* smallest converged sub-step / step (0: none) */
+  double seconds;             /* wall time of the call                        */
+  rve_increment_info last;    /* the last attempt                             */
+} rve_adaptive_info;
+
+rve_status rve_apply_macro_strain_increment_adaptive(
+    rve_t h, const double F_bar_new[9], double dt, int32_t max_cutbacks,
+    int32_t grow_after, rve_adaptive_info* info);
+
 /* Zeroes the per-cycle indicator accumulators (call at each cycle start). */
 rve_status rve_reset_fips(rve_t h);
 

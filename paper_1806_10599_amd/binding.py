@@ -79,6 +79,14 @@ class RveNonlocalFips(C.Structure):
                 ("wcyc_system", C.c_int32), ("wcyc_voxels", C.c_int32)]
 
 
+class RveAdaptiveInfo(C.Structure):
+    _fields_ = [("status", C.c_int32), ("substeps", C.c_int32),
+                ("cutbacks", C.c_int32), ("newton_iters_total", C.c_int32),
+                ("cg_iters_total", C.c_int32), ("pad", C.c_int32),
+                ("min_fraction", C.c_double), ("seconds", C.c_double),
+                ("last", RveIncrementInfo)]
+
+
 class RveWsConfig(C.Structure):
     _fields_ = [("stream", C.c_void_p), ("dev_alloc", ALLOC_FN),
                 ("dev_free", FREE_FN), ("alloc_ctx", C.c_void_p)]
@@ -102,6 +110,9 @@ def _load():
         "rve_apply_macro_strain_increment": (
             C.c_int, [C.c_void_p, P(C.c_double), C.c_double,
                       P(RveIncrementInfo)]),
+        "rve_apply_macro_strain_increment_adaptive": (
+            C.c_int, [C.c_void_p, P(C.c_double), C.c_double, C.c_int32,
+                      C.c_int32, P(RveAdaptiveInfo)]),
         "rve_reset_fips": (C.c_int, [C.c_void_p]),
         "rve_get_fields": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p,
                                      C.c_size_t, C.c_int32]),
@@ -396,6 +407,21 @@ class Rve:
                                                   float(dt), C.byref(info))
         self._check(rc, ok=(RVE_OK, RVE_ENOTCONV, RVE_ELOCAL))
         return _info_dict(info, rc)
+
+    def increment_adaptive(self, F_bar, dt, max_cutbacks=6, grow_after=2):
+        """A load step with automatic time incrementation (cutbacks on
+        ENOTCONV / ELOCAL); returns a dict (status included)."""
+        Fb = np.ascontiguousarray(F_bar, dtype=np.float64).reshape(9)
+        info = RveAdaptiveInfo()
+        rc = LIB.rve_apply_macro_strain_increment_adaptive(
+            self._h, _dptr(Fb), float(dt), int(max_cutbacks), int(grow_after),
+            C.byref(info))
+        self._check(rc, ok=(RVE_OK, RVE_ENOTCONV, RVE_ELOCAL))
+        return dict(status=rc, substeps=info.substeps, cutbacks=info.cutbacks,
+                    newton_iters_total=info.newton_iters_total,
+                    cg_iters_total=info.cg_iters_total,
+                    min_fraction=info.min_fraction, seconds=info.seconds,
+                    last=_info_dict(info.last, info.last.status))
 
     def reset_fips(self):
         self._check(LIB.rve_reset_fips(self._h))

@@ -139,6 +139,16 @@ rve_status rve_apply_macro_strain_increment(rve_t h, const double F_bar_new[9],
   });
 }
 
+rve_status rve_apply_macro_strain_increment_adaptive(
+    rve_t h, const double F_bar_new[9], double dt, int32_t max_cutbacks,
+    int32_t grow_after, rve_adaptive_info* info) {
+  return guarded(h, [&] {
+    if (!F_bar_new) throw rve::Error(RVE_EINVAL, "null F_bar_new");
+    return (rve_status)h->eng->increment_adaptive(F_bar_new, dt, max_cutbacks,
+                                                  grow_after, info);
+  });
+}
+
 rve_status rve_reset_fips(rve_t h) {
   return guarded(h, [&] {
     h->eng->reset_fips();

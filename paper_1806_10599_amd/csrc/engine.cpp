@@ -746,6 +746,128 @@ int Engine::increment(const double Fbar_new[9], double dt,
   return status;
 }
 
+// committed device arrays and their component counts (user-material state
+// variables last)
+#define RVE_SNAP_ARRAYS                                                   \
+  double* arrs[11] = {Fprev_, Pc_, Fpi_c_, chi_c_, dg_c_, pcyc_, pcyc_lit_, \
+                      wcyc_, dFt_prev_, sv_c_, nullptr};                  \
+  const int comps[11] = {9, 9, 9, 12, 12, 1, 1, 12, 9, nsv_, 0};
+
+void Engine::take_snapshot() {
+  RVE_SNAP_ARRAYS
+  size_t total = 0;
+  for (int k = 0; k < 10; ++k) total += (size_t)comps[k];
+  const size_t bytes = total * N_ * sizeof(double);
+  if (bytes > snap_cap_) {
+    if (snap_) release(snap_);
+    snap_ = nullptr;
+    snap_cap_ = 0;
+    snap_ = (double*)alloc(bytes);
+    snap_cap_ = bytes;
+  }
+  double* p = snap_;
+  for (int k = 0; k < 10; ++k) {
+    if (!comps[k]) continue;
+    const size_t b = (size_t)comps[k] * N_ * sizeof(double);
+    RVE_HIP(hipMemcpyAsync(p, arrs[k], b, hipMemcpyDeviceToDevice, st_));
+    p += (size_t)comps[k] * N_;
+  }
+  for (int i = 0; i < 9; ++i) {
+    snap_host_.Fbar[i] = Fbar_[i];
+    snap_host_.Pbar[i] = Pbar_[i];
+    snap_host_.dFlast[i] = dFlast_[i];
+    snap_host_.dFbar_prev[i] = dFbar_prev_[i];
+  }
+  snap_host_.s_prev = s_prev_;
+  snap_host_.t = t_;
+  snap_host_.increments = increments_;
+}
+
+void Engine::restore_snapshot() {
+  RVE_SNAP_ARRAYS
+  const double* p = snap_;
+  for (int k = 0; k < 10; ++k) {
+    if (!comps[k]) continue;
+    const size_t b = (size_t)comps[k] * N_ * sizeof(double);
+    RVE_HIP(hipMemcpyAsync(arrs[k], p, b, hipMemcpyDeviceToDevice, st_));
+    p += (size_t)comps[k] * N_;
+  }
+  RVE_HIP(hipStreamSynchronize(st_));
+  for (int i = 0; i < 9; ++i) {
+    Fbar_[i] = snap_host_.Fbar[i];
+    Pbar_[i] = snap_host_.Pbar[i];
+    dFlast_[i] = snap_host_.dFlast[i];
+    dFbar_prev_[i] = snap_host_.dFbar_prev[i];
+  }
+  s_prev_ = snap_host_.s_prev;
+  t_ = snap_host_.t;
+  increments_ = snap_host_.increments;
+}
+#undef RVE_SNAP_ARRAYS
+
+int Engine::increment_adaptive(const double Fbar_new[9], double dt,
+                               int max_cutbacks, int grow_after,
+                               rve_adaptive_info* info) {
+  if (max_cutbacks < 0 || max_cutbacks > 30 || grow_after < 1)
+    throw Error(RVE_EINVAL, "max_cutbacks in [0, 30] and grow_after >= 1");
+  const auto t0 = std::chrono::steady_clock::now();
+  rve_adaptive_info loc;
+  std::memset(&loc, 0, sizeof(loc));
+  double F0[9], Fn[9];
+  for (int i = 0; i < 9; ++i) {
+    F0[i] = Fbar_[i];
+    Fn[i] = Fbar_new[i];
+  }
+  const double hmin = std::ldexp(1.0, -max_cutbacks);
+  double done = 0.0, h = 1.0;
+  int streak = 0;
+  bool snapped = false;
+  int status = RVE_OK;
+  try {
+    while (done < 1.0) {
+      h = std::min(h, 1.0 - done);
+      const double f = done + h;
+      double target[9];
+      for (int i = 0; i < 9; ++i)
+        target[i] = (f == 1.0) ? Fn[i] : F0[i] + f * (Fn[i] - F0[i]);
+      rve_increment_info inc;
+      const int st = increment(target, h * dt, &inc);
+      loc.last = inc;
+      if (st == RVE_OK) {
+        ++loc.substeps;
+        loc.newton_iters_total += inc.newton_iters;
+        loc.cg_iters_total += inc.cg_iters_total;
+        if (loc.min_fraction == 0.0 || h < loc.min_fraction) loc.min_fraction = h;
+        done = f;
+        if (++streak >= grow_after) {
+          h *= 2.0;
+          streak = 0;
+        }
+        continue;
+      }
+      ++loc.cutbacks;
+      streak = 0;
+      if (!snapped) {
+        take_snapshot();   // nothing committed yet: the state of the call
+        snapped = true;
+      }
+      h *= 0.5;
+      if (h < hmin) {
+        restore_snapshot();
+        status = st;
+        break;
+      }
+    }
+  } catch (...) {
+    if (snapped) restore_snapshot();
+    throw;
+  }
+  loc.status = status;
+  loc.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (info) *info = loc;
+  return status;
+}
+
 void Engine::reset_fips() {
   launch_fill_f64(pcyc_, 0.0, N_, st_);
   launch_fill_f64(pcyc_lit_, 0.0, N_, st_);

@@ -29,6 +29,8 @@ class Engine {
   void set_user_material(rve_umat_fn fn, void* user, int32_t nstatev,
                          const double* statev0);
   int increment(const double Fbar_new[9], double dt, rve_increment_info* info);
+  int increment_adaptive(const double Fbar_new[9], double dt, int max_cutbacks,
+                         int grow_after, rve_adaptive_info* info);
   void reset_fips();
   void get_field(int field, void* dst, size_t bytes, bool on_device);
   void get_macro(double out[29]);
@@ -97,6 +99,10 @@ class Engine {
   bool learned_candidate(const double Fbar_new[9]);
   void swap_trial_sets();
   void reset_macro_state();
+  // copy of the committed state (device arrays and host macro state) for
+  // the rollback of a failed adaptive step
+  void take_snapshot();
+  void restore_snapshot();
   void require_crystal(const char* what) const;
 
   rve_config cfg_;
@@ -167,6 +173,13 @@ class Engine {
   void* umat_user_ = nullptr;
   int32_t nsv_ = 0, nsv_cap_ = 0;
   double *sv_c_ = nullptr, *sv_t_ = nullptr, *usig_ = nullptr, *udds_ = nullptr;
+  double* snap_ = nullptr;
+  size_t snap_cap_ = 0;
+  struct HostSnap {
+    double Fbar[9], Pbar[9], dFlast[9], dFbar_prev[9];
+    double s_prev, t;
+    int64_t increments;
+  } snap_host_{};
   // second trial set for the learned-vs-plain predictor comparison
   double *F2_ = nullptr, *P2_ = nullptr, *Fpi_t2_ = nullptr, *chi_t2_ = nullptr,
          *dg_t2_ = nullptr, *r64b_ = nullptr;
