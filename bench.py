@@ -94,6 +94,9 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=8)
     ap.add_argument("--large-steps", type=int, default=6,
                     help="increments of the 128^3 RVE (0: skip)")
+    ap.add_argument("--paper-workloads", action="store_true",
+                    help="also run the paper's own R = 0 histories (a few "
+                         "minutes)")
     ap.add_argument("--no-umat", action="store_true",
                     help="skip the Appendix A bridge measurement")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -319,6 +322,121 @@ def umat_run(stream, n=128 ** 3, calls=20):
             "voxels_per_s": round(n / (us * 1e-6), 1),
             "achieved_GBps": round(gbs, 1), "peak_GBps": HBM_PEAK_GBS,
             "frac": round(gbs / HBM_PEAK_GBS, 3)}
+
+
+def _eq29_per_cycle(sig, ref, per_cycle):
+    """Eq. 29 (max over each cycle of |sigma - sigma_ref| / max |sigma_ref|,
+    in %), one value per cycle."""
+    sig, ref = np.asarray(sig), np.asarray(ref)
+    scale = np.max(np.abs(ref))
+    d = np.abs(sig - ref) / scale * 100.0
+    return [float(np.max(d[c:c + per_cycle])) for c in range(0, len(d), per_cycle)]
+
+
+def _run_history(micro, hist, precision, operator, stream, adaptive=False,
+                 learned=False):
+    """Solve a whole history; returns seconds, sigma_11 per increment and
+    solver counts."""
+    import torch
+    from paper_1806_10599_amd.binding import Rve, WarmStartNet
+    from paper_1806_10599_amd.warmstart import trained_params
+    from synthetic import material_params
+    r = Rve(micro.n, projection=operator, precision=precision,
+            newton_tol=1e-6, cg_tol=1e-4, stream=stream, warm_start=learned)
+    r.set_microstructure(micro.phase, micro.quat, micro.law, material_params())
+    net = None
+    if learned:
+        net = WarmStartNet(stream=stream)
+        net.set_params(trained_params())
+        r.attach_warm_start(net)
+    sig, newton, cg, sub, cuts = [], 0, 0, 0, 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for inc in hist:
+        if inc["cycle_start"]:
+            r.reset_fips()
+        if adaptive:
+            a = r.increment_adaptive(inc["F_bar"], inc["dt"], max_cutbacks=6)
+            if a["status"] != 0:
+                raise RuntimeError(f"increment {inc['k']} failed: {a['status']}")
+            newton += a["newton_iters_total"]
+            cg += a["cg_iters_total"]
+            sub += a["substeps"]
+            cuts += a["cutbacks"]
+            sig.append(a["last"]["sigma_bar"][0, 0])
+        else:
+            info = r.increment(inc["F_bar"], inc["dt"])
+            if info["status"] != 0:
+                raise RuntimeError(f"increment {inc['k']} failed: {info['status']}")
+            newton += info["newton_iters"]
+            cg += info["cg_iters_total"]
+            sig.append(info["sigma_bar"][0, 0])
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    if net is not None:
+        r.attach_warm_start(None)
+        net.close()
+    r.close()
+    out = dict(seconds=round(sec, 3), increments=len(hist),
+               newton_per_increment=round(newton / len(hist), 3),
+               cg_per_increment=round(cg / len(hist), 2))
+    if adaptive:
+        out.update(substeps=sub, cutbacks=cuts)
+    return out, sig
+
+
+def paper_workloads(stream):
+    """The paper's own histories (R = 0 triangles of period 4 s, Eq. 28 as
+    intended; 235 grains, discrete operator, tol 1e-6):
+    * the performance case of Sec. 5: three cycles at 1 % on 32^3, 64^3 and
+      128^3, whole-history wall time of the chosen paths and of plain FP64;
+    * three cycles at 5 % on 64^3 with automatic time incrementation,
+      mixed against FP64 per cycle (Eq. 29);
+    * one hundred cycles at 1 % on 32^3: drift of mixed precision against
+      FP64 and of the continuous against the discrete operator, per cycle
+      (Eq. 29), and the stable cycle's peak stress."""
+    from synthetic import config_by_name
+    out = {}
+    perf = {}
+    for name in ("P1_32", "P1_64", "P1_128"):
+        cfg = config_by_name(name)
+        micro, hist = cfg.microstructure(), cfg.history()
+        row = {}
+        for label, prec, learned in (("mixed_learned", "mixed", True),
+                                     ("mixed", "mixed", False),
+                                     ("fp64", "fp64", False)):
+            row[label], _ = _run_history(micro, hist, prec, "discrete", stream,
+                                         learned=learned)
+        perf[f"{cfg.n}^3"] = row
+        print(f"paper workload {name} done", file=sys.stderr, flush=True)
+    out["r0_1pct_3cycles"] = perf
+    cfg = config_by_name("P2")
+    micro, hist = cfg.microstructure(), cfg.history()
+    m, sm = _run_history(micro, hist, "mixed", "discrete", stream, adaptive=True)
+    f, sf = _run_history(micro, hist, "fp64", "discrete", stream, adaptive=True)
+    out["r0_5pct_3cycles_64"] = dict(
+        mixed=m, fp64=f, peak_sigma11=float(np.max(sf)),
+        eq29_mixed_vs_fp64_pct_per_cycle=_eq29_per_cycle(sm, sf,
+                                                         cfg.inc_per_cycle))
+    print("paper workload P2 done", file=sys.stderr, flush=True)
+    cfg = config_by_name("P3")
+    micro, hist = cfg.microstructure(), cfg.history()
+    m, sm = _run_history(micro, hist, "mixed", "discrete", stream)
+    f, sf = _run_history(micro, hist, "fp64", "discrete", stream)
+    c, sc = _run_history(micro, hist, "fp64", "continuous", stream)
+    k = cfg.inc_per_cycle
+    dm = _eq29_per_cycle(sm, sf, k)
+    dc = _eq29_per_cycle(sc, sf, k)
+    peaks = [float(np.max(sf[i:i + k])) for i in range(0, len(sf), k)]
+    out["r0_1pct_100cycles_32"] = dict(
+        mixed=m, fp64=f, fp64_continuous=c,
+        eq29_mixed_vs_fp64_pct=dict(first=dm[0], last=dm[-1], max=max(dm)),
+        eq29_continuous_vs_discrete_pct=dict(first=dc[0], last=dc[-1],
+                                             max=max(dc)),
+        peak_sigma11_cycle=dict(first=peaks[0], second=peaks[1],
+                                last=peaks[-1]))
+    print("paper workload P3 done", file=sys.stderr, flush=True)
+    return out
 
 
 def predictor_stats(infos):
@@ -553,6 +671,9 @@ def main():
             out["large_rve"] = large_run(args.large_steps, stream)
     if not args.no_umat:
         out["umat_bridge"] = umat_run(stream)
+    if args.paper_workloads:
+        with torch.cuda.stream(stream):
+            out["paper_workloads"] = paper_workloads(stream)
     if calib:
         out["copy_calibration"] = calib
     if not args.no_cpu:

@@ -1,7 +1,8 @@
 """The benchmark workloads: sizes, grain counts, loading and material constants.
 
 Five configurations, from the small oracle case to the large learned-start
-case.  The material is the FCC power-law crystal with Armstrong-Frederick
+case, and the paper's own histories (R = 0 cycles at 1 % on 32^3 to 128^3,
+three cycles at 5 %, one hundred cycles at 1 %).  The material is the FCC power-law crystal with Armstrong-Frederick
 back stress used by every workload (the paper's own Cruzado law is cited but
 never written out, Sec. 3.2); particles are a stiff isotropic second phase
 (Sec. 4.4).  Stresses and moduli in MPa, time in s.
@@ -42,6 +43,7 @@ class RveConfig:
     seed: int
     batch: int = 1           # RVEs in one batch (the batching workload)
     learned: bool = False
+    kind: str = "reversed"   # cycle shape: "reversed" or "r0" (Eq. 28)
 
     @property
     def voxels(self) -> int:
@@ -53,7 +55,8 @@ class RveConfig:
 
     def history(self, cycles: int | None = None):
         return cyclic_history(self.eps_a, self.inc_per_cycle,
-                              self.cycles if cycles is None else cycles)
+                              self.cycles if cycles is None else cycles,
+                              kind=self.kind)
 
     def batch_microstructures(self):
         """The batch of independent RVEs, each from its own seed.
@@ -79,6 +82,18 @@ CONFIGS = {
                     batch=32),
     "C5": RveConfig("C5", 128, 1000, 0.05, "discrete", "mixed", 0.005, 40, 10,
                     1005, learned=True),
+    # the paper's own histories (Sec. 4.2, Sec. 5): R = 0 triangles of
+    # period 4 s, 235 grains as in its RVE
+    "P1_32": RveConfig("P1_32", 32, 235, 0.0, "discrete", "mixed", 0.01, 40,
+                       3, 2032, kind="r0"),
+    "P1_64": RveConfig("P1_64", 64, 235, 0.0, "discrete", "mixed", 0.01, 40,
+                       3, 2064, kind="r0"),
+    "P1_128": RveConfig("P1_128", 128, 235, 0.0, "discrete", "mixed", 0.01,
+                        40, 3, 2128, kind="r0"),
+    "P2": RveConfig("P2", 64, 235, 0.0, "discrete", "mixed", 0.05, 40, 3,
+                    2264, kind="r0"),
+    "P3": RveConfig("P3", 32, 235, 0.0, "discrete", "mixed", 0.01, 40, 100,
+                    2332, kind="r0"),
 }
 
 
