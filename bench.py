@@ -66,6 +66,9 @@ RM_FLOPS = {"eval": 1124, "step": 2600, "crystal": 570, "particle": 110}
 # launch, hundreds of launches per increment), so they are left to the
 # profiler.
 LIVE_CLASSES = ("return_map", "tangent", "residual_fp64")
+# learned warm start: a candidate well below the homogeneous predictor's
+# last residual is kept without evaluating the homogeneous predictor
+WARM_MODE = 2
 
 
 def parse():
@@ -129,7 +132,7 @@ def run_path(micro, hist, precision, use_graph, steps, warmup, stream,
     from synthetic import material_params
     r = Rve(micro.n, projection="discrete", precision=precision,
             newton_tol=1e-6, cg_tol=1e-4, use_graph=use_graph, stream=stream,
-            warm_start=learned, cg_chunk=cg_chunk)
+            warm_start=WARM_MODE if learned else 0, cg_chunk=cg_chunk)
     r.set_microstructure(micro.phase, micro.quat, micro.law, material_params())
     net = None
     if learned:
@@ -342,7 +345,8 @@ def _run_history(micro, hist, precision, operator, stream, adaptive=False,
     from paper_1806_10599_amd.warmstart import trained_params
     from synthetic import material_params
     r = Rve(micro.n, projection=operator, precision=precision,
-            newton_tol=1e-6, cg_tol=1e-4, stream=stream, warm_start=learned)
+            newton_tol=1e-6, cg_tol=1e-4, stream=stream,
+            warm_start=WARM_MODE if learned else 0)
     r.set_microstructure(micro.phase, micro.quat, micro.law, material_params())
     net = None
     if learned:
@@ -445,7 +449,9 @@ def predictor_stats(infos):
         cg_per_increment=float(np.mean([i["cg_iters_total"] for i in infos])),
         median_predictor_residual=float(np.median(
             [i["predictor_residual"] for i in infos])),
-        learned_start_used=float(np.mean([i["used_learned"] for i in infos])))
+        learned_start_used=float(np.mean([i["used_learned"] for i in infos])),
+        learned_kept_directly=float(np.mean(
+            [i["plain_predictor_residual"] < 0 for i in infos])))
 
 
 def oracle_sample(micro, hist, gpu_infos, budget_s):
@@ -630,8 +636,10 @@ def main():
                    "graph": args.graph,
                    "cg_chunk": args.cg_chunk,
                    "warm_start": ("homogeneous" if args.no_learned else
-                                  "learned (weights/warmstart.npy), with "
-                                  "homogeneous fallback"),
+                                  "learned (weights/warmstart.npy), kept "
+                                  "directly below half the homogeneous "
+                                  "predictor's last residual, else the "
+                                  "better of both"),
                    "timed_increments": [chosen["start"] + 1,
                                         chosen["start"] + args.steps],
                    "timed_window": ("last cycle of the history, held out from "

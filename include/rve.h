@@ -71,8 +71,14 @@ typedef struct {
   double L[3];           /* cell edge lengths (only ratios matter)           */
   int32_t projection;    /* RVE_PROJ_*                                       */
   int32_t precision;     /* RVE_PREC_*                                       */
-  int32_t warm_start;    /* 0 = homogeneous predictor, 1 = learned (needs a
-                            network loaded with rve_ws_load)                  */
+  int32_t warm_start;    /* 0 = homogeneous predictor; 1 = learned: the
+                            candidate and the homogeneous predictor are both
+                            evaluated and the smaller FP64 residual wins;
+                            2 = learned, and a candidate whose FP64 residual
+                            is below half of the homogeneous predictor's
+                            last evaluated one is kept without evaluating
+                            the homogeneous predictor (needs a network
+                            attached with rve_attach_warm_start)            */
   int32_t use_graph;     /* 1 = replay CG chunks from a captured hipGraph    */
   double newton_tol;     /* equilibrium: ||G(P)||_2 <= tol ||P||_2 (FP64)     */
   int32_t newton_max_iter;
@@ -96,7 +102,8 @@ typedef struct {
   int32_t status;            /* rve_status of the increment                   */
   double residual_rel;       /* final ||G(P)||/||P||                          */
   double predictor_residual; /* ||G(P)||/||P|| of the accepted predictor     */
-  double plain_predictor_residual; /* same for the homogeneous predictor     */
+  double plain_predictor_residual; /* same for the homogeneous predictor
+                                      (-1: not evaluated, warm_start = 2) */
   double P_bar[9];           /* <P>, row-major                                */
   double sigma_bar[9];       /* P_bar Fbar^T / det Fbar                       */
   double residual_history[RVE_MAX_NEWTON_LOG];
@@ -400,7 +407,7 @@ rve_status rve_get_fft_schedule(rve_t h, int32_t out[2], double* ms);
    receives the loss before the step; grad_host (nullable) the FP32
    gradient in parameter order.
    rve_attach_warm_start: the handle uses the network when its config has
-   warm_start = 1 (pass NULL to detach; detach before destroying the
+   warm_start = 1 or 2 (pass NULL to detach; detach before destroying the
    network).  rve_ws_features: input of the increment to F_bar_new from the
    committed state.  rve_ws_target: target of the last committed increment.
    Errors: RVE_EINVAL (bad sizes, n % 16 != 0), RVE_ESTATE (no increment

@@ -271,7 +271,9 @@ def _make_config(L, projection, precision, newton_tol, newton_max_iter, cg_tol,
     cfg.cg_max_iter = cg_max_iter
     cfg.cg_chunk = cg_chunk
     cfg.use_graph = 1 if use_graph else 0
-    cfg.warm_start = 1 if warm_start else 0
+    if warm_start not in (0, 1, 2):
+        raise ValueError("warm_start must be False/0, True/1 or 2")
+    cfg.warm_start = int(warm_start)
     torch.cuda.set_device(device)
     stream = stream if stream is not None else torch.cuda.current_stream()
     cfg.stream = C.c_void_p(stream.cuda_stream or None)

@@ -45,6 +45,8 @@ Engine::Engine(const rve_config& cfg) : cfg_(cfg) {
     throw Error(RVE_EINVAL, "unknown projection operator");
   if (cfg.precision != RVE_PREC_FP64 && cfg.precision != RVE_PREC_MIXED)
     throw Error(RVE_EINVAL, "unknown precision mode");
+  if (cfg.warm_start < 0 || cfg.warm_start > 2)
+    throw Error(RVE_EINVAL, "warm_start must be 0, 1 or 2");
   for (int d = 0; d < 3; ++d)
     if (!(cfg.L[d] > 0.0)) throw Error(RVE_EINVAL, "cell lengths must be > 0");
   if (!(cfg.newton_tol > 0.0) || cfg.newton_max_iter < 0 ||
@@ -247,6 +249,7 @@ void Engine::reset_macro_state() {
   s_prev_ = 0.0;
   t_ = 0.0;
   increments_ = 0;
+  last_plain_rel_ = 0.0;
 }
 
 void Engine::require_crystal(const char* what) const {
@@ -656,26 +659,39 @@ int Engine::increment(const double Fbar_new[9], double dt,
   int status = RVE_ENOTCONV;
   int pre_fails = -1;
   if (net_ && cfg_.warm_start && !umat_fn_ && learned_candidate(Fbar_new)) {
-    // learned candidate in F2_: evaluate it, stash it, evaluate the plain
-    // predictor, keep the one with the smaller FP64 residual
+    // learned candidate in F2_: evaluate it; with warm_start = 2 keep it at
+    // once when its FP64 residual is well below what the plain predictor
+    // reached when last evaluated, otherwise stash it, evaluate the plain
+    // predictor and keep the one with the smaller FP64 residual
     std::swap(F_, F2_);
     double relL, resL, pnL;
     const int failsL = evaluate(dg_start, dt, relL, resL, pnL);
-    swap_trial_sets();
-    std::swap(F_, F2_);
-    double pbarL[9];
-    for (int i = 0; i < 9; ++i) pbarL[i] = Pbar_new_[i];
-    pre_fails = evaluate(dg_start, dt, rel, res, pn);
-    loc.plain_predictor_residual = rel;
-    if (failsL == 0 && relL < rel) {
-      swap_trial_sets();
-      std::swap(F_, F2_);
+    if (cfg_.warm_start == 2 && failsL == 0 && last_plain_rel_ > 0.0 &&
+        relL < kLearnedDirect * last_plain_rel_) {
       rel = relL;
       res = resL;
       pn = pnL;
       pre_fails = 0;
-      for (int i = 0; i < 9; ++i) Pbar_new_[i] = pbarL[i];
       loc.used_learned = 1;
+      loc.plain_predictor_residual = -1.0;   // not evaluated
+    } else {
+      swap_trial_sets();
+      std::swap(F_, F2_);
+      double pbarL[9];
+      for (int i = 0; i < 9; ++i) pbarL[i] = Pbar_new_[i];
+      pre_fails = evaluate(dg_start, dt, rel, res, pn);
+      loc.plain_predictor_residual = rel;
+      last_plain_rel_ = rel;
+      if (failsL == 0 && relL < rel) {
+        swap_trial_sets();
+        std::swap(F_, F2_);
+        rel = relL;
+        res = resL;
+        pn = pnL;
+        pre_fails = 0;
+        for (int i = 0; i < 9; ++i) Pbar_new_[i] = pbarL[i];
+        loc.used_learned = 1;
+      }
     }
   }
   for (int i = 0; i < 9; ++i) dFlast_[i] = dF[i];
@@ -686,7 +702,10 @@ int Engine::increment(const double Fbar_new[9], double dt,
     if (it < RVE_MAX_NEWTON_LOG) loc.residual_history[it] = rel;
     if (it == 0) {
       loc.predictor_residual = rel;
-      if (!loc.used_learned) loc.plain_predictor_residual = rel;
+      if (!loc.used_learned) {
+        loc.plain_predictor_residual = rel;
+        last_plain_rel_ = rel;
+      }
     }
     loc.residual_rel = rel;
     if (fails > 0) {

@@ -164,6 +164,11 @@ class Engine {
   double* dFt_prev_ = nullptr;        // fluctuation increment of the last increment
   double dFbar_prev_[9];
   double s_prev_ = 0.0;
+  // FP64 residual of the plain predictor when it was last evaluated, and
+  // the fraction of it below which warm_start = 2 keeps a learned candidate
+  // without evaluating the plain predictor
+  double last_plain_rel_ = 0.0;
+  static constexpr double kLearnedDirect = 0.5;
   uint16_t* X0_ = nullptr;            // network input
   float* Ynet_ = nullptr;             // network output
   // user material (Appendix A): callback, state variables [nsv][N]

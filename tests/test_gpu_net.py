@@ -260,3 +260,43 @@ def test_shipped_weights_beat_the_homogeneous_predictor_on_held_out_cycle():
         a.close()
         b.close()
         net.close()
+
+
+def test_direct_acceptance_mode_keeps_clearly_better_candidates():
+    """warm_start = 2: a learned candidate whose FP64 residual is below half
+    of the homogeneous predictor's last evaluated residual is kept without
+    evaluating the homogeneous predictor; otherwise both are evaluated as in
+    mode 1.  The equilibrium is the same as without the network."""
+    from gpu_util import make_rve
+    from paper_1806_10599_amd.warmstart import trained_params
+    c = config_by_name("C3")
+    micro = c.microstructure()
+    hist = c.history()[:50]
+    net = _net(trained_params())
+    a = make_rve(micro, c.operator, "mixed")
+    b = make_rve(micro, c.operator, "mixed", warm_start=2)
+    b.attach_warm_start(net)
+    try:
+        last_plain = None
+        direct = 0
+        for j, inc in enumerate(hist):
+            if inc["cycle_start"]:
+                a.reset_fips()
+                b.reset_fips()
+            ia = a.increment(inc["F_bar"], inc["dt"])
+            ib = b.increment(inc["F_bar"], inc["dt"])
+            assert ia["status"] == 0 and ib["status"] == 0
+            s_a, s_b = ia["sigma_bar"][0, 0], ib["sigma_bar"][0, 0]
+            assert abs(s_a - s_b) <= 1e-4 * abs(s_a) + 1e-3
+            if ib["plain_predictor_residual"] < 0:
+                direct += 1
+                assert ib["used_learned"] == 1 and last_plain is not None
+                assert ib["predictor_residual"] < 0.5 * last_plain
+            else:
+                last_plain = ib["plain_predictor_residual"]
+        assert direct >= 0.5 * len(hist), direct
+    finally:
+        b.attach_warm_start(None)
+        a.close()
+        b.close()
+        net.close()
