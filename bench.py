@@ -166,13 +166,37 @@ def run_path(micro, hist, precision, use_graph, steps, warmup, stream,
     counts = r.return_map_counts() if live else None
     sched = r.fft_schedule()
     nonlocal_ = nonlocal_fips_report(r, micro.n) if with_fips else None
+    passes = (cg_pass_report(r.bench_kernels(reps=50), micro.n ** 3)
+              if precision == "mixed" and with_fips else None)
     sig = [i["sigma_bar"][0, 0] for i in timed]
     if net is not None:
         r.attach_warm_start(None)
         net.close()
     r.close()
     return dict(elapsed=elapsed, infos=timed, live=live_t, rm_counts=counts,
-                sigma11=sig, schedule=sched, start=start, nonlocal_=nonlocal_)
+                sigma11=sig, schedule=sched, start=start, nonlocal_=nonlocal_,
+                passes=passes)
+
+
+def cg_pass_report(kern, N):
+    """Achieved bandwidth of the CG-iteration kernels (FP32) from
+    back-to-back launches with the solver's launch configuration and the
+    tuned FFT schedule, on the buffers of the last increment (after the
+    timed window): algorithmic bytes per launch / average duration."""
+    out = {}
+    for k, b in PASS_BYTES_F32.items():
+        ms = kern[k]
+        gbs = N * b / (ms * 1e-3) / 1e9
+        out[k] = dict(us=round(1e3 * ms, 2), bytes_per_voxel=b,
+                      gbps=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 3))
+    mv = ("matvec_pass_a", "matvec_pass_b", "matvec_pass_c")
+    ms = sum(kern[k] for k in mv)
+    gbs = N * sum(PASS_BYTES_F32[k] for k in mv) / (ms * 1e-3) / 1e9
+    out["fft_projection_passes"] = dict(us=round(1e3 * ms, 2), gbps=round(gbs, 1),
+                                        frac=round(gbs / HBM_PEAK_GBS, 3))
+    ms_all = sum(kern[k] for k in PASS_BYTES_F32)
+    out["cg_iteration_us"] = round(1e3 * ms_all, 2)
+    return out
 
 
 def nonlocal_fips_report(r, n, width_voxels=2.0):
@@ -283,11 +307,14 @@ def large_run(steps, stream):
                         f"2-{steps} of +-{cfg.eps_a:.1%} cycles")}
     for mode in ("learned", "homogeneous"):
         r = run_path(micro, hist, "mixed", False, steps - 1, 1, stream,
-                     live=False, learned=(mode == "learned"), start=1)
+                     live=False, learned=(mode == "learned"), start=1,
+                     with_fips=(mode == "learned"))
         n3 = micro.n ** 3
         out[mode] = dict(value=round(n3 * (steps - 1) / r["elapsed"], 1),
                          ms_per_step=round(1e3 * r["elapsed"] / (steps - 1), 3),
                          **predictor_stats(r["infos"]))
+        if r["passes"]:
+            out["cg_passes"] = r["passes"]
     out["unit"] = "voxel-increments/s"
     return out
 
@@ -652,10 +679,13 @@ def main():
         "cg_per_increment": cg_per_inc,
         "predictor": predictor_stats(infos),
         "nonlocal_fips": chosen["nonlocal_"],
+        "cg_passes": chosen["passes"],
     }
     live = chosen["live"]
     if live is not None:
         out.update(live_report(live, chosen["rm_counts"], N, cg_total))
+    if out.get("fft_gbps") is None and chosen["passes"]:
+        out["fft_gbps"] = chosen["passes"]["fft_projection_passes"]["gbps"]
     if plain is not None:
         pv = N * args.steps / plain["elapsed"]
         out["plain"] = {"value": round(pv, 1), "unit": "voxel-increments/s",

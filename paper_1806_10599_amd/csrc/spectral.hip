@@ -82,6 +82,10 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return r;
 }
 
+// items whose global loads are issued together before their LDS stores
+template <typename T>
+constexpr int kStage = sizeof(T) == 4 ? 8 : 2;
+
 template <typename T, int N>
 __device__ __forceinline__ void load_twiddles(cplx<T>* tw,
                                               const cplx<T>* __restrict__ g) {
@@ -106,9 +110,49 @@ __device__ __forceinline__ void slab_fwd_body(const SlabFwdArgs<T>& a, int lb,
 
   // build the real plane(s), packed: row y' holds y' (re) and y'+H (im);
   // each thread builds both rows of a (y', z) slot and stores one complex
+  if constexpr (SRC == SRC_FIELD) {
+    // the loads of a chunk of items are issued together, then the chunk is
+    // written to LDS (same per-thread order of the sums as item by item)
+    constexpr int PER = (H * N + kBlock - 1) / kBlock;
+    constexpr int CH = PER < kStage<T> ? PER : kStage<T>;
+    for (int c0 = 0; c0 < PER; c0 += CH) {
+      T val[CH][2][CPB];
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int t = threadIdx.x + (c0 + u) * kBlock;
+        if (c0 + u < PER && t < H * N) {
+          const int yp = t / N, z = t - (t / N) * N;
+#pragma unroll
+          for (int hh = 0; hh < 2; ++hh) {
+            const int64_t v = ((int64_t)x * N + yp + hh * H) * N + z;
+#pragma unroll
+            for (int q = 0; q < CPB; ++q)
+              val[u][hh][q] = a.field[(grp * CPB + q) * cs + v];
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int t = threadIdx.x + (c0 + u) * kBlock;
+        if (c0 + u < PER && t < H * N) {
+          const int yp = t / N, z = t - (t / N) * N;
+#pragma unroll
+          for (int q = 0; q < CPB; ++q) {
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {
+              ss[q] += double(val[u][hh][q]) * double(val[u][hh][q]);
+              s1[q] += double(val[u][hh][q]);
+            }
+            lds[q * SlabGeom<N>::PLANE + yp * SlabGeom<N>::PITCH + z] =
+                cplx<T>{val[u][0][q], val[u][1][q]};
+          }
+        }
+      }
+    }
+  }
   const bool first = (SRC == SRC_KP) ? (a.sc->first != 0) : true;
   const T beta = (SRC == SRC_KP) ? T(a.sc->beta) : T(0);
-  for (int t = threadIdx.x; t < H * N; t += blockDim.x) {
+  for (int t = threadIdx.x; SRC == SRC_KP && t < H * N; t += blockDim.x) {
     const int yp = t / N, z = t - (t / N) * N;
     T out[2][CPB];
 #pragma unroll
@@ -228,14 +272,34 @@ __device__ __forceinline__ void pencil_body(const PencilArgs<T>& a, int lb,
     return;
   }
   load_twiddles<T, N>(tw, a.tw);
-  for (int t = threadIdx.x; t < 3 * N * TT; t += blockDim.x) {
-    const int j = t / (N * TT);
-    const int rem = t - j * N * TT;
-    const int kx = rem / TT, tt = rem - (rem / TT) * TT;
-    cplx<T> val = {T(0), T(0)};
-    if (tt < ncol)
-      val = a.spec[((size_t)((3 * i + j) * N + kx) * N + ky) * H + kz0 + tt];
-    lds[j * CPS + kx * TP + tt] = val;
+  {
+    constexpr int PER = (3 * N * TT + kBlock - 1) / kBlock;
+    constexpr int CH = PER < kStage<T> ? PER : kStage<T>;
+    for (int c0 = 0; c0 < PER; c0 += CH) {
+      cplx<T> val[CH];
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int t = threadIdx.x + (c0 + u) * kBlock;
+        val[u] = {T(0), T(0)};
+        if (c0 + u < PER && t < 3 * N * TT) {
+          const int j = t / (N * TT);
+          const int rem = t - j * N * TT;
+          const int kx = rem / TT, tt = rem - (rem / TT) * TT;
+          if (tt < ncol)
+            val[u] = a.spec[((size_t)((3 * i + j) * N + kx) * N + ky) * H + kz0 + tt];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int t = threadIdx.x + (c0 + u) * kBlock;
+        if (c0 + u < PER && t < 3 * N * TT) {
+          const int j = t / (N * TT);
+          const int rem = t - j * N * TT;
+          const int kx = rem / TT, tt = rem - (rem / TT) * TT;
+          lds[j * CPS + kx * TP + tt] = val[u];
+        }
+      }
+    }
   }
   __syncthreads();
   auto pm = [](int line, int kx) {
@@ -288,12 +352,33 @@ __device__ __forceinline__ void slab_inv_body(const SlabInvArgs<T, TO>& a,
   const int grp = lb - x * NG;
   load_twiddles<T, N>(tw, a.tw);
   const ColMap<N> cm;
-  for (int t = threadIdx.x; t < CPB * N * H; t += blockDim.x) {
-    const int q = t / (N * H);
-    const int rem = t - q * N * H;
-    const int ky = rem / H, kz = rem - (rem / H) * H;
-    const int c = grp * CPB + q;
-    lds[cm(q * H + kz, ky)] = a.spec[((size_t)(c * N + x) * N + ky) * H + kz];
+  {
+    constexpr int PER = (CPB * N * H + kBlock - 1) / kBlock;
+    constexpr int CH = PER < kStage<T> ? PER : kStage<T>;
+    for (int c0 = 0; c0 < PER; c0 += CH) {
+      cplx<T> val[CH];
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int t = threadIdx.x + (c0 + u) * kBlock;
+        if (c0 + u < PER && t < CPB * N * H) {
+          const int q = t / (N * H);
+          const int rem = t - q * N * H;
+          const int ky = rem / H, kz = rem - (rem / H) * H;
+          const int c = grp * CPB + q;
+          val[u] = a.spec[((size_t)(c * N + x) * N + ky) * H + kz];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int t = threadIdx.x + (c0 + u) * kBlock;
+        if (c0 + u < PER && t < CPB * N * H) {
+          const int q = t / (N * H);
+          const int rem = t - q * N * H;
+          const int ky = rem / H, kz = rem - (rem / H) * H;
+          lds[cm(q * H + kz, ky)] = val[u];
+        }
+      }
+    }
   }
   __syncthreads();
   fft_lines<N, +1>(lds, tw, CPB * H, ColMap<N>());
@@ -318,21 +403,48 @@ __device__ __forceinline__ void slab_inv_body(const SlabInvArgs<T, TO>& a,
   fft_lines<N, +1>(lds, tw, CPB * H, RowMap<N>());
 
   double acc = 0.0;
-  for (int t = threadIdx.x; t < H * N; t += blockDim.x) {
-    const int yp = t / N, z = t - (t / N) * N;
+  {
+    // the p loads of a chunk are issued together (same order of the sum)
+    constexpr int PER = (H * N + kBlock - 1) / kBlock;
+    constexpr int CH = PER < kStage<T> ? PER : kStage<T>;
+    for (int c0 = 0; c0 < PER; c0 += CH) {
+      T pv[CH][CPB][2];
+      if constexpr (DST == DST_DOT) {
 #pragma unroll
-    for (int q = 0; q < CPB; ++q) {
-      const int c = grp * CPB + q;
-      const cplx<T> zz = lds[q * SlabGeom<N>::PLANE + yp * SlabGeom<N>::PITCH + z];
+        for (int u = 0; u < CH; ++u) {
+          const int t = threadIdx.x + (c0 + u) * kBlock;
+          if (c0 + u < PER && t < H * N) {
+            const int yp = t / N, z = t - (t / N) * N;
 #pragma unroll
-      for (int hh = 0; hh < 2; ++hh) {
-        const int64_t v = ((int64_t)x * N + yp + hh * H) * N + z;
-        const T val = hh ? zz.y : zz.x;
-        a.out[c * cs + v] = TO(val);
-        if constexpr (DST == DST_DOT) {
-          acc += double(a.pdot[c * cs + v]) * double(val);
-        } else {
-          acc += double(val) * double(val);
+            for (int q = 0; q < CPB; ++q)
+#pragma unroll
+              for (int hh = 0; hh < 2; ++hh) {
+                const int64_t v = ((int64_t)x * N + yp + hh * H) * N + z;
+                pv[u][q][hh] = a.pdot[(grp * CPB + q) * cs + v];
+              }
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int t = threadIdx.x + (c0 + u) * kBlock;
+        if (!(c0 + u < PER && t < H * N)) continue;
+        const int yp = t / N, z = t - (t / N) * N;
+#pragma unroll
+        for (int q = 0; q < CPB; ++q) {
+          const int c = grp * CPB + q;
+          const cplx<T> zz = lds[q * SlabGeom<N>::PLANE + yp * SlabGeom<N>::PITCH + z];
+#pragma unroll
+          for (int hh = 0; hh < 2; ++hh) {
+            const int64_t v = ((int64_t)x * N + yp + hh * H) * N + z;
+            const T val = hh ? zz.y : zz.x;
+            a.out[c * cs + v] = TO(val);
+            if constexpr (DST == DST_DOT) {
+              acc += double(pv[u][q][hh]) * double(val);
+            } else {
+              acc += double(val) * double(val);
+            }
+          }
         }
       }
     }
