@@ -84,7 +84,7 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 
 // items whose global loads are issued together before their LDS stores
 template <typename T>
-constexpr int kStage = sizeof(T) == 4 ? 8 : 2;
+constexpr int kStage = sizeof(T) == 4 ? 8 : 1;
 
 template <typename T, int N>
 __device__ __forceinline__ void load_twiddles(cplx<T>* tw,
