@@ -308,6 +308,8 @@ LawParams Engine::law_params(double dt) const {
   lp.c_af = params_[6];
   lp.d_af = params_[7];
   lp.dt = dt;
+  lp.inv_g = 1.0 / lp.g;
+  lp.inv_a = 1.0 / (dt * lp.gdot0);
   return lp;
 }
 

@@ -130,6 +130,7 @@ constexpr int kTabLam = 8, kTabMu = 9;
 
 struct LawParams {
   double gdot0, g, nexp, c_af, d_af, dt;
+  double inv_g, inv_a;   // 1/g and 1/(dt gdot0), formed once on the host
 };
 
 struct ConstArgs {

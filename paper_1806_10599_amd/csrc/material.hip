@@ -64,11 +64,11 @@ __device__ __forceinline__ void asinh_pow(double x, double n, double& val,
     const double yinv = exp(-n * lnx);
     const double q = sqrt(1.0 + yinv * yinv);
     val = sgn(x) * (n * lnx + log1p(q));
-    der = (n / ax) / q;
+    der = n / (ax * q);
   } else {
     const double y = exp(n * lnx);
     val = sgn(x) * asinh(y);
-    der = n * y / ax / sqrt(1.0 + y * y);
+    der = n * y / (ax * sqrt(1.0 + y * y));
   }
 }
 
@@ -149,12 +149,12 @@ __device__ __forceinline__ void cp_eval(const double* Fes,
     const double Sm2 = S[4] * m0 + S[3] * m1 + S[2] * m2;
     const double tau = s0 * Sm0 + s1 * Sm1 + s2 * Sm2;
     const double chi = (chi0[al] + lp.c_af * dg[al]) / (1.0 + lp.d_af * fabs(dg[al]));
-    const double x = (tau - chi) / lp.g;
+    const double x = (tau - chi) * lp.inv_g;
     double val, der;
     asinh_pow(x, lp.nexp, val, der);
     e.chi[al] = chi;
     e.h[al] = der;
-    e.R[al] = asinh(dg[al] / a) - val;
+    e.R[al] = asinh(dg[al] * lp.inv_a) - val;
   }
 }
 
@@ -192,6 +192,7 @@ __device__ __forceinline__ void make_V(const double* Q,
 // by compare-and-swap; the swap decisions are kept for later right-hand sides.
 struct LU6 {
   double M[36];
+  double ip[6];   // reciprocals of the pivots
   uint32_t swaps;
 };
 
@@ -217,6 +218,7 @@ __device__ __forceinline__ void lu6_factor(LU6& L) {
       ++bit;
     }
     const double inv = 1.0 / L.M[6 * k + k];
+    L.ip[k] = inv;
 #pragma unroll
     for (int r = k + 1; r < 6; ++r) {
       const double f = L.M[6 * r + k] * inv;
@@ -249,7 +251,7 @@ __device__ __forceinline__ void lu6_solve(const LU6& L, double* z) {
     double acc = z[k];
 #pragma unroll
     for (int j = k + 1; j < 6; ++j) acc -= L.M[6 * k + j] * z[j];
-    z[k] = acc / L.M[6 * k + k];
+    z[k] = acc * L.ip[k];
   }
 }
 
@@ -269,11 +271,12 @@ __device__ __forceinline__ void cp_jacobian(const CpEval& e, const double* Fes,
     const double h = e.h[al];
     const double ad = fabs(dg[al]);
     const double dchi = (lp.c_af - lp.d_af * sgn(dg[al]) * e.chi[al]) / (1.0 + lp.d_af * ad);
-    D[al] = 1.0 / sqrt(a * a + dg[al] * dg[al]) + h * dchi / lp.g;
-    hg[al] = h / lp.g;
+    hg[al] = h * lp.inv_g;
+    // D holds the reciprocal of the diagonal of the local Jacobian
+    D[al] = 1.0 / (1.0 / sqrt(a * a + dg[al] * dg[al]) + hg[al] * dchi);
     double V[6];
     make_V(Q, tb, al, V);
-    const double f = hg[al] / D[al];
+    const double f = hg[al] * D[al];
 #pragma unroll
     for (int I = 0; I < 6; ++I)
 #pragma unroll
@@ -284,7 +287,8 @@ __device__ __forceinline__ void cp_jacobian(const CpEval& e, const double* Fes,
 }
 
 // out = J^-1 rhs with J = diag(D) + U W^T, U_a = hg_a w N_a, W_a = V_a
-__device__ __forceinline__ void cp_jsolve(const double* rhs, const double* D,
+// (iD = 1/D from cp_jacobian)
+__device__ __forceinline__ void cp_jsolve(const double* rhs, const double* iD,
                                           const double* hg, const double* Q,
                                           const double* __restrict__ tb,
                                           const LU6& L, double* out) {
@@ -292,7 +296,7 @@ __device__ __forceinline__ void cp_jsolve(const double* rhs, const double* D,
   double z[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
   for (int al = 0; al < 12; ++al) {
-    out[al] = rhs[al] / D[al];
+    out[al] = rhs[al] * iD[al];
     double V[6];
     make_V(Q, tb, al, V);
 #pragma unroll
@@ -304,7 +308,7 @@ __device__ __forceinline__ void cp_jsolve(const double* rhs, const double* D,
     double u = 0.0;
 #pragma unroll
     for (int J = 0; J < 6; ++J) u += VW[J] * tb[kTabN + 6 * al + J] * z[J];
-    out[al] -= hg[al] * u / D[al];
+    out[al] -= hg[al] * u * iD[al];
   }
 }
 
@@ -403,11 +407,11 @@ __device__ __forceinline__ void pr_eval(const double* Fes,
     const double tau = s0 * Sm0 + s1 * Sm1 + s2 * Sm2;
     const double chi0 = opaque(chi0p)[(kOwn * h + j) * N];
     const double chi = (chi0 + lp.c_af * t) / (1.0 + lp.d_af * fabs(t));
-    const double x = (tau - chi) / lp.g;
+    const double x = (tau - chi) * lp.inv_g;
     double val, der;
     asinh_pow(x, lp.nexp, val, der);
     hd[j] = der;
-    R[j] = asinh(t / a) - val;
+    R[j] = asinh(t * lp.inv_a) - val;
   }
   make_Q(Fe, Fes, Q);
 }
@@ -430,19 +434,20 @@ __device__ __forceinline__ void pr_step(const double* dg, const double* R,
     const int al = kOwn * h + j;
     const double* __restrict__ tb = opaque(tb0);
     const double chi0 = opaque(chi0p)[al * N];
-    const double chi = (chi0 + lp.c_af * dg[j]) / (1.0 + lp.d_af * fabs(dg[j]));
-    const double dchi = (lp.c_af - lp.d_af * sgn(dg[j]) * chi) /
-                        (1.0 + lp.d_af * fabs(dg[j]));
-    D[j] = 1.0 / sqrt(a * a + dg[j] * dg[j]) + hd[j] * dchi / lp.g;
+    const double den = 1.0 / (1.0 + lp.d_af * fabs(dg[j]));
+    const double chi = (chi0 + lp.c_af * dg[j]) * den;
+    const double dchi = (lp.c_af - lp.d_af * sgn(dg[j]) * chi) * den;
+    // D holds the reciprocal of the diagonal of the local Jacobian
+    D[j] = 1.0 / (1.0 / sqrt(a * a + dg[j] * dg[j]) + hd[j] * lp.inv_g * dchi);
     double V[6];
     make_V(Q, tb, al, V);
-    const double f = (hd[j] / lp.g) / D[j];
+    const double f = hd[j] * lp.inv_g * D[j];
 #pragma unroll
     for (int I = 0; I < 6; ++I)
 #pragma unroll
       for (int J = 0; J < 6; ++J)
         L.M[6 * I + J] += V[I] * f * VW[J] * tb[kTabN + 6 * al + J];
-    step[j] = -R[j] / D[j];
+    step[j] = -R[j] * D[j];
   }
 #pragma unroll
   for (int i = 0; i < 36; ++i) L.M[i] = ((i % 7 == 0) ? 1.0 : 0.0) + grp_sum<LPV>(L.M[i]);
@@ -464,7 +469,7 @@ __device__ __forceinline__ void pr_step(const double* dg, const double* R,
     double u = 0.0;
 #pragma unroll
     for (int J = 0; J < 6; ++J) u += VW[J] * tb[J] * z[J];
-    step[j] -= (hd[j] / lp.g) * u / D[j];
+    step[j] -= hd[j] * lp.inv_g * u * D[j];
   }
 }
 
