@@ -100,6 +100,9 @@ def parse():
     ap.add_argument("--paper-workloads", action="store_true",
                     help="also run the paper's own R = 0 histories (a few "
                          "minutes)")
+    ap.add_argument("--no-forcing", action="store_true",
+                    help="chosen path solves every Newton iteration to "
+                         "cg_tol (no inexact-Newton forcing)")
     ap.add_argument("--no-umat", action="store_true",
                     help="skip the Appendix A bridge measurement")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -123,7 +126,7 @@ def copy_calibration(stream):
 
 def run_path(micro, hist, precision, use_graph, steps, warmup, stream,
              live=True, learned=False, start=None, cg_chunk=8,
-             with_fips=False):
+             with_fips=False, forcing=False):
     """Solve the history; time its last ``steps`` increments (at least
     ``warmup`` untimed increments come first)."""
     import torch
@@ -132,7 +135,8 @@ def run_path(micro, hist, precision, use_graph, steps, warmup, stream,
     from synthetic import material_params
     r = Rve(micro.n, projection="discrete", precision=precision,
             newton_tol=1e-6, cg_tol=1e-4, use_graph=use_graph, stream=stream,
-            warm_start=WARM_MODE if learned else 0, cg_chunk=cg_chunk)
+            warm_start=WARM_MODE if learned else 0, cg_chunk=cg_chunk,
+            cg_forcing=forcing)
     r.set_microstructure(micro.phase, micro.quat, micro.law, material_params())
     net = None
     if learned:
@@ -236,7 +240,7 @@ def batch_run(steps, stream):
     vox = sum(m.n ** 3 for m in micros)
     b = BatchRve([m.n for m in micros], projection=cfg.operator,
                  precision=cfg.precision, newton_tol=1e-6, cg_tol=1e-4,
-                 use_graph=True, stream=stream)
+                 use_graph=True, stream=stream, cg_forcing=True)
     for j, m in enumerate(micros):
         b.set_microstructure(j, m.phase, m.quat, m.law, material_params())
     torch.cuda.synchronize()
@@ -263,7 +267,7 @@ def batch_run(steps, stream):
     sig_s = []
     for m in micros:
         r = Rve(m.n, projection=cfg.operator, precision=cfg.precision,
-                newton_tol=1e-6, cg_tol=1e-4, stream=stream)
+                newton_tol=1e-6, cg_tol=1e-4, stream=stream, cg_forcing=True)
         r.set_microstructure(m.phase, m.quat, m.law, material_params())
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -308,7 +312,7 @@ def large_run(steps, stream):
     for mode in ("learned", "homogeneous"):
         r = run_path(micro, hist, "mixed", False, steps - 1, 1, stream,
                      live=False, learned=(mode == "learned"), start=1,
-                     with_fips=(mode == "learned"))
+                     with_fips=(mode == "learned"), forcing=True)
         n3 = micro.n ** 3
         out[mode] = dict(value=round(n3 * (steps - 1) / r["elapsed"], 1),
                          ms_per_step=round(1e3 * r["elapsed"] / (steps - 1), 3),
@@ -629,7 +633,8 @@ def main():
         chosen = run_path(micro, hist, "mixed", args.graph, args.steps,
                           args.warmup, stream, live=not args.no_live,
                           learned=not args.no_learned, start=args.start,
-                          cg_chunk=args.cg_chunk, with_fips=True)
+                          cg_chunk=args.cg_chunk, with_fips=True,
+                          forcing=not args.no_forcing)
         plain = None
         if not args.no_plain:
             plain = run_path(micro, hist, "fp64", False, args.steps,
@@ -662,6 +667,7 @@ def main():
                    "voxels": N, "precision": "mixed FP32 FFT/CG + FP64",
                    "graph": args.graph,
                    "cg_chunk": args.cg_chunk,
+                   "cg_forcing": not args.no_forcing,
                    "warm_start": ("homogeneous" if args.no_learned else
                                   "learned (weights/warmstart.npy), kept "
                                   "directly below half the homogeneous "

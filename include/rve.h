@@ -89,6 +89,12 @@ typedef struct {
   rve_alloc_fn dev_alloc;
   rve_free_fn dev_free;
   void* alloc_ctx;
+  int32_t cg_forcing;    /* 0: every linear solve to cg_tol; 1: Newton
+                            iteration k solves to min(0.1, max(cg_tol,
+                            newton_tol / (4 r_k))), r_k = ||G(P)||/||P|| at
+                            its start, i.e. only as far as reaching the
+                            equilibrium tolerance needs (per RVE in a
+                            batch)                                        */
 } rve_config;
 
 #define RVE_MAX_NEWTON_LOG 64
@@ -495,6 +501,24 @@ rve_status rve_batch_get_fields(rve_batch_t h, int32_t b, int32_t field,
                                 void* dst, size_t dst_bytes,
                                 int32_t dst_on_device);
 rve_status rve_batch_get_macro(rve_batch_t h, int32_t b, double out[29]);
+
+/* Host only (no device work, no GPU needed): the band lists that
+   rve_get_nonlocal_fips uses, for a microstructure of n^3 voxels (phase,
+   G, quat, law as in rve_set_microstructure), cell lengths L[3] and a band
+   width.  *bands receives the number of bands and *entries the total
+   length of their voxel lists.  When band_desc / band_vox are not NULL they
+   receive, for bands in (label, plane, j) order, [bands][4] = (label,
+   plane, j, voxels) and the concatenated ascending voxel indices; they
+   must hold cap_bands and cap_entries items (call once with NULL arrays to
+   learn the counts).  Errors: RVE_EINVAL (bad sizes, labels, quaternions,
+   width, or capacities below the counts). */
+rve_status rve_fip_band_lists(int32_t n, const double L[3],
+                              const int32_t* phase, int32_t G,
+                              const double* quat, const int32_t* law,
+                              double band_width, int64_t* bands,
+                              int64_t* entries, int32_t* band_desc,
+                              int32_t* band_vox, int64_t cap_bands,
+                              int64_t cap_entries);
 
 /* rve_get_nonlocal_fips for RVE b of a batch (same arguments and rules;
    labels is that RVE's G). */

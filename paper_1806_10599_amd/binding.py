@@ -53,7 +53,7 @@ class RveConfig(C.Structure):
                 ("cg_tol", C.c_double), ("cg_max_iter", C.c_int32),
                 ("cg_chunk", C.c_int32), ("stream", C.c_void_p),
                 ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
-                ("alloc_ctx", C.c_void_p)]
+                ("alloc_ctx", C.c_void_p), ("cg_forcing", C.c_int32)]
 
 
 class RveIncrementInfo(C.Structure):
@@ -122,6 +122,12 @@ def _load():
                                             C.c_void_p, C.c_int32,
                                             C.c_void_p, C.c_void_p,
                                             C.c_int64]),
+        "rve_fip_band_lists": (C.c_int, [C.c_int32, P(C.c_double),
+                                         P(C.c_int32), C.c_int32,
+                                         P(C.c_double), P(C.c_int32),
+                                         C.c_double, P(C.c_int64),
+                                         P(C.c_int64), C.c_void_p,
+                                         C.c_void_p, C.c_int64, C.c_int64]),
         "rve_batch_get_nonlocal_fips": (C.c_int, [C.c_void_p, C.c_int32,
                                                   C.c_double,
                                                   P(RveNonlocalFips),
@@ -257,9 +263,39 @@ def _nonlocal_fips(call, labels, band_width, arrays):
     return res
 
 
+def fip_band_lists(n, phase, quat, law, band_width, L=(1.0, 1.0, 1.0)):
+    """The slip bands of Eq. 26 as the library builds them (host code, no
+    GPU needed): a list of (label, plane, j, voxel indices) in (label,
+    plane, j) order."""
+    phase = np.ascontiguousarray(phase, dtype=np.int32).reshape(-1)
+    quat = np.ascontiguousarray(quat, dtype=np.float64).reshape(-1, 4)
+    law = np.ascontiguousarray(law, dtype=np.int32).reshape(-1)
+    Lc = np.ascontiguousarray(L, dtype=np.float64)
+    nb, ne = C.c_int64(), C.c_int64()
+    args = (int(n), _dptr(Lc), _iptr(phase), quat.shape[0], _dptr(quat),
+            _iptr(law), float(band_width))
+    rc = LIB.rve_fip_band_lists(*args, C.byref(nb), C.byref(ne), None, None,
+                                0, 0)
+    if rc != RVE_OK:
+        raise RveError(rc, LIB.rve_last_error(None).decode())
+    desc = np.zeros((max(nb.value, 1), 4), dtype=np.int32)
+    vox = np.zeros(max(ne.value, 1), dtype=np.int32)
+    rc = LIB.rve_fip_band_lists(*args, C.byref(nb), C.byref(ne),
+                                desc.ctypes.data_as(C.c_void_p),
+                                vox.ctypes.data_as(C.c_void_p), nb.value,
+                                ne.value)
+    if rc != RVE_OK:
+        raise RveError(rc, LIB.rve_last_error(None).decode())
+    out, e = [], 0
+    for g, p, j, cnt in desc[:nb.value]:
+        out.append((int(g), int(p), int(j), vox[e:e + cnt].copy()))
+        e += cnt
+    return out
+
+
 def _make_config(L, projection, precision, newton_tol, newton_max_iter, cg_tol,
                  cg_max_iter, cg_chunk, use_graph, warm_start, stream, device,
-                 torch_allocator):
+                 torch_allocator, cg_forcing=False):
     cfg = RveConfig()
     LIB.rve_config_default(C.byref(cfg))
     cfg.L[:] = tuple(float(x) for x in L)
@@ -274,6 +310,7 @@ def _make_config(L, projection, precision, newton_tol, newton_max_iter, cg_tol,
     if warm_start not in (0, 1, 2):
         raise ValueError("warm_start must be False/0, True/1 or 2")
     cfg.warm_start = int(warm_start)
+    cfg.cg_forcing = 1 if cg_forcing else 0
     torch.cuda.set_device(device)
     stream = stream if stream is not None else torch.cuda.current_stream()
     cfg.stream = C.c_void_p(stream.cuda_stream or None)
@@ -312,7 +349,7 @@ class Rve:
                  precision="fp64", newton_tol=1e-6, newton_max_iter=25,
                  cg_tol=1e-4, cg_max_iter=2000, cg_chunk=8, use_graph=False,
                  warm_start=False, stream=None, device=0,
-                 torch_allocator=True):
+                 torch_allocator=True, cg_forcing=False):
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the library runs on the GPU only")
         self._lib = LIB
@@ -320,7 +357,7 @@ class Rve:
         cfg, self.stream, self._alloc = _make_config(
             L, projection, precision, newton_tol, newton_max_iter, cg_tol,
             cg_max_iter, cg_chunk, use_graph, warm_start, stream, device,
-            torch_allocator)
+            torch_allocator, cg_forcing)
         nn = (n, n, n) if np.isscalar(n) else tuple(n)
         cfg.n[:] = nn
         self.cfg = cfg
@@ -603,7 +640,7 @@ class BatchRve:
     def __init__(self, ns, L=(1.0, 1.0, 1.0), projection="discrete",
                  precision="fp64", newton_tol=1e-6, newton_max_iter=25,
                  cg_tol=1e-4, cg_max_iter=2000, cg_chunk=8, use_graph=False,
-                 stream=None, device=0, torch_allocator=True):
+                 stream=None, device=0, torch_allocator=True, cg_forcing=False):
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the library runs on the GPU only")
         self._lib = LIB
@@ -611,7 +648,7 @@ class BatchRve:
         cfg, self.stream, self._alloc = _make_config(
             L, projection, precision, newton_tol, newton_max_iter, cg_tol,
             cg_max_iter, cg_chunk, use_graph, False, stream, device,
-            torch_allocator)
+            torch_allocator, cg_forcing)
         self.cfg = cfg
         self.ns = [int(x) for x in ns]
         arr = np.ascontiguousarray(self.ns, dtype=np.int32)

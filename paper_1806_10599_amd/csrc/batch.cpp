@@ -5,6 +5,8 @@
 // leaves the work of the following iterations.
 #include "batch.hpp"
 
+#include <algorithm>
+
 #include <array>
 #include <chrono>
 #include <cmath>
@@ -209,6 +211,7 @@ BatchEngine::BatchEngine(const rve_config& cfg, int count, const int32_t* n)
   host_tables_.resize(B_);
   label_count_.assign(B_, 0);
   have_micro_.assign(B_, false);
+  rel_.assign(B_, 0.0);
   label_off_.assign(B_, 0);
   Fbar_.resize(B_);
   Pbar_.resize(B_);
@@ -407,8 +410,13 @@ void BatchEngine::cg_iteration(int parity) {
 template <typename T>
 void BatchEngine::cg_solve(std::vector<int>& iters) {
   for (int b = 0; b < B_; ++b) {
+    // per-RVE linear-solve tolerance (cg_forcing: as tight as the
+    // equilibrium tolerance needs from this RVE's residual)
+    double eta = cfg_.cg_tol;
+    if (cfg_.cg_forcing && rel_[b] > 0.0)
+      eta = std::min(0.1, std::max(cfg_.cg_tol, 0.25 * cfg_.newton_tol / rel_[b]));
     sc_host_[b].max_iters = cfg_.cg_max_iter;
-    sc_host_[b].eta2bb = cfg_.cg_tol * cfg_.cg_tol;
+    sc_host_[b].eta2bb = eta * eta;
     sc_host_[b].done = sc_host_[b].inactive;
   }
   upload_scalars();
@@ -501,6 +509,7 @@ int BatchEngine::increment(const double* Fbar_all, double dt,
       Scalars& h = sc_host_[b];
       const double res = std::sqrt(h.res2), pn = std::sqrt(h.P2);
       const double rel = pn > 0 ? res / pn : 0.0;
+      rel_[b] = rel;
       if (it < RVE_MAX_NEWTON_LOG) loc[b].residual_history[it] = rel;
       if (it == 0) loc[b].predictor_residual = loc[b].plain_predictor_residual = rel;
       loc[b].residual_rel = rel;

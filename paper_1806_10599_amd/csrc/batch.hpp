@@ -64,6 +64,7 @@ class BatchEngine {
   std::vector<std::vector<int32_t>> host_phase_;
   std::vector<bool> have_micro_;
   std::vector<FipIndex> fips_;
+  std::vector<double> rel_;   // FP64 relative residual of the current iterate
   double params_[RVE_NPARAMS];
   bool have_params_ = false;
   // per-RVE control

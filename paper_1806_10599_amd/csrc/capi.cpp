@@ -1,5 +1,6 @@
 // extern "C" entry points declared in include/rve.h.  Every call converts
 // C++ errors to rve_status; a HIP runtime error poisons the handle.
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
@@ -7,6 +8,8 @@
 #include "../../include/rve.h"
 #include "batch.hpp"
 #include "engine.hpp"
+#include "fips.hpp"
+#include "tables.hpp"
 
 struct rve_s {
   rve::Engine* eng = nullptr;
@@ -471,6 +474,62 @@ rve_status rve_batch_get_fields(rve_batch_t h, int32_t b, int32_t field,
     h->eng->get_field(b, field, dst, dst_bytes, dst_on_device != 0);
     return RVE_OK;
   });
+}
+
+rve_status rve_fip_band_lists(int32_t n, const double L[3],
+                              const int32_t* phase, int32_t G,
+                              const double* quat, const int32_t* law,
+                              double band_width, int64_t* bands,
+                              int64_t* entries, int32_t* band_desc,
+                              int32_t* band_vox, int64_t cap_bands,
+                              int64_t cap_entries) {
+  try {
+    if (n < 1 || n > 1024 || !L || !phase || G < 1 || !quat || !law || !bands ||
+        !entries)
+      throw rve::Error(RVE_EINVAL, "bad arguments");
+    const int64_t N = (int64_t)n * n * n;
+    for (int64_t v = 0; v < N; ++v)
+      if (phase[v] < 0 || phase[v] >= G)
+        throw rve::Error(RVE_EINVAL, "phase label out of [0, G)");
+    for (int g = 0; g < G; ++g) {
+      if (law[g] != 0 && law[g] != 1) throw rve::Error(RVE_EINVAL, "unknown law id");
+      const double q2 = quat[4 * g] * quat[4 * g] + quat[4 * g + 1] * quat[4 * g + 1] +
+                        quat[4 * g + 2] * quat[4 * g + 2] + quat[4 * g + 3] * quat[4 * g + 3];
+      if (!(std::fabs(q2 - 1.0) < 1e-6)) throw rve::Error(RVE_EINVAL, "quaternion not unit");
+    }
+    // the slip-plane normals of the label tables do not depend on the
+    // material constants
+    const double dummy[RVE_NPARAMS] = {1, 0, 1, 1, 1, 1, 0, 0, 1, 0.25};
+    const std::vector<double> tab = rve::label_table(G, quat, law, dummy);
+    const rve::FipLists fl = rve::fip_lists(n, L, phase, tab.data(), G, band_width);
+    const int64_t ng = (int64_t)fl.grain_label.size();
+    const int64_t nb = (int64_t)fl.band_meta.size();
+    int64_t ne = 0;
+    for (int64_t b = 0; b < nb; ++b) ne += fl.segs[ng + b].len;
+    *bands = nb;
+    *entries = ne;
+    if (band_desc || band_vox) {
+      if (cap_bands < nb || cap_entries < ne)
+        throw rve::Error(RVE_EINVAL, "capacities below the counts");
+      int64_t e = 0;
+      for (int64_t b = 0; b < nb; ++b) {
+        const auto& m = fl.band_meta[b];
+        if (band_desc)
+          for (int i = 0; i < 4; ++i) band_desc[4 * b + i] = m[i];
+        const rve::FipSeg& sg = fl.segs[ng + b];
+        if (band_vox)
+          for (int32_t i = 0; i < sg.len; ++i) band_vox[e + i] = fl.vox[sg.off + i];
+        e += sg.len;
+      }
+    }
+    return RVE_OK;
+  } catch (const rve::Error& e) {
+    g_create_error = e.what();
+    return (rve_status)e.code;
+  } catch (const std::exception& e) {
+    g_create_error = e.what();
+    return RVE_EINVAL;
+  }
 }
 
 rve_status rve_batch_get_nonlocal_fips(rve_batch_t h, int32_t b,

@@ -1,6 +1,7 @@
 // RVE engine: buffers and the increment algorithm (see engine.hpp).
 #include "engine.hpp"
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -47,6 +48,8 @@ Engine::Engine(const rve_config& cfg) : cfg_(cfg) {
     throw Error(RVE_EINVAL, "unknown precision mode");
   if (cfg.warm_start < 0 || cfg.warm_start > 2)
     throw Error(RVE_EINVAL, "warm_start must be 0, 1 or 2");
+  if (cfg.cg_forcing != 0 && cfg.cg_forcing != 1)
+    throw Error(RVE_EINVAL, "cg_forcing must be 0 or 1");
   for (int d = 0; d < 3; ++d)
     if (!(cfg.L[d] > 0.0)) throw Error(RVE_EINVAL, "cell lengths must be > 0");
   if (!(cfg.newton_tol > 0.0) || cfg.newton_max_iter < 0 ||
@@ -586,9 +589,9 @@ void Engine::set_schedule(int cpb, int tt) {
 
 // CG on G(K : x) = b with b = -r64 (text after Eq. 16), from x = 0
 template <typename T>
-void Engine::cg_solve(int& iters, bool& breakdown) {
+void Engine::cg_solve(int& iters, bool& breakdown, double eta) {
   if (!sched_cpb_) autotune<T>();
-  launch_init_scalars(sc_, cfg_.cg_max_iter, cfg_.cg_tol, st_);
+  launch_init_scalars(sc_, cfg_.cg_max_iter, eta, st_);
   launch_cg_init<T>(r64_, (T*)r_, (T*)x_, partial_red_, kRedBlocks, 9 * N_, st_);
   launch_reduce(RED_INIT, partial_red_, kRedBlocks, nullptr, nullptr, 0, 0.0,
                 sc_, nullptr, st_);
@@ -738,13 +741,19 @@ int Engine::increment(const double Fbar_new[9], double dt,
     }
     int iters = 0;
     bool bd = false;
+    // linear-solve tolerance: fixed, or (cg_forcing) only as tight as the
+    // equilibrium tolerance needs from this residual, never tighter than
+    // cg_tol
+    double eta = cfg_.cg_tol;
+    if (cfg_.cg_forcing && rel > 0.0)
+      eta = std::min(0.1, std::max(cfg_.cg_tol, 0.25 * cfg_.newton_tol / rel));
     if (fp64_) {
       tangent<double>(dt);
-      cg_solve<double>(iters, bd);
+      cg_solve<double>(iters, bd, eta);
       launch_add_to_F<double>(F_, (const double*)x_, 9 * N_, st_);
     } else {
       tangent<float>(dt);
-      cg_solve<float>(iters, bd);
+      cg_solve<float>(iters, bd, eta);
       launch_add_to_F<float>(F_, (const float*)x_, 9 * N_, st_);
     }
     RVE_HIP(hipGetLastError());

@@ -78,7 +78,7 @@ class Engine {
   void release(void* p);
   void free_all();
   template <typename T>
-  void cg_solve(int& iters, bool& breakdown);
+  void cg_solve(int& iters, bool& breakdown, double eta);
   template <typename T>
   void cg_iteration(int parity);
   template <typename T, typename Run>

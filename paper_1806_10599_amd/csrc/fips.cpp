@@ -23,12 +23,14 @@ void FipIndex::ensure(void** p, size_t& cap, size_t bytes, const Alloc& alloc,
 }
 
 #pragma clang fp contract(off)
-void FipIndex::build(int n, const double L[3], const int32_t* phase,
-                     const double* table, int G, double width,
-                     const Alloc& alloc, const Release& release) {
+FipLists fip_lists(int n, const double L[3], const int32_t* phase,
+                   const double* table, int G, double width) {
   if (!(width > 0.0) || !std::isfinite(width))
     throw Error(RVE_EINVAL, "band width must be finite and > 0");
-  built_ = false;
+  FipLists out;
+  auto& segs = out.segs;
+  auto& grain_label_ = out.grain_label;
+  auto& band_meta_ = out.band_meta;
   const int64_t N = (int64_t)n * n * n;
   std::vector<int64_t> first(G, -1), count(G, 0);
   auto crystal = [&](int g) { return table[(size_t)g * kTableStride] == 0.0; };
@@ -76,9 +78,6 @@ void FipIndex::build(int n, const double L[3], const int32_t* phase,
   }
   // grain segments (crystal labels with voxels, ascending label), then band
   // segments ordered by (label, plane, j); voxels ascending in each
-  grain_label_.clear();
-  band_meta_.clear();
-  std::vector<FipSeg> segs;
   std::vector<int64_t> goff(G, -1);
   int64_t off = 0;
   for (int g = 0; g < G; ++g) {
@@ -123,7 +122,8 @@ void FipIndex::build(int n, const double L[3], const int32_t* phase,
         off += ccount[c];
       }
     }
-  std::vector<int32_t> vox(off > 0 ? off : 1);
+  std::vector<int32_t>& vox = out.vox;
+  vox.assign(off > 0 ? off : 1, 0);
   std::vector<int64_t> gfill(G, 0);
   std::vector<int64_t> cfill(cells, 0);
   for (int64_t v = 0; v < N; ++v) {
@@ -137,7 +137,21 @@ void FipIndex::build(int n, const double L[3], const int32_t* phase,
     }
   }
   (void)grain_total;
+  out.entries = off;
+  return out;
+}
+#pragma clang fp contract(on)
+
+void FipIndex::build(int n, const double L[3], const int32_t* phase,
+                     const double* table, int G, double width,
+                     const Alloc& alloc, const Release& release) {
+  built_ = false;
+  FipLists fl = fip_lists(n, L, phase, table, G, width);
+  grain_label_ = std::move(fl.grain_label);
+  band_meta_ = std::move(fl.band_meta);
   const size_t ng = grain_label_.size(), nb = band_meta_.size();
+  const auto& vox = fl.vox;
+  const auto& segs = fl.segs;
   ensure((void**)&vox_, vox_cap_, vox.size() * sizeof(int32_t), alloc, release);
   ensure((void**)&seg_, seg_cap_, (segs.size() + 1) * sizeof(FipSeg), alloc, release);
   ensure((void**)&res_, res_cap_, (2 * ng + nb + 1) * sizeof(double), alloc, release);
@@ -152,7 +166,7 @@ void FipIndex::build(int n, const double L[3], const int32_t* phase,
   width_ = width;
   built_ = true;
 }
-#pragma clang fp contract(on)
+
 
 void FipIndex::evaluate(const double* pcyc, const double* pcyc_lit,
                         const double* w, int64_t cstride, int64_t base,

@@ -41,6 +41,19 @@ void launch_fip_band_means(const int32_t* vox, const FipSeg* seg, int nseg,
                            double* val, int32_t* sys, hipStream_t s);
 void launch_fip_argmax(const double* v, int64_t n, FipMax* out, hipStream_t s);
 
+// host band lists (no device work): grain segments (ascending label), then
+// band segments in (label, plane, j) order, offsets into vox; vox holds the
+// voxel indices of every segment, ascending within a segment
+struct FipLists {
+  std::vector<FipSeg> segs;
+  std::vector<int32_t> vox;
+  std::vector<int32_t> grain_label;                  // per grain segment
+  std::vector<std::array<int32_t, 4>> band_meta;     // label, plane, j, len
+  int64_t entries = 0;                               // used entries of vox
+};
+FipLists fip_lists(int n, const double L[3], const int32_t* phase,
+                   const double* table, int G, double width);
+
 class FipIndex {
  public:
   using Alloc = std::function<void*(size_t)>;

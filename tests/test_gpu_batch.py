@@ -35,8 +35,8 @@ def _micros():
             make_microstructure(16, 4, 14)]
 
 
-def _run_single(micro, hist, operator, precision):
-    r = make_rve(micro, operator, precision)
+def _run_single(micro, hist, operator, precision, **kw):
+    r = make_rve(micro, operator, precision, **kw)
     try:
         out = []
         for inc in hist:
@@ -49,11 +49,15 @@ def _run_single(micro, hist, operator, precision):
         r.close()
 
 
-@pytest.mark.parametrize("operator", ["continuous", "discrete"])
-def test_batch_fp64_matches_single_rves(operator):
+@pytest.mark.parametrize("operator,forcing", [("continuous", False),
+                                              ("discrete", False),
+                                              ("discrete", True)])
+def test_batch_fp64_matches_single_rves(operator, forcing):
+    # with cg_forcing each RVE of the batch takes its own linear-solve
+    # tolerances, the same as a single handle would
     micros = _micros()
     hist = config_by_name("C1").history()[:4]
-    b = _batch(micros, operator, "fp64")
+    b = _batch(micros, operator, "fp64", cg_forcing=forcing)
     try:
         binfo = []
         for inc in hist:
@@ -61,7 +65,8 @@ def test_batch_fp64_matches_single_rves(operator):
                 b.reset_fips()
             binfo.append(b.increment(inc["F_bar"], inc["dt"]))
         for j, m in enumerate(micros):
-            sinfo, sf, smac = _run_single(m, hist, operator, "fp64")
+            sinfo, sf, smac = _run_single(m, hist, operator, "fp64",
+                                          cg_forcing=forcing)
             for k in range(len(hist)):
                 assert binfo[k][j]["status"] == 0
                 assert binfo[k][j]["newton_iters"] == sinfo[k]["newton_iters"]

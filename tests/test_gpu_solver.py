@@ -306,3 +306,36 @@ def test_full_size_chosen_path_sampled_against_oracle():
         r.attach_warm_start(None)
         r.close()
         net.close()
+
+
+def test_cg_forcing_reaches_the_same_equilibrium_with_fewer_cg_iterations():
+    """cg_forcing = 1 solves Newton iteration k only to
+    min(0.1, max(cg_tol, newton_tol / (4 r_k))): every increment still ends
+    at ||G(P)|| <= tol ||P|| (FP64), the macroscopic stress agrees with the
+    fixed-tolerance run to the equilibrium tolerance, and the CG count
+    drops."""
+    from paper_1806_10599_amd.binding import Rve
+    c = config_by_name("C2")
+    micro = c.microstructure()
+    hist = c.history()[:12]
+    runs = {}
+    for forcing in (False, True):
+        r = Rve(micro.n, projection=c.operator, precision="mixed",
+                newton_tol=1e-6, cg_tol=1e-4, cg_forcing=forcing)
+        r.set_microstructure(micro.phase, micro.quat, micro.law,
+                             material_params())
+        try:
+            infos = []
+            for inc in hist:
+                info = r.increment(inc["F_bar"], inc["dt"])
+                assert info["status"] == 0
+                assert info["residual_rel"] <= 1e-6
+                infos.append(info)
+            runs[forcing] = infos
+        finally:
+            r.close()
+    cg = {k: sum(i["cg_iters_total"] for i in v) for k, v in runs.items()}
+    assert cg[True] < 0.95 * cg[False], cg
+    for a, b in zip(runs[False], runs[True]):
+        sa, sb = a["sigma_bar"][0, 0], b["sigma_bar"][0, 0]
+        assert abs(sa - sb) <= 1e-5 * max(abs(sa), 1.0)
