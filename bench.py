@@ -100,6 +100,11 @@ def parse():
     ap.add_argument("--paper-workloads", action="store_true",
                     help="also run the paper's own R = 0 histories (a few "
                          "minutes)")
+    ap.add_argument("--fft-schedule", default=None,
+                    help="force the CG-matvec FFT schedule of the chosen path "
+                         "as CPB,TT (e.g. 1,8) instead of tuning it; counter "
+                         "runs serialize kernels, which makes tuning there "
+                         "meaningless")
     ap.add_argument("--no-forcing", action="store_true",
                     help="chosen path solves every Newton iteration to "
                          "cg_tol (no inexact-Newton forcing)")
@@ -126,7 +131,7 @@ def copy_calibration(stream):
 
 def run_path(micro, hist, precision, use_graph, steps, warmup, stream,
              live=True, learned=False, start=None, cg_chunk=8,
-             with_fips=False, forcing=False):
+             with_fips=False, forcing=False, schedule=None):
     """Solve the history; time its last ``steps`` increments (at least
     ``warmup`` untimed increments come first)."""
     import torch
@@ -138,6 +143,8 @@ def run_path(micro, hist, precision, use_graph, steps, warmup, stream,
             warm_start=WARM_MODE if learned else 0, cg_chunk=cg_chunk,
             cg_forcing=forcing)
     r.set_microstructure(micro.phase, micro.quat, micro.law, material_params())
+    if schedule:
+        r.set_fft_schedule(*schedule)
     net = None
     if learned:
         net = WarmStartNet(stream=stream)
@@ -379,6 +386,8 @@ def _run_history(micro, hist, precision, operator, stream, adaptive=False,
             newton_tol=1e-6, cg_tol=1e-4, stream=stream,
             warm_start=WARM_MODE if learned else 0)
     r.set_microstructure(micro.phase, micro.quat, micro.law, material_params())
+    if schedule:
+        r.set_fft_schedule(*schedule)
     net = None
     if learned:
         net = WarmStartNet(stream=stream)
@@ -634,7 +643,10 @@ def main():
                           args.warmup, stream, live=not args.no_live,
                           learned=not args.no_learned, start=args.start,
                           cg_chunk=args.cg_chunk, with_fips=True,
-                          forcing=not args.no_forcing)
+                          forcing=not args.no_forcing,
+                          schedule=(tuple(int(x) for x in
+                                          args.fft_schedule.split(","))
+                                    if args.fft_schedule else None))
         plain = None
         if not args.no_plain:
             plain = run_path(micro, hist, "fp64", False, args.steps,
