@@ -108,7 +108,10 @@ Engine::Engine(const rve_config& cfg) : cfg_(cfg) {
   RVE_HIP(hipMemsetAsync(sc_, 0, sizeof(Scalars), st_));
   phase_ = (int32_t*)alloc(N_ * sizeof(int32_t));
   table_ = nullptr;
-  RVE_HIP(hipHostMalloc((void**)&sc_host_, sizeof(Scalars), hipHostMallocDefault));
+  // slot 0: synchronous reads; slots 1, 2: the CG chunks' look-ahead reads
+  RVE_HIP(hipHostMalloc((void**)&sc_host_, 3 * sizeof(Scalars), hipHostMallocDefault));
+  RVE_HIP(hipEventCreateWithFlags(&chunk_ev_[0], hipEventDisableTiming));
+  RVE_HIP(hipEventCreateWithFlags(&chunk_ev_[1], hipEventDisableTiming));
 
   std::vector<double> tw = twiddles(n_);
   std::vector<float> tw32(tw.begin(), tw.end());
@@ -141,6 +144,8 @@ Engine::~Engine() {
   if (st_) hipStreamSynchronize(st_);
   free_all();
   if (sc_host_) hipHostFree(sc_host_);
+  for (hipEvent_t e : chunk_ev_)
+    if (e) hipEventDestroy(e);
   if (own_stream_) hipStreamDestroy(own_stream_);
 }
 
@@ -596,9 +601,12 @@ void Engine::cg_solve(int& iters, bool& breakdown, double eta) {
   launch_reduce(RED_INIT, partial_red_, kRedBlocks, nullptr, nullptr, 0, 0.0,
                 sc_, nullptr, st_);
   RVE_HIP(hipGetLastError());
-  Scalars h;
+  // Chunks are queued one ahead of the host's convergence check: chunk k+1
+  // is enqueued before the scalars of chunk k are waited for, so the device
+  // never idles during that round trip.  A chunk queued after convergence
+  // does nothing (every CG kernel returns at once when `done` is set).
   int parity = 0;
-  for (;;) {
+  auto enqueue = [&](int slot) {
     if (cfg_.use_graph) {
       if (!graph_) capture_graph<T>();
       RVE_HIP(hipGraphLaunch(graph_, st_));
@@ -609,12 +617,24 @@ void Engine::cg_solve(int& iters, bool& breakdown, double eta) {
         parity ^= 1;
       }
       launch_cg_close(partial_red_, kRedBlocks, sc_, st_);
-      RVE_HIP(hipGetLastError());
     }
-    read_scalars(h);
-    timer_.flush();
+    RVE_HIP(hipMemcpyAsync(sc_host_ + 1 + slot, sc_, sizeof(Scalars),
+                           hipMemcpyDeviceToHost, st_));
+    RVE_HIP(hipEventRecord(chunk_ev_[slot], st_));
+    RVE_HIP(hipGetLastError());
+  };
+  Scalars h;
+  int k = 0;
+  enqueue(0);
+  for (;;) {
+    enqueue((k + 1) & 1);
+    RVE_HIP(hipEventSynchronize(chunk_ev_[k & 1]));
+    h = sc_host_[1 + (k & 1)];
     if (h.done) break;
+    ++k;
   }
+  // the live timings of this solve are read at the next synchronous scalar
+  // read, once the queued chunk has drained
   iters = h.iters;
   breakdown = h.breakdown != 0;
 }

@@ -125,7 +125,8 @@ class Engine {
   void* spec64_;      // complex double (aliases spec_ in fp64 mode)
   double *partial_inv_, *partial_red_, *psum_, *psq_, *pbar_;
   Scalars* sc_;
-  Scalars* sc_host_ = nullptr;
+  Scalars* sc_host_ = nullptr;          // pinned: [0] sync reads, [1..2] chunks
+  hipEvent_t chunk_ev_[2] = {nullptr, nullptr};
   int32_t* phase_;
   double* table_;
   void *tw32_, *tw64_, *vt32_, *vt64_;

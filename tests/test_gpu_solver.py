@@ -188,15 +188,17 @@ def test_live_kernel_timing_counts_and_leaves_results_unchanged(graph):
         t = b.kernel_timing(reset=True)
         assert t["return_map"][1] == evals and t["residual_fp64"][1] == evals
         assert t["tangent"][1] == newton
+        # launches past convergence: the rest of the converging chunk and
+        # the chunk queued ahead of the host check (they return at once)
         chunk = 8
         for k in ("matvec_kp", "matvec_pass_a", "matvec_pass_b",
                   "matvec_pass_c", "cg_update"):
             ms, n = t[k]
             assert ms > 0.0
             if graph:   # whole chunks are replayed
-                assert n % chunk == 0 and cg <= n < cg + chunk * newton
+                assert n % chunk == 0 and cg <= n < cg + 2 * chunk * newton
             else:
-                assert cg <= n < cg + chunk * newton
+                assert cg <= n < cg + 2 * chunk * newton
         assert all(v == (0.0, 0) for v in b.kernel_timing().values())
         cnt = b.return_map_counts(reset=True)
         assert cnt["crystal"] + cnt["particle"] == evals * micro.n ** 3
