@@ -49,27 +49,23 @@ __device__ __forceinline__ double sgn(double x) {
   return (x > 0.0) ? 1.0 : ((x < 0.0) ? -1.0 : 0.0);
 }
 
-// asinh(|x|^n sign x) and its derivative; for |x|^n > 1 the identity
-// asinh(y) = ln y + ln(1 + sqrt(1 + y^-2)) avoids forming the power.
+// asinh(|x|^n sign x) and its derivative, without branches: with
+// y = |x|^n and s = min(y, 1/y) = exp(-|n ln|x||),
+//   y >= 1: asinh(y) = n ln|x| + log1p(q),                q = sqrt(1 + s^2)
+//   y <  1: asinh(y) = log1p(s + s^2 / (1 + q))
+// (both exact; the first never forms the power), and
+// d asinh(y)/dx = (n / |x|) y / sqrt(1 + y^2) = (n / |x|) (y >= 1 ? 1 : s) / q.
+// Every lane of a wavefront runs the same instructions whatever its regime.
 __device__ __forceinline__ void asinh_pow(double x, double n, double& val,
                                           double& der) {
   const double ax = fabs(x);
-  if (ax == 0.0) {
-    val = 0.0;
-    der = 0.0;
-    return;
-  }
-  const double lnx = log(ax);
-  if (n * lnx > 0.0) {
-    const double yinv = exp(-n * lnx);
-    const double q = sqrt(1.0 + yinv * yinv);
-    val = sgn(x) * (n * lnx + log1p(q));
-    der = n / (ax * q);
-  } else {
-    const double y = exp(n * lnx);
-    val = sgn(x) * asinh(y);
-    der = n * y / (ax * sqrt(1.0 + y * y));
-  }
+  const double e = n * log(ax);          // ln y (-inf at x = 0)
+  const bool big = e > 0.0;
+  const double s = exp(-fabs(e));        // 0 at x = 0
+  const double q = sqrt(1.0 + s * s);
+  const double L = log1p(big ? q : s + s * s / (1.0 + q));
+  val = sgn(x) * ((big ? e : 0.0) + L);
+  der = (ax > 0.0) ? (n / ax) * (big ? 1.0 : s) / q : 0.0;
 }
 
 __device__ __forceinline__ void mm3(const double* A, const double* B,
