@@ -117,6 +117,27 @@ def parse():
     return ap.parse_args()
 
 
+def copy_bandwidth(stream, nbytes=1 << 30, reps=10):
+    """Achievable HBM bandwidth on this GPU: a plain device-to-device copy of
+    nbytes (read + write counted), timed with events on the stream."""
+    import torch
+    with torch.cuda.stream(stream):
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        b.copy_(a)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(
+            enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            b.copy_(a)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / reps
+    del a, b
+    return round(2 * nbytes / sec / 1e9, 1)
+
+
 def copy_calibration(stream):
     """A plain copy kernel of known size: reads and writes 2^26 floats."""
     import torch
@@ -531,8 +552,15 @@ def oracle_sample(micro, hist, gpu_infos, budget_s):
     newton = np.mean([i["newton_iters"] for i in gpu_infos])
     cgit = np.mean([i["cg_iters_total"] for i in gpu_infos])
     sec_per_inc = (newton + 1) * (t_const + t_res) + cgit * t_mv
+    cpu = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next(l.split(":", 1)[1].strip() for l in f
+                       if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return dict(value=o.N / sec_per_inc, unit="voxel-increments/s",
-                cores=len(os.sched_getaffinity(0)), kind="oracle",
+                cores=len(os.sched_getaffinity(0)), kind="oracle", cpu=cpu,
                 sample=(f"64^3 increment 1 building blocks on this host: "
                         f"1 constitutive eval {t_const:.2f}s, 1 FP64 residual "
                         f"{t_res:.2f}s, {reps} CG matvecs {t_mv:.2f}s each; "
@@ -732,6 +760,14 @@ def main():
             out["paper_workloads"] = paper_workloads(stream)
     if calib:
         out["copy_calibration"] = calib
+    cbw = copy_bandwidth(stream)
+    out["measured_copy_gbps"] = cbw
+    if out.get("roofline") and out["roofline"].get("unit") == "GB/s":
+        out["roofline"]["frac_of_measured_copy"] = round(
+            out["roofline"]["achieved"] / cbw, 4)
+    if out.get("cg_passes"):
+        out["cg_passes"]["fft_projection_passes"]["frac_of_measured_copy"] = \
+            round(out["cg_passes"]["fft_projection_passes"]["gbps"] / cbw, 3)
     if not args.no_cpu:
         # the oracle implements the homogeneous-predictor method: scale its
         # sample by the plain path's counts when they are there
