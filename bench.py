@@ -46,12 +46,12 @@ FP64_PEAK_TFLOPS = 78.6
 # path (each datum read or written once; the packed half spectrum of nine
 # components is 9 x n^3/2 complex = 36 B per voxel)
 PASS_BYTES_F32 = {
-    # K (81 floats), r, p_old in; p, K:p out
-    "matvec_kp": 4 * (81 + 9 + 9 + 9 + 9),
+    # K (81 floats), r, p_old, x in; p, K:p, x out (the previous iteration's
+    # x += alpha p_old rides on the direction kernel)
+    "matvec_kp": 4 * (81 + 9 + 9 + 9 + 9 + 9 + 9),
     "matvec_pass_a": 4 * 9 + 36,                    # K:p in, half spectrum out
     "matvec_pass_b": 36 + 36,                       # spectrum in and out
-    "matvec_pass_c": 36 + 4 * 9 + 4 * 9,            # spectrum, p in; Ap out
-    "cg_update": 4 * 9 * 6,                         # x, r, p, Ap in; x, r out
+    "matvec_pass_c": 36 + 4 * 9 + 4 * 9,            # spectrum, r in; r out
 }
 # algorithmic FP64 flops of the return mapping (add, mul, div, sqrt and each
 # elementary function count 1; a fused multiply-add counts 2): per residual

@@ -349,14 +349,18 @@ rve_status rve_debug_set_field(rve_t h, int32_t field, const double* src,
    stream, using the launch configuration and buffers of the last increment
    (needs at least one committed increment).  ms_out[count], count <= 8,
    indexed by kernel class:
-     0 matvec pass A (forward z/y FFTs of K:p),
+     0 matvec pass A (forward z/y FFTs of K:p; publishes the CG step
+       alpha = r.r / p.(K:p), equal to r.r / p.G(K:p) since p lies in the
+       range of the orthogonal projection G),
      1 pass B (x FFTs and the projection of Sec. 2.2),
-     2 pass C (inverse y/z FFTs and p.Ap),
-     3 CG vector update,
+     2 pass C (inverse y/z FFTs, r -= alpha G(K:p) and the new r.r),
+     3 unused (the CG vector update rides on classes 2 and 7; reported
+       as 0),
      4 FP64 return mapping (Sec. 3.2, Eq. 22),
      5 tangent (Eq. 13),
      6 FP64 residual G(P) (Eq. 11; three kernels),
-     7 CG direction and K:p (Eqs. 15-16).
+     7 CG direction, the previous iteration's x += alpha p and K:p
+       (Eqs. 15-16).
    Only scratch buffers are written; the committed state is untouched. */
 rve_status rve_bench_kernels(rve_t h, int32_t reps, double* ms_out,
                              int32_t count);

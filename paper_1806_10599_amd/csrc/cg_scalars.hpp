@@ -49,6 +49,8 @@ __device__ __forceinline__ void cg_scalar_update(int op, double tot,
     sc->done = sc->converged;
     sc->alpha = 0.0;
     sc->beta = 0.0;
+    sc->alphas[0] = sc->alphas[1] = 0.0;
+    sc->halt[0] = sc->halt[1] = 0;
   } else if (op == RED_ALPHA) {
     sc->pAp = tot;
     if (!(tot > 0.0) || !isfinite(tot)) {
@@ -116,6 +118,7 @@ __device__ __forceinline__ BetaStep cg_beta_consume(const double* partial,
     if (conv) sc->converged = 1;
     if (d.stop) {
       sc->done = 1;
+      sc->halt[p] = 1;
     } else {
       sc->beta = d.beta;
       sc->rr = rr;
@@ -149,6 +152,31 @@ __device__ __forceinline__ AlphaStep cg_alpha_consume(const double* partial,
     }
   }
   return d;
+}
+
+// In block 0 of the forward pass of parity p: reduce the p.(K:p) partials of
+// the direction kernel and publish alpha_k = r.r / p.(K:p).  Since p lies in
+// the range of the projection G (r and every direction are outputs of G, up
+// to rounding) and G is an orthogonal projection, p.G(K:p) = p.(K:p): alpha
+// is known before the FFT passes, and the inverse pass can apply
+// r -= alpha G(K:p) itself.
+__device__ __forceinline__ void cg_alpha_publish(const double* partial,
+                                                 int count, Scalars* sc,
+                                                 int p, double* red) {
+  const double pAp = cg_sum_partials(partial, count, red);
+  if (threadIdx.x == 0) {
+    sc->pAp = pAp;
+    if (!(pAp > 0.0) || !isfinite(pAp)) {
+      sc->breakdown = 1;
+      sc->done = 1;
+      sc->halt[p] = 1;
+      sc->iters = sc->its[p] + 1;
+    } else {
+      const double al = sc->rrs[p] / pAp;
+      sc->alpha = al;
+      sc->alphas[p] = al;
+    }
+  }
 }
 
 }  // namespace rve

@@ -100,6 +100,11 @@ struct Scalars {
   // completed updates published by the direction kernel of parity q
   double rrs[2];
   int32_t its[2];
+  // alpha of the iteration of parity q (published by its forward pass), and
+  // whether the CG run has stopped as of that iteration (no update may
+  // follow: the direction kernel of the next iteration returns at once)
+  double alphas[2];
+  int32_t halt[2];
 };
 
 constexpr int kBlock = 256;

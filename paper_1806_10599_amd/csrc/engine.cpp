@@ -93,7 +93,6 @@ Engine::Engine(const rve_config& cfg) : cfg_(cfg) {
   r_ = alloc(9 * N_ * tsz);
   p0_ = alloc(9 * N_ * tsz);
   p1_ = alloc(9 * N_ * tsz);
-  Ap_ = alloc(9 * N_ * tsz);
   Kp_ = alloc(9 * N_ * tsz);
   spec_ = alloc(9 * N_ / 2 * 2 * tsz);
   spec64_ = fp64_ ? spec_ : alloc(9 * N_ / 2 * 2 * sizeof(double));
@@ -102,6 +101,7 @@ Engine::Engine(const rve_config& cfg) : cfg_(cfg) {
   // room for the partials of any schedule (one component per slab block)
   partial_inv_ = (double*)alloc(9 * n_ * sizeof(double));
   partial_red_ = (double*)alloc(kRedBlocks * sizeof(double));
+  partial_kp_ = (double*)alloc(kKpMaxBlocks * sizeof(double));
   psum_ = (double*)alloc(9 * n_ * sizeof(double));
   psq_ = (double*)alloc(9 * n_ * sizeof(double));
   sc_ = (Scalars*)alloc(sizeof(Scalars));
@@ -414,13 +414,16 @@ void Engine::cg_iteration_steps(int parity, Run&& run) {
   const bool dbl = sizeof(T) == sizeof(double);
   T* p_new = (T*)(parity ? p0_ : p1_);
   const int nslab = slab_blocks(n_, dbl, sched_cpb_);
-  // beta from the last update's r.r partials, p = r + beta p_old and
-  // y = K : p in one streaming pass, then G(y)
+  // beta from the last inverse pass's r.r partials, the previous
+  // iteration's x += alpha p_old, p = r + beta p_old and y = K : p with the
+  // p . y partials, in one streaming pass
   run(7, [&] {
     launch_kp<T>((const T*)K_, (const T*)r_, (const T*)(parity ? p1_ : p0_),
-                 p_new, (T*)Kp_, sc_, N_, st_, partial_red_, kRedBlocks,
-                 parity);
+                 p_new, (T*)Kp_, sc_, N_, st_, partial_inv_, nslab, parity,
+                 (T*)x_, partial_kp_);
   });
+  // G(y); pass A publishes alpha = r.r / p.y, pass C applies r -= alpha G(y)
+  // and writes the new r.r partials
   SpectralLaunch<T> L;
   L.src = SRC_FIELD;
   L.in_field = (const T*)Kp_;
@@ -428,8 +431,11 @@ void Engine::cg_iteration_steps(int parity, Run&& run) {
   L.spec = (cplx<T>*)spec_;
   L.tw = (const cplx<T>*)(dbl ? tw64_ : tw32_);
   L.vt = (const T*)(dbl ? vt64_ : vt32_);
-  L.dst = DST_DOT;
-  L.out_T = (T*)Ap_;
+  L.dst = DST_CG;
+  L.r_io = (T*)r_;
+  L.pkp = partial_kp_;
+  L.pkp_count = kp_blocks(N_);
+  L.parity = parity;
   L.partial_inv = partial_inv_;
   L.sc = sc_;
   L.cpb = sched_cpb_;
@@ -444,12 +450,6 @@ void Engine::cg_iteration_steps(int parity, Run&& run) {
   } else {
     run(-1, [&] { launch_G<T>(n_, L, st_); });
   }
-  // alpha from the p.Ap partials of pass C, then x += alpha p, r -= alpha Ap
-  run(3, [&] {
-    launch_cg_update<T>((T*)x_, (T*)r_, L.p_new, (const T*)Ap_, sc_,
-                        partial_red_, kRedBlocks, 9 * N_, st_, partial_inv_,
-                        nslab, parity);
-  });
 }
 
 template <typename T>
@@ -472,7 +472,8 @@ void Engine::capture_graph() {
   if (!(timer_.mask() & kCgClasses)) {
     RVE_HIP(hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal));
     for (int j = 0; j < cfg_.cg_chunk; ++j) cg_iteration<T>(j & 1);
-    launch_cg_close(partial_red_, kRedBlocks, sc_, st_);
+    launch_cg_close(partial_inv_, slab_blocks(n_, sizeof(T) == 8, sched_cpb_),
+                    sc_, st_);
     RVE_HIP(hipStreamEndCapture(st_, &graph_def_));
   } else {
     RVE_HIP(hipGraphCreate(&graph_def_, 0));
@@ -507,7 +508,10 @@ void Engine::capture_graph() {
       }
     };
     for (int j = 0; j < cfg_.cg_chunk; ++j) cg_iteration_steps<T>(j & 1, step);
-    step(-1, [&] { launch_cg_close(partial_red_, kRedBlocks, sc_, st_); });
+    step(-1, [&] {
+      launch_cg_close(partial_inv_,
+                      slab_blocks(n_, sizeof(T) == 8, sched_cpb_), sc_, st_);
+    });
   }
   RVE_HIP(hipGraphInstantiate(&graph_, graph_def_, nullptr, nullptr, 0));
 }
@@ -526,6 +530,7 @@ void Engine::autotune() {
   for (int cpb : {1, 3})
     for (int tt : {4, 8, 16})
       if (schedule_valid(n_, dbl, cpb, tt)) cand.push_back({cpb, tt});
+  // alpha = 0 in every slot: the timed passes leave r unchanged
   launch_bench_scalars(sc_, st_);
   launch_kp<T>((const T*)K_, (const T*)r_, (const T*)p0_, (T*)p1_, (T*)Kp_,
                sc_, N_, st_);
@@ -542,8 +547,8 @@ void Engine::autotune() {
       L.spec = (cplx<T>*)spec_;
       L.tw = (const cplx<T>*)(dbl ? tw64_ : tw32_);
       L.vt = (const T*)(dbl ? vt64_ : vt32_);
-      L.dst = DST_DOT;
-      L.out_T = (T*)Ap_;
+      L.dst = DST_CG;
+      L.r_io = (T*)r_;
       L.partial_inv = partial_inv_;
       L.sc = sc_;
       L.cpb = cand[c].first;
@@ -616,7 +621,8 @@ void Engine::cg_solve(int& iters, bool& breakdown, double eta) {
         cg_iteration<T>(parity);
         parity ^= 1;
       }
-      launch_cg_close(partial_red_, kRedBlocks, sc_, st_);
+      launch_cg_close(partial_inv_,
+                      slab_blocks(n_, sizeof(T) == 8, sched_cpb_), sc_, st_);
     }
     RVE_HIP(hipMemcpyAsync(sc_host_ + 1 + slot, sc_, sizeof(Scalars),
                            hipMemcpyDeviceToHost, st_));
@@ -1276,8 +1282,8 @@ void Engine::bench_kernels(int reps, double* ms, int count) {
     L.spec = (cplx<T>*)spec_;
     L.tw = (const cplx<T>*)(dbl ? tw64_ : tw32_);
     L.vt = (const T*)(dbl ? vt64_ : vt32_);
-    L.dst = DST_DOT;
-    L.out_T = (T*)Ap_;
+    L.dst = DST_CG;
+    L.r_io = (T*)r_;
     L.partial_inv = partial_inv_;
     L.sc = sc_;
     L.passes = mask;
@@ -1285,31 +1291,24 @@ void Engine::bench_kernels(int reps, double* ms, int count) {
     L.tt = sched_tt_;
     launch_G<T>(n_, L, st_);
   };
+  // the CG kernels as a CG run launches them, with alpha = 0 and p = r
+  // (x += 0 p_old, r -= 0 G(y)): the vectors keep their values
   launch_bench_scalars(sc_, st_);
   timed(7, [&] {
     if (fp64_)
       launch_kp<double>((const double*)K_, (const double*)r_,
                         (const double*)p0_, (double*)p1_, (double*)Kp_, sc_,
-                        N_, st_);
+                        N_, st_, nullptr, 0, 0, (double*)x_, partial_kp_);
     else
       launch_kp<float>((const float*)K_, (const float*)r_, (const float*)p0_,
-                       (float*)p1_, (float*)Kp_, sc_, N_, st_);
+                       (float*)p1_, (float*)Kp_, sc_, N_, st_, nullptr, 0, 0,
+                       (float*)x_, partial_kp_);
   });
   for (int b = 0; b < 3; ++b) {
     timed(b, [&] {
       if (fp64_) passes(double{}, 1 << b); else passes(float{}, 1 << b);
     });
   }
-  timed(3, [&] {
-    if (fp64_)
-      launch_cg_update<double>((double*)x_, (double*)r_, (const double*)p1_,
-                               (const double*)Ap_, sc_, partial_red_,
-                               kRedBlocks, 9 * N_, st_);
-    else
-      launch_cg_update<float>((float*)x_, (float*)r_, (const float*)p1_,
-                              (const float*)Ap_, sc_, partial_red_, kRedBlocks,
-                              9 * N_, st_);
-  });
   RVE_HIP(hipGetLastError());
   RVE_HIP(hipEventDestroy(ev[0]));
   RVE_HIP(hipEventDestroy(ev[1]));

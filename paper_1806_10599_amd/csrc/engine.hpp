@@ -119,11 +119,11 @@ class Engine {
   double *F_, *P_, *Fpi_t_, *chi_t_, *dg_t_, *r64_;
   void* K_;      // [81][N] float (mixed) or double (fp64)
   // CG vectors (T) and spectra
-  void *x_, *r_, *p0_, *p1_, *Ap_;
+  void *x_, *r_, *p0_, *p1_;
   void* Kp_;     // K : p of the current CG direction
   void* spec_;        // complex T
   void* spec64_;      // complex double (aliases spec_ in fp64 mode)
-  double *partial_inv_, *partial_red_, *psum_, *psq_, *pbar_;
+  double *partial_inv_, *partial_red_, *partial_kp_, *psum_, *psq_, *pbar_;
   Scalars* sc_;
   Scalars* sc_host_ = nullptr;          // pinned: [0] sync reads, [1..2] chunks
   hipEvent_t chunk_ev_[2] = {nullptr, nullptr};

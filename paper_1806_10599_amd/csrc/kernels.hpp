@@ -6,7 +6,7 @@
 namespace rve {
 
 enum { SRC_FIELD = 0, SRC_KP = 1 };
-enum { DST_NORM = 0, DST_DOT = 1 };
+enum { DST_NORM = 0, DST_DOT = 1, DST_CG = 2 };
 
 template <typename T>
 struct SlabFwdArgs {
@@ -22,6 +22,12 @@ struct SlabFwdArgs {
   const Scalars* sc;
   int64_t cs;          // component stride of the real fields (N^3, or the
                        // voxel count of a batch arena)
+  // optional (CG run): block 0 reduces these p.(K:p) partials and publishes
+  // alpha in slot `parity` of scw (cg_alpha_publish)
+  const double* pkp = nullptr;
+  int pkp_count = 0;
+  int parity = 0;
+  Scalars* scw = nullptr;
 };
 
 template <typename T>
@@ -42,6 +48,10 @@ struct SlabInvArgs {
   double* partial;     // per block
   const Scalars* sc;   // optional early exit
   int64_t cs;          // component stride of out / pdot
+  // DST_CG: r -= alpha G(y) in place with alpha = sc->alphas[parity]; the
+  // partials are those of the new r . r (out is not written)
+  T* rio = nullptr;
+  int parity = 0;
 };
 
 template <typename T>
@@ -61,6 +71,12 @@ struct SpectralLaunch {
   double* out_d = nullptr;
   double* partial_inv = nullptr;
   Scalars* sc = nullptr;
+  // CG run (dst = DST_CG): the p.(K:p) partials for pass A's alpha, the
+  // residual updated in place by pass C, and the iteration's parity
+  const double* pkp = nullptr;
+  int pkp_count = 0;
+  T* r_io = nullptr;
+  int parity = 0;
   int passes = 7;   // bit 0: pass A, bit 1: pass B, bit 2: pass C
   int cpb = 0;      // components per slab block in passes A and C (1 or 3;
                     // 0: the default of the grid edge and precision)
@@ -216,10 +232,17 @@ void launch_cg_update(T* x, T* r, const T* p, const T* Ap, Scalars* sc,
                       double* partial, int nblk, int64_t n9, hipStream_t s,
                       const double* partial_in = nullptr, int count_in = 0,
                       int parity = 0);
+// partial: r.r partials of the last inverse pass (a CG run; the kernel also
+// applies the previous iteration's x += alpha p_old when x != null); null:
+// first, beta and alpha from the scalars.  pkp: per-block p . (K : p), one
+// entry per block of the grid (kp_blocks).
 template <typename T>
 void launch_kp(const T* K, const T* r, const T* p_old, T* p_new, T* y,
                Scalars* sc, int64_t N, hipStream_t s,
-               const double* partial = nullptr, int count = 0, int parity = 0);
+               const double* partial = nullptr, int count = 0, int parity = 0,
+               T* x = nullptr, double* pkp = nullptr);
+constexpr int kKpMaxBlocks = 4096;
+int kp_blocks(int64_t N);
 // the CG decision after the last update of a chunk (even chunk length)
 void launch_cg_close(const double* partial, int count, Scalars* sc,
                      hipStream_t s);

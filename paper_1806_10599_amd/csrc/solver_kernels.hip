@@ -112,63 +112,104 @@ void launch_cg_update(T* x, T* r, const T* p, const T* Ap, Scalars* sc,
 // CG direction and material product (Sec. 2.1, Eqs. 15-16): per voxel
 // p = r (first iteration) or r + beta p_old, then y = K : p
 // (y_c = sum_d K[9c + d] p_d); streams K once, coalesced per component.
-// With partial != null the kernel first reduces the r.r partials of the last
-// update itself (cg_beta_consume); otherwise it takes first and beta from
-// the scalars.
+// With partial != null (a CG run) the kernel first reduces the r.r partials
+// of the last inverse pass itself (cg_beta_consume) and, from the second
+// iteration on, applies the previous iteration's x += alpha p_old (its alpha
+// was published by that iteration's forward pass) while p_old streams by;
+// it returns at once when the previous iteration halted the run, and applies
+// only the pending x update when this one stops it.  Without partial it
+// takes first, beta and alpha from the scalars (kernel timing).  With pkp
+// != null each block writes its partial of p . (K : p).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void kp_kernel(
     const T* __restrict__ K, const T* __restrict__ r,
     const T* __restrict__ p_old, T* __restrict__ p_new, T* __restrict__ y,
-    Scalars* __restrict__ sc, int64_t N, const double* __restrict__ partial,
-    int count, int parity) {
+    T* __restrict__ x, Scalars* __restrict__ sc, int64_t N,
+    const double* __restrict__ partial, int count,
+    double* __restrict__ pkp, int parity) {
   __shared__ double red[kBlock];
-  if (sc->done) return;
-  bool first;
-  T beta;
+  bool first, upd;
+  T beta, alpha_prev;
   if (partial) {
+    // every flag read here was written by an earlier launch: block 0 of this
+    // launch publishes slot `parity` (and done), which no block reads
+    const int q = parity ^ 1;
+    if (sc->halt[q]) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) sc->halt[parity] = 1;
+      return;
+    }
     const BetaStep d = cg_beta_consume(partial, count, sc, parity, red);
-    if (d.stop) return;
     first = d.first;
+    if (first && sc->done) return;  // b = 0: nothing to solve
+    upd = !first && x != nullptr;
+    alpha_prev = T(sc->alphas[q]);
+    if (d.stop) {
+      for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+           upd && v < N; v += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int dd = 0; dd < 9; ++dd)
+          x[dd * N + v] += alpha_prev * p_old[dd * N + v];
+      }
+      return;
+    }
     beta = T(d.beta);
   } else {
+    if (sc->done) return;
     first = sc->first != 0;
     beta = T(sc->beta);
+    upd = x != nullptr;
+    alpha_prev = T(sc->alpha);
   }
+  double acc = 0.0;
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < N;
        v += (int64_t)gridDim.x * blockDim.x) {
     T pd[9];
 #pragma unroll
     for (int d = 0; d < 9; ++d) {
       T val = r[d * N + v];
-      if (!first) val += beta * p_old[d * N + v];
+      if (!first || upd) {
+        const T po = p_old[d * N + v];
+        if (!first) val += beta * po;
+        if (upd) x[d * N + v] += alpha_prev * po;
+      }
       pd[d] = val;
       p_new[d * N + v] = val;
     }
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
-      T acc = T(0);
+      T acc_c = T(0);
 #pragma unroll
-      for (int d = 0; d < 9; ++d) acc += K[(9 * c + d) * N + v] * pd[d];
-      y[c * N + v] = acc;
+      for (int d = 0; d < 9; ++d) acc_c += K[(9 * c + d) * N + v] * pd[d];
+      y[c * N + v] = acc_c;
+      acc += double(pd[c]) * double(acc_c);
     }
   }
+  if (pkp) {
+    const double t = block_reduce(acc, red);
+    if (threadIdx.x == 0) pkp[blockIdx.x] = t;
+  }
+}
+
+int kp_blocks(int64_t N) {
+  const int64_t g = (N + kBlock - 1) / kBlock;
+  return (int)(g < kKpMaxBlocks ? g : kKpMaxBlocks);
 }
 
 template <typename T>
 void launch_kp(const T* K, const T* r, const T* p_old, T* p_new, T* y,
                Scalars* sc, int64_t N, hipStream_t s, const double* partial,
-               int count, int parity) {
-  const int64_t g = (N + kBlock - 1) / kBlock;
-  launch((kp_kernel<T>), dim3((unsigned)(g < 4096 ? g : 4096)), dim3(kBlock),
-         0, s, K, r, p_old, p_new, y, sc, N, partial, count, parity);
+               int count, int parity, T* x, double* pkp) {
+  launch((kp_kernel<T>), dim3((unsigned)kp_blocks(N)), dim3(kBlock), 0, s, K,
+         r, p_old, p_new, y, x, sc, N, partial, count, pkp, parity);
 }
 
 template void launch_kp<float>(const float*, const float*, const float*,
                                float*, float*, Scalars*, int64_t, hipStream_t,
-                               const double*, int, int);
+                               const double*, int, int, float*, double*);
 template void launch_kp<double>(const double*, const double*, const double*,
                                 double*, double*, Scalars*, int64_t,
-                                hipStream_t, const double*, int, int);
+                                hipStream_t, const double*, int, int, double*,
+                                double*);
 
 template <typename T>
 __global__ void add_to_F_kernel(double* __restrict__ F,
@@ -265,6 +306,7 @@ __global__ void bench_scalars_kernel(Scalars* sc) {
     sc->first = 1;
     sc->alpha = 0.0;
     sc->beta = 0.0;
+    sc->alphas[0] = sc->alphas[1] = 0.0;
   }
 }
 

@@ -19,6 +19,7 @@
 //
 // Only the delta_ik structure of the operator is used: row i of the output
 // depends on row i of the input, so pass B never needs all nine components.
+#include "cg_scalars.hpp"
 #include "common.hpp"
 #include "fft.hpp"
 #include "kernels.hpp"
@@ -403,13 +404,17 @@ __device__ __forceinline__ void slab_inv_body(const SlabInvArgs<T, TO>& a,
   fft_lines<N, +1>(lds, tw, CPB * H, RowMap<N>());
 
   double acc = 0.0;
+  T alpha = T(0);
+  if constexpr (DST == DST_CG) alpha = T(a.sc->alphas[a.parity]);
   {
-    // the p loads of a chunk are issued together (same order of the sum)
+    // the p (or r) loads of a chunk are issued together (same order of the
+    // sum)
     constexpr int PER = (H * N + kBlock - 1) / kBlock;
     constexpr int CH = PER < kStage<T> ? PER : kStage<T>;
     for (int c0 = 0; c0 < PER; c0 += CH) {
       T pv[CH][CPB][2];
-      if constexpr (DST == DST_DOT) {
+      if constexpr (DST == DST_DOT || DST == DST_CG) {
+        const T* src = (DST == DST_CG) ? a.rio : a.pdot;
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
           const int t = threadIdx.x + (c0 + u) * kBlock;
@@ -420,7 +425,7 @@ __device__ __forceinline__ void slab_inv_body(const SlabInvArgs<T, TO>& a,
 #pragma unroll
               for (int hh = 0; hh < 2; ++hh) {
                 const int64_t v = ((int64_t)x * N + yp + hh * H) * N + z;
-                pv[u][q][hh] = a.pdot[(grp * CPB + q) * cs + v];
+                pv[u][q][hh] = src[(grp * CPB + q) * cs + v];
               }
           }
         }
@@ -438,10 +443,15 @@ __device__ __forceinline__ void slab_inv_body(const SlabInvArgs<T, TO>& a,
           for (int hh = 0; hh < 2; ++hh) {
             const int64_t v = ((int64_t)x * N + yp + hh * H) * N + z;
             const T val = hh ? zz.y : zz.x;
-            a.out[c * cs + v] = TO(val);
-            if constexpr (DST == DST_DOT) {
+            if constexpr (DST == DST_CG) {
+              const T rn = pv[u][q][hh] - alpha * val;
+              a.rio[c * cs + v] = rn;
+              acc += double(rn) * double(rn);
+            } else if constexpr (DST == DST_DOT) {
+              a.out[c * cs + v] = TO(val);
               acc += double(pv[u][q][hh]) * double(val);
             } else {
+              a.out[c * cs + v] = TO(val);
               acc += double(val) * double(val);
             }
           }
@@ -475,6 +485,8 @@ __global__ __launch_bounds__(kBlock) void slab_fwd_kernel(SlabFwdArgs<T> a) {
   __shared__ double red[kBlock];
   if (a.sc && a.sc->done) return;
   slab_fwd_body<T, N, CPB, SRC>(a, xcd_remap(blockIdx.x, gridDim.x), lds, tw, red);
+  if (a.pkp && blockIdx.x == 0)
+    cg_alpha_publish(a.pkp, a.pkp_count, a.scw, a.parity, red);
 }
 
 template <typename T, int N, int TT>
@@ -625,6 +637,12 @@ void launch_G_passes(const SpectralLaunch<T>& L, hipStream_t s) {
     fa.psum = L.psum;
     fa.psq = L.psq;
     fa.sc = L.sc;
+    if (L.pkp) {
+      fa.pkp = L.pkp;
+      fa.pkp_count = L.pkp_count;
+      fa.parity = L.parity;
+      fa.scw = L.sc;
+    }
     launch((slab_fwd_kernel<T, N, CPB, SRC_FIELD>), dim3(nslab),
                        dim3(kBlock), 0, s, fa);
   } else {
@@ -653,6 +671,19 @@ void launch_G_passes(const SpectralLaunch<T>& L, hipStream_t s) {
                      dim3(kBlock), 0, s, pa);
   }
   if (!(L.passes & 4)) {
+  } else if (L.dst == DST_CG) {
+    SlabInvArgs<T, T> ia{};
+    ia.cs = (int64_t)N * N * N;
+    ia.spec = L.spec;
+    ia.tw = L.tw;
+    ia.out = nullptr;
+    ia.pdot = nullptr;
+    ia.partial = L.partial_inv;
+    ia.sc = L.sc;
+    ia.rio = L.r_io;
+    ia.parity = L.parity;
+    launch((slab_inv_kernel<T, T, N, CPB, DST_CG>), dim3(nslab),
+                       dim3(kBlock), 0, s, ia);
   } else if (L.dst == DST_DOT) {
     SlabInvArgs<T, T> ia{};
     ia.cs = (int64_t)N * N * N;

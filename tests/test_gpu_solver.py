@@ -192,7 +192,7 @@ def test_live_kernel_timing_counts_and_leaves_results_unchanged(graph):
         # the chunk queued ahead of the host check (they return at once)
         chunk = 8
         for k in ("matvec_kp", "matvec_pass_a", "matvec_pass_b",
-                  "matvec_pass_c", "cg_update"):
+                  "matvec_pass_c"):
             ms, n = t[k]
             assert ms > 0.0
             if graph:   # whole chunks are replayed
