@@ -35,14 +35,16 @@ constexpr double LOCAL_RFLOOR = 1e-10;
 // Voigt order 11, 22, 33, 23, 13, 12
 __device__ constexpr double VW[6] = {1, 1, 1, 2, 2, 2};
 
-// Hides the table pointer's value from the optimizer so that table entries
-// are re-read (from cache) at each use instead of being hoisted out of the
-// local Newton loop into registers, which would exhaust the register file.
-// The asm is empty: no instruction is emitted and no memory is accessed.
+// Hides an offset of zero from the optimizer so that table entries are
+// re-read (from cache) at each use instead of being hoisted out of the local
+// Newton loop into registers, which would exhaust the register file.  The
+// pointer itself stays visible, so the loads remain global-memory loads
+// (not flat ones).  The asm is empty: no instruction is emitted and no
+// memory is accessed.
 __device__ __forceinline__ const double* opaque(const double* p) {
-  uint64_t u = (uint64_t)p;
-  asm volatile("" : "+v"(u));
-  return (const double*)u;
+  int64_t z = 0;
+  asm volatile("" : "+v"(z));
+  return p + z;
 }
 
 __device__ __forceinline__ double sgn(double x) {
@@ -81,11 +83,14 @@ __device__ __forceinline__ void mm3(const double* A, const double* B,
 // S (Voigt) = C : E (Voigt), C_IJ from the table
 __device__ __forceinline__ void cmul6(const double* __restrict__ Cv,
                                       const double* E, double* S) {
+  double We[6];
+#pragma unroll
+  for (int J = 0; J < 6; ++J) We[J] = VW[J] * E[J];
 #pragma unroll
   for (int I = 0; I < 6; ++I) {
     double acc = 0.0;
 #pragma unroll
-    for (int J = 0; J < 6; ++J) acc += Cv[6 * I + J] * VW[J] * E[J];
+    for (int J = 0; J < 6; ++J) acc += Cv[6 * I + J] * We[J];
     S[I] = acc;
   }
 }
@@ -273,11 +278,14 @@ __device__ __forceinline__ void cp_jacobian(const CpEval& e, const double* Fes,
     double V[6];
     make_V(Q, tb, al, V);
     const double f = hg[al] * D[al];
+    // row factor of the rank-one term, formed once per slip
+    double w[6];
+#pragma unroll
+    for (int J = 0; J < 6; ++J) w[J] = f * VW[J] * tb[kTabN + 6 * al + J];
 #pragma unroll
     for (int I = 0; I < 6; ++I)
 #pragma unroll
-      for (int J = 0; J < 6; ++J)
-        L.M[6 * I + J] += V[I] * f * VW[J] * tb[kTabN + 6 * al + J];
+      for (int J = 0; J < 6; ++J) L.M[6 * I + J] += V[I] * w[J];
   }
   lu6_factor(L);
 }
@@ -438,11 +446,14 @@ __device__ __forceinline__ void pr_step(const double* dg, const double* R,
     double V[6];
     make_V(Q, tb, al, V);
     const double f = hd[j] * lp.inv_g * D[j];
+    // row factor of the rank-one term, formed once per slip
+    double w[6];
+#pragma unroll
+    for (int J = 0; J < 6; ++J) w[J] = f * VW[J] * tb[kTabN + 6 * al + J];
 #pragma unroll
     for (int I = 0; I < 6; ++I)
 #pragma unroll
-      for (int J = 0; J < 6; ++J)
-        L.M[6 * I + J] += V[I] * f * VW[J] * tb[kTabN + 6 * al + J];
+      for (int J = 0; J < 6; ++J) L.M[6 * I + J] += V[I] * w[J];
     step[j] = -R[j] * D[j];
   }
 #pragma unroll
