@@ -56,7 +56,7 @@ __device__ __forceinline__ double sgn(double x) {
 //   y >= 1: asinh(y) = n ln|x| + log1p(q),                q = sqrt(1 + s^2)
 //   y <  1: asinh(y) = log1p(s + s^2 / (1 + q))
 // (both exact; the first never forms the power), and
-// d asinh(y)/dx = (n / |x|) y / sqrt(1 + y^2) = (n / |x|) (y >= 1 ? 1 : s) / q.
+// d asinh(y)/dx = (n / |x|) y / sqrt(1 + y^2) = n (y >= 1 ? 1 : s) / (|x| q).
 // Every lane of a wavefront runs the same instructions whatever its regime.
 __device__ __forceinline__ void asinh_pow(double x, double n, double& val,
                                           double& der) {
@@ -67,7 +67,16 @@ __device__ __forceinline__ void asinh_pow(double x, double n, double& val,
   const double q = sqrt(1.0 + s * s);
   const double L = log1p(big ? q : s + s * s / (1.0 + q));
   val = sgn(x) * ((big ? e : 0.0) + L);
-  der = (ax > 0.0) ? (n / ax) * (big ? 1.0 : s) / q : 0.0;
+  der = (ax > 0.0) ? n * (big ? 1.0 : s) / (ax * q) : 0.0;
+}
+
+// asinh(u) in one branch-free form, exact for every u:
+// asinh(|u|) = log1p(|u| + u^2 / (1 + sqrt(1 + u^2))), with the quotient
+// written as |u| (|u| / (1 + q)) so that it cannot overflow.
+__device__ __forceinline__ double asinh_bf(double u) {
+  const double au = fabs(u);
+  const double q = sqrt(1.0 + au * au);
+  return copysign(log1p(au + au * (au / (1.0 + q))), u);
 }
 
 __device__ __forceinline__ void mm3(const double* A, const double* B,
@@ -155,7 +164,7 @@ __device__ __forceinline__ void cp_eval(const double* Fes,
     asinh_pow(x, lp.nexp, val, der);
     e.chi[al] = chi;
     e.h[al] = der;
-    e.R[al] = asinh(dg[al] * lp.inv_a) - val;
+    e.R[al] = asinh_bf(dg[al] * lp.inv_a) - val;
   }
 }
 
@@ -415,7 +424,7 @@ __device__ __forceinline__ void pr_eval(const double* Fes,
     double val, der;
     asinh_pow(x, lp.nexp, val, der);
     hd[j] = der;
-    R[j] = asinh(t * lp.inv_a) - val;
+    R[j] = asinh_bf(t * lp.inv_a) - val;
   }
   make_Q(Fe, Fes, Q);
 }
