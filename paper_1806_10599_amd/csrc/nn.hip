@@ -36,6 +36,15 @@ __device__ __forceinline__ int wrap(int i, int n) {
 // ------------------------------------------------------------- convolution
 // EPI: 0 bias + ReLU -> bf16; 1 bias, linear -> f32; 2 no bias, multiply by
 // the mask (mask_act > 0) -> bf16 (backward through the previous ReLU)
+//
+// A block of four waves computes kConvTPW consecutive 16-voxel tiles per
+// wave (with n % 16 == 0 and kConvTPW = 4, one wave covers one z line of an
+// edge-64 grid and the block four neighbouring y lines).  The B fragments
+// of the nine taps of one dx slice are staged in LDS once per block and
+// read from there by every wave for all of its tiles; the A rows come from
+// global memory (neighbouring tiles and taps re-read them from cache).
+constexpr int kConvTPW = 4;
+
 template <int CIN, int COUT, int EPI>
 __global__ __launch_bounds__(256) void conv_mfma_kernel(
     const uint16_t* __restrict__ X, const uint16_t* __restrict__ Wf,
@@ -43,51 +52,89 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(
     float* __restrict__ Yf, const uint16_t* __restrict__ mask_act, int n,
     int64_t N, int cout_real) {
   constexpr int KC = CIN / 16, NT = COUT / 16;
+  constexpr int SLICE = 9 * KC * NT * 64 * 4;  // bf16 of one dx slice
+  __shared__ __align__(8) uint16_t wl[SLICE];
   const int lane = threadIdx.x & 63;
-  const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int64_t v0 = tile * 16;
-  if (v0 >= N) return;
-  const int z0 = (int)(v0 % n);
-  const int y = (int)((v0 / n) % n);
-  const int x = (int)(v0 / ((int64_t)n * n));
   const int row = lane & 15, grp = lane >> 4;
-  f32x4 acc[NT];
+  const int64_t tile0 =
+      ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kConvTPW;
+  int xs0[kConvTPW], ys0[kConvTPW], zs0[kConvTPW];
+  bool ok[kConvTPW];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
-  for (int tap = 0; tap < 27; ++tap) {
-    const int dx = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dz = tap % 3 - 1;
-    const int xs = wrap(x + dx, n), ys = wrap(y + dy, n),
-              zs = wrap(z0 + row + dz, n);
-    const int64_t vin = ((int64_t)xs * n + ys) * n + zs;
-    const uint16_t* xr = X + vin * CIN + 4 * grp;
+  for (int u = 0; u < kConvTPW; ++u) {
+    const int64_t v0 = (tile0 + u) * 16;
+    ok[u] = v0 < N;
+    const int64_t vv = ok[u] ? v0 : 0;
+    zs0[u] = (int)(vv % n);
+    ys0[u] = (int)((vv / n) % n);
+    xs0[u] = (int)(vv / ((int64_t)n * n));
+  }
+  f32x4 acc[kConvTPW][NT];
 #pragma unroll
-    for (int kc = 0; kc < KC; ++kc) {
-      const bf16x4 a = *reinterpret_cast<const bf16x4*>(xr + 16 * kc);
+  for (int u = 0; u < kConvTPW; ++u)
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        const bf16x4 b = *reinterpret_cast<const bf16x4*>(
-            Wf + ((((size_t)tap * KC + kc) * NT + nt) * 64 + lane) * 4);
-        acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[nt], 0,
-                                                            0, 0);
+    for (int t = 0; t < NT; ++t) acc[u][t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  for (int sl = 0; sl < 3; ++sl) {
+    // stage the fragments of taps 9 sl .. 9 sl + 8 (8-byte copies: the
+    // fragment arrays are 8-byte aligned, as every B-fragment load assumes)
+    __syncthreads();
+    {
+      const uint2* src = reinterpret_cast<const uint2*>(Wf + (size_t)sl * SLICE);
+      uint2* dst = reinterpret_cast<uint2*>(wl);
+      for (int i = threadIdx.x; i < SLICE / 4; i += 256) dst[i] = src[i];
+    }
+    __syncthreads();
+    const int dx = sl - 1;
+    for (int tl = 0; tl < 9; ++tl) {
+      const int dy = tl / 3 - 1, dz = tl % 3 - 1;
+      const uint16_t* xr[kConvTPW];
+#pragma unroll
+      for (int u = 0; u < kConvTPW; ++u) {
+        const int xs = wrap(xs0[u] + dx, n), ys = wrap(ys0[u] + dy, n),
+                  zs = wrap(zs0[u] + row + dz, n);
+        xr[u] = X + (((int64_t)xs * n + ys) * n + zs) * CIN + 4 * grp;
+      }
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc) {
+        bf16x4 b[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+          b[nt] = *reinterpret_cast<const bf16x4*>(
+              wl + (((tl * KC + kc) * NT + nt) * 64 + lane) * 4);
+        bf16x4 a[kConvTPW];
+#pragma unroll
+        for (int u = 0; u < kConvTPW; ++u)
+          a[u] = *reinterpret_cast<const bf16x4*>(xr[u] + 16 * kc);
+#pragma unroll
+        for (int u = 0; u < kConvTPW; ++u)
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt)
+            acc[u][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(
+                a[u], b[nt], acc[u][nt], 0, 0, 0);
       }
     }
   }
 #pragma unroll
-  for (int nt = 0; nt < NT; ++nt) {
-    const int co = nt * 16 + row;
-    // the bias has only the real output channels
-    const float bv = (EPI == 2 || co >= cout_real) ? 0.f : bias[co];
+  for (int u = 0; u < kConvTPW; ++u) {
+    if (!ok[u]) continue;
+    const int64_t v0 = (tile0 + u) * 16;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int64_t v = v0 + 4 * grp + i;
-      float val = acc[nt][i] + bv;
-      if constexpr (EPI == 0) {
-        Yb[v * COUT + co] = f2bf(val > 0.f ? val : 0.f);
-      } else if constexpr (EPI == 1) {
-        Yf[v * COUT + co] = val;
-      } else {
-        const float m = bf2f(mask_act[v * COUT + co]);
-        Yb[v * COUT + co] = f2bf(m > 0.f ? val : 0.f);
+    for (int nt = 0; nt < NT; ++nt) {
+      const int co = nt * 16 + row;
+      // the bias has only the real output channels
+      const float bv = (EPI == 2 || co >= cout_real) ? 0.f : bias[co];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t v = v0 + 4 * grp + i;
+        float val = acc[u][nt][i] + bv;
+        if constexpr (EPI == 0) {
+          Yb[v * COUT + co] = f2bf(val > 0.f ? val : 0.f);
+        } else if constexpr (EPI == 1) {
+          Yf[v * COUT + co] = val;
+        } else {
+          const float m = bf2f(mask_act[v * COUT + co]);
+          Yb[v * COUT + co] = f2bf(m > 0.f ? val : 0.f);
+        }
       }
     }
   }
@@ -278,9 +325,10 @@ void conv_t(const uint16_t* X, const uint16_t* Wf, const float* b, uint16_t* Yb,
             float* Yf, const uint16_t* mask, int n, int64_t N, int creal,
             hipStream_t s) {
   const int64_t tiles = N / 16;
+  const int64_t per_block = 4 * kConvTPW;
   hipLaunchKernelGGL((conv_mfma_kernel<CIN, COUT, EPI>),
-                     dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, s, X, Wf,
-                     b, Yb, Yf, mask, n, N, creal);
+                     dim3((unsigned)((tiles + per_block - 1) / per_block)),
+                     dim3(256), 0, s, X, Wf, b, Yb, Yf, mask, n, N, creal);
 }
 }  // namespace
 
