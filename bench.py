@@ -396,7 +396,7 @@ def _eq29_per_cycle(sig, ref, per_cycle):
 
 
 def _run_history(micro, hist, precision, operator, stream, adaptive=False,
-                 learned=False):
+                 learned=False, forcing=False):
     """Solve a whole history; returns seconds, sigma_11 per increment and
     solver counts."""
     import torch
@@ -405,10 +405,8 @@ def _run_history(micro, hist, precision, operator, stream, adaptive=False,
     from synthetic import material_params
     r = Rve(micro.n, projection=operator, precision=precision,
             newton_tol=1e-6, cg_tol=1e-4, stream=stream,
-            warm_start=WARM_MODE if learned else 0)
+            warm_start=WARM_MODE if learned else 0, cg_forcing=forcing)
     r.set_microstructure(micro.phase, micro.quat, micro.law, material_params())
-    if schedule:
-        r.set_fft_schedule(*schedule)
     net = None
     if learned:
         net = WarmStartNet(stream=stream)
@@ -467,11 +465,13 @@ def paper_workloads(stream):
         cfg = config_by_name(name)
         micro, hist = cfg.microstructure(), cfg.history()
         row = {}
+        # the chosen path (mixed, learned start, inexact-Newton forcing),
+        # mixed alone, plain FP64
         for label, prec, learned in (("mixed_learned", "mixed", True),
                                      ("mixed", "mixed", False),
                                      ("fp64", "fp64", False)):
             row[label], _ = _run_history(micro, hist, prec, "discrete", stream,
-                                         learned=learned)
+                                         learned=learned, forcing=learned)
         perf[f"{cfg.n}^3"] = row
         print(f"paper workload {name} done", file=sys.stderr, flush=True)
     out["r0_1pct_3cycles"] = perf
