@@ -8,18 +8,10 @@
 
 namespace rve {
 
-// fixed-order tree over the block (deterministic for a given block size)
+// fixed-order reduction over the block (deterministic for a given block
+// size)
 __device__ __forceinline__ double cg_block_reduce(double v, double* red) {
-  const int t = threadIdx.x;
-  red[t] = v;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (t < s) red[t] += red[t + s];
-    __syncthreads();
-  }
-  const double r = red[0];
-  __syncthreads();
-  return r;
+  return block_sum_fixed(v, red);
 }
 
 // sum of partial[0 .. count) by one block: each thread sums a strided

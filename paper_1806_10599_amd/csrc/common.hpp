@@ -109,4 +109,21 @@ struct Scalars {
 
 constexpr int kBlock = 256;
 
+// Deterministic block sum (blockDim.x a multiple of 64; every thread of the
+// block must call it): a butterfly inside each wavefront (both lanes of a
+// pair add the same two numbers, so every lane ends with the same value),
+// then the wave sums in wave order.  red holds at least blockDim.x / 64
+// doubles.  The same inputs give the same bits in every block and launch.
+__device__ __forceinline__ double block_sum_fixed(double v, double* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int nw = (int)(blockDim.x >> 6);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = red[0];
+  for (int i = 1; i < nw; ++i) r += red[i];
+  __syncthreads();
+  return r;
+}
+
 }  // namespace rve

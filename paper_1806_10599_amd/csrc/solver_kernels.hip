@@ -12,16 +12,7 @@ namespace rve {
 namespace {
 
 __device__ __forceinline__ double block_reduce(double v, double* red) {
-  const int t = threadIdx.x;
-  red[t] = v;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (t < s) red[t] += red[t + s];
-    __syncthreads();
-  }
-  const double r = red[0];
-  __syncthreads();
-  return r;
+  return block_sum_fixed(v, red);
 }
 
 }  // namespace

@@ -70,17 +70,8 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 }
 
 __device__ __forceinline__ double block_sum(double v, double* red) {
-  // fixed-order tree reduction over the block (deterministic)
-  const int t = threadIdx.x;
-  red[t] = v;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (t < s) red[t] += red[t + s];
-    __syncthreads();
-  }
-  double r = red[0];
-  __syncthreads();
-  return r;
+  // fixed-order reduction over the block (deterministic)
+  return block_sum_fixed(v, red);
 }
 
 // items whose global loads are issued together before their LDS stores
