@@ -69,6 +69,8 @@ LIVE_CLASSES = ("return_map", "tangent", "residual_fp64")
 # learned warm start: a candidate well below the homogeneous predictor's
 # last residual is kept without evaluating the homogeneous predictor
 WARM_MODE = 2
+# inexact-Newton forcing mode of the chosen path (set from --forcing-mode)
+FORCING = 2
 
 
 def parse():
@@ -105,6 +107,11 @@ def parse():
                          "as CPB,TT (e.g. 1,8) instead of tuning it; counter "
                          "runs serialize kernels, which makes tuning there "
                          "meaningless")
+    ap.add_argument("--forcing-mode", type=int, default=2, choices=(1, 2),
+                    help="inexact-Newton forcing of the chosen, batch and "
+                         "128^3 paths (1: only as tight as the equilibrium "
+                         "tolerance needs; 2: also never tighter than 0.05 "
+                         "of the residual)")
     ap.add_argument("--no-forcing", action="store_true",
                     help="chosen path solves every Newton iteration to "
                          "cg_tol (no inexact-Newton forcing)")
@@ -268,7 +275,7 @@ def batch_run(steps, stream):
     vox = sum(m.n ** 3 for m in micros)
     b = BatchRve([m.n for m in micros], projection=cfg.operator,
                  precision=cfg.precision, newton_tol=1e-6, cg_tol=1e-4,
-                 use_graph=True, stream=stream, cg_forcing=True)
+                 use_graph=True, stream=stream, cg_forcing=FORCING)
     for j, m in enumerate(micros):
         b.set_microstructure(j, m.phase, m.quat, m.law, material_params())
     torch.cuda.synchronize()
@@ -295,7 +302,7 @@ def batch_run(steps, stream):
     sig_s = []
     for m in micros:
         r = Rve(m.n, projection=cfg.operator, precision=cfg.precision,
-                newton_tol=1e-6, cg_tol=1e-4, stream=stream, cg_forcing=True)
+                newton_tol=1e-6, cg_tol=1e-4, stream=stream, cg_forcing=FORCING)
         r.set_microstructure(m.phase, m.quat, m.law, material_params())
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -340,7 +347,7 @@ def large_run(steps, stream):
     for mode in ("learned", "homogeneous"):
         r = run_path(micro, hist, "mixed", False, steps - 1, 1, stream,
                      live=False, learned=(mode == "learned"), start=1,
-                     with_fips=(mode == "learned"), forcing=True)
+                     with_fips=(mode == "learned"), forcing=FORCING)
         n3 = micro.n ** 3
         out[mode] = dict(value=round(n3 * (steps - 1) / r["elapsed"], 1),
                          ms_per_step=round(1e3 * r["elapsed"] / (steps - 1), 3),
@@ -471,7 +478,8 @@ def paper_workloads(stream):
                                      ("mixed", "mixed", False),
                                      ("fp64", "fp64", False)):
             row[label], _ = _run_history(micro, hist, prec, "discrete", stream,
-                                         learned=learned, forcing=learned)
+                                         learned=learned,
+                                         forcing=FORCING if learned else 0)
         perf[f"{cfg.n}^3"] = row
         print(f"paper workload {name} done", file=sys.stderr, flush=True)
     out["r0_1pct_3cycles"] = perf
@@ -656,6 +664,8 @@ def main():
                           "notes for how the path would shard)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    global FORCING
+    FORCING = args.forcing_mode
     import torch
     from synthetic import config_by_name
     cfg = config_by_name(args.config)
@@ -671,7 +681,7 @@ def main():
                           args.warmup, stream, live=not args.no_live,
                           learned=not args.no_learned, start=args.start,
                           cg_chunk=args.cg_chunk, with_fips=True,
-                          forcing=not args.no_forcing,
+                          forcing=0 if args.no_forcing else FORCING,
                           schedule=(tuple(int(x) for x in
                                           args.fft_schedule.split(","))
                                     if args.fft_schedule else None))
@@ -707,7 +717,7 @@ def main():
                    "voxels": N, "precision": "mixed FP32 FFT/CG + FP64",
                    "graph": args.graph,
                    "cg_chunk": args.cg_chunk,
-                   "cg_forcing": not args.no_forcing,
+                   "cg_forcing": 0 if args.no_forcing else FORCING,
                    "warm_start": ("homogeneous" if args.no_learned else
                                   "learned (weights/warmstart.npy), kept "
                                   "directly below half the homogeneous "

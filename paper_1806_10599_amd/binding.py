@@ -310,7 +310,9 @@ def _make_config(L, projection, precision, newton_tol, newton_max_iter, cg_tol,
     if warm_start not in (0, 1, 2):
         raise ValueError("warm_start must be False/0, True/1 or 2")
     cfg.warm_start = int(warm_start)
-    cfg.cg_forcing = 1 if cg_forcing else 0
+    if cg_forcing not in (0, 1, 2):
+        raise ValueError("cg_forcing must be False/0, True/1 or 2")
+    cfg.cg_forcing = int(cg_forcing)
     torch.cuda.set_device(device)
     stream = stream if stream is not None else torch.cuda.current_stream()
     cfg.stream = C.c_void_p(stream.cuda_stream or None)

@@ -4,6 +4,7 @@
 // once with per-RVE convergence: an RVE that has converged (or failed)
 // leaves the work of the following iterations.
 #include "batch.hpp"
+#include "newton.hpp"
 
 #include <algorithm>
 
@@ -28,6 +29,8 @@ BatchEngine::BatchEngine(const rve_config& cfg, int count, const int32_t* n)
   if (count < 1 || count > 255 || !n)
     throw Error(RVE_EINVAL, "a batch holds 1 to 255 RVEs");
   if (cfg.warm_start) throw Error(RVE_EINVAL, "batches take the homogeneous predictor");
+  if (cfg.cg_forcing < 0 || cfg.cg_forcing > 2)
+    throw Error(RVE_EINVAL, "cg_forcing must be 0, 1 or 2");
   if (cfg.projection != RVE_PROJ_CONTINUOUS && cfg.projection != RVE_PROJ_DISCRETE)
     throw Error(RVE_EINVAL, "unknown projection operator");
   if (cfg.precision != RVE_PREC_FP64 && cfg.precision != RVE_PREC_MIXED)
@@ -412,9 +415,8 @@ void BatchEngine::cg_solve(std::vector<int>& iters) {
   for (int b = 0; b < B_; ++b) {
     // per-RVE linear-solve tolerance (cg_forcing: as tight as the
     // equilibrium tolerance needs from this RVE's residual)
-    double eta = cfg_.cg_tol;
-    if (cfg_.cg_forcing && rel_[b] > 0.0)
-      eta = std::min(0.1, std::max(cfg_.cg_tol, 0.25 * cfg_.newton_tol / rel_[b]));
+    const double eta = forcing_eta(cfg_.cg_forcing, cfg_.cg_tol,
+                                   cfg_.newton_tol, rel_[b]);
     sc_host_[b].max_iters = cfg_.cg_max_iter;
     sc_host_[b].eta2bb = eta * eta;
     sc_host_[b].done = sc_host_[b].inactive;

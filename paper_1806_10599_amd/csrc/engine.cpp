@@ -1,5 +1,6 @@
 // RVE engine: buffers and the increment algorithm (see engine.hpp).
 #include "engine.hpp"
+#include "newton.hpp"
 
 #include <algorithm>
 #include <chrono>
@@ -48,8 +49,8 @@ Engine::Engine(const rve_config& cfg) : cfg_(cfg) {
     throw Error(RVE_EINVAL, "unknown precision mode");
   if (cfg.warm_start < 0 || cfg.warm_start > 2)
     throw Error(RVE_EINVAL, "warm_start must be 0, 1 or 2");
-  if (cfg.cg_forcing != 0 && cfg.cg_forcing != 1)
-    throw Error(RVE_EINVAL, "cg_forcing must be 0 or 1");
+  if (cfg.cg_forcing < 0 || cfg.cg_forcing > 2)
+    throw Error(RVE_EINVAL, "cg_forcing must be 0, 1 or 2");
   for (int d = 0; d < 3; ++d)
     if (!(cfg.L[d] > 0.0)) throw Error(RVE_EINVAL, "cell lengths must be > 0");
   if (!(cfg.newton_tol > 0.0) || cfg.newton_max_iter < 0 ||
@@ -770,9 +771,8 @@ int Engine::increment(const double Fbar_new[9], double dt,
     // linear-solve tolerance: fixed, or (cg_forcing) only as tight as the
     // equilibrium tolerance needs from this residual, never tighter than
     // cg_tol
-    double eta = cfg_.cg_tol;
-    if (cfg_.cg_forcing && rel > 0.0)
-      eta = std::min(0.1, std::max(cfg_.cg_tol, 0.25 * cfg_.newton_tol / rel));
+    const double eta = forcing_eta(cfg_.cg_forcing, cfg_.cg_tol,
+                                   cfg_.newton_tol, rel);
     if (fp64_) {
       tangent<double>(dt);
       cg_solve<double>(iters, bd, eta);

@@ -1,0 +1,30 @@
+// Host-side control of the Newton iteration shared by single and batched
+// solves.
+#pragma once
+
+#include <algorithm>
+#include <cstdint>
+
+namespace rve {
+
+// Share of the residual used by the superlinear term of forcing mode 2.
+constexpr double kForcingTheta = 0.05;
+
+// Relative tolerance of the linear solve of a Newton iteration that starts
+// at the FP64 relative residual rel (inexact Newton; the equilibrium test
+// itself never changes):
+//   0: cg_tol;
+//   1: min(0.1, max(cg_tol, newton_tol / (4 rel))): only as tight as
+//      reaching the equilibrium tolerance needs;
+//   2: as 1, but never tighter than kForcingTheta * rel either: far from
+//      equilibrium the next residual is dominated by the quadratic term of
+//      Newton's method, which a tighter solve cannot reduce.
+inline double forcing_eta(int32_t mode, double cg_tol, double newton_tol,
+                          double rel) {
+  if (mode == 0 || !(rel > 0.0)) return cg_tol;
+  double eta = std::max(cg_tol, 0.25 * newton_tol / rel);
+  if (mode == 2) eta = std::max(eta, kForcingTheta * rel);
+  return std::min(0.1, eta);
+}
+
+}  // namespace rve

@@ -48,3 +48,16 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
         f'LIBPATH = {str(tmp_path / "missing.so")!r}')
     with pytest.raises(ImportError):
         exec(compile(src, spec.origin, "exec"), mod.__dict__)
+
+
+def test_binding_rejects_bad_solver_modes_before_touching_a_device():
+    # argument checks of the binding run on the host (no GPU needed)
+    from paper_1806_10599_amd import binding
+    args = dict(L=(1.0, 1.0, 1.0), projection="discrete", precision="mixed",
+                newton_tol=1e-6, newton_max_iter=25, cg_tol=1e-4,
+                cg_max_iter=500, cg_chunk=8, use_graph=False, stream=None,
+                device=0, torch_allocator=False)
+    with pytest.raises(ValueError, match="cg_forcing"):
+        binding._make_config(warm_start=0, cg_forcing=3, **args)
+    with pytest.raises(ValueError, match="warm_start"):
+        binding._make_config(warm_start=5, cg_forcing=1, **args)

@@ -49,9 +49,10 @@ def _run_single(micro, hist, operator, precision, **kw):
         r.close()
 
 
-@pytest.mark.parametrize("operator,forcing", [("continuous", False),
-                                              ("discrete", False),
-                                              ("discrete", True)])
+@pytest.mark.parametrize("operator,forcing", [("continuous", 0),
+                                              ("discrete", 0),
+                                              ("discrete", 1),
+                                              ("discrete", 2)])
 def test_batch_fp64_matches_single_rves(operator, forcing):
     # with cg_forcing each RVE of the batch takes its own linear-solve
     # tolerances, the same as a single handle would
