@@ -109,9 +109,9 @@ def parse():
                          "meaningless")
     ap.add_argument("--forcing-mode", type=int, default=2, choices=(1, 2),
                     help="inexact-Newton forcing of the chosen, batch and "
-                         "128^3 paths (1: only as tight as the equilibrium "
-                         "tolerance needs; 2: also never tighter than 0.05 "
-                         "of the residual)")
+                         "128^3 paths (1: only as tight as a quarter of the "
+                         "equilibrium tolerance needs; 2: half of it, and "
+                         "never tighter than 0.05 of the residual)")
     ap.add_argument("--no-forcing", action="store_true",
                     help="chosen path solves every Newton iteration to "
                          "cg_tol (no inexact-Newton forcing)")

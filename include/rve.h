@@ -93,11 +93,11 @@ typedef struct {
                             iteration k solves to min(0.1, max(cg_tol,
                             newton_tol / (4 r_k))), r_k = ||G(P)||/||P|| at
                             its start, i.e. only as far as reaching the
-                            equilibrium tolerance needs; 2: as 1 and never
-                            tighter than 0.05 r_k either (far from
-                            equilibrium the quadratic term of Newton's
-                            method dominates the next residual).  Per RVE
-                            in a batch; other values are EINVAL.         */
+                            equilibrium tolerance needs; 2: min(0.1,
+                            max(cg_tol, newton_tol / (2 r_k), 0.05 r_k))
+                            (far from equilibrium the quadratic term of
+                            Newton's method dominates the next residual).
+                            Per RVE in a batch; other values are EINVAL. */
 } rve_config;
 
 #define RVE_MAX_NEWTON_LOG 64

@@ -15,14 +15,18 @@ constexpr double kForcingTheta = 0.05;
 // itself never changes):
 //   0: cg_tol;
 //   1: min(0.1, max(cg_tol, newton_tol / (4 rel))): only as tight as
-//      reaching the equilibrium tolerance needs;
-//   2: as 1, but never tighter than kForcingTheta * rel either: far from
-//      equilibrium the next residual is dominated by the quadratic term of
-//      Newton's method, which a tighter solve cannot reduce.
+//      reaching the equilibrium tolerance needs (the linear part of the
+//      next residual at most a quarter of the tolerance);
+//   2: min(0.1, max(cg_tol, newton_tol / (2 rel), kForcingTheta * rel)):
+//      half of the tolerance for the linear part (the quadratic remainder
+//      of the last correction is orders of magnitude below it), and never
+//      tighter than kForcingTheta * rel: far from equilibrium the next
+//      residual is dominated by the quadratic term of Newton's method,
+//      which a tighter solve cannot reduce.
 inline double forcing_eta(int32_t mode, double cg_tol, double newton_tol,
                           double rel) {
   if (mode == 0 || !(rel > 0.0)) return cg_tol;
-  double eta = std::max(cg_tol, 0.25 * newton_tol / rel);
+  double eta = std::max(cg_tol, (mode == 2 ? 0.5 : 0.25) * newton_tol / rel);
   if (mode == 2) eta = std::max(eta, kForcingTheta * rel);
   return std::min(0.1, eta);
 }

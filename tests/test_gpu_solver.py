@@ -312,8 +312,9 @@ def test_full_size_chosen_path_sampled_against_oracle():
 
 def test_cg_forcing_reaches_the_same_equilibrium_with_fewer_cg_iterations():
     """cg_forcing = 1 solves Newton iteration k only to
-    min(0.1, max(cg_tol, newton_tol / (4 r_k))), cg_forcing = 2 also never
-    below 0.05 r_k: every increment still ends at ||G(P)|| <= tol ||P||
+    min(0.1, max(cg_tol, newton_tol / (4 r_k))), cg_forcing = 2 to
+    min(0.1, max(cg_tol, newton_tol / (2 r_k), 0.05 r_k)): every increment
+    still ends at ||G(P)|| <= tol ||P||
     (FP64), the macroscopic stress agrees with the fixed-tolerance run to
     the equilibrium tolerance, and the CG count drops (mode 2 below
     mode 1)."""
