@@ -1,5 +1,6 @@
 // Device-side CG scalar logic (text after Eq. 16: alpha = r.r / p.Ap,
-// beta = r_new.r_new / r.r, stop at ||r|| <= eta ||b|| or p.Ap <= 0) and the
+// beta = r_new.r_new / r.r, stop at ||r|| <= eta ||b|| or p.Ap <= 0; the
+// single-RVE path forms p.Ap as p.(K:p), see cg_alpha_publish) and the
 // fixed-order reductions of the per-block partial sums.
 #pragma once
 
@@ -83,8 +84,9 @@ struct BetaStep {
   double beta;
 };
 
-// In the direction kernel of parity p: reduce the r.r partials of the last
-// update (RED_BETA's decision), unless this is iteration 0.
+// In the direction kernel of parity p (and in the chunk-closing kernel):
+// reduce the r.r partials of the last inverse pass (RED_BETA's decision),
+// unless this is iteration 0.
 __device__ __forceinline__ BetaStep cg_beta_consume(const double* partial,
                                                     int count, Scalars* sc,
                                                     int p, double* red) {
@@ -114,33 +116,6 @@ __device__ __forceinline__ BetaStep cg_beta_consume(const double* partial,
     } else {
       sc->beta = d.beta;
       sc->rr = rr;
-    }
-  }
-  return d;
-}
-
-struct AlphaStep {
-  bool stop;    // p.Ap <= 0 (or non-finite): breakdown
-  double alpha;
-};
-
-// In the update kernel of parity p: reduce the p.Ap partials of the inverse
-// pass (RED_ALPHA's decision).
-__device__ __forceinline__ AlphaStep cg_alpha_consume(const double* partial,
-                                                      int count, Scalars* sc,
-                                                      int p, double* red) {
-  const double pAp = cg_sum_partials(partial, count, red);
-  AlphaStep d;
-  d.stop = !(pAp > 0.0) || !isfinite(pAp);
-  d.alpha = d.stop ? 0.0 : sc->rrs[p] / pAp;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    sc->pAp = pAp;
-    if (d.stop) {
-      sc->breakdown = 1;
-      sc->done = 1;
-      sc->iters = sc->its[p] + 1;
-    } else {
-      sc->alpha = d.alpha;
     }
   }
   return d;

@@ -225,13 +225,6 @@ void launch_predict(double* F, const double* Fprev, const double dFbar[9],
 template <typename T>
 void launch_cg_init(const double* r64, T* r, T* x, double* partial, int nblk,
                     int64_t n9, hipStream_t s);
-// partial_in / partial: reduce the producer's partials in every block and
-// take the CG decision there (see cg_scalars.hpp); null: use the scalars
-template <typename T>
-void launch_cg_update(T* x, T* r, const T* p, const T* Ap, Scalars* sc,
-                      double* partial, int nblk, int64_t n9, hipStream_t s,
-                      const double* partial_in = nullptr, int count_in = 0,
-                      int parity = 0);
 // partial: r.r partials of the last inverse pass (a CG run; the kernel also
 // applies the previous iteration's x += alpha p_old when x != null); null:
 // first, beta and alpha from the scalars.  pkp: per-block p . (K : p), one

@@ -60,46 +60,6 @@ void launch_cg_init(const double* r64, T* r, T* x, double* partial, int nblk,
                      r, x, partial, n9);
 }
 
-// x += alpha p, r -= alpha Ap, partial sums of the new r.r.  With
-// partial_in != null the kernel first reduces the p.Ap partials of the
-// inverse pass itself (cg_alpha_consume); otherwise it takes alpha from the
-// scalars.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void cg_update_kernel(
-    T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
-    const T* __restrict__ Ap, Scalars* __restrict__ sc,
-    double* __restrict__ partial, int64_t n9,
-    const double* __restrict__ partial_in, int count_in, int parity) {
-  __shared__ double red[kBlock];
-  if (sc->done) return;
-  T alpha;
-  if (partial_in) {
-    const AlphaStep d = cg_alpha_consume(partial_in, count_in, sc, parity, red);
-    if (d.stop) return;
-    alpha = T(d.alpha);
-  } else {
-    alpha = T(sc->alpha);
-  }
-  double acc = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n9;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    x[i] += alpha * p[i];
-    const T rn = r[i] - alpha * Ap[i];
-    r[i] = rn;
-    acc += double(rn) * double(rn);
-  }
-  const double t = block_reduce(acc, red);
-  if (threadIdx.x == 0) partial[blockIdx.x] = t;
-}
-
-template <typename T>
-void launch_cg_update(T* x, T* r, const T* p, const T* Ap, Scalars* sc,
-                      double* partial, int nblk, int64_t n9, hipStream_t s,
-                      const double* partial_in, int count_in, int parity) {
-  launch((cg_update_kernel<T>), dim3(nblk), dim3(kBlock), 0, s, x, r, p, Ap,
-         sc, partial, n9, partial_in, count_in, parity);
-}
-
 // CG direction and material product (Sec. 2.1, Eqs. 15-16): per voxel
 // p = r (first iteration) or r + beta p_old, then y = K : p
 // (y_c = sum_d K[9c + d] p_d); streams K once, coalesced per component.
@@ -441,14 +401,6 @@ template void launch_cg_init<float>(const double*, float*, float*, double*,
                                     int, int64_t, hipStream_t);
 template void launch_cg_init<double>(const double*, double*, double*, double*,
                                      int, int64_t, hipStream_t);
-template void launch_cg_update<float>(float*, float*, const float*,
-                                      const float*, Scalars*, double*, int,
-                                      int64_t, hipStream_t, const double*, int,
-                                      int);
-template void launch_cg_update<double>(double*, double*, const double*,
-                                       const double*, Scalars*, double*, int,
-                                       int64_t, hipStream_t, const double*,
-                                       int, int);
 template void launch_add_to_F<float>(double*, const float*, int64_t,
                                      hipStream_t);
 template void launch_add_to_F<double>(double*, const double*, int64_t,
