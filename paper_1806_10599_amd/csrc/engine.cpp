@@ -611,14 +611,17 @@ void Engine::cg_solve(int& iters, bool& breakdown, double eta) {
   // is enqueued before the scalars of chunk k are waited for, so the device
   // never idles during that round trip.  A chunk queued after convergence
   // does nothing (every CG kernel returns at once when `done` is set).
+  // With direct launches the length of the chunk queued ahead (even, at
+  // most cg_chunk, at least 2) follows the r.r decay seen so far, so that
+  // little is queued past the expected convergence.
   int parity = 0;
-  auto enqueue = [&](int slot) {
+  auto enqueue = [&](int slot, int len) {
     if (cfg_.use_graph) {
       if (!graph_) capture_graph<T>();
       RVE_HIP(hipGraphLaunch(graph_, st_));
       timer_.replayed(graph_pairs_);
     } else {
-      for (int j = 0; j < cfg_.cg_chunk; ++j) {
+      for (int j = 0; j < len; ++j) {
         cg_iteration<T>(parity);
         parity ^= 1;
       }
@@ -630,14 +633,41 @@ void Engine::cg_solve(int& iters, bool& breakdown, double eta) {
     RVE_HIP(hipEventRecord(chunk_ev_[slot], st_));
     RVE_HIP(hipGetLastError());
   };
+  const int full = cfg_.cg_chunk;
+  int len[2] = {full, full};   // lengths of the chunks in the two slots
+  // the two latest known points (iterations, r.r) of the residual history
+  double it0 = -1.0, rr0 = 0.0, it1 = -1.0, rr1 = 0.0, eta2bb = 0.0;
+  auto next_len = [&](int inflight) {
+    if (cfg_.use_graph || !(it0 >= 0.0) || !(it1 > it0) || !(rr1 > 0.0) ||
+        !(rr0 > rr1) || !(eta2bb > 0.0))
+      return full;
+    // geometric decay per iteration between the two points
+    const double lrho = std::log(rr1 / rr0) / (it1 - it0);
+    const double need = std::log(eta2bb / rr1) / lrho;  // iterations left
+    const double after = need - inflight;
+    if (!std::isfinite(after)) return full;
+    int m = (int)std::ceil(after);
+    m += m & 1;
+    return std::min(full, std::max(2, m));
+  };
   Scalars h;
   int k = 0;
-  enqueue(0);
+  enqueue(0, len[0]);
   for (;;) {
-    enqueue((k + 1) & 1);
+    len[(k + 1) & 1] = next_len(len[k & 1]);
+    enqueue((k + 1) & 1, len[(k + 1) & 1]);
     RVE_HIP(hipEventSynchronize(chunk_ev_[k & 1]));
     h = sc_host_[1 + (k & 1)];
     if (h.done) break;
+    if (it1 < 0.0) {  // the start of the solve: r.r = ||b||^2 at iteration 0
+      it1 = 0.0;
+      rr1 = h.bb;
+    }
+    it0 = it1;
+    rr0 = rr1;
+    it1 = (double)h.iters;
+    rr1 = h.rr_new;
+    eta2bb = h.eta2bb;
     ++k;
   }
   // the live timings of this solve are read at the next synchronous scalar
