@@ -902,7 +902,7 @@ void launch_return_map(const ConstArgs& a, hipStream_t s) {
 
 void launch_rm_count(const int32_t* iters, const int32_t* evals, int64_t N,
                      unsigned long long* stats, hipStream_t s) {
-  hipLaunchKernelGGL(rm_count_kernel, dim3(64), dim3(256), 0, s, iters, evals,
+  hipLaunchKernelGGL(rm_count_kernel, dim3(512), dim3(256), 0, s, iters, evals,
                      N, stats);
 }
 
