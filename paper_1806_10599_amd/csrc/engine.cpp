@@ -1203,13 +1203,13 @@ void Engine::debug_set_field(int field, const double* src, size_t bytes) {
   RVE_HIP(hipStreamSynchronize(st_));
 }
 
-// Average duration (ms) of each hot-path kernel, timed with HIP events on
-// the engine's stream over `reps` launches of the solver's own launch
-// configuration, on the buffers of the last increment:
-//   0 pass A (K:p, direction update, z/y FFT)   1 pass B (x FFT, projection)
-//   2 pass C (inverse y/z FFT, p.Ap)            3 CG vector update
+// Kernel classes of the live timing and of bench_kernels:
+//   0 pass A (z/y FFT of K:p)                   1 pass B (x FFT, projection)
+//   2 pass C (inverse y/z FFT, r -= alpha G(K:p), r.r)
+//   3 unused (the vector update rides on classes 2 and 7)
 //   4 return mapping (FP64)                     5 tangent
 //   6 FP64 residual G(P) (three passes + reduction)
+//   7 direction, previous x update and K:p
 void Engine::set_timing(uint32_t mask) {
   if (mask == timer_.mask()) return;
   // captured CG graphs hold (or lack) the timing events: capture again

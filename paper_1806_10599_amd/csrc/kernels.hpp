@@ -6,6 +6,8 @@
 namespace rve {
 
 enum { SRC_FIELD = 0, SRC_KP = 1 };
+// pass C outputs: the field (||out||^2 partials), the field and p . out
+// partials (batched CG), r -= alpha out in place (single-RVE CG)
 enum { DST_NORM = 0, DST_DOT = 1, DST_CG = 2 };
 
 template <typename T>

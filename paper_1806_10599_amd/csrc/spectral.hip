@@ -15,7 +15,8 @@
 //     the 1/N^3 of the inverse transform, inverse FFT along x.
 //   pass C (one block per x-slab and component group): inverse of pass A,
 //     writing the real field and a per-block FP64 partial (||out||^2, or the
-//     CG dot p . Ap).
+//     batched CG's dot p . Ap), or, in a single-RVE CG iteration, applying
+//     r -= alpha G(K:p) in place with the partials of the new r . r.
 //
 // Only the delta_ik structure of the operator is used: row i of the output
 // depends on row i of the input, so pass B never needs all nine components.
