@@ -161,6 +161,27 @@ def test_graph_capture_equals_direct_launches():
         b.close()
 
 
+def test_cg_chunk_length_changes_only_where_the_host_checks():
+    """The host checks CG convergence once per chunk (queued one ahead, the
+    queued chunk sized from the observed r.r decay); the device iteration
+    and its stopping decision do not depend on it: any chunk length gives
+    the same bits."""
+    c = config_by_name("C2")
+    micro = c.microstructure()
+    hist = c.history()[:3]
+    runs = {}
+    for chunk in (2, 8, 32):
+        r = make_rve(micro, c.operator, "mixed", cg_chunk=chunk, cg_forcing=2)
+        try:
+            infos = [r.increment(inc["F_bar"], inc["dt"]) for inc in hist]
+            assert all(i["status"] == 0 for i in infos)
+            runs[chunk] = ([(i["cg_iters_total"], i["residuals"]) for i in infos],
+                           r.get_state())
+        finally:
+            r.close()
+    assert runs[2] == runs[8] == runs[32]
+
+
 @pytest.mark.parametrize("graph", [False, True])
 def test_live_kernel_timing_counts_and_leaves_results_unchanged(graph):
     """Live event timing brackets each launch of the chosen classes in the
