@@ -52,19 +52,32 @@ def test_single_crystal_fips_closed_form():
                           np.array([[1.0, 0, 0, 0]]))
     p1 = p2 = 1.0
     chis = 0.0
-    pc = w = 0.0
+    pc = plit = w = 0.0
     for eps in (0.003, 0.006, 0.003, 0.0):
         info = rve.increment(macro_F(eps), 0.1, **TIGHT)
         assert info.status == OK
         dgam, st = scalar_single_crystal_step(1 + eps, p1, p2, chis, 0.1, P)
         p1, p2, chis = st["p1"], st["p2"], st["chi"]
+        # dLp = dgam diag(8, -4, -4) / sqrt(6): dLp:dLp = 16 dgam^2
         pc += np.sqrt(32.0 / 3.0) * abs(dgam)       # sqrt(2/3 dLp:dLp)
+        plit += 16.0 * dgam ** 2 / 0.1              # Eq. 23 integrand x dt
         w += st["tau"] * dgam
         assert np.allclose(rve.pcyc, pc, rtol=1e-9, atol=1e-15)
+        assert np.allclose(rve.pcyc_lit, plit, rtol=1e-9, atol=1e-18)
         wa = rve.wcyc[:, np.abs(rve.dg[0]) > 1e-12]
         assert wa.shape[1] == 8
         assert np.allclose(wa, w, rtol=1e-8, atol=1e-12)
         assert np.isclose(info.P_bar[0, 0], st["P1"], rtol=1e-10)
+    assert plit > 0.0   # the history does yield
+    # a new cycle starts from zero accumulators (reading: per-cycle sums)
+    rve.reset_fips()
+    info = rve.increment(macro_F(0.003), 0.1, **TIGHT)
+    assert info.status == OK
+    dgam, st = scalar_single_crystal_step(1.003, p1, p2, chis, 0.1, P)
+    assert np.allclose(rve.pcyc, np.sqrt(32.0 / 3.0) * abs(dgam), rtol=1e-9,
+                       atol=1e-15)
+    assert np.allclose(rve.pcyc_lit, 16.0 * dgam ** 2 / 0.1, rtol=1e-9,
+                       atol=1e-18)
 
 
 def _laminate_reference(rveA_q, lawA, lawB, history, phiA):
