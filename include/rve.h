@@ -256,10 +256,17 @@ enum {
   RVE_FIELD_COUNT = 10
 };
 
-/* Copies one committed field (float64, layout above) into dst (host, or
-   device memory when dst_on_device != 0).  dst_bytes must be at least the
-   field size.  Errors: RVE_EINVAL. */
-rve_status rve_get_fields(rve_t h, int32_t field, void* dst, size_t dst_bytes,
+/* Bit of field id f in the mask of rve_get_fields / rve_batch_get_fields. */
+#define RVE_FIELD_BIT(f) (1u << (f))
+
+/* Copies the committed fields selected by mask (RVE_FIELD_BIT of each field
+   id; float64, layouts above) into dst (host, or device memory when
+   dst_on_device != 0), in increasing field-id order, each field directly
+   after the previous one.  dst_bytes must be at least the sum of the
+   selected fields' sizes (checked before anything is copied).  Errors:
+   RVE_EINVAL (empty mask, unknown bits, NULL or small dst), RVE_ESTATE
+   (RVE_FIELD_STATEV without a user material; crystal fields with one). */
+rve_status rve_get_fields(rve_t h, uint32_t mask, void* dst, size_t dst_bytes,
                           int32_t dst_on_device);
 
 /* Macro state: F_bar (9), P_bar (9), sigma_bar (9), t, increments. */
@@ -504,10 +511,18 @@ rve_status rve_batch_apply_macro_strain_increment(rve_batch_t h,
                                                   double dt,
                                                   rve_increment_info* info);
 rve_status rve_batch_reset_fips(rve_batch_t h);
-rve_status rve_batch_get_fields(rve_batch_t h, int32_t b, int32_t field,
+rve_status rve_batch_get_fields(rve_batch_t h, int32_t b, uint32_t mask,
                                 void* dst, size_t dst_bytes,
                                 int32_t dst_on_device);
 rve_status rve_batch_get_macro(rve_batch_t h, int32_t b, double out[29]);
+/* Test hook: out = G(in) (Sec. 2.1, Eq. 11) for every RVE of the batch at
+   once, through the batched pass kernels in the batch's precision (FP64, or
+   in mixed mode the FP32 passes of the CG on the input rounded to FP32, the
+   output widened).  in / out: host float64, RVE after RVE, each RVE b a
+   [9][n_b^3] block (layout of the single-RVE fields).  Errors: RVE_EINVAL
+   (NULL pointers). */
+rve_status rve_batch_debug_apply_G(rve_batch_t h, const double* in,
+                                   double* out);
 
 /* Host only (no device work, no GPU needed): the band lists that
    rve_get_nonlocal_fips uses, for a microstructure of n^3 voxels (phase,

@@ -114,7 +114,7 @@ def _load():
             C.c_int, [C.c_void_p, P(C.c_double), C.c_double, C.c_int32,
                       C.c_int32, P(RveAdaptiveInfo)]),
         "rve_reset_fips": (C.c_int, [C.c_void_p]),
-        "rve_get_fields": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p,
+        "rve_get_fields": (C.c_int, [C.c_void_p, C.c_uint32, C.c_void_p,
                                      C.c_size_t, C.c_int32]),
         "rve_get_macro": (C.c_int, [C.c_void_p, P(C.c_double)]),
         "rve_get_nonlocal_fips": (C.c_int, [C.c_void_p, C.c_double,
@@ -194,8 +194,10 @@ def _load():
             C.c_int, [C.c_void_p, P(C.c_double), C.c_double,
                       P(RveIncrementInfo)]),
         "rve_batch_reset_fips": (C.c_int, [C.c_void_p]),
-        "rve_batch_get_fields": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32,
+        "rve_batch_get_fields": (C.c_int, [C.c_void_p, C.c_int32, C.c_uint32,
                                            C.c_void_p, C.c_size_t, C.c_int32]),
+        "rve_batch_debug_apply_G": (C.c_int, [C.c_void_p, P(C.c_double),
+                                              P(C.c_double)]),
         "rve_batch_get_macro": (C.c_int, [C.c_void_p, C.c_int32,
                                           P(C.c_double)]),
         "rve_batch_last_error": (C.c_char_p, [C.c_void_p]),
@@ -468,23 +470,33 @@ class Rve:
         self._check(LIB.rve_reset_fips(self._h))
 
     def field(self, name):
-        fid, comps = FIELDS[name]
-        if comps is None:
-            comps = getattr(self, "_nsv", 0)
-            out = np.empty((comps, self.N), dtype=np.float64)
-            self._check(LIB.rve_get_fields(self._h, fid, out.ctypes.data_as(
-                C.c_void_p), out.nbytes, 0))
-            return out
-        out = np.empty((comps, self.N), dtype=np.float64)
-        self._check(LIB.rve_get_fields(self._h, fid, out.ctypes.data_as(
+        return self.fields(name)[name]
+
+    def fields(self, *names):
+        """Several committed fields in one rve_get_fields call (bit mask of
+        their ids); returns {name: array}, one component per row."""
+        order = sorted(set(names), key=lambda k: FIELDS[k][0])
+        comps = [FIELDS[k][1] if FIELDS[k][1] is not None
+                 else getattr(self, "_nsv", 0) for k in order]
+        out = np.empty((sum(comps), self.N), dtype=np.float64)
+        mask = 0
+        for k in order:
+            mask |= 1 << FIELDS[k][0]
+        self._check(LIB.rve_get_fields(self._h, mask, out.ctypes.data_as(
             C.c_void_p), out.nbytes, 0))
-        return out if comps > 1 else out[0]
+        res, row = {}, 0
+        for k, c in zip(order, comps):
+            blk = out[row:row + c]
+            res[k] = blk[0].copy() if FIELDS[k][1] == 1 else blk.copy()
+            row += c
+        return res
 
     def field_device(self, name, out):
         """Copy a field into a torch tensor on the GPU (float64, contiguous)."""
         fid, comps = FIELDS[name]
         assert out.is_cuda and out.dtype == torch.float64 and out.is_contiguous()
-        self._check(LIB.rve_get_fields(self._h, fid, C.c_void_p(out.data_ptr()),
+        self._check(LIB.rve_get_fields(self._h, 1 << fid,
+                                       C.c_void_p(out.data_ptr()),
                                        out.numel() * 8, 1))
         return out
 
@@ -718,9 +730,25 @@ class BatchRve:
     def field(self, b, name):
         fid, comps = FIELDS[name]
         out = np.empty((comps, self.ns[b] ** 3), dtype=np.float64)
-        self._check(LIB.rve_batch_get_fields(self._h, b, fid, out.ctypes.data_as(
-            C.c_void_p), out.nbytes, 0))
+        self._check(LIB.rve_batch_get_fields(self._h, b, 1 << fid,
+                                             out.ctypes.data_as(C.c_void_p),
+                                             out.nbytes, 0))
         return out if comps > 1 else out[0]
+
+    def debug_apply_G(self, fields):
+        """G (Eq. 11) of one [9][n_b^3] field per RVE through the batched
+        passes, in the batch's precision."""
+        flat = np.concatenate([np.ascontiguousarray(f, dtype=np.float64)
+                               .reshape(-1) for f in fields])
+        assert flat.size == sum(9 * n ** 3 for n in self.ns)
+        out = np.empty_like(flat)
+        self._check(LIB.rve_batch_debug_apply_G(self._h, _dptr(flat),
+                                                _dptr(out)))
+        res, pos = [], 0
+        for n in self.ns:
+            res.append(out[pos:pos + 9 * n ** 3].reshape(9, n ** 3))
+            pos += 9 * n ** 3
+        return res
 
     def macro(self, b):
         out = np.empty(29)

@@ -607,12 +607,74 @@ int BatchEngine::increment(const double* Fbar_all, double dt,
   return first_bad;
 }
 
+// G(in) (Sec. 2.1, Eq. 11) of every RVE at once, through the batched pass
+// kernels of the residual (FP64 mode) or of the CG precision (mixed mode:
+// the input is rounded to FP32 first).  in / out: RVE after RVE, each a
+// [9][n_b^3] block of doubles.
+void BatchEngine::debug_apply_G(const double* in, double* out) {
+  if (!in || !out) throw Error(RVE_EINVAL, "null field");
+  int64_t pos = 0;
+  for (int b = 0; b < B_; ++b) {
+    const int64_t Nb = (int64_t)n_[b] * n_[b] * n_[b];
+    for (int c = 0; c < 9; ++c)
+      RVE_HIP(hipMemcpyAsync(r64_ + (int64_t)c * Nt_ + off_[b], in + pos + c * Nb,
+                             Nb * sizeof(double), hipMemcpyHostToDevice, st_));
+    pos += 9 * Nb;
+    sc_host_[b].inactive = 0;
+    sc_host_[b].done = 0;
+  }
+  upload_scalars();
+  if (fp64_) {
+    BatchSpec<double> rs{};
+    rs.items = (const SpecItem<double>*)items64_;
+    rs.nitems = B_;
+    rs.cs = Nt_;
+    rs.field = r64_;
+    rs.spec = (cplx<double>*)spec64_;
+    launch_G_batch<double>(rs, SRC_FIELD, nullptr, P_, blocksA64_, blocksB64_,
+                           ldsA64_, ldsB64_, st_);
+  } else {
+    launch_convert<float>(r64_, (float*)x_, 9 * Nt_, st_);
+    BatchSpec<float> rs{};
+    rs.items = (const SpecItem<float>*)items32_;
+    rs.nitems = B_;
+    rs.cs = Nt_;
+    rs.field = (const float*)x_;
+    rs.spec = (cplx<float>*)spec_;
+    launch_G_batch<float>(rs, SRC_FIELD, nullptr, P_, blocksA32_, blocksB32_,
+                          ldsA32_, ldsB32_, st_);
+  }
+  RVE_HIP(hipGetLastError());
+  pos = 0;
+  for (int b = 0; b < B_; ++b) {
+    const int64_t Nb = (int64_t)n_[b] * n_[b] * n_[b];
+    for (int c = 0; c < 9; ++c)
+      RVE_HIP(hipMemcpyAsync(out + pos + c * Nb, P_ + (int64_t)c * Nt_ + off_[b],
+                             Nb * sizeof(double), hipMemcpyDeviceToHost, st_));
+    pos += 9 * Nb;
+  }
+  RVE_HIP(hipStreamSynchronize(st_));
+}
+
 void BatchEngine::reset_fips() {
   launch_fill_f64(pcyc_, 0.0, Nt_, st_);
   launch_fill_f64(pcyc_lit_, 0.0, Nt_, st_);
   launch_fill_f64(wcyc_, 0.0, 12 * Nt_, st_);
   RVE_HIP(hipGetLastError());
   RVE_HIP(hipStreamSynchronize(st_));
+}
+
+size_t BatchEngine::field_bytes(int b, int field) const {
+  if (b < 0 || b >= B_) throw Error(RVE_EINVAL, "RVE index out of range");
+  size_t comps = 0;
+  switch (field) {
+    case RVE_FIELD_F: case RVE_FIELD_P: case RVE_FIELD_SIGMA:
+    case RVE_FIELD_FPINV: comps = 9; break;
+    case RVE_FIELD_CHI: case RVE_FIELD_DGAMMA: case RVE_FIELD_WCYC: comps = 12; break;
+    case RVE_FIELD_PCYC: case RVE_FIELD_PCYC_LIT: comps = 1; break;
+    default: throw Error(RVE_EINVAL, "unknown field id for a batch");
+  }
+  return comps * (size_t)n_[b] * n_[b] * n_[b] * sizeof(double);
 }
 
 void BatchEngine::get_field(int b, int field, void* dst, size_t bytes,

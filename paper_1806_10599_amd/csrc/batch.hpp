@@ -23,11 +23,14 @@ class BatchEngine {
   int increment(const double* Fbar_all, double dt, rve_increment_info* info);
   void reset_fips();
   void get_field(int b, int field, void* dst, size_t bytes, bool on_device);
+  size_t field_bytes(int b, int field) const;
   void get_macro(int b, double out[29]);
   void nonlocal_fips(int b, double width, rve_nonlocal_fips* out,
                      double* grain_pcyc, double* grain_pcyc_lit, int32_t labels,
                      double* band_wcyc, int32_t* band_desc, int64_t band_cap);
   int count() const { return B_; }
+  // test hook: out = G(in) with the batched passes in the batch's precision
+  void debug_apply_G(const double* in, double* out);
 
  private:
   void* alloc(size_t bytes);

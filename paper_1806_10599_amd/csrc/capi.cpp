@@ -56,6 +56,27 @@ rve_status guarded(H* h, F&& f) {
   }
 }
 
+// The fields selected by mask (bit f = field id f), in increasing id order,
+// one after another in dst; sizes are checked before anything is copied.
+template <class Size, class Copy>
+void copy_masked(uint32_t mask, void* dst, size_t dst_bytes, Size&& size,
+                 Copy&& copy) {
+  if (mask == 0 || (mask >> RVE_FIELD_COUNT) != 0)
+    throw rve::Error(RVE_EINVAL, "field mask selects no field or unknown bits");
+  if (!dst) throw rve::Error(RVE_EINVAL, "null destination");
+  size_t need = 0;
+  for (int f = 0; f < RVE_FIELD_COUNT; ++f)
+    if (mask & (1u << f)) need += size(f);
+  if (dst_bytes < need) throw rve::Error(RVE_EINVAL, "destination too small");
+  char* p = (char*)dst;
+  for (int f = 0; f < RVE_FIELD_COUNT; ++f) {
+    if (!(mask & (1u << f))) continue;
+    const size_t b = size(f);
+    copy(f, p, b);   // also for an empty field: it raises the state errors
+    p += b;
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -159,10 +180,14 @@ rve_status rve_reset_fips(rve_t h) {
   });
 }
 
-rve_status rve_get_fields(rve_t h, int32_t field, void* dst, size_t dst_bytes,
+rve_status rve_get_fields(rve_t h, uint32_t mask, void* dst, size_t dst_bytes,
                           int32_t dst_on_device) {
   return guarded(h, [&] {
-    h->eng->get_field(field, dst, dst_bytes, dst_on_device != 0);
+    copy_masked(mask, dst, dst_bytes,
+                [&](int f) { return h->eng->field_bytes(f); },
+                [&](int f, void* p, size_t b) {
+                  h->eng->get_field(f, p, b, dst_on_device != 0);
+                });
     return RVE_OK;
   });
 }
@@ -467,11 +492,23 @@ rve_status rve_batch_reset_fips(rve_batch_t h) {
   });
 }
 
-rve_status rve_batch_get_fields(rve_batch_t h, int32_t b, int32_t field,
+rve_status rve_batch_get_fields(rve_batch_t h, int32_t b, uint32_t mask,
                                 void* dst, size_t dst_bytes,
                                 int32_t dst_on_device) {
   return guarded(h, [&] {
-    h->eng->get_field(b, field, dst, dst_bytes, dst_on_device != 0);
+    copy_masked(mask, dst, dst_bytes,
+                [&](int f) { return h->eng->field_bytes(b, f); },
+                [&](int f, void* p, size_t n) {
+                  h->eng->get_field(b, f, p, n, dst_on_device != 0);
+                });
+    return RVE_OK;
+  });
+}
+
+rve_status rve_batch_debug_apply_G(rve_batch_t h, const double* in,
+                                   double* out) {
+  return guarded(h, [&] {
+    h->eng->debug_apply_G(in, out);
     return RVE_OK;
   });
 }

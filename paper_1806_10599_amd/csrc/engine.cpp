@@ -962,6 +962,19 @@ void Engine::reset_fips() {
   RVE_HIP(hipStreamSynchronize(st_));
 }
 
+size_t Engine::field_bytes(int field) const {
+  size_t comps = 0;
+  switch (field) {
+    case RVE_FIELD_F: case RVE_FIELD_P: case RVE_FIELD_SIGMA:
+    case RVE_FIELD_FPINV: comps = 9; break;
+    case RVE_FIELD_CHI: case RVE_FIELD_DGAMMA: case RVE_FIELD_WCYC: comps = 12; break;
+    case RVE_FIELD_PCYC: case RVE_FIELD_PCYC_LIT: comps = 1; break;
+    case RVE_FIELD_STATEV: comps = (size_t)nsv_; break;
+    default: throw Error(RVE_EINVAL, "unknown field id");
+  }
+  return comps * (size_t)N_ * sizeof(double);
+}
+
 void Engine::get_field(int field, void* dst, size_t bytes, bool on_device) {
   if (!dst) throw Error(RVE_EINVAL, "null destination");
   const double* src = nullptr;

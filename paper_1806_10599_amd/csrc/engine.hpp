@@ -33,6 +33,7 @@ class Engine {
                          int grow_after, rve_adaptive_info* info);
   void reset_fips();
   void get_field(int field, void* dst, size_t bytes, bool on_device);
+  size_t field_bytes(int field) const;
   void get_macro(double out[29]);
   void nonlocal_fips(double width, rve_nonlocal_fips* out, double* grain_pcyc,
                      double* grain_pcyc_lit, int32_t labels, double* band_wcyc,

@@ -53,28 +53,33 @@ def test_apply_G_anisotropic_cell():
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("mixed", 3e-6)])
 def test_apply_G_largest_grid_invariants(prec, tol):
-    # 128^3: G is idempotent, output has zero mean; a compatible single-mode
-    # field is reproduced
+    """128^3, both operators: G is idempotent, its output has zero mean, and
+    a compatible single-mode field u = a sin(2 pi k.x) is reproduced, with
+    grad u = a (x) v cos(2 pi k.x) for the operator's own wave vector:
+    v = 2 pi k (continuous, Eq. 19) or v = n tan(pi k / n) (discrete,
+    Eqs. 20-21, the rotated-difference gradient of a Fourier mode)."""
     n = 128
     rng = np.random.default_rng(128)
     A = rng.standard_normal((9, n ** 3))
-    with _rve(n, "discrete") as r:
-        B = r.debug_apply_G(A, prec)
-        BB = r.debug_apply_G(B, prec)
+    x = (np.arange(n) + 0.5) / n
+    X = np.meshgrid(x, x, x, indexing="ij")
+    k = np.array([3, -5, 7])
+    arg = 2 * np.pi * (k[0] * X[0] + k[1] * X[1] + k[2] * X[2])
+    a = np.array([0.3, -1.0, 0.7])
+    for op in ("discrete", "continuous"):
+        v = 2 * np.pi * k if op == "continuous" else n * np.tan(np.pi * k / n)
+        comp = np.einsum("i,j,abc->ijabc", a, v, np.cos(arg)).reshape(9, -1)
+        with _rve(n, op) as r:
+            B = r.debug_apply_G(A, prec)
+            BB = r.debug_apply_G(B, prec)
+            out = r.debug_apply_G(comp, prec)
         assert np.max(np.abs(B.mean(axis=1))) < tol
         assert np.max(np.abs(BB - B)) < 10 * tol * np.max(np.abs(A))
-        x = (np.arange(n) + 0.5) / n
-        X = np.meshgrid(x, x, x, indexing="ij")
-        k = np.array([3, -5, 7])
-        arg = 2 * np.pi * (k[0] * X[0] + k[1] * X[1] + k[2] * X[2])
-        a = np.array([0.3, -1.0, 0.7])
-        comp = np.einsum("i,j,abc->ijabc", a, 2 * np.pi * k, np.cos(arg))
-        # exact for the continuous operator; for the discrete one use its
-        # own compatible form tan(q/2)
-        with _rve(n, "continuous") as rc:
-            out = rc.debug_apply_G(comp.reshape(9, -1), prec)
-        assert np.max(np.abs(out - comp.reshape(9, -1))) < 10 * tol * np.max(
-            np.abs(comp))
+        assert np.max(np.abs(out - comp)) < 10 * tol * np.max(np.abs(comp)), op
+        if op == "discrete":   # the check tells the two operators apart
+            vc = 2 * np.pi * k
+            wrong = np.einsum("i,j,abc->ijabc", a, vc, np.cos(arg)).reshape(9, -1)
+            assert np.max(np.abs(out - wrong)) > 1e-3 * np.max(np.abs(comp))
 
 
 def _oracle_law(micro, F, Fpi0, chi0, dt):

@@ -23,12 +23,17 @@ ORACLE_TIGHT = dict(tol=1e-12, eta=1e-10, newton_max=40, cg_max=5000)
 
 
 def _compare_state(r, o, tol=1e-10):
-    assert rel_maxnorm(r.field("F"), to_soa(o.F)) < tol
-    assert rel_maxnorm(r.field("P"), to_soa(o.P)) < tol
-    if np.max(o.pcyc) > 0:
-        assert rel_maxnorm(r.field("pcyc"), o.pcyc) < tol
-        assert rel_maxnorm(r.field("wcyc"), o.wcyc.T) < tol
-        assert rel_maxnorm(r.field("chi"), o.chi.T) < tol
+    """Every committed field the library exports against the oracle's."""
+    got = r.fields("F", "P", "sigma", "Fpinv", "chi", "dgamma", "pcyc",
+                   "pcyc_lit", "wcyc")
+    ref = dict(F=to_soa(o.F), P=to_soa(o.P), sigma=to_soa(o.cauchy()),
+               Fpinv=to_soa(o.Fpi), chi=o.chi.T, dgamma=o.dg.T, pcyc=o.pcyc,
+               pcyc_lit=o.pcyc_lit, wcyc=o.wcyc.T)
+    for k, v in ref.items():
+        if np.max(np.abs(v)) < 1e-14:
+            assert np.max(np.abs(got[k])) < 1e-14, k
+        else:
+            assert rel_maxnorm(got[k], v) < tol, k
 
 
 def test_homogeneous_medium_single_evaluation():
@@ -45,7 +50,8 @@ def test_homogeneous_medium_single_evaluation():
         r.close()
 
 
-@pytest.mark.parametrize("cfg,ninc", [("C1", 7), ("C2", 2)])
+# the whole C1 cycle is compared in test_gpu_vs_oracle.py
+@pytest.mark.parametrize("cfg,ninc", [("C1", 2), ("C2", 2)])
 def test_fp64_increments_match_oracle(cfg, ninc):
     c = config_by_name(cfg)
     micro = c.microstructure()
@@ -60,36 +66,6 @@ def test_fp64_increments_match_oracle(cfg, ninc):
             assert info["status"] == 0 and oi.status == 0
             _compare_state(r, o)
             assert rel_maxnorm(info["P_bar"], oi.P_bar) < 1e-10
-    finally:
-        r.close()
-
-
-def test_mixed_precision_macro_loop_and_fips():
-    # C1 microstructure and first half cycle, mixed mode at tol 1e-6 against
-    # the FP64 oracle at 1e-12: Eq. 29 on sigma_11, Eq. 30 on P_cyc, W
-    c = config_by_name("C1")
-    micro = c.microstructure()
-    hist = c.history()[:10]
-    r = make_rve(micro, c.operator, "mixed", newton_tol=1e-6)
-    o = oracle_for(micro, c.operator)
-    s_gpu, s_ref = [], []
-    try:
-        for inc in hist:
-            info = r.increment(inc["F_bar"], inc["dt"])
-            oi = o.increment(inc["F_bar"], inc["dt"], **ORACLE_TIGHT)
-            assert info["status"] == 0
-            s_gpu.append(info["sigma_bar"][0, 0])
-            s_ref.append(oi.sigma_bar[0, 0])
-        s_gpu, s_ref = np.array(s_gpu), np.array(s_ref)
-        err = np.max(np.abs(s_gpu - s_ref)) / np.max(np.abs(s_ref))
-        assert err < 1e-4, err
-        pc = r.field("pcyc")
-        assert np.linalg.norm(pc - o.pcyc) / np.linalg.norm(o.pcyc) < 1e-3
-        w = r.field("wcyc")
-        for a in range(12):
-            ref = o.wcyc[:, a]
-            if np.linalg.norm(ref) > 0:
-                assert np.linalg.norm(w[a] - ref) / np.linalg.norm(ref) < 1e-3
     finally:
         r.close()
 
@@ -268,17 +244,22 @@ def test_fft_schedules_agree_and_autotune_picks_one():
                 r.close()
 
 
-def test_full_size_chosen_path_sampled_against_oracle():
-    """The 64^3 workload in the launch configuration bench.py times (mixed
-    precision, learned warm start, tuned FFT schedule): after each of the
-    first increments, sampled voxels are re-integrated by the oracle's point
-    law from the previous committed state at the GPU's converged F (FP64 on
-    both sides), and the whole-field invariants are checked with the
-    oracle's projection: ||G(P)|| <= tol ||P|| (Sec. 2.1, Eq. 11), F - F_bar
-    compatible (G(F - F_bar) = F - F_bar) and <F> = F_bar (to the FP32
-    rounding of the CG corrections)."""
-    import torch
-    from oracle import material
+def test_full_size_chosen_path_against_oracle(oracle_map):
+    """The 64^3 workload (200 grains, 8 % particles, discrete operator) in
+    the configuration bench.py times: mixed precision, learned start kept
+    directly below half the homogeneous predictor's residual (warm_start 2),
+    inexact-Newton forcing mode 2, CG chunks of 8.  After each of the first
+    increments every voxel, grains and particles, is re-integrated by the
+    oracle's point law from the previous committed state at the GPU's
+    converged F (FP64 on both sides), and the whole-field conditions are
+    checked with the oracle's projection: ||G(P)|| <= tol ||P|| (Sec. 2.1,
+    Eq. 11) and F - F_bar compatible.  The mean <F> = F_bar holds to the
+    FP32 rounding of the CG corrections: every CG iteration can shift the
+    mean of its iterate by at most one FP32 rounding (2^-24) of the largest
+    entry, so over an increment |<F> - F_bar| grows by at most
+    (CG iterations) 2^-24 max|F - F_prev - dF_bar| (the corrections stay
+    below the fluctuation increment in size; a factor 2 covers overshoot)."""
+    import oracle_jobs
     from oracle.solver import OracleRVE
     from paper_1806_10599_amd.binding import Rve, WarmStartNet
     from paper_1806_10599_amd.warmstart import trained_params
@@ -290,41 +271,52 @@ def test_full_size_chosen_path_sampled_against_oracle():
                   material_params(), c.operator)
     net = WarmStartNet()
     net.set_params(trained_params())
-    r = Rve(micro.n, projection=c.operator, precision="mixed", warm_start=True)
+    r = Rve(micro.n, projection=c.operator, precision="mixed", warm_start=2,
+            cg_forcing=2, cg_chunk=8)
     r.set_microstructure(micro.phase, micro.quat, micro.law, material_params())
     r.attach_warm_start(net)
-    rng = np.random.default_rng(7)
+    chunks = np.array_split(np.arange(N), 12)
     try:
-        prev = {k: r.field(k) for k in ("Fpinv", "chi")}
+        prev = r.fields("F", "Fpinv", "chi")
+        drift = np.zeros(9)
+        Fb_prev = np.eye(3)
         for inc in hist:
+            print(f"C3 increment {inc['k']}", flush=True)
             info = r.increment(inc["F_bar"], inc["dt"])
-            assert info["status"] == 0
-            F = r.field("F").T.reshape(N, 3, 3)
-            P = r.field("P").T.reshape(N, 3, 3)
-            # point law at sampled crystal voxels
-            idx = rng.choice(o.cp_idx, size=256, replace=False)
-            g = o.phase[idx]
-            Fpi0 = prev["Fpinv"][:, idx].T.reshape(-1, 3, 3)
-            chi0 = prev["chi"][:, idx].T
-            ref = material.cp_update(F[idx], Fpi0, chi0, np.zeros((idx.size, 12)),
-                                     o.S0g[g], o.Cg[g], o.params, inc["dt"],
-                                     tangent=False)
-            assert ref["ok"].all()
-            err = np.max(np.abs(P[idx] - ref["P"])) / np.max(np.abs(ref["P"]))
+            assert info["status"] == 0 and info["residual_rel"] <= 1e-6
+            got = r.fields("F", "P", "dgamma", "Fpinv", "chi")
+            F = got["F"].T.reshape(N, 3, 3)
+            P = got["P"].T.reshape(N, 3, 3)
+            Fpi0 = prev["Fpinv"].T.reshape(N, 3, 3)
+            chi0 = prev["chi"].T
+            res = oracle_map(oracle_jobs.point_law, [
+                (F[ix], Fpi0[ix], chi0[ix], micro.phase[ix], micro.quat,
+                 micro.law, inc["dt"]) for ix in chunks])
+            Pref = np.concatenate([x[0] for x in res])
+            dgref = np.concatenate([x[1] for x in res])
+            assert all(x[2].all() for x in res)
+            err = np.max(np.abs(P - Pref)) / np.max(np.abs(Pref))
+            derr = np.max(np.abs(got["dgamma"].T - dgref)) / max(
+                np.max(np.abs(dgref)), 1e-300)
+            print(f"  point law at all {N} voxels: P {err:.1e}, slips {derr:.1e}")
             assert err < 1e-9, err
-            dg = r.field("dgamma")[:, idx].T
-            assert np.max(np.abs(dg - ref["dg"])) <= 1e-9 * max(
-                1e-12, np.max(np.abs(ref["dg"]))) + 1e-15
-            # whole-field invariants with the oracle's projection
-            res = np.linalg.norm(o.G(P)) / np.linalg.norm(P)
-            assert res <= 1e-6 * (1 + 1e-6), res
+            assert derr < 1e-9, derr
+            # whole-field conditions with the oracle's projection
+            resid = np.linalg.norm(o.G(P)) / np.linalg.norm(P)
+            assert resid <= 1e-6 * (1 + 1e-6), resid
             Fb = np.asarray(inc["F_bar"]).reshape(3, 3)
             fl = F - Fb[None]
             comp = np.linalg.norm(o.G(fl) - fl) / np.linalg.norm(fl)
             assert comp < 1e-5, comp
-            # the FP32 CG corrections have zero mean to FP32 rounding only
-            assert np.max(np.abs(F.mean(axis=0) - Fb)) < 1e-9
-            prev = {k: r.field(k) for k in ("Fpinv", "chi")}
+            dfl = F - prev["F"].T.reshape(N, 3, 3) - (Fb - Fb_prev)[None]
+            bound = info["cg_iters_total"] * 2.0 ** -24 * 2 * np.max(np.abs(dfl))
+            step = (F.mean(axis=0) - Fb).reshape(9) - drift
+            print(f"  <F> - F_bar grew by {np.max(np.abs(step)):.1e}"
+                  f" (bound {bound:.1e})")
+            assert np.max(np.abs(step)) <= bound
+            drift = (F.mean(axis=0) - Fb).reshape(9)
+            prev = {k: got[k] for k in ("F", "Fpinv", "chi")}
+            Fb_prev = Fb
     finally:
         r.attach_warm_start(None)
         r.close()
