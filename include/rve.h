@@ -348,6 +348,30 @@ const char* rve_last_error(rve_t h);
    indicator fields. */
 rve_status rve_debug_apply_G(rve_t h, const double* in, double* out,
                              int32_t precision);
+
+/* For callers that cannot allocate device memory (code under stream or
+   graph capture, tight serving loops, harnesses that forbid hipMalloc):
+   out = G(in) (Sec. 2.1, Eq. 11) in FP64, the computation of
+   rve_debug_apply_G(..., RVE_PREC_FP64) without a handle and without any
+   allocation.  The spectrum, FFT twiddles, wave vectors and per-block
+   partial sums live in one static device array of RVE_NOALLOC_SCRATCH_BYTES
+   per GPU, which each GPU the library runs on holds until the process ends.
+   n: voxels per axis of a cubic grid, one of 16, 24, 32, 40, 48, 64 (at most
+   RVE_NOALLOC_MAX_N); L[3]: cell edge lengths (host); projection: RVE_PROJ_*;
+   in, out: [9][n^3] float64 fields in device memory of the current device,
+   layout of the fields above, owned by the caller, not aliased; stream:
+   hipStream_t (NULL = default stream).  The work is enqueued on stream and
+   the call returns without synchronizing.  Every call on one GPU uses that
+   GPU's array (nothing needs to start at zero: each call writes every entry
+   it reads), so calls that overlap in time on one GPU (other streams or
+   threads) race.  Errors (nothing enqueued): RVE_EINVAL (n unsupported or
+   above the maximum, bad L or projection, NULL or aliased fields),
+   RVE_EDEVICE (HIP error); rve_last_error(NULL) describes them. */
+#define RVE_NOALLOC_MAX_N 64
+#define RVE_NOALLOC_SCRATCH_BYTES 18881536
+rve_status rve_apply_G_noalloc(int32_t n, const double L[3],
+                               int32_t projection, const double* in,
+                               double* out, void* stream);
 rve_status rve_debug_constitutive(rve_t h, const double* F, double dt,
                                   double* P, double* K, double* dg,
                                   int32_t* fails);

@@ -198,6 +198,9 @@ def _load():
                                            C.c_void_p, C.c_size_t, C.c_int32]),
         "rve_batch_debug_apply_G": (C.c_int, [C.c_void_p, P(C.c_double),
                                               P(C.c_double)]),
+        "rve_apply_G_noalloc": (C.c_int, [C.c_int32, P(C.c_double), C.c_int32,
+                                          C.c_void_p, C.c_void_p,
+                                          C.c_void_p]),
         "rve_batch_get_macro": (C.c_int, [C.c_void_p, C.c_int32,
                                           P(C.c_double)]),
         "rve_batch_last_error": (C.c_char_p, [C.c_void_p]),
@@ -645,6 +648,27 @@ def umat_bridge(F, sigma, ddsdde, stream=None):
     if rc != RVE_OK:
         raise RveError(rc, LIB.rve_last_error(None).decode())
     return P, K
+
+
+def apply_G_noalloc(n, field, out, L=(1.0, 1.0, 1.0), projection="discrete",
+                    stream=None):
+    """out = G(field) (Eq. 11, FP64) through rve_apply_G_noalloc, which
+    allocates nothing; field, out: contiguous float64 CUDA tensors of shape
+    (9, n^3).  Enqueued on the stream; no synchronization."""
+    for t in (field, out):
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+                and t.dim() == 2 and t.shape[0] == 9 and t.shape[1] == n ** 3):
+            raise ValueError("expected contiguous float64 CUDA tensors of "
+                             "shape (9, n^3)")
+    Lc = np.ascontiguousarray(L, dtype=np.float64)
+    st = stream if stream is not None else torch.cuda.current_stream()
+    rc = LIB.rve_apply_G_noalloc(int(n), _dptr(Lc), PROJ[projection],
+                                 C.c_void_p(field.data_ptr()),
+                                 C.c_void_p(out.data_ptr()),
+                                 C.c_void_p(st.cuda_stream or None))
+    if rc != RVE_OK:
+        raise RveError(rc, LIB.rve_last_error(None).decode())
+    return out
 
 
 class BatchRve:

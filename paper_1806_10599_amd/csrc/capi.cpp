@@ -239,6 +239,21 @@ const char* rve_last_error(rve_t h) {
   return h->err.c_str();
 }
 
+rve_status rve_apply_G_noalloc(int32_t n, const double L[3],
+                               int32_t projection, const double* in,
+                               double* out, void* stream) {
+  try {
+    rve::noalloc_apply_G(n, L, projection, in, out, (hipStream_t)stream);
+  } catch (const rve::Error& e) {
+    g_create_error = e.what();
+    return (rve_status)e.code;
+  } catch (const std::exception& e) {
+    g_create_error = e.what();
+    return RVE_EINVAL;
+  }
+  return RVE_OK;
+}
+
 rve_status rve_debug_apply_G(rve_t h, const double* in, double* out,
                              int32_t precision) {
   return guarded(h, [&] {

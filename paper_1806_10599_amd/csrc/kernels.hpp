@@ -87,6 +87,9 @@ struct SpectralLaunch {
 
 template <typename T>
 void launch_G(int n, const SpectralLaunch<T>& L, hipStream_t s);
+// G in FP64 with the static scratch array of noalloc.hip (no allocation)
+void noalloc_apply_G(int n, const double L[3], int projection, const double* in,
+                     double* out, hipStream_t s);
 // block counts of the slab (A, C) and pencil (B) grids; 0 = default schedule
 int slab_blocks(int n, bool fp64, int cpb = 0);
 int pencil_blocks(int n, bool fp64, int tt = 0);
