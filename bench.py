@@ -117,6 +117,12 @@ def parse():
                          "cg_tol (no inexact-Newton forcing)")
     ap.add_argument("--no-umat", action="store_true",
                     help="skip the Appendix A bridge measurement")
+    ap.add_argument("--no-ablations", action="store_true",
+                    help="skip the ablation rows (forcing, precision, "
+                         "extrapolated start) of the chosen path")
+    ap.add_argument("--no-paper-case", action="store_true",
+                    help="skip the paper's Sec. 5 case on 32^3 (three R = 0 "
+                         "cycles at 1 %%, chosen and FP64 paths)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain elementwise copy of 256 MiB "
                          "(read + write), the reference kernel that scales "
@@ -159,17 +165,26 @@ def copy_calibration(stream):
 
 def run_path(micro, hist, precision, use_graph, steps, warmup, stream,
              live=True, learned=False, start=None, cg_chunk=8,
-             with_fips=False, forcing=False, schedule=None):
+             with_fips=False, forcing=False, schedule=None, check=False,
+             sample_all=False, warm_start=None):
     """Solve the history; time its last ``steps`` increments (at least
-    ``warmup`` untimed increments come first)."""
+    ``warmup`` untimed increments come first).
+
+    check: the committed state before the last timed increment and the
+    fields after it are copied out (outside the timed region: the K steps
+    are timed as two bracketed intervals, increments 1..K-1 and K) for the
+    oracle's error checks.  sample_all: the two increments before the timed
+    window run with every hot-path kernel class timed live (the CG kernels
+    included), to rank the kernels by their share of an increment."""
     import torch
-    from paper_1806_10599_amd.binding import Rve, WarmStartNet
+    from paper_1806_10599_amd.binding import (KERNEL_CLASSES, Rve,
+                                              WarmStartNet)
     from paper_1806_10599_amd.warmstart import trained_params
     from synthetic import material_params
+    ws = (WARM_MODE if learned else 0) if warm_start is None else warm_start
     r = Rve(micro.n, projection="discrete", precision=precision,
             newton_tol=1e-6, cg_tol=1e-4, use_graph=use_graph, stream=stream,
-            warm_start=WARM_MODE if learned else 0, cg_chunk=cg_chunk,
-            cg_forcing=forcing)
+            warm_start=ws, cg_chunk=cg_chunk, cg_forcing=forcing)
     r.set_microstructure(micro.phase, micro.quat, micro.law, material_params())
     if schedule:
         r.set_fft_schedule(*schedule)
@@ -178,29 +193,58 @@ def run_path(micro, hist, precision, use_graph, steps, warmup, stream,
         net = WarmStartNet(stream=stream)
         net.set_params(trained_params())
         r.attach_warm_start(net)
-    if live:
-        r.set_kernel_timing(LIVE_CLASSES)
     start = max(warmup, len(hist) - steps) if start is None else max(warmup, start)
-    for inc in hist[:start]:
+    sample, sample_cg = None, 0
+    for j, inc in enumerate(hist[:start]):
+        if sample_all and j == start - 2:
+            torch.cuda.synchronize()
+            r.set_kernel_timing(KERNEL_CLASSES)
+            r.kernel_timing(reset=True)
         if inc["cycle_start"]:
             r.reset_fips()
         info = r.increment(inc["F_bar"], inc["dt"])
         if info["status"] != 0:
             raise RuntimeError(f"increment {inc['k']} failed: {info['status']}")
+        if sample_all and j >= start - 2:
+            sample_cg = sample_cg + info["cg_iters_total"]
+    if sample_all:
+        torch.cuda.synchronize()
+        sample = dict(increments=[int(hist[start - 2]["k"]),
+                                  int(hist[start - 1]["k"])],
+                      timing=r.kernel_timing(reset=True), cg_total=sample_cg)
+        r.set_kernel_timing(())
+    if live:
+        r.set_kernel_timing(LIVE_CLASSES)
     torch.cuda.synchronize()
     r.kernel_timing(reset=True)
     r.return_map_counts(reset=True)
-    t0 = time.perf_counter()
+    window = hist[start:start + steps]
     timed = []
-    for inc in hist[start:start + steps]:
-        if inc["cycle_start"]:
-            r.reset_fips()
-        info = r.increment(inc["F_bar"], inc["dt"])
-        if info["status"] != 0:
-            raise RuntimeError(f"increment {inc['k']} failed: {info['status']}")
-        timed.append(info)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    chk = None
+    elapsed = 0.0
+    parts = [window[:-1], window[-1:]] if check else [window]
+    for part in parts:
+        if check and part is parts[1]:
+            before = r.fields("Fpinv", "chi")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for inc in part:
+            if inc["cycle_start"]:
+                r.reset_fips()
+            info = r.increment(inc["F_bar"], inc["dt"])
+            if info["status"] != 0:
+                raise RuntimeError(f"increment {inc['k']} failed: "
+                                   f"{info['status']}")
+            timed.append(info)
+        torch.cuda.synchronize()
+        elapsed += time.perf_counter() - t0
+    if check:
+        after = r.fields("F", "P", "dgamma")
+        inc = window[-1]
+        chk = dict(k=int(inc["k"]), F_bar=np.asarray(inc["F_bar"]),
+                   dt=inc["dt"], Fpi0=before["Fpinv"], chi0=before["chi"],
+                   F=after["F"], P=after["P"], dg=after["dgamma"],
+                   residual_rel=timed[-1]["residual_rel"])
     live_t = r.kernel_timing() if live else None
     counts = r.return_map_counts() if live else None
     sched = r.fft_schedule()
@@ -214,7 +258,7 @@ def run_path(micro, hist, precision, use_graph, steps, warmup, stream,
     r.close()
     return dict(elapsed=elapsed, infos=timed, live=live_t, rm_counts=counts,
                 sigma11=sig, schedule=sched, start=start, nonlocal_=nonlocal_,
-                passes=passes)
+                passes=passes, check=chk, sample=sample)
 
 
 def cg_pass_report(kern, N):
@@ -278,16 +322,27 @@ def batch_run(steps, stream):
                  use_graph=True, stream=stream, cg_forcing=FORCING)
     for j, m in enumerate(micros):
         b.set_microstructure(j, m.phase, m.quat, m.law, material_params())
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
     newton = []
-    for inc in hist:
-        infos = b.increment(inc["F_bar"], inc["dt"])
-        if any(i["status"] != 0 for i in infos):
-            raise RuntimeError("batched increment failed")
-        newton.append(max(i["newton_iters"] for i in infos))
-    torch.cuda.synchronize()
-    t_batch = time.perf_counter() - t0
+    t_batch = 0.0
+    # timed as two bracketed intervals (increments 1..K-1 and K) so that
+    # RVE 0's committed state before the last one can be copied out for
+    # the oracle's error checks
+    for pi, part in enumerate((hist[:-1], hist[-1:])):
+        if pi == 1:
+            before = {f: b.field(0, f) for f in ("Fpinv", "chi")}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for inc in part:
+            infos = b.increment(inc["F_bar"], inc["dt"])
+            if any(i["status"] != 0 for i in infos):
+                raise RuntimeError("batched increment failed")
+            newton.append(max(i["newton_iters"] for i in infos))
+        torch.cuda.synchronize()
+        t_batch += time.perf_counter() - t0
+    chk = dict(k=int(hist[-1]["k"]), F_bar=np.asarray(hist[-1]["F_bar"]),
+               dt=hist[-1]["dt"], Fpi0=before["Fpinv"], chi0=before["chi"],
+               F=b.field(0, "F"), P=b.field(0, "P"), dg=b.field(0, "dgamma"),
+               residual_rel=infos[0]["residual_rel"])
     sig_b = [b.macro(j)["sigma_bar"][0, 0] for j in range(len(micros))]
     # statistical volume element: Eqs. 25-26 per RVE, mean and standard
     # deviation over the RVEs (bands two voxel edges wide)
@@ -326,7 +381,8 @@ def batch_run(steps, stream):
             "batched_over_one_by_one": round(t_single / t_batch, 3),
             "sigma11_max_rel_diff_vs_one_by_one": float(
                 np.max(np.abs(sig_b - sig_s)) / np.max(np.abs(sig_s))),
-            "sve_nonlocal_fips": sve}
+            "sve_nonlocal_fips": sve,
+            "_check": chk, "_micro0": micros[0]}
 
 
 def large_run(steps, stream):
@@ -347,7 +403,10 @@ def large_run(steps, stream):
     for mode in ("learned", "homogeneous"):
         r = run_path(micro, hist, "mixed", False, steps - 1, 1, stream,
                      live=False, learned=(mode == "learned"), start=1,
-                     with_fips=(mode == "learned"), forcing=FORCING)
+                     with_fips=(mode == "learned"), forcing=FORCING,
+                     check=(mode == "learned"))
+        if r["check"] is not None:
+            out["_check"], out["_micro"] = r["check"], micro
         n3 = micro.n ** 3
         out[mode] = dict(value=round(n3 * (steps - 1) / r["elapsed"], 1),
                          ms_per_step=round(1e3 * r["elapsed"] / (steps - 1), 3),
@@ -512,6 +571,27 @@ def paper_workloads(stream):
     return out
 
 
+def paper_case(stream):
+    """The performance case of the paper (Sec. 5): three R = 0 cycles at
+    1 % (Eq. 28 as intended, 40 increments per cycle) on a 32^3 RVE of 235
+    grains, discrete operator, tol 1e-6; whole-history wall time of the
+    chosen path (mixed, learned start, forcing) and of plain FP64, and
+    their macroscopic loops against each other (Eq. 29)."""
+    from synthetic import config_by_name
+    cfg = config_by_name("P1_32")
+    micro, hist = cfg.microstructure(), cfg.history()
+    ch, s_ch = _run_history(micro, hist, "mixed", "discrete", stream,
+                            learned=True, forcing=FORCING)
+    fp, s_fp = _run_history(micro, hist, "fp64", "discrete", stream)
+    s_ch, s_fp = np.array(s_ch), np.array(s_fp)
+    return {"workload": (f"{cfg.n}^3 RVE, {cfg.grains} grains, 3 R = 0 cycles "
+                         f"at 1 %, 40 increments per cycle, tol 1e-6"),
+            "chosen": ch, "fp64": fp,
+            "chosen_over_fp64": round(fp["seconds"] / ch["seconds"], 3),
+            "eq29_chosen_vs_fp64": float(np.max(np.abs(s_ch - s_fp))
+                                         / np.max(np.abs(s_fp)))}
+
+
 def predictor_stats(infos):
     return dict(
         newton_per_increment=float(np.mean([i["newton_iters"] for i in infos])),
@@ -578,6 +658,187 @@ def oracle_sample(micro, hist, gpu_infos, budget_s):
                 seconds_per_increment=sec_per_inc)
 
 
+# ----------------------------------------------------------------- oracle leg
+# Everything below up to PMC_SUMMARY calls the CPU oracle: the end-to-end
+# oracle timing of the 16^3 history and the error checks of the GPU results
+# against the oracle.  It runs only in the cpu_baseline leg (not with
+# --no-cpu), after the timed GPU legs or in a separate process on its own
+# cores while they run.
+
+def _oracle_point_law_chunk(args):
+    """The oracle's point law at given F from a committed state (crystal
+    grains and SVK particles): returns (P, slips, ok)."""
+    from oracle import crystal, material
+    from synthetic import material_params
+    F, Fpi0, chi0, label, quat, law, dt = args
+    p = material_params()
+    S0g, Cg = crystal.grain_tables(quat, p)
+    lam, mu = crystal.lame_from_young(p[8], p[9])
+    n = F.shape[0]
+    P = np.zeros((n, 3, 3))
+    dg = np.zeros((n, 12))
+    ok = np.ones(n, dtype=bool)
+    cp = np.nonzero(law[label] == 0)[0]
+    el = np.nonzero(law[label] == 1)[0]
+    if cp.size:
+        g = label[cp]
+        out = material.cp_update(F[cp], Fpi0[cp], chi0[cp],
+                                 np.zeros((cp.size, 12)), S0g[g], Cg[g], p,
+                                 dt, tangent=False)
+        P[cp], dg[cp], ok[cp] = out["P"], out["dg"], out["ok"]
+    if el.size:
+        P[el] = material.svk_update(F[el], lam, mu, False)["P"]
+    return P, dg, ok
+
+
+def oracle_errors(chk, micro, operator, pool, max_voxels=None, residual=True):
+    """Errors of a GPU-solved increment against the oracle: the equilibrium
+    residual ||G(P)|| / ||P|| with the oracle's G (Eq. 11), the point law
+    re-integrated by the oracle from the committed state at the GPU's F
+    (every voxel, or a seeded sample of max_voxels), and <F> - F_bar."""
+    from oracle.solver import OracleRVE
+    from synthetic import material_params
+    N = micro.n ** 3
+    F = chk["F"].T.reshape(N, 3, 3)
+    P = chk["P"].T.reshape(N, 3, 3)
+    Fpi0 = chk["Fpi0"].T.reshape(N, 3, 3)
+    chi0 = chk["chi0"].T
+    dg = chk["dg"].T
+    out = {"increment": chk["k"], "gpu_residual_rel": chk["residual_rel"]}
+    if residual:
+        o = OracleRVE((micro.n,) * 3, micro.phase, micro.quat, micro.law,
+                      material_params(), operator)
+        out["residual_rel_oracle_G"] = float(np.linalg.norm(o.G(P))
+                                             / np.linalg.norm(P))
+        fl = F - chk["F_bar"].reshape(1, 3, 3)
+        out["incompatibility_rel_oracle_G"] = float(
+            np.linalg.norm(o.G(fl) - fl) / np.linalg.norm(fl))
+    idx = np.arange(N)
+    if max_voxels is not None and max_voxels < N:
+        idx = np.sort(np.random.default_rng(11).choice(N, max_voxels,
+                                                       replace=False))
+    chunks = np.array_split(idx, max(1, min(len(idx) // 8192, 64)))
+    res = list(pool.map(_oracle_point_law_chunk, [
+        (F[c], Fpi0[c], chi0[c], micro.phase[c], micro.quat, micro.law,
+         chk["dt"]) for c in chunks]))
+    Pref = np.concatenate([x[0] for x in res])
+    dgref = np.concatenate([x[1] for x in res])
+    out["point_law_voxels"] = int(len(idx))
+    out["point_law_local_failures"] = int(sum((~x[2]).sum() for x in res))
+    out["point_law_P_max_rel"] = float(np.max(np.abs(P[idx] - Pref))
+                                       / np.max(np.abs(Pref)))
+    out["point_law_slip_max_rel"] = float(np.max(np.abs(dg[idx] - dgref))
+                                          / max(np.max(np.abs(dgref)), 1e-300))
+    out["mean_F_minus_F_bar_max"] = float(np.max(np.abs(
+        F.mean(axis=0) - chk["F_bar"].reshape(3, 3))))
+    return out
+
+
+def _c1_oracle_history(q, cores):
+    """Child process: the oracle solves the 16^3 history end to end (20
+    increments, tol 1e-6, CG 1e-4, the tolerances of the GPU paths)."""
+    try:
+        os.sched_setaffinity(0, cores)
+    except (AttributeError, OSError):
+        pass
+    from oracle.solver import OracleRVE
+    from synthetic import config_by_name, material_params
+    cfg = config_by_name("C1")
+    micro = cfg.microstructure()
+    hist = cfg.history()
+    o = OracleRVE((micro.n,) * 3, micro.phase, micro.quat, micro.law,
+                  material_params(), cfg.operator)
+    sig, newton, cg = [], 0, 0
+    t0 = time.perf_counter()
+    for inc in hist:
+        if inc["cycle_start"]:
+            o.reset_fips()
+        info = o.increment(inc["F_bar"], inc["dt"], tol=1e-6, eta=1e-4)
+        if info.status != 0:
+            q.put(dict(error=f"oracle increment {inc['k']}: {info.status}"))
+            return
+        sig.append(float(info.sigma_bar[0, 0]))
+        newton += info.newton_iters
+        cg += info.cg_iters_total
+    sec = time.perf_counter() - t0
+    q.put(dict(seconds=sec, increments=len(hist), voxels=micro.n ** 3,
+               newton=newton, cg=cg, sigma11=sig, cores=len(cores)))
+
+
+class OracleLeg:
+    """The CPU oracle beside the GPU run: the 16^3 history timed end to end
+    in a child process pinned to half of this process's cores (started
+    before the GPU legs, which keep the other half), then error checks of
+    the GPU results after the timed legs."""
+
+    def __init__(self):
+        import multiprocessing as mp
+        cores = sorted(os.sched_getaffinity(0))
+        half = max(1, len(cores) // 2)
+        self.gpu_cores = set(cores[:half]) if len(cores) > 1 else set(cores)
+        self.cpu_cores = set(cores[half:]) if len(cores) > 1 else set(cores)
+        self.all_cores = set(cores)
+        ctx = mp.get_context("spawn")
+        self.q = ctx.Queue()
+        saved = {k: os.environ.get(k) for k in THREAD_VARS}
+        for k in THREAD_VARS:
+            os.environ[k] = str(len(self.cpu_cores))
+        self.proc = ctx.Process(target=_c1_oracle_history,
+                                args=(self.q, self.cpu_cores), daemon=True)
+        self.proc.start()
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+        try:
+            os.sched_setaffinity(0, self.gpu_cores)
+        except OSError:
+            pass
+
+    def c1_result(self, timeout=900):
+        import queue
+        t0 = time.perf_counter()
+        while True:
+            try:
+                res = self.q.get(timeout=30)
+                break
+            except queue.Empty:
+                waited = time.perf_counter() - t0
+                if waited > timeout or not self.proc.is_alive():
+                    res = dict(error="the oracle's 16^3 history did not finish")
+                    break
+                print(f"bench: oracle 16^3 history still running "
+                      f"({waited:.0f} s waited)", file=sys.stderr, flush=True)
+        self.proc.join(timeout=30)
+        try:
+            os.sched_setaffinity(0, self.all_cores)
+        except OSError:
+            pass
+        return res
+
+    def pool(self):
+        import concurrent.futures as cf
+        import multiprocessing as mp
+        return cf.ProcessPoolExecutor(
+            max_workers=max(1, min(16, len(self.all_cores))),
+            mp_context=mp.get_context("spawn"))
+
+
+THREAD_VARS = ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")
+
+
+def gpu_c1_history(stream):
+    """The 16^3 history on the GPU in FP64 with the homogeneous predictor
+    (the oracle's method), same tolerances: seconds and sigma_11."""
+    import torch
+    from synthetic import config_by_name
+    cfg = config_by_name("C1")
+    micro = cfg.microstructure()
+    out, sig = _run_history(micro, cfg.history(), "fp64", cfg.operator, stream)
+    return out, sig, micro.n ** 3
+
+
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_traffic_c3_64cubed.json")
 
 
@@ -599,9 +860,15 @@ def pmc_traffic(kernel):
         return None
 
 
-def live_report(live, rmc, N, cg_total):
+def live_report(live, rmc, N, cg_total, sample=None):
     """Per-kernel live durations, FFT bandwidth and the dominant kernel's
-    roofline from the event timings of the timed region."""
+    roofline from the event timings of the timed region.  The dominant
+    kernel is the one with the largest total time per increment over the
+    sample increments in which every hot-path kernel was timed (the CG
+    kernels are not timed in the timed region: one event pair per launch
+    would cost several per cent of the throughput); its roofline uses the
+    timed region's live durations when it is timed there, else the
+    sample's."""
     avg_ms = {k: (ms / n if n else None) for k, (ms, n) in live.items()}
     total_ms = {k: ms for k, (ms, n) in live.items()}
     launches = {k: n for k, (ms, n) in live.items()}
@@ -638,7 +905,30 @@ def live_report(live, rmc, N, cg_total):
 
     timed = {k: v for k, v in total_ms.items() if launches[k]}
     dom = max(timed, key=lambda k: timed[k])
-    roof = hbm(dom) if dom in PASS_BYTES_F32 else (alu() if dom == "return_map" else None)
+    share = None
+    if sample is not None:
+        st = {k: ms for k, (ms, n) in sample["timing"].items() if n}
+        tot = sum(st.values())
+        share = {k: round(v / tot, 4) for k, v in
+                 sorted(st.items(), key=lambda kv: -kv[1])}
+        dom = max(st, key=lambda k: st[k])
+    if dom in LIVE_CLASSES or sample is None:
+        roof = (hbm(dom) if dom in PASS_BYTES_F32 else
+                (alu() if dom == "return_map" else None))
+        if roof is not None:
+            roof["timed_over"] = "timed region (HIP events per launch)"
+    else:
+        ms, n = sample["timing"][dom]
+        per_launch = N * PASS_BYTES_F32[dom] * sample["cg_total"] / n
+        ach = per_launch / (ms / n * 1e-3) / 1e9
+        roof = dict(kernel=dom, bound="hbm", achieved=round(ach, 1),
+                    peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(ach / HBM_PEAK_GBS, 4), traffic=pmc_traffic(dom),
+                    bytes_per_launch=round(per_launch),
+                    avg_ms=round(ms / n, 5), launches=n,
+                    timed_over=("increments %d-%d before the timed region, "
+                                "every kernel timed (HIP events per launch)"
+                                % tuple(sample["increments"])))
     rep = {
         "fft_gbps": round(fft_gbs, 1) if fft_gbs else None,
         "kernel_avg_ms_live": {k: (round(v, 5) if v else v)
@@ -648,12 +938,19 @@ def live_report(live, rmc, N, cg_total):
         "return_map_work": dict(rmc, flops=rm_flops),
         "roofline": roof,
     }
+    if share is not None:
+        rep["kernel_time_share_sample"] = dict(
+            increments=sample["increments"], share=share)
     for k in PASS_BYTES_F32:
         if launches[k] and k != dom:
             rep[k + "_roofline"] = hbm(k)
     if launches["return_map"] and dom != "return_map":
         rep["return_map_roofline"] = alu()
     return rep
+
+
+def progress(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
 def main():
@@ -674,6 +971,9 @@ def main():
     if max(args.warmup, args.start or 0) + args.steps > len(hist):
         raise SystemExit(f"the {cfg.name} history has {len(hist)} increments; "
                          f"warmup + steps must not exceed it")
+    # the oracle's end-to-end run of the 16^3 history starts first, in a
+    # child process on half of the cores (the GPU legs keep the other half)
+    oleg = None if args.no_cpu else OracleLeg()
     stream = torch.cuda.Stream()
     calib = copy_calibration(stream) if args.copy_calibration else None
     with torch.cuda.stream(stream):
@@ -684,12 +984,30 @@ def main():
                           forcing=0 if args.no_forcing else FORCING,
                           schedule=(tuple(int(x) for x in
                                           args.fft_schedule.split(","))
-                                    if args.fft_schedule else None))
+                                    if args.fft_schedule else None),
+                          check=oleg is not None,
+                          sample_all=not args.no_live)
+        progress("chosen path done")
         plain = None
         if not args.no_plain:
             plain = run_path(micro, hist, "fp64", False, args.steps,
                              args.warmup, stream, live=False, start=args.start,
                              cg_chunk=args.cg_chunk)
+            progress("plain path done")
+        ablations = None
+        if not args.no_ablations:
+            # what each addition of the chosen path contributes: the same
+            # window solved with one more addition at a time
+            ablations = {}
+            for label, prec, ws, frc in (
+                    ("fp64_forcing", "fp64", 0, FORCING),
+                    ("mixed_forcing", "mixed", 0, FORCING),
+                    ("mixed_forcing_extrapolated_start", "mixed", 3, FORCING)):
+                ablations[label] = run_path(
+                    micro, hist, prec, False, args.steps, args.warmup, stream,
+                    live=False, start=args.start, cg_chunk=args.cg_chunk,
+                    forcing=frc, warm_start=ws)
+                progress(f"ablation {label} done")
     N = micro.n ** 3
     value = N * args.steps / chosen["elapsed"]
     infos = chosen["infos"]
@@ -739,7 +1057,8 @@ def main():
     }
     live = chosen["live"]
     if live is not None:
-        out.update(live_report(live, chosen["rm_counts"], N, cg_total))
+        out.update(live_report(live, chosen["rm_counts"], N, cg_total,
+                               chosen["sample"]))
     if out.get("fft_gbps") is None and chosen["passes"]:
         out["fft_gbps"] = chosen["passes"]["fft_projection_passes"]["gbps"]
     if plain is not None:
@@ -757,17 +1076,50 @@ def main():
         s_p = np.array(plain["sigma11"])
         out["sigma11_max_rel_diff_vs_plain"] = float(
             np.max(np.abs(s_c - s_p)) / np.max(np.abs(s_p)))
+        if ablations is not None:
+            rows = {"fp64 (plain)": out["plain"]}
+            for label, res in ablations.items():
+                v = N * args.steps / res["elapsed"]
+                rows[label] = dict(
+                    value=round(v, 1),
+                    ms_per_step=round(1e3 * res["elapsed"] / args.steps, 3),
+                    over_plain=round(v / pv, 3),
+                    sigma11_max_rel_diff_vs_plain=float(
+                        np.max(np.abs(np.array(res["sigma11"]) - s_p))
+                        / np.max(np.abs(s_p))),
+                    **predictor_stats(res["infos"]))
+            rows["mixed_forcing_learned_start (chosen)"] = dict(
+                value=out["value"], ms_per_step=out["ms_per_step"],
+                over_plain=out["chosen_over_plain"], **out["predictor"])
+            out["ablations"] = {
+                "window": out["config"]["timed_increments"],
+                "note": ("each row adds one thing to the one before: "
+                         "inexact-Newton forcing (mode %d), FP32 FFT/CG, the "
+                         "extrapolated start (last fluctuation increment x "
+                         "load ratio, kept by the rule of the learned "
+                         "start), the learned start" % FORCING),
+                "rows": rows}
     if not args.no_batch:
         with torch.cuda.stream(stream):
             out["batch"] = batch_run(args.batch_steps, stream)
+        progress("batch done")
     if args.large_steps > 1:
         with torch.cuda.stream(stream):
             out["large_rve"] = large_run(args.large_steps, stream)
+        progress("128^3 done")
     if not args.no_umat:
         out["umat_bridge"] = umat_run(stream)
+    if not args.no_paper_case:
+        with torch.cuda.stream(stream):
+            out["paper_case_32"] = paper_case(stream)
+        progress("paper case done")
     if args.paper_workloads:
         with torch.cuda.stream(stream):
             out["paper_workloads"] = paper_workloads(stream)
+    c1_gpu = None
+    if oleg is not None:
+        with torch.cuda.stream(stream):
+            c1_gpu = gpu_c1_history(stream)
     if calib:
         out["copy_calibration"] = calib
     cbw = copy_bandwidth(stream)
@@ -778,11 +1130,57 @@ def main():
     if out.get("cg_passes"):
         out["cg_passes"]["fft_projection_passes"]["frac_of_measured_copy"] = \
             round(out["cg_passes"]["fft_projection_passes"]["gbps"] / cbw, 3)
-    if not args.no_cpu:
+    batch_chk = out.get("batch", {}).pop("_check", None)
+    batch_micro = out.get("batch", {}).pop("_micro0", None)
+    large_chk = out.get("large_rve", {}).pop("_check", None)
+    large_micro = out.get("large_rve", {}).pop("_micro", None)
+    if oleg is not None:
+        # the oracle leg: its end-to-end run of the 16^3 history (done in
+        # the child meanwhile), error checks of the GPU results, and the
+        # bounded sample of the 64^3 workload itself
+        progress("waiting for the oracle's 16^3 history")
+        c1 = oleg.c1_result()
+        progress("oracle 16^3 history done; error checks")
+        errs = {}
+        with oleg.pool() as pool:
+            errs["chosen_64"] = oracle_errors(chosen["check"], micro,
+                                              cfg.operator, pool)
+            if batch_chk is not None:
+                errs["batch_rve0"] = oracle_errors(batch_chk, batch_micro,
+                                                   "discrete", pool)
+                errs["batch_rve0"]["edge"] = batch_micro.n
+            if large_chk is not None:
+                errs["large_128"] = oracle_errors(
+                    large_chk, large_micro, "discrete", pool,
+                    max_voxels=131072, residual=False)
+                errs["large_128"]["note"] = (
+                    "point law on a seeded sample of voxels; the dense-DFT "
+                    "oracle G at 128^3 takes minutes and is compared "
+                    "element-wise in the tests instead")
+        out["error_vs_oracle"] = errs
+        progress("error checks done; oracle sample of the 64^3 workload")
         # the oracle implements the homogeneous-predictor method: scale its
         # sample by the plain path's counts when they are there
         ref = plain["infos"] if plain is not None else infos
-        out["cpu_baseline"] = oracle_sample(micro, hist, ref, args.cpu_seconds)
+        cb = oracle_sample(micro, hist, ref, args.cpu_seconds)
+        if "error" not in c1 and c1_gpu is not None:
+            g_out, g_sig, n1 = c1_gpu
+            vo = n1 * c1["increments"] / c1["seconds"]
+            vg = n1 * g_out["increments"] / g_out["seconds"]
+            sg, so = np.array(g_sig), np.array(c1["sigma11"])
+            cb["end_to_end_16"] = dict(
+                workload=("16^3 RVE, 8 grains, continuous operator, 20 "
+                          "increments of a +-1 % cycle, tol 1e-6, homogeneous "
+                          "predictor, FP64, solved end to end"),
+                oracle_seconds=round(c1["seconds"], 2),
+                oracle_value=round(vo, 1), oracle_cores=c1["cores"],
+                gpu_fp64_seconds=g_out["seconds"], gpu_fp64_value=round(vg, 1),
+                gpu_over_oracle=round(vg / vo, 1),
+                eq29_gpu_vs_oracle=float(np.max(np.abs(sg - so))
+                                         / np.max(np.abs(so))))
+        elif "error" in c1:
+            cb["end_to_end_16"] = c1
+        out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 
 

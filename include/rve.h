@@ -78,7 +78,13 @@ typedef struct {
                             is below half of the homogeneous predictor's
                             last evaluated one is kept without evaluating
                             the homogeneous predictor (needs a network
-                            attached with rve_attach_warm_start)            */
+                            attached with rve_attach_warm_start);
+                            3 = as 2 with the extrapolation F_prev + dF_bar
+                            + c G(dFt_prev) in place of the network: the
+                            last fluctuation increment scaled by the load
+                            ratio c = dF_bar : dF_bar_prev / |dF_bar_prev|^2
+                            (the baseline the learned start is measured
+                            against; no network needed)                      */
   int32_t use_graph;     /* 1 = replay CG chunks from a captured hipGraph    */
   double newton_tol;     /* equilibrium: ||G(P)||_2 <= tol ||P||_2 (FP64)     */
   int32_t newton_max_iter;
@@ -433,7 +439,10 @@ rve_status rve_get_fft_schedule(rve_t h, int32_t out[2], double* ms);
 /* ---- learned warm start -------------------------------------------------
    A small network predicts the fluctuation increment of the next load
    increment from the committed state, so that the Newton iteration of
-   Sec. 2.1 (Eqs. 12-16) starts nearer to equilibrium.  Its prediction is
+   Sec. 2.1 (Eqs. 12-16) starts nearer to equilibrium.  It predicts, per
+   |dF_bar|, the correction to the extrapolation c dFt_prev (the last
+   converged fluctuation increment scaled by the load ratio c = dF_bar :
+   dF_bar_prev / |dF_bar_prev|^2, warm_start = 3 on its own); the sum is
    projected by G (Sec. 2.1, Eq. 11) and kept only when its FP64
    equilibrium residual is smaller than the homogeneous predictor's; Newton
    then runs to the same tolerance either way.
@@ -444,7 +453,10 @@ rve_status rve_get_fft_schedule(rve_t h, int32_t out[2], double* ms);
    t = (dx+1)*9 + (dy+1)*3 + (dz+1)) followed by b[cout].
    Device buffers (caller-owned, dst/src on the device):
      features  uint16 bf16 [N][48]  (channel list in the design notes)
-     targets   float [N][16] (first 9: fluctuation increment / |dFbar|)
+     targets   float [N][16] (first 9: the committed increment's fluctuation
+               increment / |dFbar| less cos times the one before it / its
+               |dFbar|, cos the cosine between the two dFbar: the part the
+               extrapolation misses)
      outputs   float [N][16]
    rve_ws_train_step: one Adam step (lr, betas 0.9/0.999, eps 1e-8) on the
    mean squared error over the 9 real output channels of one sample; *loss

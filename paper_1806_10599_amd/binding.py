@@ -312,8 +312,9 @@ def _make_config(L, projection, precision, newton_tol, newton_max_iter, cg_tol,
     cfg.cg_max_iter = cg_max_iter
     cfg.cg_chunk = cg_chunk
     cfg.use_graph = 1 if use_graph else 0
-    if warm_start not in (0, 1, 2):
-        raise ValueError("warm_start must be False/0, True/1 or 2")
+    if warm_start not in (0, 1, 2, 3):
+        raise ValueError("warm_start must be False/0, True/1, 2 or 3 "
+                         "(extrapolation)")
     cfg.warm_start = int(warm_start)
     if cg_forcing not in (0, 1, 2):
         raise ValueError("cg_forcing must be False/0, True/1 or 2")

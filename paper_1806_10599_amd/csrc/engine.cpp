@@ -47,8 +47,8 @@ Engine::Engine(const rve_config& cfg) : cfg_(cfg) {
     throw Error(RVE_EINVAL, "unknown projection operator");
   if (cfg.precision != RVE_PREC_FP64 && cfg.precision != RVE_PREC_MIXED)
     throw Error(RVE_EINVAL, "unknown precision mode");
-  if (cfg.warm_start < 0 || cfg.warm_start > 2)
-    throw Error(RVE_EINVAL, "warm_start must be 0, 1 or 2");
+  if (cfg.warm_start < 0 || cfg.warm_start > 3)
+    throw Error(RVE_EINVAL, "warm_start must be 0, 1, 2 or 3");
   if (cfg.cg_forcing < 0 || cfg.cg_forcing > 2)
     throw Error(RVE_EINVAL, "cg_forcing must be 0, 1 or 2");
   for (int d = 0; d < 3; ++d)
@@ -89,6 +89,7 @@ Engine::Engine(const rve_config& cfg) : cfg_(cfg) {
   dg_t_ = (double*)alloc(f12);
   r64_ = (double*)alloc(f9);
   dFt_prev_ = (double*)alloc(f9);
+  dFt_pp_ = (double*)alloc(f9);
   K_ = alloc(81 * N_ * tsz);
   x_ = alloc(9 * N_ * tsz);
   r_ = alloc(9 * N_ * tsz);
@@ -239,6 +240,7 @@ void Engine::set_microstructure(const int32_t* phase, int32_t G,
   launch_fill_f64(pcyc_lit_, 0.0, N_, st_);
   launch_fill_f64(wcyc_, 0.0, 12 * N_, st_);
   launch_fill_f64(dFt_prev_, 0.0, 9 * N_, st_);
+  launch_fill_f64(dFt_pp_, 0.0, 9 * N_, st_);
   RVE_HIP(hipGetLastError());
   RVE_HIP(hipStreamSynchronize(st_));
   reset_macro_state();
@@ -254,8 +256,10 @@ void Engine::reset_macro_state() {
     Pbar_[i] = 0.0;
     dFlast_[i] = 0.0;
     dFbar_prev_[i] = 0.0;
+    dFbar_pp_[i] = 0.0;
   }
   s_prev_ = 0.0;
+  s_pp_ = 0.0;
   t_ = 0.0;
   increments_ = 0;
   last_plain_rel_ = 0.0;
@@ -293,6 +297,7 @@ void Engine::set_user_material(rve_umat_fn fn, void* user, int32_t nstatev,
   launch_fill_f64(pcyc_lit_, 0.0, N_, st_);
   launch_fill_f64(wcyc_, 0.0, 12 * N_, st_);
   launch_fill_f64(dFt_prev_, 0.0, 9 * N_, st_);
+  launch_fill_f64(dFt_pp_, 0.0, 9 * N_, st_);
   RVE_HIP(hipGetLastError());
   RVE_HIP(hipStreamSynchronize(st_));
   reset_macro_state();
@@ -677,6 +682,8 @@ void Engine::cg_solve(int& iters, bool& breakdown, double eta) {
 }
 
 void Engine::commit(double dt) {
+  // fluctuation increments of this increment and of the one before it
+  std::swap(dFt_prev_, dFt_pp_);
   nn_fluct_increment(F_, Fprev_, dFlast_, dFt_prev_, N_, st_);
   CommitArgs c{};
   c.F = F_;
@@ -720,15 +727,20 @@ int Engine::increment(const double Fbar_new[9], double dt,
   double rel = 0, res = 0, pn = 0;
   int status = RVE_ENOTCONV;
   int pre_fails = -1;
-  if (net_ && cfg_.warm_start && !umat_fn_ && learned_candidate(Fbar_new)) {
-    // learned candidate in F2_: evaluate it; with warm_start = 2 keep it at
-    // once when its FP64 residual is well below what the plain predictor
-    // reached when last evaluated, otherwise stash it, evaluate the plain
-    // predictor and keep the one with the smaller FP64 residual
+  const bool candidate =
+      cfg_.warm_start && !umat_fn_ &&
+      (cfg_.warm_start == 3 ? extrapolated_candidate(Fbar_new)
+                            : (net_ && learned_candidate(Fbar_new)));
+  if (candidate) {
+    // learned (or extrapolated) candidate in F2_: evaluate it; with
+    // warm_start = 2 or 3 keep it at once when its FP64 residual is well
+    // below what the plain predictor reached when last evaluated, otherwise
+    // stash it, evaluate the plain predictor and keep the one with the
+    // smaller FP64 residual
     std::swap(F_, F2_);
     double relL, resL, pnL;
     const int failsL = evaluate(dg_start, dt, relL, resL, pnL);
-    if (cfg_.warm_start == 2 && failsL == 0 && last_plain_rel_ > 0.0 &&
+    if (cfg_.warm_start >= 2 && failsL == 0 && last_plain_rel_ > 0.0 &&
         relL < kLearnedDirect * last_plain_rel_) {
       rel = relL;
       res = resL;
@@ -781,9 +793,11 @@ int Engine::increment(const double Fbar_new[9], double dt,
       for (int i = 0; i < 9; ++i) s2 += dF[i] * dF[i];
       for (int i = 0; i < 9; ++i) {
         Fbar_[i] = Fbar_new[i];
+        dFbar_pp_[i] = dFbar_prev_[i];
         dFbar_prev_[i] = dF[i];
         (void)dot;
       }
+      s_pp_ = s_prev_;
       s_prev_ = std::sqrt(s2);
       t_ += dt;
       ++increments_;
@@ -835,14 +849,14 @@ int Engine::increment(const double Fbar_new[9], double dt,
 // committed device arrays and their component counts (user-material state
 // variables last)
 #define RVE_SNAP_ARRAYS                                                   \
-  double* arrs[11] = {Fprev_, Pc_, Fpi_c_, chi_c_, dg_c_, pcyc_, pcyc_lit_, \
-                      wcyc_, dFt_prev_, sv_c_, nullptr};                  \
-  const int comps[11] = {9, 9, 9, 12, 12, 1, 1, 12, 9, nsv_, 0};
+  double* arrs[12] = {Fprev_, Pc_, Fpi_c_, chi_c_, dg_c_, pcyc_, pcyc_lit_, \
+                      wcyc_, dFt_prev_, dFt_pp_, sv_c_, nullptr};         \
+  const int comps[12] = {9, 9, 9, 12, 12, 1, 1, 12, 9, 9, nsv_, 0};
 
 void Engine::take_snapshot() {
   RVE_SNAP_ARRAYS
   size_t total = 0;
-  for (int k = 0; k < 10; ++k) total += (size_t)comps[k];
+  for (int k = 0; k < 11; ++k) total += (size_t)comps[k];
   const size_t bytes = total * N_ * sizeof(double);
   if (bytes > snap_cap_) {
     if (snap_) release(snap_);
@@ -852,7 +866,7 @@ void Engine::take_snapshot() {
     snap_cap_ = bytes;
   }
   double* p = snap_;
-  for (int k = 0; k < 10; ++k) {
+  for (int k = 0; k < 11; ++k) {
     if (!comps[k]) continue;
     const size_t b = (size_t)comps[k] * N_ * sizeof(double);
     RVE_HIP(hipMemcpyAsync(p, arrs[k], b, hipMemcpyDeviceToDevice, st_));
@@ -863,8 +877,10 @@ void Engine::take_snapshot() {
     snap_host_.Pbar[i] = Pbar_[i];
     snap_host_.dFlast[i] = dFlast_[i];
     snap_host_.dFbar_prev[i] = dFbar_prev_[i];
+    snap_host_.dFbar_pp[i] = dFbar_pp_[i];
   }
   snap_host_.s_prev = s_prev_;
+  snap_host_.s_pp = s_pp_;
   snap_host_.t = t_;
   snap_host_.increments = increments_;
 }
@@ -872,7 +888,7 @@ void Engine::take_snapshot() {
 void Engine::restore_snapshot() {
   RVE_SNAP_ARRAYS
   const double* p = snap_;
-  for (int k = 0; k < 10; ++k) {
+  for (int k = 0; k < 11; ++k) {
     if (!comps[k]) continue;
     const size_t b = (size_t)comps[k] * N_ * sizeof(double);
     RVE_HIP(hipMemcpyAsync(arrs[k], p, b, hipMemcpyDeviceToDevice, st_));
@@ -884,8 +900,10 @@ void Engine::restore_snapshot() {
     Pbar_[i] = snap_host_.Pbar[i];
     dFlast_[i] = snap_host_.dFlast[i];
     dFbar_prev_[i] = snap_host_.dFbar_prev[i];
+    dFbar_pp_[i] = snap_host_.dFbar_pp[i];
   }
   s_prev_ = snap_host_.s_prev;
+  s_pp_ = snap_host_.s_pp;
   t_ = snap_host_.t;
   increments_ = snap_host_.increments;
 }
@@ -1369,17 +1387,23 @@ void Engine::swap_trial_sets() {
 void Engine::attach_net(Net* net) {
   if (net && n_ % 16) throw Error(RVE_EINVAL, "the network needs n divisible by 16");
   if (net && !X0_) {
-    const size_t f9 = 9 * N_ * sizeof(double), f12 = 12 * N_ * sizeof(double);
     X0_ = (uint16_t*)alloc(N_ * kFeat * sizeof(uint16_t));
     Ynet_ = (float*)alloc(N_ * kOut * sizeof(float));
-    F2_ = (double*)alloc(f9);
-    P2_ = (double*)alloc(f9);
-    Fpi_t2_ = (double*)alloc(f9);
-    chi_t2_ = (double*)alloc(f12);
-    dg_t2_ = (double*)alloc(f12);
-    r64b_ = (double*)alloc(f9);
   }
+  if (net) second_trial_set();
   net_ = net;
+}
+
+// buffers of a candidate predictor evaluated beside the homogeneous one
+void Engine::second_trial_set() {
+  if (F2_) return;
+  const size_t f9 = 9 * N_ * sizeof(double), f12 = 12 * N_ * sizeof(double);
+  F2_ = (double*)alloc(f9);
+  P2_ = (double*)alloc(f9);
+  Fpi_t2_ = (double*)alloc(f9);
+  chi_t2_ = (double*)alloc(f12);
+  dg_t2_ = (double*)alloc(f12);
+  r64b_ = (double*)alloc(f9);
 }
 
 void Engine::feature_args(const double Fbar_new[9], FeatArgs& a, double& s_k) {
@@ -1420,12 +1444,18 @@ void Engine::features(const double Fbar_new[9], uint16_t* dst) {
 void Engine::target(float* dst) {
   if (increments_ < 1) throw Error(RVE_ESTATE, "no committed increment yet");
   if (!dst) throw Error(RVE_EINVAL, "null destination");
-  nn_target(dFt_prev_, s_prev_ > 0 ? 1.0 / s_prev_ : 0.0, dst, N_, st_);
+  // the part of the last fluctuation increment that the extrapolation of
+  // the one before it (scaled by the load ratio) misses, per |dF_bar|
+  double dot = 0.0;
+  for (int i = 0; i < 9; ++i) dot += dFbar_prev_[i] * dFbar_pp_[i];
+  const double coef = (s_prev_ > 0 && s_pp_ > 0) ? dot / (s_prev_ * s_pp_ * s_pp_) : 0.0;
+  nn_target(dFt_prev_, s_prev_ > 0 ? 1.0 / s_prev_ : 0.0, dFt_pp_, coef, dst,
+            N_, st_);
   RVE_HIP(hipGetLastError());
   RVE_HIP(hipStreamSynchronize(st_));
 }
 
-// F2_ = plain predictor + G(network prediction) (the prediction is projected
+// F2_ = plain predictor + G(extrapolation + network correction) (projected
 // so that it is compatible, periodic and of zero mean)
 bool Engine::learned_candidate(const double Fbar_new[9]) {
   if (increments_ < 1) return false;  // no history for the features yet
@@ -1436,11 +1466,36 @@ bool Engine::learned_candidate(const double Fbar_new[9]) {
   a.X = X0_;
   nn_features(a, st_);
   net_->forward(X0_, n_, Ynet_, st_);
+  // the network predicts the correction to the extrapolation c dFt_prev
+  // (c = dF_bar : dF_bar_prev / |dF_bar_prev|^2), per |dF_bar|
   nn_output_to_field(Ynet_, s_k, P2_, N_, st_);
+  if (s_prev_ > 0) {
+    double dot = 0.0;
+    for (int i = 0; i < 9; ++i) dot += (Fbar_new[i] - Fbar_[i]) * dFbar_prev_[i];
+    nn_axpy_field(P2_, dFt_prev_, dot / (s_prev_ * s_prev_), 9 * N_, st_);
+  }
   apply_G_fp64(P2_, r64b_);
   RVE_HIP(hipMemcpyAsync(F2_, F_, 9 * N_ * sizeof(double),
                          hipMemcpyDeviceToDevice, st_));
-  nn_axpy_field(F2_, r64b_, 9 * N_, st_);
+  nn_axpy_field(F2_, r64b_, 1.0, 9 * N_, st_);
+  RVE_HIP(hipGetLastError());
+  return true;
+}
+
+// F2_ = plain predictor + c G(dFt_prev): the last converged fluctuation
+// increment scaled by the load ratio c = (dF_bar : dF_bar_prev) /
+// |dF_bar_prev|^2 (the exact predictor of a linear material), the
+// zero-cost extrapolation the learned start is measured against
+bool Engine::extrapolated_candidate(const double Fbar_new[9]) {
+  if (increments_ < 1 || !(s_prev_ > 0)) return false;
+  double dot = 0.0;
+  for (int i = 0; i < 9; ++i) dot += (Fbar_new[i] - Fbar_[i]) * dFbar_prev_[i];
+  const double c = dot / (s_prev_ * s_prev_);
+  second_trial_set();
+  apply_G_fp64(dFt_prev_, r64b_);
+  RVE_HIP(hipMemcpyAsync(F2_, F_, 9 * N_ * sizeof(double),
+                         hipMemcpyDeviceToDevice, st_));
+  nn_axpy_field(F2_, r64b_, c, 9 * N_, st_);
   RVE_HIP(hipGetLastError());
   return true;
 }

@@ -98,6 +98,8 @@ class Engine {
   void tangent(double dt);
   void feature_args(const double Fbar_new[9], FeatArgs& a, double& s_k);
   bool learned_candidate(const double Fbar_new[9]);
+  bool extrapolated_candidate(const double Fbar_new[9]);
+  void second_trial_set();
   void swap_trial_sets();
   void reset_macro_state();
   // copy of the committed state (device arrays and host macro state) for
@@ -164,8 +166,11 @@ class Engine {
   unsigned long long* rm_stats_ = nullptr;
   Net* net_ = nullptr;
   double* dFt_prev_ = nullptr;        // fluctuation increment of the last increment
+  double* dFt_pp_ = nullptr;          // ... and of the increment before it
   double dFbar_prev_[9];
-  double s_prev_ = 0.0;
+  double dFbar_pp_[9];
+  double s_prev_ = 0.0;               // |dF_bar| of the last increment
+  double s_pp_ = 0.0;                 // ... and of the one before it
   // FP64 residual of the plain predictor when it was last evaluated, and
   // the fraction of it below which warm_start = 2 keeps a learned candidate
   // without evaluating the plain predictor
@@ -183,8 +188,8 @@ class Engine {
   double* snap_ = nullptr;
   size_t snap_cap_ = 0;
   struct HostSnap {
-    double Fbar[9], Pbar[9], dFlast[9], dFbar_prev[9];
-    double s_prev, t;
+    double Fbar[9], Pbar[9], dFlast[9], dFbar_prev[9], dFbar_pp[9];
+    double s_prev, s_pp, t;
     int64_t increments;
   } snap_host_{};
   // second trial set for the learned-vs-plain predictor comparison

@@ -465,18 +465,21 @@ void nn_features(const FeatArgs& a, hipStream_t s) {
 
 // T[v][c] = dFt[c][v] / s for c < 9, zero padding up to kOut
 __global__ void target_kernel(const double* __restrict__ dFt, double inv_s,
+                              const double* __restrict__ dFt2, double coef,
                               float* __restrict__ T, int64_t N) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= N) return;
 #pragma unroll
   for (int c = 0; c < kOut; ++c)
-    T[v * kOut + c] = (c < kOutReal) ? (float)(dFt[c * N + v] * inv_s) : 0.f;
+    T[v * kOut + c] = (c < kOutReal) ? (float)(dFt[c * N + v] * inv_s -
+                                               coef * dFt2[c * N + v])
+                                     : 0.f;
 }
 
-void nn_target(const double* dFt, double inv_s, float* T, int64_t N,
-               hipStream_t s) {
+void nn_target(const double* dFt, double inv_s, const double* dFt2,
+               double coef, float* T, int64_t N, hipStream_t s) {
   hipLaunchKernelGGL(target_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256),
-                     0, s, dFt, inv_s, T, N);
+                     0, s, dFt, inv_s, dFt2, coef, T, N);
 }
 
 // out[c][v] = scale * Y[v][c], c < 9
@@ -515,14 +518,15 @@ void nn_fluct_increment(const double* Fnew, const double* Fold,
 }
 
 __global__ void axpy_kernel(double* __restrict__ F, const double* __restrict__ d,
-                            int64_t n9) {
+                            double a, int64_t n9) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n9;
        i += (int64_t)gridDim.x * blockDim.x)
-    F[i] += d[i];
+    F[i] += a * d[i];
 }
 
-void nn_axpy_field(double* F, const double* d, int64_t n9, hipStream_t s) {
-  hipLaunchKernelGGL(axpy_kernel, dim3(2048), dim3(256), 0, s, F, d, n9);
+void nn_axpy_field(double* F, const double* d, double a, int64_t n9,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(axpy_kernel, dim3(2048), dim3(256), 0, s, F, d, a, n9);
 }
 
 }  // namespace rve

@@ -47,14 +47,17 @@ struct FeatArgs {
   int64_t N;
 };
 void nn_features(const FeatArgs& a, hipStream_t s);
-void nn_target(const double* dFt, double inv_s, float* T, int64_t N,
-               hipStream_t s);
+// T = dFt inv_s - coef dFt2 (first 9 channels; float [N][16])
+void nn_target(const double* dFt, double inv_s, const double* dFt2,
+               double coef, float* T, int64_t N, hipStream_t s);
 void nn_output_to_field(const float* Y, double scale, double* out, int64_t N,
                         hipStream_t s);
 void nn_fluct_increment(const double* Fnew, const double* Fold,
                         const double dFbar[9], double* out, int64_t N,
                         hipStream_t s);
-void nn_axpy_field(double* F, const double* d, int64_t n9, hipStream_t s);
+// F += a d
+void nn_axpy_field(double* F, const double* d, double a, int64_t n9,
+                   hipStream_t s);
 
 class Net {
  public:

@@ -300,3 +300,48 @@ def test_direct_acceptance_mode_keeps_clearly_better_candidates():
         a.close()
         b.close()
         net.close()
+
+
+def test_learned_correction_beats_the_extrapolated_start_on_held_out_cycle():
+    """The network predicts the correction to the extrapolated start (last
+    fluctuation increment x load ratio, warm_start = 3); on the held-out
+    fifth 64^3 cycle, in the benchmark's configuration (direct acceptance,
+    forcing mode 2), the corrected start needs fewer Newton corrections and
+    CG iterations than the extrapolation alone, at the same equilibrium."""
+    from gpu_util import make_rve
+    from paper_1806_10599_amd.warmstart import trained_params
+    c = config_by_name("C3")
+    micro = c.microstructure()
+    hist = c.history()
+    first = next(j for j, inc in enumerate(hist) if inc["cycle"] == c.cycles - 1)
+    net = _net(trained_params())
+    a = make_rve(micro, c.operator, "mixed", warm_start=3, cg_forcing=2)
+    b = make_rve(micro, c.operator, "mixed", warm_start=2, cg_forcing=2)
+    b.attach_warm_start(net)
+    try:
+        ra, rb = [], []
+        for j, inc in enumerate(hist):
+            if inc["cycle_start"]:
+                a.reset_fips()
+                b.reset_fips()
+            ia = a.increment(inc["F_bar"], inc["dt"])
+            ib = b.increment(inc["F_bar"], inc["dt"])
+            assert ia["status"] == 0 and ib["status"] == 0
+            if j >= first:
+                ra.append(ia)
+                rb.append(ib)
+        na = sum(i["newton_iters"] for i in ra)
+        nb = sum(i["newton_iters"] for i in rb)
+        ca = sum(i["cg_iters_total"] for i in ra)
+        cb = sum(i["cg_iters_total"] for i in rb)
+        print(f"held-out cycle: extrapolated Newton {na} CG {ca}, "
+              f"learned Newton {nb} CG {cb}")
+        assert nb <= na and cb < ca
+        for x, y in zip(ra, rb):
+            s_a, s_b = x["sigma_bar"][0, 0], y["sigma_bar"][0, 0]
+            assert abs(s_a - s_b) <= 1e-5 * abs(s_a) + 1e-3
+    finally:
+        b.attach_warm_start(None)
+        a.close()
+        b.close()
+        net.close()

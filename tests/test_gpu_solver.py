@@ -358,3 +358,40 @@ def test_cg_forcing_reaches_the_same_equilibrium_with_fewer_cg_iterations():
         for a, b in zip(runs[0], runs[mode]):
             sa, sb = a["sigma_bar"][0, 0], b["sigma_bar"][0, 0]
             assert abs(sa - sb) <= 1e-5 * max(abs(sa), 1.0)
+
+
+def test_extrapolated_start_reaches_the_same_equilibrium():
+    """warm_start = 3 (the baseline the learned start is measured against):
+    the last fluctuation increment scaled by the load ratio, projected by G
+    and kept by the rule of warm_start = 2; every increment still ends at
+    ||G(P)|| <= tol ||P|| and on the homogeneous-predictor run's macro
+    stress to the equilibrium tolerance, and the extrapolation lowers the
+    predictor residual away from load reversals."""
+    from paper_1806_10599_amd.binding import Rve
+    c = config_by_name("C2")
+    micro = c.microstructure()
+    hist = c.history()[:8]
+    runs = {}
+    for ws in (0, 3):
+        r = Rve(micro.n, projection=c.operator, precision="mixed",
+                newton_tol=1e-6, cg_tol=1e-4, cg_forcing=2, warm_start=ws)
+        r.set_microstructure(micro.phase, micro.quat, micro.law,
+                             material_params())
+        try:
+            infos = []
+            for inc in hist:
+                info = r.increment(inc["F_bar"], inc["dt"])
+                assert info["status"] == 0 and info["residual_rel"] <= 1e-6
+                infos.append(info)
+            runs[ws] = infos
+        finally:
+            r.close()
+    for a, b in zip(runs[0], runs[3]):
+        sa, sb = a["sigma_bar"][0, 0], b["sigma_bar"][0, 0]
+        assert abs(sa - sb) <= 1e-5 * max(abs(sa), 1.0)
+    assert runs[3][0]["used_learned"] == 0         # no history yet
+    used = [i["used_learned"] for i in runs[3][1:]]
+    assert sum(used) >= len(used) - 1
+    p0 = np.median([i["predictor_residual"] for i in runs[0][2:]])
+    p3 = np.median([i["predictor_residual"] for i in runs[3][2:]])
+    assert p3 < 0.5 * p0, (p3, p0)
