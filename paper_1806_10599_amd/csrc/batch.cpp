@@ -477,6 +477,7 @@ int BatchEngine::increment(const double* Fbar_all, double dt,
   }
   LawParams lp{params_[3], params_[4], params_[5], params_[6], params_[7], dt,
                1.0 / params_[4], 1.0 / (dt * params_[3])};
+  lp.nint = flow_exponent_int(lp.nexp);
   const double* dg_start = dg_c_;
   std::vector<int> iters(B_, 0);
   for (int it = 0; it <= cfg_.newton_max_iter; ++it) {

@@ -109,6 +109,7 @@ Engine::Engine(const rve_config& cfg) : cfg_(cfg) {
   sc_ = (Scalars*)alloc(sizeof(Scalars));
   RVE_HIP(hipMemsetAsync(sc_, 0, sizeof(Scalars), st_));
   phase_ = (int32_t*)alloc(N_ * sizeof(int32_t));
+  order_ = (int32_t*)alloc(N_ * sizeof(int32_t));
   table_ = nullptr;
   // slot 0: synchronous reads; slots 1, 2: the CG chunks' look-ahead reads
   RVE_HIP(hipHostMalloc((void**)&sc_host_, 3 * sizeof(Scalars), hipHostMallocDefault));
@@ -221,6 +222,16 @@ void Engine::set_microstructure(const int32_t* phase, int32_t G,
                          hipMemcpyHostToDevice, st_));
   RVE_HIP(hipMemcpyAsync(phase_, phase, N_ * sizeof(int32_t),
                          hipMemcpyHostToDevice, st_));
+  // work order of the return mapping: crystal voxels first (in index
+  // order), then the particle voxels, so that the wavefronts that iterate
+  // the local Newton solve carry no particle lanes
+  order_host_.clear();
+  order_host_.reserve(N_);
+  for (int pass = 0; pass < 2; ++pass)
+    for (int64_t v = 0; v < N_; ++v)
+      if ((law[phase[v]] == 0) == (pass == 0)) order_host_.push_back((int32_t)v);
+  RVE_HIP(hipMemcpyAsync(order_, order_host_.data(), N_ * sizeof(int32_t),
+                         hipMemcpyHostToDevice, st_));
   phase_host_.assign(phase, phase + N_);
   table_host_ = tab;
   G_ = G;
@@ -324,6 +335,7 @@ LawParams Engine::law_params(double dt) const {
   lp.dt = dt;
   lp.inv_g = 1.0 / lp.g;
   lp.inv_a = 1.0 / (dt * lp.gdot0);
+  lp.nint = flow_exponent_int(lp.nexp);
   return lp;
 }
 
@@ -363,6 +375,7 @@ int Engine::evaluate(const double* dg_start, double dt, double& rel,
   a.iters = timer_.on(4) ? rm_iters_ : nullptr;
   a.evals = timer_.on(4) ? rm_evals_ : nullptr;
   a.lp = law_params(dt);
+  a.order = order_;
   a.N = N_;
   if (umat_fn_) {
     // user material: sigma and its Jaumann tangent, then P (Eq. A.1)
@@ -402,6 +415,7 @@ void Engine::tangent(double dt) {
   a.table = table_;
   a.K = (T*)K_;
   a.lp = law_params(dt);
+  a.order = order_;
   a.N = N_;
   if (umat_fn_) {
     // user material: K from the last evaluation's sigma and tangent (Eq. A.16)
@@ -1185,6 +1199,7 @@ void Engine::debug_constitutive(const double* F, double dt, double* P, double* K
   a.dg = dg_t_;
   a.fails = &sc_->fails;
   a.lp = law_params(dt);
+  a.order = order_;
   a.N = N_;
   launch_return_map(a, st_);
   if (K) {
@@ -1326,6 +1341,7 @@ void Engine::bench_kernels(int reps, double* ms, int count) {
     a.dg = dg_t_;
     a.fails = &sc_->fails;
     a.lp = law_params(dt);
+    a.order = order_;
     a.N = N_;
     launch_return_map(a, st_);
   });

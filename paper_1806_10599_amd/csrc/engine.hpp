@@ -131,6 +131,8 @@ class Engine {
   Scalars* sc_host_ = nullptr;          // pinned: [0] sync reads, [1..2] chunks
   hipEvent_t chunk_ev_[2] = {nullptr, nullptr};
   int32_t* phase_;
+  int32_t* order_;                 // return-mapping work order (crystal first)
+  std::vector<int32_t> order_host_;
   double* table_;
   void *tw32_, *tw64_, *vt32_, *vt64_;
   int nslab32_, nslab64_;

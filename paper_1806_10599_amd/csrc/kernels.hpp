@@ -152,7 +152,14 @@ constexpr int kTabLam = 8, kTabMu = 9;
 struct LawParams {
   double gdot0, g, nexp, c_af, d_af, dt;
   double inv_g, inv_a;   // 1/g and 1/(dt gdot0), formed once on the host
+  int32_t nint;          // nexp when it is an integer in [1, 64], else 0
 };
+
+// the flow-rule exponent as an integer when it is one (powers by products)
+inline int32_t flow_exponent_int(double n) {
+  const int32_t ni = (int32_t)n;
+  return ((double)ni == n && ni >= 1 && ni <= 64) ? ni : 0;
+}
 
 struct ConstArgs {
   const double* F;       // [9][N]
@@ -173,6 +180,8 @@ struct ConstArgs {
   const uint8_t* vrve;   // batch: RVE of each voxel (null for one RVE)
   Scalars* scs;          // batch: per-RVE flags (skip when inactive) and
                          // per-RVE failure counts (fails unused)
+  const int32_t* order;  // optional voxel of each work item: crystal voxels
+                         // first, then the particle voxels (null: identity)
 };
 
 template <typename TK>
@@ -188,6 +197,7 @@ struct TangentArgs {
   int64_t N;
   const uint8_t* vrve;
   const Scalars* scs;
+  const int32_t* order;  // optional work order (as ConstArgs::order)
 };
 
 void launch_return_map(const ConstArgs& a, hipStream_t s);

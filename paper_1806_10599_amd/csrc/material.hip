@@ -13,15 +13,25 @@
 // The 12 slips solve R_a = asinh(dg_a/a) - asinh(|x_a|^n sign x_a) = 0
 // (a = dt gdot0), which has the roots of dg_a = a |x_a|^n sign x_a but stays
 // well scaled under large overstress.  Damped Newton with backtracking on
-// |R|^2/2; a failed warm-started solve is retried from zero slips.
+// |R|^2/2; a failed warm-started solve is retried from zero slips.  R is
+// formed in FP64 with one logarithm per slip (flow_residual); the Jacobian,
+// which only steers the iteration towards the root of R, in FP32.
 //
 // The 12x12 Jacobian is diag(D) + U W^T with rank-6 factors (the resolved
 // stresses depend on the slips only through the symmetric elastic strain),
 // so each Newton step and each tangent column costs one 6x6 solve
 // (Sherman-Morrison-Woodbury) instead of a 12x12 one.
 //
+// Work order: crystal voxels first, then the particle voxels (an index list
+// built with the microstructure), so that wavefronts iterating the local
+// solve carry no particle lanes.
+//
 // Particles: isotropic St-Venant-Kirchhoff, P = F S, S = lam tr(E) I + 2 mu E.
 #include "kernels.hpp"
+
+#ifndef RVE_TAN_MINB32
+#define RVE_TAN_MINB32 2
+#endif
 
 namespace rve {
 
@@ -51,16 +61,37 @@ __device__ __forceinline__ double sgn(double x) {
   return (x > 0.0) ? 1.0 : ((x < 0.0) ? -1.0 : 0.0);
 }
 
-// asinh(|x|^n sign x) and its derivative, without branches: with
-// y = |x|^n and s = min(y, 1/y) = exp(-|n ln|x||),
+// asinh(|x|^n sign x) and its derivative d/dx = n y / (|x| sqrt(1 + y^2)),
+// y = |x|^n.  For the integer exponents of the flow rule y is formed by
+// repeated squaring and asinh(y) = log1p(y + y (y / (1 + sqrt(1 + y^2))))
+// (an exact identity that needs no logarithm of |x| and no exponential);
+// past |x| = 1e7 (y^2 would leave the FP64 range) and for other exponents
+// the form through s = min(y, 1/y) = exp(-|n ln|x||) is used:
 //   y >= 1: asinh(y) = n ln|x| + log1p(q),                q = sqrt(1 + s^2)
-//   y <  1: asinh(y) = log1p(s + s^2 / (1 + q))
-// (both exact; the first never forms the power), and
-// d asinh(y)/dx = (n / |x|) y / sqrt(1 + y^2) = n (y >= 1 ? 1 : s) / (|x| q).
-// Every lane of a wavefront runs the same instructions whatever its regime.
-__device__ __forceinline__ void asinh_pow(double x, double n, double& val,
-                                          double& der) {
+//   y <  1: asinh(y) = log1p(s + s^2 / (1 + q)).
+__device__ __forceinline__ double ipow_n(double b, int ni) {
+  if (ni == 20) {   // the workloads' exponent: five products
+    const double b2 = b * b, b4 = b2 * b2, b8 = b4 * b4, b16 = b8 * b8;
+    return b16 * b4;
+  }
+  double y = 1.0;
+  for (int e = ni; e; e >>= 1) {   // uniform over the wavefront
+    if (e & 1) y *= b;
+    b *= b;
+  }
+  return y;
+}
+
+__device__ __forceinline__ void asinh_pow(double x, double n, int ni,
+                                          double& val, double& der) {
   const double ax = fabs(x);
+  if (ni > 0 && ax < 1e7) {
+    const double y = ipow_n(ax, ni);
+    const double q = sqrt(fma(y, y, 1.0));
+    val = copysign(log1p(y + y * (y / (1.0 + q))), x);
+    der = (ax > 0.0) ? n * (y / (ax * q)) : 0.0;
+    return;
+  }
   const double e = n * log(ax);          // ln y (-inf at x = 0)
   const bool big = e > 0.0;
   const double s = exp(-fabs(e));        // 0 at x = 0
@@ -68,6 +99,42 @@ __device__ __forceinline__ void asinh_pow(double x, double n, double& val,
   const double L = log1p(big ? q : s + s * s / (1.0 + q));
   val = sgn(x) * ((big ? e : 0.0) + L);
   der = (ax > 0.0) ? n * (big ? 1.0 : s) / (ax * q) : 0.0;
+}
+
+// The local residual R = asinh(u) - asinh(|x|^n sign x), u = dg / a, with
+// one logarithm: asinh(u) = su ln A, A = |u| + sqrt(1 + u^2), and
+// asinh(|x|^n sign x) = sx ln B, B = y + sqrt(1 + y^2), y = |x|^n, so
+// R = s ln(A / B) when the signs agree (or one is zero; s the nonzero one)
+// and R = su ln(A B) when they differ -- exact identities.  Near the root
+// A / B is close to one and ln(A / B) carries an absolute error of a few
+// units of 1e-16 (the two-logarithm difference carries that much relative
+// to ln A).  The derivative of asinh(|x|^n sign x) (Jacobian only) is
+// returned in single precision.  Past |x| = 1e7 and for non-integer n the
+// two functions are evaluated apart (asinh_pow, asinh_bf).
+__device__ __forceinline__ double asinh_bf(double u);
+__device__ __forceinline__ void flow_residual(double t, double inv_a, double x,
+                                              double n, int ni, double& R,
+                                              float& der) {
+  const double ax = fabs(x);
+  if (ni > 0 && ax < 1e7) {
+    const double y = ipow_n(ax, ni);
+    const double B = y + sqrt(fma(y, y, 1.0));
+    const double au = fabs(t * inv_a);
+    const double A = au + sqrt(fma(au, au, 1.0));
+    const double su = (t > 0.0) ? 1.0 : ((t < 0.0) ? -1.0 : 0.0);
+    const double sx = (x > 0.0) ? 1.0 : ((x < 0.0) ? -1.0 : 0.0);
+    const bool differ = su * sx < 0.0;
+    const double s = (su != 0.0) ? su : sx;
+    R = s * log(differ ? A * B : A / B);
+    const float yf = (float)y;
+    const float r = (y >= 1e18) ? 1.0f : yf * rsqrtf(fmaf(yf, yf, 1.0f));
+    der = (ax > 1e-30) ? (float)n * r * __builtin_amdgcn_rcpf((float)ax) : 0.0f;
+    return;
+  }
+  double val, d;
+  asinh_pow(x, n, ni, val, d);
+  R = asinh_bf(t * inv_a) - val;
+  der = (float)d;
 }
 
 // asinh(u) in one branch-free form, exact for every u:
@@ -108,11 +175,24 @@ struct CpEval {
   double Fe[9];
   double S[6];
   double chi[12];
-  double R[12];
   double h[12];   // d asinh(|x|^n sign x) / dx, x = (tau - chi)/g
 };
 
-// Return-mapping residual at slips dg.  Fes = F Fp^-1_0.
+// d/dx asinh(|x|^n sign x) = n y / (|x| sqrt(1 + y^2)), y = |x|^n (FP64;
+// the same branches as asinh_pow, without the function value)
+__device__ __forceinline__ double flow_slope(double x, double n, int ni) {
+  const double ax = fabs(x);
+  if (ni > 0 && ax < 1e7) {
+    const double y = ipow_n(ax, ni);
+    return (ax > 0.0) ? n * (y / (ax * sqrt(fma(y, y, 1.0)))) : 0.0;
+  }
+  double val, der;
+  asinh_pow(x, n, ni, val, der);
+  return der;
+}
+
+// State at the converged slips dg for the tangent (elastic deformation,
+// stress, back stresses, flow slopes).  Fes = F Fp^-1_0.
 __device__ __forceinline__ void cp_eval(const double* Fes,
                                         const double* chi0, const double* dg,
                                         const double* __restrict__ tb,
@@ -160,11 +240,8 @@ __device__ __forceinline__ void cp_eval(const double* Fes,
     const double tau = s0 * Sm0 + s1 * Sm1 + s2 * Sm2;
     const double chi = (chi0[al] + lp.c_af * dg[al]) / (1.0 + lp.d_af * fabs(dg[al]));
     const double x = (tau - chi) * lp.inv_g;
-    double val, der;
-    asinh_pow(x, lp.nexp, val, der);
     e.chi[al] = chi;
-    e.h[al] = der;
-    e.R[al] = asinh_bf(dg[al] * lp.inv_a) - val;
+    e.h[al] = flow_slope(x, lp.nexp, lp.nint);
   }
 }
 
@@ -179,34 +256,37 @@ __device__ __forceinline__ void make_Q(const double* Fe, const double* Fes,
                      Fe[6 + i] * Fes[6 + j];
 }
 
-// V_a = sym((Q s_a) (x) m_a) in Voigt order
-__device__ __forceinline__ void make_V(const double* Q,
-                                       const double* __restrict__ tb, int al,
-                                       double* V) {
-  const double s0 = tb[kTabS + 3 * al], s1 = tb[kTabS + 3 * al + 1],
-               s2 = tb[kTabS + 3 * al + 2];
-  const double m[3] = {tb[kTabM + 3 * al], tb[kTabM + 3 * al + 1],
-                       tb[kTabM + 3 * al + 2]};
-  double qs[3];
+// V_a = sym((Q s_a) (x) m_a) in Voigt order, in the precision T of Q
+template <typename T>
+__device__ __forceinline__ void make_V(const T* Q, const double* __restrict__ tb,
+                                       int al, T* V) {
+  const T s0 = (T)tb[kTabS + 3 * al], s1 = (T)tb[kTabS + 3 * al + 1],
+          s2 = (T)tb[kTabS + 3 * al + 2];
+  const T m[3] = {(T)tb[kTabM + 3 * al], (T)tb[kTabM + 3 * al + 1],
+                  (T)tb[kTabM + 3 * al + 2]};
+  T qs[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) qs[i] = Q[3 * i] * s0 + Q[3 * i + 1] * s1 + Q[3 * i + 2] * s2;
   V[0] = qs[0] * m[0];
   V[1] = qs[1] * m[1];
   V[2] = qs[2] * m[2];
-  V[3] = 0.5 * (qs[1] * m[2] + qs[2] * m[1]);
-  V[4] = 0.5 * (qs[0] * m[2] + qs[2] * m[0]);
-  V[5] = 0.5 * (qs[0] * m[1] + qs[1] * m[0]);
+  V[3] = T(0.5) * (qs[1] * m[2] + qs[2] * m[1]);
+  V[4] = T(0.5) * (qs[0] * m[2] + qs[2] * m[0]);
+  V[5] = T(0.5) * (qs[0] * m[1] + qs[1] * m[0]);
 }
 
 // Gaussian elimination of the 6x6 capacitance matrix with partial pivoting
 // by compare-and-swap; the swap decisions are kept for later right-hand sides.
-struct LU6 {
-  double M[36];
-  double ip[6];   // reciprocals of the pivots
+template <typename T>
+struct LU6T {
+  T M[36];
+  T ip[6];   // reciprocals of the pivots
   uint32_t swaps;
 };
+using LU6 = LU6T<double>;
 
-__device__ __forceinline__ void lu6_factor(LU6& L) {
+template <typename T>
+__device__ __forceinline__ void lu6_factor(LU6T<T>& L) {
   uint32_t sw = 0;
   int bit = 0;
 #pragma unroll
@@ -219,7 +299,7 @@ __device__ __forceinline__ void lu6_factor(LU6& L) {
         // the step that made them (the solve applies swap k, then step k)
 #pragma unroll
         for (int j = k; j < 6; ++j) {
-          const double t = L.M[6 * k + j];
+          const T t = L.M[6 * k + j];
           L.M[6 * k + j] = L.M[6 * r + j];
           L.M[6 * r + j] = t;
         }
@@ -227,11 +307,11 @@ __device__ __forceinline__ void lu6_factor(LU6& L) {
       sw |= (s ? 1u : 0u) << bit;
       ++bit;
     }
-    const double inv = 1.0 / L.M[6 * k + k];
+    const T inv = T(1) / L.M[6 * k + k];
     L.ip[k] = inv;
 #pragma unroll
     for (int r = k + 1; r < 6; ++r) {
-      const double f = L.M[6 * r + k] * inv;
+      const T f = L.M[6 * r + k] * inv;
       L.M[6 * r + k] = f;
 #pragma unroll
       for (int j = k + 1; j < 6; ++j) L.M[6 * r + j] -= f * L.M[6 * k + j];
@@ -240,14 +320,15 @@ __device__ __forceinline__ void lu6_factor(LU6& L) {
   L.swaps = sw;
 }
 
-__device__ __forceinline__ void lu6_solve(const LU6& L, double* z) {
+template <typename T>
+__device__ __forceinline__ void lu6_solve(const LU6T<T>& L, T* z) {
   int bit = 0;
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
 #pragma unroll
     for (int r = k + 1; r < 6; ++r) {
       if ((L.swaps >> bit) & 1u) {
-        const double t = z[k];
+        const T t = z[k];
         z[k] = z[r];
         z[r] = t;
       }
@@ -258,39 +339,45 @@ __device__ __forceinline__ void lu6_solve(const LU6& L, double* z) {
   }
 #pragma unroll
   for (int k = 5; k >= 0; --k) {
-    double acc = z[k];
+    T acc = z[k];
 #pragma unroll
     for (int j = k + 1; j < 6; ++j) acc -= L.M[6 * k + j] * z[j];
     z[k] = acc * L.ip[k];
   }
 }
 
-// Diagonal D, factor h and the factored capacitance matrix at the slips dg.
+// Diagonal D, factor h and the factored capacitance matrix at the slips dg,
+// in the precision T (the state e comes from an FP64 evaluation).
+template <typename T>
 __device__ __forceinline__ void cp_jacobian(const CpEval& e, const double* Fes,
                                             const double* dg,
                                             const double* __restrict__ tb,
                                             const LawParams& lp, double a,
-                                            double* D, double* hg, double* Q,
-                                            LU6& L) {
+                                            T* D, T* hg, T* Q, LU6T<T>& L) {
   tb = opaque(tb);
-  make_Q(e.Fe, Fes, Q);
 #pragma unroll
-  for (int i = 0; i < 36; ++i) L.M[i] = (i % 7 == 0) ? 1.0 : 0.0;
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      Q[3 * i + j] = (T)(e.Fe[i] * Fes[j] + e.Fe[3 + i] * Fes[3 + j] +
+                         e.Fe[6 + i] * Fes[6 + j]);
+#pragma unroll
+  for (int i = 0; i < 36; ++i) L.M[i] = (i % 7 == 0) ? T(1) : T(0);
 #pragma unroll
   for (int al = 0; al < 12; ++al) {
-    const double h = e.h[al];
     const double ad = fabs(dg[al]);
     const double dchi = (lp.c_af - lp.d_af * sgn(dg[al]) * e.chi[al]) / (1.0 + lp.d_af * ad);
-    hg[al] = h * lp.inv_g;
+    const double hgd = e.h[al] * lp.inv_g;
+    hg[al] = (T)hgd;
     // D holds the reciprocal of the diagonal of the local Jacobian
-    D[al] = 1.0 / (1.0 / sqrt(a * a + dg[al] * dg[al]) + hg[al] * dchi);
-    double V[6];
+    D[al] = (T)(1.0 / (1.0 / sqrt(a * a + dg[al] * dg[al]) + hgd * dchi));
+    T V[6];
     make_V(Q, tb, al, V);
-    const double f = hg[al] * D[al];
+    const T f = hg[al] * D[al];
     // row factor of the rank-one term, formed once per slip
-    double w[6];
+    T w[6];
 #pragma unroll
-    for (int J = 0; J < 6; ++J) w[J] = f * VW[J] * tb[kTabN + 6 * al + J];
+    for (int J = 0; J < 6; ++J) w[J] = f * (T)(VW[J] * tb[kTabN + 6 * al + J]);
 #pragma unroll
     for (int I = 0; I < 6; ++I)
 #pragma unroll
@@ -301,16 +388,17 @@ __device__ __forceinline__ void cp_jacobian(const CpEval& e, const double* Fes,
 
 // out = J^-1 rhs with J = diag(D) + U W^T, U_a = hg_a w N_a, W_a = V_a
 // (iD = 1/D from cp_jacobian)
-__device__ __forceinline__ void cp_jsolve(const double* rhs, const double* iD,
-                                          const double* hg, const double* Q,
+template <typename T>
+__device__ __forceinline__ void cp_jsolve(const T* rhs, const T* iD,
+                                          const T* hg, const T* Q,
                                           const double* __restrict__ tb,
-                                          const LU6& L, double* out) {
+                                          const LU6T<T>& L, T* out) {
   tb = opaque(tb);
-  double z[6] = {0, 0, 0, 0, 0, 0};
+  T z[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
   for (int al = 0; al < 12; ++al) {
     out[al] = rhs[al] * iD[al];
-    double V[6];
+    T V[6];
     make_V(Q, tb, al, V);
 #pragma unroll
     for (int I = 0; I < 6; ++I) z[I] += V[I] * out[al];
@@ -318,10 +406,32 @@ __device__ __forceinline__ void cp_jsolve(const double* rhs, const double* iD,
   lu6_solve(L, z);
 #pragma unroll
   for (int al = 0; al < 12; ++al) {
-    double u = 0.0;
+    T u = 0;
 #pragma unroll
-    for (int J = 0; J < 6; ++J) u += VW[J] * tb[kTabN + 6 * al + J] * z[J];
+    for (int J = 0; J < 6; ++J) u += (T)(VW[J] * tb[kTabN + 6 * al + J]) * z[J];
     out[al] -= hg[al] * u * iD[al];
+  }
+}
+
+// C = A B (3x3, row-major) and S = C : E (Voigt, C_IJ from the table) in T
+template <typename T>
+__device__ __forceinline__ void mm3t(const T* A, const T* B, T* C) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      C[3 * i + j] = A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] +
+                     A[3 * i + 2] * B[6 + j];
+}
+template <typename T>
+__device__ __forceinline__ void cmul6t(const double* __restrict__ Cv,
+                                       const T* E, T* S) {
+#pragma unroll
+  for (int I = 0; I < 6; ++I) {
+    T acc = 0;
+#pragma unroll
+    for (int J = 0; J < 6; ++J) acc += (T)(Cv[6 * I + J] * VW[J]) * E[J];
+    S[I] = acc;
   }
 }
 
@@ -373,7 +483,7 @@ __device__ __forceinline__ void pr_eval(const double* Fes,
                                         const double* step, double lam,
                                         const double* __restrict__ tb0,
                                         const LawParams& lp, double a,
-                                        double* R, double* hd, double* Q) {
+                                        double* R, float* hd, float* Q) {
   double dFe[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) dFe[i] = 0.0;
@@ -421,71 +531,115 @@ __device__ __forceinline__ void pr_eval(const double* Fes,
     const double chi0 = opaque(chi0p)[(kOwn * h + j) * N];
     const double chi = (chi0 + lp.c_af * t) / (1.0 + lp.d_af * fabs(t));
     const double x = (tau - chi) * lp.inv_g;
-    double val, der;
-    asinh_pow(x, lp.nexp, val, der);
+    float der;
+    flow_residual(t, lp.inv_a, x, lp.nexp, lp.nint, R[j], der);
     hd[j] = der;
-    R[j] = asinh_bf(t * lp.inv_a) - val;
   }
-  make_Q(Fe, Fes, Q);
+  // Q = Fe^T Fes for the Jacobian, which only steers the Newton iteration
+  // (its root is that of R, formed in FP64): single precision
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      Q[3 * i + j] = (float)(Fe[i] * Fes[j] + Fe[3 + i] * Fes[3 + j] +
+                             Fe[6 + i] * Fes[6 + j]);
 }
 
-// Newton step of the own slips: step = -J^-1 R, J = diag(D) + U W^T
+// V_a = sym((Q s_a) (x) m_a) in Voigt order, single precision
+__device__ __forceinline__ void make_Vf(const float* Q,
+                                        const double* __restrict__ tb, int al,
+                                        float* V) {
+  const float s0 = (float)tb[kTabS + 3 * al], s1 = (float)tb[kTabS + 3 * al + 1],
+              s2 = (float)tb[kTabS + 3 * al + 2];
+  const float m0 = (float)tb[kTabM + 3 * al], m1 = (float)tb[kTabM + 3 * al + 1],
+              m2 = (float)tb[kTabM + 3 * al + 2];
+  float qs[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) qs[i] = Q[3 * i] * s0 + Q[3 * i + 1] * s1 + Q[3 * i + 2] * s2;
+  V[0] = qs[0] * m0;
+  V[1] = qs[1] * m1;
+  V[2] = qs[2] * m2;
+  V[3] = 0.5f * (qs[1] * m2 + qs[2] * m1);
+  V[4] = 0.5f * (qs[0] * m2 + qs[2] * m0);
+  V[5] = 0.5f * (qs[0] * m1 + qs[1] * m0);
+}
+
+template <int LPV>
+__device__ __forceinline__ float grp_sumf(float x) {
+  x = x + __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(
+              __builtin_bit_cast(int, x), 0xB1, 0xF, 0xF, false));
+  if constexpr (LPV == 4)
+    x = x + __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(
+                __builtin_bit_cast(int, x), 0x4E, 0xF, 0xF, false));
+  return x;
+}
+
+// Newton step of the own slips: step = -J^-1 R, J = diag(D) + U W^T.  The
+// Jacobian only steers the iteration (the root is that of the FP64
+// residual R), so it is formed and solved in single precision: the step
+// is then exact to single-precision rounding, which leaves the local
+// Newton iteration converging as before to the FP64 root.
 template <int LPV, int kOwn = 12 / LPV>
 __device__ __forceinline__ void pr_step(const double* dg, const double* R,
-                                        const double* hd, const double* Q,
+                                        const float* hd, const float* Q,
                                         const double* __restrict__ chi0p,
                                         int64_t N, int h,
                                         const double* __restrict__ tb0,
                                         const LawParams& lp, double a,
                                         double* step) {
-  LU6 L;
+  LU6T<float> L;
 #pragma unroll
-  for (int i = 0; i < 36; ++i) L.M[i] = 0.0;
-  double D[kOwn];
+  for (int i = 0; i < 36; ++i) L.M[i] = 0.0f;
+  float D[kOwn];
+  const float inv_g = (float)lp.inv_g, c_af = (float)lp.c_af,
+              d_af = (float)lp.d_af, a2 = (float)(a * a);
 #pragma unroll
   for (int j = 0; j < kOwn; ++j) {
     const int al = kOwn * h + j;
     const double* __restrict__ tb = opaque(tb0);
-    const double chi0 = opaque(chi0p)[al * N];
-    const double den = 1.0 / (1.0 + lp.d_af * fabs(dg[j]));
-    const double chi = (chi0 + lp.c_af * dg[j]) * den;
-    const double dchi = (lp.c_af - lp.d_af * sgn(dg[j]) * chi) * den;
+    const float chi0 = (float)opaque(chi0p)[al * N];
+    const float dgf = (float)dg[j];
+    const float den = 1.0f / (1.0f + d_af * fabsf(dgf));
+    const float chi = (chi0 + c_af * dgf) * den;
+    const float sg = (dgf > 0.0f) ? 1.0f : ((dgf < 0.0f) ? -1.0f : 0.0f);
+    const float dchi = (c_af - d_af * sg * chi) * den;
     // D holds the reciprocal of the diagonal of the local Jacobian
-    D[j] = 1.0 / (1.0 / sqrt(a * a + dg[j] * dg[j]) + hd[j] * lp.inv_g * dchi);
-    double V[6];
-    make_V(Q, tb, al, V);
-    const double f = hd[j] * lp.inv_g * D[j];
+    D[j] = 1.0f / (rsqrtf(a2 + dgf * dgf) + hd[j] * inv_g * dchi);
+    float V[6];
+    make_Vf(Q, tb, al, V);
+    const float f = hd[j] * inv_g * D[j];
     // row factor of the rank-one term, formed once per slip
-    double w[6];
+    float w[6];
 #pragma unroll
-    for (int J = 0; J < 6; ++J) w[J] = f * VW[J] * tb[kTabN + 6 * al + J];
+    for (int J = 0; J < 6; ++J) w[J] = f * (float)(VW[J] * tb[kTabN + 6 * al + J]);
 #pragma unroll
     for (int I = 0; I < 6; ++I)
 #pragma unroll
       for (int J = 0; J < 6; ++J) L.M[6 * I + J] += V[I] * w[J];
-    step[j] = -R[j] * D[j];
+    step[j] = -R[j] * (double)D[j];
   }
 #pragma unroll
-  for (int i = 0; i < 36; ++i) L.M[i] = ((i % 7 == 0) ? 1.0 : 0.0) + grp_sum<LPV>(L.M[i]);
+  for (int i = 0; i < 36; ++i) L.M[i] = ((i % 7 == 0) ? 1.0f : 0.0f) + grp_sumf<LPV>(L.M[i]);
   lu6_factor(L);
-  double z[6] = {0, 0, 0, 0, 0, 0};
+  float z[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
   for (int j = 0; j < kOwn; ++j) {
-    double V[6];
-    make_V(Q, opaque(tb0), kOwn * h + j, V);
+    float V[6];
+    make_Vf(Q, opaque(tb0), kOwn * h + j, V);
+    const float sj = (float)step[j];
 #pragma unroll
-    for (int I = 0; I < 6; ++I) z[I] += V[I] * step[j];
+    for (int I = 0; I < 6; ++I) z[I] += V[I] * sj;
   }
 #pragma unroll
-  for (int I = 0; I < 6; ++I) z[I] = grp_sum<LPV>(z[I]);
+  for (int I = 0; I < 6; ++I) z[I] = grp_sumf<LPV>(z[I]);
   lu6_solve(L, z);
 #pragma unroll
   for (int j = 0; j < kOwn; ++j) {
     const double* __restrict__ tb = opaque(tb0) + kTabN + 6 * (kOwn * h + j);
-    double u = 0.0;
+    float u = 0.0f;
 #pragma unroll
-    for (int J = 0; J < 6; ++J) u += VW[J] * tb[J] * z[J];
-    step[j] -= hd[j] * lp.inv_g * u * D[j];
+    for (int J = 0; J < 6; ++J) u += (float)(VW[J] * tb[J]) * z[J];
+    step[j] -= (double)(hd[j] * inv_g * u * D[j]);
   }
 }
 
@@ -506,7 +660,8 @@ __device__ __forceinline__ bool pr_local_solve(const double* Fes,
                                                const double* __restrict__ tb,
                                                const LawParams& lp, double a,
                                                int& iters, int& evals) {
-  double R[kOwn], hd[kOwn], Q[9], step[kOwn];
+  double R[kOwn], step[kOwn];
+  float hd[kOwn], Q[9];
 #pragma unroll
   for (int j = 0; j < kOwn; ++j) step[j] = 0.0;
   pr_eval<LPV>(Fes, chi0p, N, h, dg, step, 0.0, tb, lp, a, R, hd, Q);
@@ -564,9 +719,10 @@ template <int LPV, int MINB>
 __global__ __launch_bounds__(256, MINB) void return_map_group_kernel(ConstArgs A) {
   constexpr int kOwn = 12 / LPV;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t v = t / LPV;
+  const int64_t g = t / LPV;
   const int h = (int)(t % LPV);
-  if (v >= A.N) return;  // all lanes of a voxel leave together
+  if (g >= A.N) return;  // all lanes of a voxel leave together
+  const int64_t v = A.order ? (int64_t)A.order[g] : g;
   if (A.vrve && A.scs[A.vrve[v]].inactive) return;
   const int64_t N = A.N;
   const double* __restrict__ tb = A.table + (int64_t)A.phase[v] * kTableStride;
@@ -607,8 +763,7 @@ __global__ __launch_bounds__(256, MINB) void return_map_group_kernel(ConstArgs A
     }
     return;
   }
-  double Fpi0[9], dg[kOwn];
-  load9(A.Fpi0, v, N, Fpi0);
+  double dg[kOwn];
   double warm = 0.0;
 #pragma unroll
   for (int j = 0; j < kOwn; ++j) {
@@ -617,7 +772,11 @@ __global__ __launch_bounds__(256, MINB) void return_map_group_kernel(ConstArgs A
   }
   warm = grp_max<LPV>(warm);
   double Fes[9];
-  mm3(F, Fpi0, Fes);
+  {
+    double Fpi0[9];
+    load9(A.Fpi0, v, N, Fpi0);
+    mm3(F, Fpi0, Fes);
+  }
   const double a = A.lp.dt * A.lp.gdot0;
   const double* chi0p = A.chi0 + v;
   int iters = 0, evals = 0;
@@ -633,6 +792,8 @@ __global__ __launch_bounds__(256, MINB) void return_map_group_kernel(ConstArgs A
   if (!ok && h == 0) atomicAdd(A.vrve ? &A.scs[A.vrve[v]].fails : A.fails, 1);
   // final state: Fp^-1 = Fp^-1_0 (I - sum dg s (x) m), Fe = F Fp^-1,
   // S = C : Ee, P = Fe S Fp^-T
+  double Fpi0[9];
+  load9(opaque(A.Fpi0), v, N, Fpi0);
   double dFpi[9], dFe[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) dFpi[i] = dFe[i] = 0.0;
@@ -727,10 +888,13 @@ __global__ __launch_bounds__(256) void rm_count_kernel(
   if (threadIdx.x < 4) atomicAdd(&stats[threadIdx.x], red[threadIdx.x][0]);
 }
 
+// FP32 linear algebra (mixed mode) fits two waves per SIMD without spills
 template <typename TK>
-__global__ __launch_bounds__(128) void tangent_kernel(TangentArgs<TK> A) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= A.N) return;
+__global__ __launch_bounds__(128, sizeof(TK) == 4 ? RVE_TAN_MINB32 : 1) void
+tangent_kernel(TangentArgs<TK> A) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.N) return;
+  const int64_t v = A.order ? (int64_t)A.order[i] : i;
   if (A.vrve && A.scs[A.vrve[v]].inactive) return;
   const int64_t N = A.N;
   const double* __restrict__ tb = A.table + (int64_t)A.phase[v] * kTableStride;
@@ -770,6 +934,10 @@ __global__ __launch_bounds__(128) void tangent_kernel(TangentArgs<TK> A) {
           }
     return;
   }
+  // the state at the converged slips in FP64; the linear algebra of the
+  // tangent (6x6 factorisation, nine Woodbury solves) and its assembly in
+  // the precision of K (FP32 for the single-precision CG of mixed mode)
+  using TC = TK;
   double Fpi0[9], chi0[12], dg[12];
   load9(A.Fpi0, v, N, Fpi0);
 #pragma unroll
@@ -782,32 +950,42 @@ __global__ __launch_bounds__(128) void tangent_kernel(TangentArgs<TK> A) {
   const double a = A.lp.dt * A.lp.gdot0;
   CpEval e;
   cp_eval(Fes, chi0, dg, tb, A.lp, a, e);
-  double D[12], hg[12], Q[9];
-  LU6 L;
+  TC D[12], hg[12], Q[9];
+  LU6T<TC> L;
   cp_jacobian(e, Fes, dg, tb, A.lp, a, D, hg, Q, L);
-  double Fpi[9];
+  TC Fpi[9], Fe[9], Fpi0c[9], Fesc[9];
+  {
+    double Fpid[9];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) Fpi[i] = Fpi0[i];
+    for (int i = 0; i < 9; ++i) Fpid[i] = Fpi0[i];
 #pragma unroll
-  for (int al = 0; al < 12; ++al) {
-    const double s0 = tb[kTabS + 3 * al], s1 = tb[kTabS + 3 * al + 1],
-                 s2 = tb[kTabS + 3 * al + 2];
-    const double m0 = tb[kTabM + 3 * al], m1 = tb[kTabM + 3 * al + 1],
-                 m2 = tb[kTabM + 3 * al + 2];
+    for (int al = 0; al < 12; ++al) {
+      const double s0 = tb[kTabS + 3 * al], s1 = tb[kTabS + 3 * al + 1],
+                   s2 = tb[kTabS + 3 * al + 2];
+      const double m0 = tb[kTabM + 3 * al], m1 = tb[kTabM + 3 * al + 1],
+                   m2 = tb[kTabM + 3 * al + 2];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const double u = dg[al] * (Fpi0[3 * i] * s0 + Fpi0[3 * i + 1] * s1 +
-                                 Fpi0[3 * i + 2] * s2);
-      Fpi[3 * i] -= u * m0;
-      Fpi[3 * i + 1] -= u * m1;
-      Fpi[3 * i + 2] -= u * m2;
+      for (int i = 0; i < 3; ++i) {
+        const double u = dg[al] * (Fpi0[3 * i] * s0 + Fpi0[3 * i + 1] * s1 +
+                                   Fpi0[3 * i + 2] * s2);
+        Fpid[3 * i] -= u * m0;
+        Fpid[3 * i + 1] -= u * m1;
+        Fpid[3 * i + 2] -= u * m2;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      Fpi[i] = (TC)Fpid[i];
+      Fe[i] = (TC)e.Fe[i];
+      Fpi0c[i] = (TC)Fpi0[i];
+      Fesc[i] = (TC)Fes[i];
     }
   }
-  const double Sf[9] = {e.S[0], e.S[5], e.S[4], e.S[5], e.S[1],
-                        e.S[3], e.S[4], e.S[3], e.S[2]};
-  double PS[9], FeS[9], B[9];
-  mm3(Fpi, Sf, PS);   // Fp^-1 S
-  mm3(e.Fe, Sf, FeS);  // Fe S
+  const TC Sf[9] = {(TC)e.S[0], (TC)e.S[5], (TC)e.S[4], (TC)e.S[5], (TC)e.S[1],
+                    (TC)e.S[3], (TC)e.S[4], (TC)e.S[3], (TC)e.S[2]};
+  TC PS[9], FeS[9], B[9];
+  mm3t(Fpi, Sf, PS);   // Fp^-1 S
+  mm3t(Fe, Sf, FeS);   // Fe S
 #pragma unroll
   for (int l = 0; l < 3; ++l)
 #pragma unroll
@@ -819,51 +997,53 @@ __global__ __launch_bounds__(128) void tangent_kernel(TangentArgs<TK> A) {
   for (int kl = 0; kl < 9; ++kl) {
     const int k = kl / 3, l = kl - 3 * (kl / 3);
     // rows k of Fe and l of Fp^-1, B row l: selects keep them in registers
-    double fk[3], pl[3], Bl[3];
+    TC fk[3], pl[3], Bl[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      fk[c] = (k == 0) ? e.Fe[c] : ((k == 1) ? e.Fe[3 + c] : e.Fe[6 + c]);
+      fk[c] = (k == 0) ? Fe[c] : ((k == 1) ? Fe[3 + c] : Fe[6 + c]);
       pl[c] = (l == 0) ? Fpi[c] : ((l == 1) ? Fpi[3 + c] : Fpi[6 + c]);
       Bl[c] = (l == 0) ? B[c] : ((l == 1) ? B[3 + c] : B[6 + c]);
     }
     // dR/dF_kl: b_a = (h_a/g) fk . N_a pl  (dtau_a/dF = Fe N_a Fp^-T)
-    double b[12], gcol[12];
+    TC b[12], gcol[12];
 #pragma unroll
     for (int al = 0; al < 12; ++al) {
       const double* Na = tb + kTabN + 6 * al;
-      const double Np0 = Na[0] * pl[0] + Na[5] * pl[1] + Na[4] * pl[2];
-      const double Np1 = Na[5] * pl[0] + Na[1] * pl[1] + Na[3] * pl[2];
-      const double Np2 = Na[4] * pl[0] + Na[3] * pl[1] + Na[2] * pl[2];
+      const TC N0 = (TC)Na[0], N1 = (TC)Na[1], N2 = (TC)Na[2], N3 = (TC)Na[3],
+               N4 = (TC)Na[4], N5 = (TC)Na[5];
+      const TC Np0 = N0 * pl[0] + N5 * pl[1] + N4 * pl[2];
+      const TC Np1 = N5 * pl[0] + N1 * pl[1] + N3 * pl[2];
+      const TC Np2 = N4 * pl[0] + N3 * pl[1] + N2 * pl[2];
       b[al] = hg[al] * (fk[0] * Np0 + fk[1] * Np1 + fk[2] * Np2);
     }
     cp_jsolve(b, D, hg, Q, tb, L, gcol);  // d dg / d F_kl
     // sigma = C : sym(fk (x) pl) - C : sum_a g_a V_a
-    double E[6], acc6[6] = {0, 0, 0, 0, 0, 0}, acc9[9];
+    TC E[6], acc6[6] = {0, 0, 0, 0, 0, 0}, acc9[9];
     E[0] = fk[0] * pl[0];
     E[1] = fk[1] * pl[1];
     E[2] = fk[2] * pl[2];
-    E[3] = 0.5 * (fk[1] * pl[2] + fk[2] * pl[1]);
-    E[4] = 0.5 * (fk[0] * pl[2] + fk[2] * pl[0]);
-    E[5] = 0.5 * (fk[0] * pl[1] + fk[1] * pl[0]);
+    E[3] = TC(0.5) * (fk[1] * pl[2] + fk[2] * pl[1]);
+    E[4] = TC(0.5) * (fk[0] * pl[2] + fk[2] * pl[0]);
+    E[5] = TC(0.5) * (fk[0] * pl[1] + fk[1] * pl[0]);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) acc9[i] = 0.0;
+    for (int i = 0; i < 9; ++i) acc9[i] = 0;
 #pragma unroll
     for (int al = 0; al < 12; ++al) {
-      double V[6];
+      TC V[6];
       make_V(Q, tb, al, V);
 #pragma unroll
       for (int I = 0; I < 6; ++I) acc6[I] += gcol[al] * V[I];
-      const double s[3] = {tb[kTabS + 3 * al], tb[kTabS + 3 * al + 1],
-                           tb[kTabS + 3 * al + 2]};
-      const double m[3] = {tb[kTabM + 3 * al], tb[kTabM + 3 * al + 1],
-                           tb[kTabM + 3 * al + 2]};
-      double u[3], vv[3], w[3], y[3];
+      const TC s[3] = {(TC)tb[kTabS + 3 * al], (TC)tb[kTabS + 3 * al + 1],
+                       (TC)tb[kTabS + 3 * al + 2]};
+      const TC m[3] = {(TC)tb[kTabM + 3 * al], (TC)tb[kTabM + 3 * al + 1],
+                       (TC)tb[kTabM + 3 * al + 2]};
+      TC u[3], vv[3], w[3], y[3];
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        u[i] = Fes[3 * i] * s[0] + Fes[3 * i + 1] * s[1] + Fes[3 * i + 2] * s[2];
+        u[i] = Fesc[3 * i] * s[0] + Fesc[3 * i + 1] * s[1] + Fesc[3 * i + 2] * s[2];
         vv[i] = PS[3 * i] * m[0] + PS[3 * i + 1] * m[1] + PS[3 * i + 2] * m[2];
         w[i] = FeS[3 * i] * m[0] + FeS[3 * i + 1] * m[1] + FeS[3 * i + 2] * m[2];
-        y[i] = Fpi0[3 * i] * s[0] + Fpi0[3 * i + 1] * s[1] + Fpi0[3 * i + 2] * s[2];
+        y[i] = Fpi0c[3 * i] * s[0] + Fpi0c[3 * i + 1] * s[1] + Fpi0c[3 * i + 2] * s[2];
       }
 #pragma unroll
       for (int i = 0; i < 3; ++i)
@@ -873,18 +1053,18 @@ __global__ __launch_bounds__(128) void tangent_kernel(TangentArgs<TK> A) {
     }
 #pragma unroll
     for (int I = 0; I < 6; ++I) E[I] -= acc6[I];
-    double sg[6];
-    cmul6(Cv, E, sg);
-    const double sf[9] = {sg[0], sg[5], sg[4], sg[5], sg[1],
-                          sg[3], sg[4], sg[3], sg[2]};
-    double Fs[9];
-    mm3(e.Fe, sf, Fs);
+    TC sg[6];
+    cmul6t(Cv, E, sg);
+    const TC sf[9] = {sg[0], sg[5], sg[4], sg[5], sg[1],
+                      sg[3], sg[4], sg[3], sg[2]};
+    TC Fs[9];
+    mm3t(Fe, sf, Fs);
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
-        double K = Fs[3 * i] * Fpi[3 * j] + Fs[3 * i + 1] * Fpi[3 * j + 1] +
-                   Fs[3 * i + 2] * Fpi[3 * j + 2] - acc9[3 * i + j];
+        TC K = Fs[3 * i] * Fpi[3 * j] + Fs[3 * i + 1] * Fpi[3 * j + 1] +
+               Fs[3 * i + 2] * Fpi[3 * j + 2] - acc9[3 * i + j];
         if (i == k) K += Bl[j];
         A.K[(int64_t)(9 * (3 * i + j) + kl) * N + v] = TK(K);
       }
