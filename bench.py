@@ -53,19 +53,23 @@ PASS_BYTES_F32 = {
     "matvec_pass_b": 36 + 36,                       # spectrum in and out
     "matvec_pass_c": 36 + 4 * 9 + 4 * 9,            # spectrum, r in; r out
 }
-# algorithmic FP64 flops of the return mapping (add, mul, div, sqrt and each
-# elementary function count 1; a fused multiply-add counts 2): per residual
-# evaluation, per local Newton step (Jacobian, 6x6 capacitance factor and
-# Woodbury solve), per crystal voxel (set-up and final stress) and per
-# particle voxel
-RM_FLOPS = {"eval": 1124, "step": 2600, "crystal": 570, "particle": 110}
-# kernel classes timed live in the timed region: the dominant kernel (the
-# return mapping; the kernel trace of the same command ranks every kernel by
-# total time) and the other once-per-Newton-step kernels.  Timing the CG
-# kernels live would cost about 6 % of the throughput (one event pair per
-# launch, hundreds of launches per increment), so they are left to the
-# profiler.
-LIVE_CLASSES = ("return_map", "tangent", "residual_fp64")
+# algorithmic flops of the return mapping (add, mul, div, sqrt and each
+# elementary function count 1, a fused multiply-add 2; counted once per voxel
+# from the algorithm, not from the instruction stream), FP64 and FP32 apart:
+# per residual evaluation (plastic and elastic deformation, stress, 12
+# resolved shears, back stresses, the one-logarithm residuals; FP32 flow
+# slopes), per local Newton step (FP32 Jacobian: 12 rank-one updates of the
+# 6x6 capacitance matrix, its LU factorisation, the Woodbury solve; FP64
+# step and convergence tests), per crystal voxel (set-up, final Fp^-1 and
+# P) and per particle voxel
+RM_FLOPS = {"eval64": 1206, "eval32": 72, "step64": 60, "step32": 2350,
+            "crystal64": 825, "particle64": 90}
+# kernel classes timed live in the timed region (one event pair per launch):
+# the K:p direction kernel (the dominant kernel of the CG iteration) and the
+# once-per-Newton-step kernels.  The three FFT passes are timed live over
+# the sample increments before the timed region (one event pair per launch
+# of four CG kernels costs several per cent of the throughput).
+LIVE_CLASSES = ("return_map", "tangent", "residual_fp64", "matvec_kp")
 # learned warm start: a candidate well below the homogeneous predictor's
 # last residual is kept without evaluating the homogeneous predictor
 WARM_MODE = 2
@@ -879,9 +883,11 @@ def live_report(live, rmc, N, cg_total, sample=None):
     mv_ms = sum(total_ms[k] for k in mv)
     fft_gbs = (N * cg_total * sum(PASS_BYTES_F32[k] for k in mv)
                / (mv_ms * 1e-3) / 1e9) if all(launches[k] for k in mv) else None
-    rm_flops = (RM_FLOPS["eval"] * rmc["evals"] + RM_FLOPS["step"] * rmc["steps"]
-                + RM_FLOPS["crystal"] * rmc["crystal"]
-                + RM_FLOPS["particle"] * rmc["particle"])
+    rm_f64 = (RM_FLOPS["eval64"] * rmc["evals"] + RM_FLOPS["step64"] * rmc["steps"]
+              + RM_FLOPS["crystal64"] * rmc["crystal"]
+              + RM_FLOPS["particle64"] * rmc["particle"])
+    rm_f32 = RM_FLOPS["eval32"] * rmc["evals"] + RM_FLOPS["step32"] * rmc["steps"]
+    rm_flops = rm_f64 + rm_f32
 
     def hbm(k):
         per_launch = N * PASS_BYTES_F32[k] * cg_total / launches[k]
@@ -893,6 +899,8 @@ def live_report(live, rmc, N, cg_total, sample=None):
                     launches=launches[k])
 
     def alu():
+        # FP32 work is charged at the FP64 rate: this build disables the
+        # packed FP32 instructions that double the FP32 vector peak
         per_launch = rm_flops / launches["return_map"]
         ach = per_launch / (avg_ms["return_map"] * 1e-3) / 1e12
         return dict(kernel="return_map", bound="alu", achieved=round(ach, 3),
@@ -900,6 +908,8 @@ def live_report(live, rmc, N, cg_total, sample=None):
                     frac=round(ach / FP64_PEAK_TFLOPS, 4),
                     traffic=pmc_traffic("return_map"),
                     flops_per_launch=round(per_launch),
+                    flops_fp64_per_launch=round(rm_f64 / launches["return_map"]),
+                    flops_fp32_per_launch=round(rm_f32 / launches["return_map"]),
                     avg_ms=round(avg_ms["return_map"], 4),
                     launches=launches["return_map"])
 
@@ -935,7 +945,8 @@ def live_report(live, rmc, N, cg_total, sample=None):
                                for k, v in avg_ms.items()},
         "kernel_total_ms_live": {k: round(v, 3) for k, v in total_ms.items()},
         "kernel_launches_live": launches,
-        "return_map_work": dict(rmc, flops=rm_flops),
+        "return_map_work": dict(rmc, flops=rm_flops, flops_fp64=rm_f64,
+                                flops_fp32=rm_f32),
         "roofline": roof,
     }
     if share is not None:
