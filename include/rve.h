@@ -522,9 +522,17 @@ rve_status rve_umat_bridge(const double* F, const double* sigma,
    does no further work in that increment.  Results per RVE are those of a
    single handle with the same configuration up to the summation order of
    the reductions.
-   cfg: projection, precision, tolerances, use_graph, stream and allocator
-   as for rve_create; cfg.n is ignored (grids come from n[count]); cfg.L is
-   each RVE's cell; warm_start must be 0.  All RVEs share the material
+   cfg: projection, precision, tolerances, stream and allocator as for
+   rve_create; cfg.n is ignored (grids come from n[count]); cfg.L is each
+   RVE's cell; warm_start must be 0.  cfg.use_graph selects how an
+   increment runs: 0 = one launch per pass for the whole batch, the Newton
+   decisions and a check per cg_chunk CG iterations on the host; 1 = the
+   Newton decisions on the device, each linear solve of all RVEs in one
+   persistent launch (grid barriers between the passes of a CG iteration;
+   the launch stops when every RVE's CG is done), the predictor and the
+   first four Newton iterations replayed from one captured graph, further
+   iterations launched one at a time.  Both give the same results bit for
+   bit.  All RVEs share the material
    constants: rve_batch_set_microstructure rejects params that differ from
    those of an earlier call.  Voxel layouts, fields and info records are those
    of the single-RVE calls, per RVE b.

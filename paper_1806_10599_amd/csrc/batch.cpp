@@ -210,6 +210,17 @@ BatchEngine::BatchEngine(const rve_config& cfg, int count, const int32_t* n)
   RVE_HIP(hipMemcpyAsync(vrve_, vr.data(), Nt_, hipMemcpyHostToDevice, st_));
   RVE_HIP(hipStreamSynchronize(st_));
 
+  if (cfg_.use_graph) {
+    log_ = (BatchLog*)alloc(B_ * sizeof(BatchLog));
+    log_host_.resize(B_);
+    // grid-barrier words of the persistent CG kernel, then its error flag
+    bar_ = (unsigned*)alloc((kBatchBarWords + 1) * sizeof(unsigned));
+    launch_fill_i32((int32_t*)bar_, 0, kBatchBarWords + 1, st_);
+    persist_lds_ = fp64_ ? std::max(ldsA64_, ldsB64_) : std::max(ldsA32_, ldsB32_);
+    persist_grid_ = fp64_ ? cg_batch_persistent_grid<double>(persist_lds_)
+                          : cg_batch_persistent_grid<float>(persist_lds_);
+    RVE_HIP(hipStreamSynchronize(st_));
+  }
   host_phase_.resize(B_);
   host_tables_.resize(B_);
   label_count_.assign(B_, 0);
@@ -228,8 +239,8 @@ BatchEngine::BatchEngine(const rve_config& cfg, int count, const int32_t* n)
 }
 
 BatchEngine::~BatchEngine() {
-  if (graph_) hipGraphExecDestroy(graph_);
-  if (graph_def_) hipGraphDestroy(graph_def_);
+  if (inc_graph_) hipGraphExecDestroy(inc_graph_);
+  if (inc_graph_def_) hipGraphDestroy(inc_graph_def_);
   if (st_) hipStreamSynchronize(st_);
   for (auto& a : allocs_) {
     if (cfg_.dev_free)
@@ -427,21 +438,11 @@ void BatchEngine::cg_solve(std::vector<int>& iters) {
   RVE_HIP(hipGetLastError());
   int parity = 0;
   for (;;) {
-    if (cfg_.use_graph) {
-      if (!graph_) {
-        RVE_HIP(hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal));
-        for (int j = 0; j < cfg_.cg_chunk; ++j) cg_iteration<T>(j & 1);
-        RVE_HIP(hipStreamEndCapture(st_, &graph_def_));
-        RVE_HIP(hipGraphInstantiate(&graph_, graph_def_, nullptr, nullptr, 0));
-      }
-      RVE_HIP(hipGraphLaunch(graph_, st_));
-    } else {
-      for (int j = 0; j < cfg_.cg_chunk; ++j) {
-        cg_iteration<T>(parity);
-        parity ^= 1;
-      }
-      RVE_HIP(hipGetLastError());
+    for (int j = 0; j < cfg_.cg_chunk; ++j) {
+      cg_iteration<T>(parity);
+      parity ^= 1;
     }
+    RVE_HIP(hipGetLastError());
     read_scalars();
     bool all = true;
     for (int b = 0; b < B_; ++b) all = all && sc_host_[b].done;
@@ -454,6 +455,7 @@ int BatchEngine::increment(const double* Fbar_all, double dt,
                            rve_increment_info* info) {
   for (int b = 0; b < B_; ++b)
     if (!have_micro_[b]) throw Error(RVE_ESTATE, "every RVE needs a microstructure");
+  if (cfg_.use_graph) return increment_device(Fbar_all, dt, info);
   if (!(dt > 0.0) || !std::isfinite(dt)) throw Error(RVE_EINVAL, "dt must be > 0");
   for (int b = 0; b < B_; ++b) {
     const double* Fb = Fbar_all + 9 * b;
@@ -604,6 +606,214 @@ int BatchEngine::increment(const double* Fbar_all, double dt,
         loc[b].sigma_bar[3 * i + j] = s / J;
       }
     if (info) info[b] = loc[b];
+  }
+  return first_bad;
+}
+
+// ---------------------------------------------- device-controlled increment
+// One Newton iteration's evaluation: return mapping at the committed state
+// (slips from dg_start), FP64 residual G(P) and norms, the device decision.
+void BatchEngine::newton_eval_device(int it, const LawParams& lp,
+                                     const double* dg_start) {
+  ConstArgs a{};
+  a.F = F_;
+  a.Fpi0 = Fpi_c_;
+  a.chi0 = chi_c_;
+  a.dg0 = dg_start;
+  a.phase = phase_;
+  a.table = table_;
+  a.P = P_;
+  a.Fpi = Fpi_t_;
+  a.chi = chi_t_;
+  a.dg = dg_t_;
+  a.fails = nullptr;
+  a.lp = lp;
+  a.N = Nt_;
+  a.vrve = vrve_;
+  a.scs = sc_;
+  launch_return_map(a, st_);
+  BatchSpec<double> rs = spec<double>(false, 0);
+  launch_G_batch<double>(rs, SRC_FIELD, nullptr, r64_, blocksA64_, blocksB64_,
+                         ldsA64_, ldsB64_, st_);
+  launch_reduce_batch(RED_RESID, red_inv64_, B_, sc_, st_);
+  NewtonCtl ctl{cfg_.newton_tol, cfg_.cg_tol, cfg_.newton_max_iter,
+                cfg_.cg_max_iter, cfg_.cg_forcing};
+  launch_newton_control_batch(sc_, log_, B_, it, ctl, st_);
+}
+
+// One Newton iteration's linear solve: tangent, CG of every running RVE in
+// one persistent launch, F += dF.
+template <typename T>
+void BatchEngine::newton_solve_device(int it, const LawParams& lp) {
+  (void)it;
+  const bool dbl = sizeof(T) == sizeof(double);
+  TangentArgs<T> t{F_, Fpi_c_, chi_c_, dg_t_, phase_, table_, (T*)K_, lp, Nt_,
+                   vrve_, sc_};
+  launch_tangent<T>(t, st_);
+  launch_cg_init_batch<T>(seg_, B_, seg_blocks_, Nt_, r64_, (T*)r_, (T*)x_, st_);
+  launch_reduce_batch(RED_INIT, red_seg_, B_, sc_, st_);
+  BatchCG<T> c{};
+  c.even = spec<T>(true, 0);
+  c.odd = spec<T>(true, 1);
+  c.seg = seg_;
+  c.seg_blocks = seg_blocks_;
+  c.red_inv = dbl ? red_inv64_ : red_inv32_;
+  c.red_seg = red_seg_;
+  c.scs = sc_;
+  c.nitems = B_;
+  c.blocksA = dbl ? blocksA64_ : blocksA32_;
+  c.blocksB = dbl ? blocksB64_ : blocksB32_;
+  c.cs = Nt_;
+  c.x = (T*)x_;
+  c.r = (T*)r_;
+  c.Ap = (T*)Ap_;
+  c.max_iters = cfg_.cg_max_iter + 1;
+  c.bar = bar_;
+  c.err = (int*)(bar_ + kBatchBarWords);
+  // arrival counts to zero (the generation may keep its value; the flag too)
+  launch_fill_i32((int32_t*)bar_ + 1, 0, kBatchBarWords - 1, st_);
+  launch_cg_batch_persistent<T>(c, persist_grid_, persist_lds_, st_);
+  launch_add_to_F<T>(F_, (const T*)x_, 9 * Nt_, st_);
+}
+
+void BatchEngine::read_logs() {
+  RVE_HIP(hipMemcpyAsync(log_host_.data(), log_, B_ * sizeof(BatchLog),
+                         hipMemcpyDeviceToHost, st_));
+  RVE_HIP(hipStreamSynchronize(st_));
+}
+
+int BatchEngine::increment_device(const double* Fbar_all, double dt,
+                                  rve_increment_info* info) {
+  if (!(dt > 0.0) || !std::isfinite(dt)) throw Error(RVE_EINVAL, "dt must be > 0");
+  for (int b = 0; b < B_; ++b) {
+    const double* Fb = Fbar_all + 9 * b;
+    for (int i = 0; i < 9; ++i)
+      if (!std::isfinite(Fb[i])) throw Error(RVE_EINVAL, "non-finite F_bar");
+    if (!(det3(Fb) > 0.0)) throw Error(RVE_EINVAL, "det(F_bar) must be > 0");
+  }
+  const auto t0 = std::chrono::steady_clock::now();
+  std::vector<double> dF(9 * B_);
+  for (int b = 0; b < B_; ++b)
+    for (int i = 0; i < 9; ++i) dF[i + 9 * b] = Fbar_all[9 * b + i] - Fbar_[b][i];
+  RVE_HIP(hipMemcpyAsync(dF_dev_, dF.data(), 9 * B_ * sizeof(double),
+                         hipMemcpyHostToDevice, st_));
+  for (int b = 0; b < B_; ++b) {
+    sc_host_[b].inactive = 0;
+    sc_host_[b].commit = 0;
+    sc_host_[b].fails = 0;
+    sc_host_[b].done = 0;
+    std::memset(&log_host_[b], 0, sizeof(BatchLog));
+    log_host_[b].status = 1;
+  }
+  upload_scalars();
+  RVE_HIP(hipMemcpyAsync(log_, log_host_.data(), B_ * sizeof(BatchLog),
+                         hipMemcpyHostToDevice, st_));
+  LawParams lp{params_[3], params_[4], params_[5], params_[6], params_[7], dt,
+               1.0 / params_[4], 1.0 / (dt * params_[3])};
+  lp.nint = flow_exponent_int(lp.nexp);
+  const int ncap = std::min(kGraphNewton, cfg_.newton_max_iter);
+  auto solve = [&](int it) {
+    if (fp64_) newton_solve_device<double>(it, lp);
+    else newton_solve_device<float>(it, lp);
+  };
+  // the predictor and Newton iterations 0..ncap, captured once per dt
+  if (!inc_graph_ || inc_graph_dt_ != dt) {
+    if (inc_graph_) RVE_HIP(hipGraphExecDestroy(inc_graph_));
+    if (inc_graph_def_) RVE_HIP(hipGraphDestroy(inc_graph_def_));
+    inc_graph_ = nullptr;
+    inc_graph_def_ = nullptr;
+    RVE_HIP(hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal));
+    launch_predict_batch(F_, Fprev_, vrve_, dF_dev_, Nt_, st_);
+    for (int it = 0; it <= ncap; ++it) {
+      newton_eval_device(it, lp, it == 0 ? dg_c_ : dg_t_);
+      if (it < ncap) solve(it);
+    }
+    RVE_HIP(hipStreamEndCapture(st_, &inc_graph_def_));
+    RVE_HIP(hipGraphInstantiate(&inc_graph_, inc_graph_def_, nullptr, nullptr, 0));
+    inc_graph_dt_ = dt;
+  }
+  RVE_HIP(hipGraphLaunch(inc_graph_, st_));
+  read_logs();
+  // RVEs still iterating after the captured iterations go on one Newton
+  // iteration at a time
+  for (int it = ncap; it < cfg_.newton_max_iter; ++it) {
+    bool any = false;
+    for (int b = 0; b < B_; ++b) any = any || log_host_[b].status == 1;
+    if (!any) break;
+    solve(it);
+    newton_eval_device(it + 1, lp, dg_t_);
+    RVE_HIP(hipGetLastError());
+    read_logs();
+  }
+  unsigned flag = 0;
+  RVE_HIP(hipMemcpyAsync(&flag, bar_ + kBatchBarWords, sizeof(flag),
+                         hipMemcpyDeviceToHost, st_));
+  RVE_HIP(hipStreamSynchronize(st_));
+  if (flag != 0)
+    throw Error(RVE_EDEVICE, "persistent CG: a grid barrier waited past its bound");
+  CommitBatchArgs c{};
+  c.vrve = vrve_;
+  c.scs = sc_;
+  c.dF = dF_dev_;
+  c.F = F_;
+  c.P = P_;
+  c.Fpi_t = Fpi_t_;
+  c.chi_t = chi_t_;
+  c.dg_t = dg_t_;
+  c.Fprev = Fprev_;
+  c.Pc = Pc_;
+  c.Fpi_c = Fpi_c_;
+  c.chi_c = chi_c_;
+  c.dg_c = dg_c_;
+  c.dFt = dFt_;
+  c.phase = phase_;
+  c.table = table_;
+  c.pcyc = pcyc_;
+  c.pcyc_lit = pcyc_lit_;
+  c.wcyc = wcyc_;
+  c.dt = dt;
+  c.N = Nt_;
+  launch_commit_batch(c, st_);
+  RVE_HIP(hipGetLastError());
+  RVE_HIP(hipStreamSynchronize(st_));
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int first_bad = RVE_OK;
+  for (int b = 0; b < B_; ++b) {
+    const BatchLog& L = log_host_[b];
+    rve_increment_info loc;
+    std::memset(&loc, 0, sizeof(loc));
+    loc.status = (L.status == 1) ? RVE_ENOTCONV : L.status;
+    loc.newton_iters = L.newton_iters;
+    loc.cg_iters_total = L.cg_total;
+    loc.cg_breakdowns = L.breakdowns;
+    loc.local_failures = L.fails;
+    loc.residual_rel = L.rel;
+    loc.predictor_residual = loc.plain_predictor_residual = L.predictor_rel;
+    for (int k = 0; k < RVE_MAX_NEWTON_LOG && k < kBatchLog; ++k) {
+      loc.residual_history[k] = L.res_hist[k];
+      loc.cg_iters[k] = L.cg_hist[k];
+    }
+    for (int i = 0; i < 9; ++i) loc.P_bar[i] = L.pbar[i];
+    loc.seconds = secs;
+    const double* Fbar_new = Fbar_all + 9 * b;
+    const double J = det3(Fbar_new);
+    if (loc.status == RVE_OK) {
+      for (int i = 0; i < 9; ++i) {
+        Fbar_[b][i] = Fbar_new[i];
+        Pbar_[b][i] = loc.P_bar[i];
+      }
+      t_[b] += dt;
+      ++increments_[b];
+    } else if (first_bad == RVE_OK) {
+      first_bad = loc.status;
+    }
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double s = 0.0;
+        for (int k = 0; k < 3; ++k) s += loc.P_bar[3 * i + k] * Fbar_new[3 * j + k];
+        loc.sigma_bar[3 * i + j] = s / J;
+      }
+    if (info) info[b] = loc;
   }
   return first_bad;
 }

@@ -43,6 +43,15 @@ class BatchEngine {
   void cg_solve(std::vector<int>& iters);
   template <typename T>
   BatchSpec<T> spec(bool cg, int parity) const;
+  // device-controlled increment (use_graph): Newton decisions on the
+  // device, CG in one persistent launch per linear solve, the predictor and
+  // the first Newton iterations replayed from a captured graph
+  int increment_device(const double* Fbar_all, double dt,
+                       rve_increment_info* info);
+  template <typename T>
+  void newton_solve_device(int it, const LawParams& lp);
+  void newton_eval_device(int it, const LawParams& lp, const double* dg_start);
+  void read_logs();
 
   rve_config cfg_;
   int B_;
@@ -88,8 +97,16 @@ class BatchEngine {
   std::vector<std::array<double, 9>> Fbar_, Pbar_;
   std::vector<double> t_;
   std::vector<int64_t> increments_;
-  hipGraphExec_t graph_ = nullptr;
-  hipGraph_t graph_def_ = nullptr;
+  // device-controlled increments
+  BatchLog* log_ = nullptr;
+  std::vector<BatchLog> log_host_;
+  unsigned* bar_ = nullptr;             // {count, generation, error}
+  int persist_grid_ = 0;
+  size_t persist_lds_ = 0;
+  hipGraphExec_t inc_graph_ = nullptr;  // predictor + first iterations
+  hipGraph_t inc_graph_def_ = nullptr;
+  double inc_graph_dt_ = -1.0;
+  static constexpr int kGraphNewton = 4;  // Newton iterations in the graph
 };
 
 }  // namespace rve

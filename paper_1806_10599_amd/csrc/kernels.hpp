@@ -134,6 +134,8 @@ void launch_G_batch(const BatchSpec<T>& b, int src, T* out_T, double* out_d,
                     hipStream_t s);
 template <typename T>
 void batch_lds(int n, size_t& slab, size_t& pencil);
+
+
 bool batch_supported(int n);
 template <typename T>
 void batch_allow_lds(size_t slab, size_t pencil);
@@ -292,6 +294,35 @@ struct RedItem {
   int nss;
   double invN3;
 };
+// CG of a whole batch in one launch of resident blocks (grid barriers between
+// passes); even / odd: the pass arguments of even and odd iterations (p_old
+// and p_new swapped)
+template <typename T>
+struct BatchCG {
+  BatchSpec<T> even, odd;
+  const SegItem* seg;
+  int seg_blocks;
+  const RedItem* red_inv;   // p.Ap partials of the inverse pass
+  const RedItem* red_seg;   // r.r partials of the update
+  Scalars* scs;
+  int nitems;
+  int blocksA, blocksB;
+  int64_t cs;
+  T* x;
+  T* r;
+  T* Ap;
+  int max_iters;            // iterations of this launch at most
+  unsigned* bar;            // barrier state (kBatchBarWords words, zero at
+                            // start but for the generation)
+  int* err;                 // set when a barrier waited past its bound
+};
+constexpr int kBatchBarWords = 32 * 10;
+template <typename T>
+void launch_cg_batch_persistent(const BatchCG<T>& c, int grid, size_t lds,
+                                hipStream_t s);
+// blocks of the persistent CG kernel that are resident at once
+template <typename T>
+int cg_batch_persistent_grid(size_t lds);
 template <typename T>
 void launch_cg_init_batch(const SegItem* items, int nitems, int blocks,
                           int64_t cs, const double* r64, T* r, T* x,
@@ -329,5 +360,31 @@ struct CommitBatchArgs {
   int64_t N;
 };
 void launch_commit_batch(const CommitBatchArgs& a, hipStream_t s);
+
+// Device-side Newton control of a batch (Sec. 2.1): per RVE the record of
+// its increment, written by the control kernel after each FP64 residual
+constexpr int kBatchLog = 64;
+struct BatchLog {
+  int32_t status;        // 1 running, else RVE_OK / RVE_ENOTCONV / RVE_ELOCAL
+  int32_t newton_iters;
+  int32_t cg_total;
+  int32_t breakdowns;
+  int32_t fails;
+  int32_t pad;
+  double rel;            // last relative residual ||G(P)|| / ||P||
+  double predictor_rel;
+  double pbar[9];
+  double res_hist[kBatchLog];
+  int32_t cg_hist[kBatchLog];
+};
+struct NewtonCtl {
+  double newton_tol, cg_tol;
+  int32_t newton_max, cg_max, forcing;
+};
+// after the residual of Newton iteration it: book the previous solve's CG
+// count, take the decision (commit, local failure, out of budget) and give
+// running RVEs their linear-solve tolerance
+void launch_newton_control_batch(Scalars* scs, BatchLog* log, int nitems,
+                                 int it, const NewtonCtl& ctl, hipStream_t s);
 
 }  // namespace rve

@@ -1,8 +1,9 @@
-// Host-side control of the Newton iteration shared by single and batched
-// solves.
+// Control of the Newton iteration shared by single and batched solves.
 #pragma once
 
-#include <algorithm>
+#include <hip/hip_runtime.h>
+
+#include <cmath>
 #include <cstdint>
 
 namespace rve {
@@ -23,12 +24,13 @@ constexpr double kForcingTheta = 0.05;
 //      tighter than kForcingTheta * rel: far from equilibrium the next
 //      residual is dominated by the quadratic term of Newton's method,
 //      which a tighter solve cannot reduce.
-inline double forcing_eta(int32_t mode, double cg_tol, double newton_tol,
-                          double rel) {
+// (host and device: the batch takes the decision on the device)
+__host__ __device__ inline double forcing_eta(int32_t mode, double cg_tol,
+                                              double newton_tol, double rel) {
   if (mode == 0 || !(rel > 0.0)) return cg_tol;
-  double eta = std::max(cg_tol, (mode == 2 ? 0.5 : 0.25) * newton_tol / rel);
-  if (mode == 2) eta = std::max(eta, kForcingTheta * rel);
-  return std::min(0.1, eta);
+  double eta = fmax(cg_tol, (mode == 2 ? 0.5 : 0.25) * newton_tol / rel);
+  if (mode == 2) eta = fmax(eta, kForcingTheta * rel);
+  return fmin(0.1, eta);
 }
 
 }  // namespace rve

@@ -4,8 +4,10 @@
 //   fixed-order (deterministic) reductions (text after Eq. 16), the Newton
 //   update F += dF, the commit of the increment with the fatigue indicators
 //   of Sec. 3.3, Eqs. 23-24.
+#include "batch_cg.hpp"
 #include "cg_scalars.hpp"
 #include "kernels.hpp"
+#include "newton.hpp"
 
 namespace rve {
 
@@ -412,33 +414,13 @@ template void launch_convert<double>(const double*, double*, int64_t,
 
 
 // ------------------------------------------------------------------ batch
-__device__ __forceinline__ int seg_item(const SegItem* items, int nitems) {
-  int r = 0;
-  while (r + 1 < nitems && items[r + 1].blk0 <= (int)blockIdx.x) ++r;
-  return r;
-}
-
-// per RVE: r = -r64 (active) or 0 (inactive), x = 0, partial sums of r.r
+// (block bodies in batch_cg.hpp)
 template <typename T>
 __global__ __launch_bounds__(kBlock) void cg_init_batch_kernel(
     const SegItem* __restrict__ items, int nitems, int64_t cs,
     const double* __restrict__ r64, T* __restrict__ r, T* __restrict__ x) {
-  __shared__ double red[kBlock];
-  const SegItem& it = items[seg_item(items, nitems)];
-  const bool act = !it.sc->inactive;
-  const int lb = blockIdx.x - it.blk0;
-  const int64_t nv = it.n9 / 9;
-  double acc = 0.0;
-  for (int64_t e = (int64_t)lb * blockDim.x + threadIdx.x; e < it.n9;
-       e += (int64_t)it.nblk * blockDim.x) {
-    const int64_t i = (e / nv) * cs + it.off + (e % nv);
-    const T b = act ? T(-r64[i]) : T(0);
-    r[i] = b;
-    x[i] = T(0);
-    acc += double(b) * double(b);
-  }
-  const double t = block_reduce(acc, red);
-  if (threadIdx.x == 0) it.partial[lb] = t;
+  __shared__ double red[kBlock / 64];
+  cg_init_batch_block<T>(items, nitems, cs, r64, r, x, blockIdx.x, red);
 }
 
 template <typename T>
@@ -454,23 +436,8 @@ __global__ __launch_bounds__(kBlock) void cg_update_batch_kernel(
     const SegItem* __restrict__ items, int nitems, int64_t cs,
     T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
     const T* __restrict__ Ap) {
-  __shared__ double red[kBlock];
-  const SegItem& it = items[seg_item(items, nitems)];
-  if (it.sc->done) return;
-  const T alpha = T(it.sc->alpha);
-  const int lb = blockIdx.x - it.blk0;
-  const int64_t nv = it.n9 / 9;
-  double acc = 0.0;
-  for (int64_t e = (int64_t)lb * blockDim.x + threadIdx.x; e < it.n9;
-       e += (int64_t)it.nblk * blockDim.x) {
-    const int64_t i = (e / nv) * cs + it.off + (e % nv);
-    x[i] += alpha * p[i];
-    const T rn = r[i] - alpha * Ap[i];
-    r[i] = rn;
-    acc += double(rn) * double(rn);
-  }
-  const double t = block_reduce(acc, red);
-  if (threadIdx.x == 0) it.partial[lb] = t;
+  __shared__ double red[kBlock / 64];
+  cg_update_batch_block<T>(items, nitems, cs, x, r, p, Ap, blockIdx.x, red);
 }
 
 template <typename T>
@@ -481,75 +448,67 @@ void launch_cg_update_batch(const SegItem* items, int nitems, int blocks,
                      0, s, items, nitems, cs, x, r, p, Ap);
 }
 
-// one block per RVE, same scalar logic as the single-RVE reduction
+// one block per RVE
 __global__ __launch_bounds__(kBlock) void reduce_batch_kernel(
     int op, const RedItem* __restrict__ items, Scalars* __restrict__ scs) {
-  __shared__ double red[kBlock];
-  const RedItem& it = items[blockIdx.x];
-  Scalars* sc = scs + blockIdx.x;
-  if (op == RED_RESID && sc->inactive) return;
-  if ((op == RED_ALPHA || op == RED_BETA) && sc->done) return;
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < it.count; i += blockDim.x) acc += it.partial[i];
-  const double tot = block_reduce(acc, red);
-  if (op == RED_RESID) {
-    double a2 = 0.0;
-    for (int i = threadIdx.x; i < 9 * it.nss; i += blockDim.x) a2 += it.psq[i];
-    const double P2 = block_reduce(a2, red);
-    for (int c = 0; c < 9; ++c) {
-      double a1 = 0.0;
-      for (int i = threadIdx.x; i < it.nss; i += blockDim.x)
-        a1 += it.psum[c * it.nss + i];
-      const double m = block_reduce(a1, red);
-      if (threadIdx.x == 0) sc->pbar[c] = m * it.invN3;
-    }
-    if (threadIdx.x == 0) {
-      sc->res2 = tot;
-      sc->P2 = P2;
-    }
-    return;
-  }
-  if (threadIdx.x != 0) return;
-  if (op == RED_INIT) {
-    sc->bb = tot;
-    sc->rr = tot;
-    sc->eta2bb = sc->eta2bb * tot;
-    sc->iters = 0;
-    sc->first = 1;
-    sc->breakdown = 0;
-    sc->converged = (tot == 0.0) ? 1 : 0;
-    sc->done = (sc->converged || sc->inactive) ? 1 : 0;
-    sc->alpha = 0.0;
-    sc->beta = 0.0;
-  } else if (op == RED_ALPHA) {
-    sc->pAp = tot;
-    if (!(tot > 0.0) || !isfinite(tot)) {
-      sc->breakdown = 1;
-      sc->done = 1;
-      sc->iters += 1;
-    } else {
-      sc->alpha = sc->rr / tot;
-    }
-  } else if (op == RED_BETA) {
-    sc->iters += 1;
-    sc->rr_new = tot;
-    sc->first = 0;
-    if (tot <= sc->eta2bb) {
-      sc->converged = 1;
-      sc->done = 1;
-    } else if (sc->iters >= sc->max_iters || !isfinite(tot)) {
-      sc->done = 1;
-    } else {
-      sc->beta = tot / sc->rr;
-      sc->rr = tot;
-    }
-  }
+  __shared__ double red[kBlock / 64];
+  reduce_batch_block(op, items, scs, blockIdx.x, red);
 }
 
 void launch_reduce_batch(int op, const RedItem* items, int nitems,
                          Scalars* scs, hipStream_t s) {
   hipLaunchKernelGGL(reduce_batch_kernel, dim3(nitems), dim3(kBlock), 0, s, op,
                      items, scs);
+}
+
+__global__ void newton_control_batch_kernel(Scalars* __restrict__ scs,
+                                            BatchLog* __restrict__ log,
+                                            int nitems, int it, NewtonCtl ctl) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nitems) return;
+  Scalars& sc = scs[b];
+  BatchLog& L = log[b];
+  if (L.status != 1) return;
+  if (it > 0) {  // the linear solve of the previous iteration
+    if (it - 1 < kBatchLog) L.cg_hist[it - 1] = sc.iters;
+    L.cg_total += sc.iters;
+    L.breakdowns += sc.breakdown ? 1 : 0;
+  }
+  const double res = sqrt(sc.res2), pn = sqrt(sc.P2);
+  const double rel = pn > 0.0 ? res / pn : 0.0;
+  if (it < kBatchLog) L.res_hist[it] = rel;
+  if (it == 0) L.predictor_rel = rel;
+  L.rel = rel;
+  for (int c = 0; c < 9; ++c) L.pbar[c] = sc.pbar[c];
+  L.newton_iters = it;
+  int st = 1;
+  if (sc.fails > 0) {
+    L.fails = sc.fails;
+    st = -5;   // RVE_ELOCAL
+  } else if (res <= ctl.newton_tol * pn) {
+    st = 0;    // RVE_OK
+    sc.commit = 1;
+  } else if (it >= ctl.newton_max) {
+    st = -4;   // RVE_ENOTCONV
+  }
+  L.status = st;
+  if (st != 1) {
+    sc.inactive = 1;
+    sc.done = 1;
+    return;
+  }
+  const double eta = forcing_eta(ctl.forcing, ctl.cg_tol, ctl.newton_tol, rel);
+  sc.max_iters = ctl.cg_max;
+  sc.eta2bb = eta * eta;
+  sc.done = 0;
+  sc.fails = 0;
+}
+
+void launch_newton_control_batch(Scalars* scs, BatchLog* log, int nitems,
+                                 int it, const NewtonCtl& ctl, hipStream_t s) {
+  hipLaunchKernelGGL(newton_control_batch_kernel,
+                     dim3((unsigned)((nitems + 63) / 64)), dim3(64), 0, s, scs,
+                     log, nitems, it, ctl);
 }
 
 __global__ void predict_batch_kernel(double* __restrict__ F,

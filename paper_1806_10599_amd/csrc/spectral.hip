@@ -20,6 +20,7 @@
 //
 // Only the delta_ik structure of the operator is used: row i of the output
 // depends on row i of the input, so pass B never needs all nine components.
+#include "batch_cg.hpp"
 #include "cg_scalars.hpp"
 #include "common.hpp"
 #include "fft.hpp"
@@ -507,20 +508,23 @@ __global__ __launch_bounds__(kBlock) void slab_inv_kernel(SlabInvArgs<T, TO> a) 
 #define RVE_BATCH_SIZES(X) X(16) X(24) X(32) X(40) X(48) X(64)
 
 template <typename T>
-__device__ __forceinline__ int batch_item(const BatchSpec<T>& b, int pass) {
-  const int blk = blockIdx.x;
+__device__ __forceinline__ int batch_item(const BatchSpec<T>& b, int pass,
+                                          int blk) {
   int r = 0;
   while (r + 1 < b.nitems && b.items[r + 1].blk[pass] <= blk) ++r;
   return r;
 }
 
+// Each pass as a block body (blk: the block it plays, a launch's blockIdx.x
+// or a virtual block of the persistent CG kernel) and a one-launch kernel.
 template <typename T, int SRC>
-__global__ __launch_bounds__(kBlock) void slab_fwd_batch_kernel(BatchSpec<T> b) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int r = batch_item(b, 0);
+__device__ __forceinline__ void slab_fwd_batch_block(const BatchSpec<T>& b,
+                                                     int blk,
+                                                     unsigned char* smem) {
+  const int r = batch_item(b, 0, blk);
   const SpecItem<T>& it = b.items[r];
   if (SRC == SRC_KP ? it.sc->done : it.sc->inactive) return;
-  const int lb = blockIdx.x - it.blk[0];
+  const int lb = blk - it.blk[0];
   SlabFwdArgs<T> a{};
   a.cs = b.cs;
   a.field = b.field ? b.field + it.off : nullptr;
@@ -547,14 +551,20 @@ __global__ __launch_bounds__(kBlock) void slab_fwd_batch_kernel(BatchSpec<T> b) 
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kBlock) void pencil_batch_kernel(BatchSpec<T> b,
-                                                              int cg) {
+template <typename T, int SRC>
+__global__ __launch_bounds__(kBlock) void slab_fwd_batch_kernel(BatchSpec<T> b) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int r = batch_item(b, 1);
+  slab_fwd_batch_block<T, SRC>(b, blockIdx.x, smem);
+}
+
+template <typename T>
+__device__ __forceinline__ void pencil_batch_block(const BatchSpec<T>& b,
+                                                   int cg, int blk,
+                                                   unsigned char* smem) {
+  const int r = batch_item(b, 1, blk);
   const SpecItem<T>& it = b.items[r];
   if (cg ? it.sc->done : it.sc->inactive) return;
-  const int lb = blockIdx.x - it.blk[1];
+  const int lb = blk - it.blk[1];
   PencilArgs<T> a{};
   a.spec = b.spec + it.soff;
   a.tw = it.tw;
@@ -573,14 +583,21 @@ __global__ __launch_bounds__(kBlock) void pencil_batch_kernel(BatchSpec<T> b,
   }
 }
 
-template <typename T, typename TO, int DST>
-__global__ __launch_bounds__(kBlock) void slab_inv_batch_kernel(BatchSpec<T> b,
-                                                                TO* out) {
+template <typename T>
+__global__ __launch_bounds__(kBlock) void pencil_batch_kernel(BatchSpec<T> b,
+                                                              int cg) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int r = batch_item(b, 0);
+  pencil_batch_block<T>(b, cg, blockIdx.x, smem);
+}
+
+template <typename T, typename TO, int DST>
+__device__ __forceinline__ void slab_inv_batch_block(const BatchSpec<T>& b,
+                                                     TO* out, int blk,
+                                                     unsigned char* smem) {
+  const int r = batch_item(b, 0, blk);
   const SpecItem<T>& it = b.items[r];
   if (DST == DST_DOT ? it.sc->done : it.sc->inactive) return;
-  const int lb = blockIdx.x - it.blk[0];
+  const int lb = blk - it.blk[0];
   SlabInvArgs<T, TO> a{};
   a.cs = b.cs;
   a.spec = b.spec + it.soff;
@@ -602,6 +619,174 @@ __global__ __launch_bounds__(kBlock) void slab_inv_batch_kernel(BatchSpec<T> b,
 #undef RVE_CASE
   }
 }
+
+template <typename T, typename TO, int DST>
+__global__ __launch_bounds__(kBlock) void slab_inv_batch_kernel(BatchSpec<T> b,
+                                                                TO* out) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  slab_inv_batch_block<T, TO, DST>(b, out, blockIdx.x, smem);
+}
+
+// ------------------------------------------------- persistent batched CG
+// The CG iterations of every RVE of a batch in one launch of resident
+// blocks: each iteration runs the three FFT/projection passes of G(K:p)
+// (p = r + beta p_old fused into the first), the per-RVE p.Ap reduction,
+// the vector update and the r.r reduction, each over all RVEs' blocks,
+// with a grid-wide barrier between them; it stops when every RVE's CG is
+// done (converged, broken down or at its cap).  A barrier that waits
+// beyond a bound (blocks not all resident) sets an error flag and lets the
+// kernel run out instead of hanging; the host turns the flag into an error.
+// Barrier state (unsigned words, one 128-byte line each part): [0] the
+// generation, [32 (1 + g)] the arrival count of group g = blockIdx.x % 8
+// (the hardware deals consecutive blocks round-robin over the eight XCDs),
+// [32 * 9] the count of groups arrived.  The last block of a group arrives
+// at the group count, the last group releases everyone by advancing the
+// generation: eight-way instead of all-block contention on one atomic.
+constexpr int kBarGroups = 8;
+static_assert(32 * (kBarGroups + 2) == kBatchBarWords, "barrier layout");
+
+__device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned nblocks,
+                                             int* err) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+      const unsigned g = blockIdx.x % kBarGroups;
+      const unsigned members =
+          nblocks / kBarGroups + (g < nblocks % kBarGroups ? 1u : 0u);
+      const unsigned groups = nblocks < kBarGroups ? nblocks : kBarGroups;
+      const unsigned gen =
+          __hip_atomic_load(&bar[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+      unsigned* gcount = bar + 32 * (1 + g);
+      unsigned* top = bar + 32 * (1 + kBarGroups);
+      const unsigned a = __hip_atomic_fetch_add(gcount, 1u, __ATOMIC_ACQ_REL,
+                                                __HIP_MEMORY_SCOPE_AGENT) + 1u;
+      bool release = false;
+      if (a == members) {
+        __hip_atomic_store(gcount, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned t = __hip_atomic_fetch_add(top, 1u, __ATOMIC_ACQ_REL,
+                                                  __HIP_MEMORY_SCOPE_AGENT) + 1u;
+        if (t == groups) {
+          __hip_atomic_store(top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELEASE,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+          release = true;
+        }
+      }
+      if (!release) {
+        // bounded wait (about a second); another block's timeout ends it too
+        long spins = 0;
+        while (__hip_atomic_load(&bar[0], __ATOMIC_ACQUIRE,
+                                 __HIP_MEMORY_SCOPE_AGENT) == gen) {
+          if (++spins > 2000000L) {
+            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+          }
+          if ((spins & 255) == 0 &&
+              __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            break;
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+    }
+    __threadfence();
+  }
+  __syncthreads();
+  return __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+}
+
+// the passes as calls (not inlined into one body, which would hold the
+// registers of all of them at once)
+template <typename T>
+__device__ __noinline__ void pc_slab_fwd(const BatchSpec<T>& b, int blk,
+                                         unsigned char* smem) {
+  slab_fwd_batch_block<T, SRC_KP>(b, blk, smem);
+}
+template <typename T>
+__device__ __noinline__ void pc_pencil(const BatchSpec<T>& b, int blk,
+                                       unsigned char* smem) {
+  pencil_batch_block<T>(b, 1, blk, smem);
+}
+template <typename T>
+__device__ __noinline__ void pc_slab_inv(const BatchSpec<T>& b, T* Ap, int blk,
+                                         unsigned char* smem) {
+  slab_inv_batch_block<T, T, DST_DOT>(b, Ap, blk, smem);
+}
+template <typename T>
+__device__ __noinline__ void pc_update(const BatchCG<T>& c, const T* p, int blk,
+                                       double* red) {
+  cg_update_batch_block<T>(c.seg, c.nitems, c.cs, c.x, c.r, p, c.Ap, blk, red);
+}
+__device__ __noinline__ void pc_reduce(int op, const RedItem* items,
+                                       Scalars* scs, int b, double* red) {
+  reduce_batch_block(op, items, scs, b, red);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void cg_batch_persistent_kernel(
+    BatchCG<T> c) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double red[kBlock / 64];
+  __shared__ int active;
+  for (int j = 0; j < c.max_iters; ++j) {
+    // every block takes the same decision from the same scalars
+    if (threadIdx.x == 0) active = 0;
+    __syncthreads();
+    for (int b = threadIdx.x; b < c.nitems; b += blockDim.x)
+      if (!c.scs[b].done) active = 1;
+    __syncthreads();
+    if (!active) break;
+    const BatchSpec<T>& b = (j & 1) ? c.odd : c.even;
+    for (int vb = blockIdx.x; vb < c.blocksA; vb += gridDim.x)
+      pc_slab_fwd<T>(b, vb, smem);
+    if (!grid_barrier(c.bar, gridDim.x, c.err)) return;
+    for (int vb = blockIdx.x; vb < c.blocksB; vb += gridDim.x)
+      pc_pencil<T>(b, vb, smem);
+    if (!grid_barrier(c.bar, gridDim.x, c.err)) return;
+    for (int vb = blockIdx.x; vb < c.blocksA; vb += gridDim.x)
+      pc_slab_inv<T>(b, c.Ap, vb, smem);
+    if (!grid_barrier(c.bar, gridDim.x, c.err)) return;
+    for (int r = blockIdx.x; r < c.nitems; r += gridDim.x)
+      pc_reduce(RED_ALPHA, c.red_inv, c.scs, r, red);
+    if (!grid_barrier(c.bar, gridDim.x, c.err)) return;
+    for (int vb = blockIdx.x; vb < c.seg_blocks; vb += gridDim.x)
+      pc_update<T>(c, b.p_new, vb, red);
+    if (!grid_barrier(c.bar, gridDim.x, c.err)) return;
+    for (int r = blockIdx.x; r < c.nitems; r += gridDim.x)
+      pc_reduce(RED_BETA, c.red_seg, c.scs, r, red);
+    if (!grid_barrier(c.bar, gridDim.x, c.err)) return;
+  }
+}
+
+template <typename T>
+void launch_cg_batch_persistent(const BatchCG<T>& c, int grid, size_t lds,
+                                hipStream_t s) {
+  hipLaunchKernelGGL((cg_batch_persistent_kernel<T>), dim3(grid), dim3(kBlock),
+                     lds, s, c);
+}
+
+template <typename T>
+int cg_batch_persistent_grid(size_t lds) {
+  int dev = 0, per_cu = 0;
+  RVE_HIP(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  RVE_HIP(hipGetDeviceProperties(&prop, dev));
+  RVE_HIP(hipFuncSetAttribute(
+      reinterpret_cast<const void*>(&cg_batch_persistent_kernel<T>),
+      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  RVE_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &per_cu, reinterpret_cast<const void*>(&cg_batch_persistent_kernel<T>),
+      kBlock, lds));
+  if (per_cu < 1) throw Error(-3, "persistent CG kernel does not fit a CU");
+  return per_cu * prop.multiProcessorCount;
+}
+
+template void launch_cg_batch_persistent<float>(const BatchCG<float>&, int,
+                                                size_t, hipStream_t);
+template void launch_cg_batch_persistent<double>(const BatchCG<double>&, int,
+                                                 size_t, hipStream_t);
+template int cg_batch_persistent_grid<float>(size_t);
+template int cg_batch_persistent_grid<double>(size_t);
 
 // ---------------------------------------------------------------- launchers
 // three component planes per slab block fit the LDS budget of one block

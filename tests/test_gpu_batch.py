@@ -173,3 +173,76 @@ def test_c4_batch_workload_first_increment():
             assert np.max(np.abs(s_b - s_s)) <= 1e-4 * np.max(np.abs(s_s))
     finally:
         b.close()
+
+
+@pytest.mark.parametrize("precision,forcing", [("fp64", 0), ("mixed", 2)])
+def test_device_controlled_batch_equals_host_driven(precision, forcing):
+    """use_graph: the Newton decisions taken on the device, each linear
+    solve of every RVE in one persistent launch (grid barriers between the
+    passes), the predictor and the first Newton iterations replayed from a
+    captured graph.  The arithmetic is that of the host-driven batch, so
+    the results are the same bits: statuses, Newton and CG counts, residual
+    histories and every committed field."""
+    micros = _micros()
+    hist = config_by_name("C1").history()[:6]
+    runs = []
+    for graph in (False, True):
+        b = _batch(micros, "discrete", precision, cg_forcing=forcing,
+                   use_graph=graph)
+        try:
+            infos = []
+            for inc in hist:
+                if inc["cycle_start"]:
+                    b.reset_fips()
+                infos.append(b.increment(inc["F_bar"], inc["dt"]))
+            fields = [{k: b.field(j, k) for k in ("F", "P", "chi", "pcyc",
+                                                  "wcyc", "dgamma")}
+                      for j in range(len(micros))]
+            runs.append((infos, fields))
+        finally:
+            b.close()
+    (ia, fa), (ib, fb) = runs
+    for xa, xb in zip(ia, ib):
+        for a, c in zip(xa, xb):
+            assert a["status"] == c["status"] == 0
+            for k in ("newton_iters", "cg_iters_total", "cg_iters",
+                      "residuals"):
+                assert a[k] == c[k], k
+            assert np.array_equal(a["sigma_bar"], c["sigma_bar"])
+    for da, db in zip(fa, fb):
+        for k in da:
+            assert np.array_equal(da[k], db[k]), k
+
+
+def test_device_controlled_batch_past_the_captured_iterations():
+    """A tight tolerance needs more Newton iterations than the captured
+    graph holds: the rest run one at a time, the same bits as host-driven;
+    and a Newton budget below the graph's iterations stops there."""
+    micros = _micros()[:2]
+    hist = config_by_name("C1").history()[:2]
+    runs = []
+    for graph in (False, True):
+        b = _batch(micros, "discrete", "fp64", newton_tol=1e-12, cg_tol=1e-10,
+                   newton_max_iter=40, cg_max_iter=5000, use_graph=graph)
+        try:
+            infos = [b.increment(inc["F_bar"], inc["dt"]) for inc in hist]
+            runs.append((infos, [b.field(j, "F") for j in range(2)]))
+        finally:
+            b.close()
+    (ia, fa), (ib, fb) = runs
+    assert max(i["newton_iters"] for x in ib for i in x) > 4
+    for xa, xb in zip(ia, ib):
+        for a, c in zip(xa, xb):
+            assert a["status"] == c["status"] == 0
+            assert a["newton_iters"] == c["newton_iters"]
+            assert a["residuals"] == c["residuals"]
+    for a, c in zip(fa, fb):
+        assert np.array_equal(a, c)
+    b = _batch(micros, "discrete", "fp64", newton_tol=1e-12, cg_tol=1e-10,
+               newton_max_iter=2, use_graph=True)
+    try:
+        infos = b.increment(hist[0]["F_bar"], hist[0]["dt"])
+        assert all(i["status"] == -4 and i["newton_iters"] == 2 for i in infos)
+        assert b.macro(0)["increments"] == 0
+    finally:
+        b.close()
