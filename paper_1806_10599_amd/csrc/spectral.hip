@@ -685,7 +685,7 @@ __device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned nblocks,
           if ((spins & 255) == 0 &&
               __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
             break;
-          __builtin_amdgcn_s_sleep(1);
+          __builtin_amdgcn_s_sleep(8);
         }
       }
     }
