@@ -18,7 +18,9 @@ increment:
 * mixed precision at 1e-6 (plain, and the configuration the benchmark
   times: learned start kept directly, inexact-Newton forcing) to 1e-4 on the
   macroscopic loop (Eq. 29) and 1e-3 on the indicator fields (Eq. 30) over
-  the whole cycle.
+  the whole cycle; the 64^3 workload's first three increments, FP64 and
+  the benchmarked configuration, against stored oracle values
+  (tests/golden/make_c3_start.py).
 * G (Eq. 11) element by element at the largest grid (128^3) for both
   operators, and through the batched passes at every batch edge.
 
@@ -302,4 +304,68 @@ def test_c2_through_first_reversal_matches_stored_oracle():
         for name in ("pcyc", "pcyc_lit"):
             _close(got[name][idx], g[name], 1e-10, name)
     finally:
+        r.close()
+
+
+@pytest.mark.parametrize("path", ["fp64", "chosen"])
+def test_c3_start_against_stored_oracle(path):
+    """The 64^3 workload (200 grains, 8 % particles, discrete operator of
+    Eq. 21) over the first three increments of its cycle, when plastic slip
+    has spread to most voxels, against the oracle's stored solution at an
+    equilibrium tolerance of 1e-9 (tests/golden/make_c3_start.py).
+
+    chosen: the configuration the benchmark times (mixed precision at 1e-6,
+    learned start kept directly, forcing mode 2, CG chunks of 8) held to
+    Eq. 29 (<= 1e-4 on sigma_11 and on every entry of the macroscopic
+    stress at every increment) and Eq. 30 (<= 1e-3 on F, P, both forms of
+    P_cyc and every system's W_cyc at 4096 sampled voxels).
+    fp64: the FP64 path at 1e-12 to 1e-8 relative, ten times the oracle's
+    own 1e-9 equilibrium tolerance (its solution is only that close to the
+    exact one)."""
+    from paper_1806_10599_amd.binding import WarmStartNet
+    from paper_1806_10599_amd.warmstart import trained_params
+    from synthetic import config_by_name
+    g = np.load(os.path.join(HERE, "golden", "c3_start.npz"))
+    c = config_by_name("C3")
+    micro = c.microstructure()
+    hist = c.history()[:len(g["k"])]
+    idx = g["idx"]
+    net = None
+    if path == "chosen":
+        r = make_rve(micro, c.operator, "mixed", newton_tol=1e-6,
+                     warm_start=2, cg_forcing=2, cg_chunk=8)
+        net = WarmStartNet()
+        net.set_params(trained_params())
+        r.attach_warm_start(net)
+        tol29, tol30 = 1e-4, 1e-3
+    else:
+        r = make_rve(micro, c.operator, "fp64", **TIGHT)
+        tol29 = tol30 = 1e-8
+    try:
+        s = []
+        for k, inc in enumerate(hist):
+            info = r.increment(inc["F_bar"], inc["dt"])
+            assert info["status"] == 0
+            s.append(info["sigma_bar"].reshape(9))
+            print(f"C3 {path} increment {inc['k']}: newton "
+                  f"{info['newton_iters']} cg {info['cg_iters_total']}",
+                  flush=True)
+        s = np.asarray(s)
+        e11 = _eq29(s[:, 0], g["sigma_bar"][:, 0])
+        eall = _eq29(s, g["sigma_bar"])
+        got = r.fields("F", "P", "pcyc", "pcyc_lit", "wcyc")
+        e30 = {k: _eq30(got[k][:, idx].T, g[k]) for k in ("F", "P")}
+        for k in ("pcyc", "pcyc_lit"):
+            e30[k] = _eq30(got[k][idx], g[k])
+        e30["wcyc"] = max(_eq30(got["wcyc"][a, idx], g["wcyc"][:, a])
+                          for a in range(12))
+        print(f"C3 {path}: Eq. 29 sigma_11 {e11:.2e}, all entries {eall:.2e};"
+              " Eq. 30 " + ", ".join(f"{k} {v:.2e}" for k, v in e30.items()))
+        assert e11 < tol29 and eall < tol29, (e11, eall)
+        for k, v in e30.items():
+            assert v < tol30, (k, v)
+    finally:
+        if net is not None:
+            r.attach_warm_start(None)
+            net.close()
         r.close()
