@@ -53,6 +53,23 @@ PASS_BYTES_F32 = {
     "matvec_pass_b": 36 + 36,                       # spectrum in and out
     "matvec_pass_c": 36 + 4 * 9 + 4 * 9,            # spectrum, r in; r out
 }
+# the same with the direction step and K:p folded into pass A (fused
+# schedule): K, r, p_old, x in; p, x, half spectrum out; no K:p round trip
+PASS_BYTES_F32_FUSED = {
+    "matvec_pass_a": 4 * (81 + 9 + 9 + 9 + 9 + 9) + 36,
+    "matvec_pass_b": 36 + 36,
+    "matvec_pass_c": 36 + 4 * 9 + 4 * 9,
+}
+
+
+def pass_bytes(fused):
+    return PASS_BYTES_F32_FUSED if fused else PASS_BYTES_F32
+
+
+def live_classes(fused):
+    """Kernel classes timed live in the timed region: the once-per-Newton
+    kernels and the K:p kernel (pass A when K:p is folded into it)."""
+    return LIVE_CLASSES[:3] + (("matvec_pass_a",) if fused else ("matvec_kp",))
 # algorithmic flops of the return mapping (add, mul, div, sqrt and each
 # elementary function count 1, a fused multiply-add 2; counted once per voxel
 # from the algorithm, not from the instruction stream), FP64 and FP32 apart:
@@ -217,8 +234,9 @@ def run_path(micro, hist, precision, use_graph, steps, warmup, stream,
                                   int(hist[start - 1]["k"])],
                       timing=r.kernel_timing(reset=True), cg_total=sample_cg)
         r.set_kernel_timing(())
+    fused = bool(r.fft_schedule()["fused"])
     if live:
-        r.set_kernel_timing(LIVE_CLASSES)
+        r.set_kernel_timing(live_classes(fused))
     torch.cuda.synchronize()
     r.kernel_timing(reset=True)
     r.return_map_counts(reset=True)
@@ -253,7 +271,8 @@ def run_path(micro, hist, precision, use_graph, steps, warmup, stream,
     counts = r.return_map_counts() if live else None
     sched = r.fft_schedule()
     nonlocal_ = nonlocal_fips_report(r, micro.n) if with_fips else None
-    passes = (cg_pass_report(r.bench_kernels(reps=50), micro.n ** 3)
+    passes = (cg_pass_report(r.bench_kernels(reps=50), micro.n ** 3,
+                             sched["fused"])
               if precision == "mixed" and with_fips else None)
     sig = [i["sigma_bar"][0, 0] for i in timed]
     if net is not None:
@@ -265,23 +284,26 @@ def run_path(micro, hist, precision, use_graph, steps, warmup, stream,
                 passes=passes, check=chk, sample=sample)
 
 
-def cg_pass_report(kern, N):
+def cg_pass_report(kern, N, fused=False):
     """Achieved bandwidth of the CG-iteration kernels (FP32) from
     back-to-back launches with the solver's launch configuration and the
     tuned FFT schedule, on the buffers of the last increment (after the
     timed window): algorithmic bytes per launch / average duration."""
     out = {}
-    for k, b in PASS_BYTES_F32.items():
+    pb = pass_bytes(fused)
+    for k, b in pb.items():
         ms = kern[k]
         gbs = N * b / (ms * 1e-3) / 1e9
         out[k] = dict(us=round(1e3 * ms, 2), bytes_per_voxel=b,
                       gbps=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 3))
     mv = ("matvec_pass_a", "matvec_pass_b", "matvec_pass_c")
     ms = sum(kern[k] for k in mv)
-    gbs = N * sum(PASS_BYTES_F32[k] for k in mv) / (ms * 1e-3) / 1e9
+    gbs = N * sum(pb[k] for k in mv) / (ms * 1e-3) / 1e9
     out["fft_projection_passes"] = dict(us=round(1e3 * ms, 2), gbps=round(gbs, 1),
                                         frac=round(gbs / HBM_PEAK_GBS, 3))
-    ms_all = sum(kern[k] for k in PASS_BYTES_F32)
+    if fused:
+        out["fft_projection_passes"]["includes"] = "direction step and K:p (pass A)"
+    ms_all = sum(kern[k] for k in pb)
     out["cg_iteration_us"] = round(1e3 * ms_all, 2)
     return out
 
@@ -326,6 +348,7 @@ def batch_run(steps, stream):
                  use_graph=False, stream=stream, cg_forcing=FORCING)
     for j, m in enumerate(micros):
         b.set_microstructure(j, m.phase, m.quat, m.law, material_params())
+    b.tune_fft_schedules()   # per edge, outside the timed increments
     newton = []
     t_batch = 0.0
     # timed as two bracketed intervals (increments 1..K-1 and K) so that
@@ -348,6 +371,7 @@ def batch_run(steps, stream):
                F=b.field(0, "F"), P=b.field(0, "P"), dg=b.field(0, "dgamma"),
                residual_rel=infos[0]["residual_rel"])
     sig_b = [b.macro(j)["sigma_bar"][0, 0] for j in range(len(micros))]
+    scheds = {str(e): v for e, v in b.fft_schedules().items()}
     # statistical volume element: Eqs. 25-26 per RVE, mean and standard
     # deviation over the RVEs (bands two voxel edges wide)
     fb = [b.nonlocal_fips(j, arrays=False) for j in range(len(micros))]
@@ -366,6 +390,7 @@ def batch_run(steps, stream):
                   use_graph=True, stream=stream, cg_forcing=FORCING)
     for j, m in enumerate(micros):
         bd.set_microstructure(j, m.phase, m.quat, m.law, material_params())
+    bd.tune_fft_schedules()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for inc in hist:
@@ -381,6 +406,7 @@ def batch_run(steps, stream):
         r = Rve(m.n, projection=cfg.operator, precision=cfg.precision,
                 newton_tol=1e-6, cg_tol=1e-4, stream=stream, cg_forcing=FORCING)
         r.set_microstructure(m.phase, m.quat, m.law, material_params())
+        r.tune_fft_schedule()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for inc in hist:
@@ -401,6 +427,7 @@ def batch_run(steps, stream):
             "max_newton_per_increment": float(np.mean(newton)),
             "launches": ("one launch per pass for the whole batch, Newton "
                          "decisions and CG chunk checks on the host"),
+            "fft_schedules": scheds,
             "persistent_graph": {
                 "persistent": True,
                 "graph": ("predictor and the first four Newton iterations "
@@ -516,6 +543,7 @@ def _run_history(micro, hist, precision, operator, stream, adaptive=False,
         net.set_params(trained_params())
         r.attach_warm_start(net)
     sig, newton, cg, sub, cuts = [], 0, 0, 0, 0
+    r.tune_fft_schedule()   # outside the timed history
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for inc in hist:
@@ -879,16 +907,20 @@ def gpu_c1_history(stream):
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_traffic_c3_64cubed.json")
 
 
-def pmc_traffic(kernel):
+def pmc_traffic(kernel, fused=False):
     """HBM bytes per dispatch of a kernel class from the committed
     FETCH_SIZE/WRITE_SIZE runs (scaled by the copy-kernel calibration), or
-    None when there is no such measurement or the kernel's source file has
-    changed since it was taken."""
+    None when there is no such measurement, the kernel's source file has
+    changed since it was taken, or the CG schedule (K:p folded into pass A
+    or not) differs from the measured one."""
     import hashlib
     try:
         with open(PMC_SUMMARY) as f:
             summ = json.load(f)
         k = summ["kernels"][kernel]
+        if (kernel.startswith("matvec_")
+                and bool(summ.get("fused", False)) != bool(fused)):
+            return None
         with open(os.path.join(ROOT, k["source"]), "rb") as f:
             if hashlib.sha256(f.read()).hexdigest() != k["source_sha256"]:
                 return None
@@ -897,7 +929,7 @@ def pmc_traffic(kernel):
         return None
 
 
-def live_report(live, rmc, N, cg_total, sample=None):
+def live_report(live, rmc, N, cg_total, sample=None, fused=False):
     """Per-kernel live durations, FFT bandwidth and the dominant kernel's
     roofline from the event timings of the timed region.  The dominant
     kernel is the one with the largest total time per increment over the
@@ -906,6 +938,7 @@ def live_report(live, rmc, N, cg_total, sample=None):
     would cost several per cent of the throughput); its roofline uses the
     timed region's live durations when it is timed there, else the
     sample's."""
+    pb = pass_bytes(fused)
     avg_ms = {k: (ms / n if n else None) for k, (ms, n) in live.items()}
     total_ms = {k: ms for k, (ms, n) in live.items()}
     launches = {k: n for k, (ms, n) in live.items()}
@@ -914,7 +947,7 @@ def live_report(live, rmc, N, cg_total, sample=None):
     # return at once and move nothing)
     mv = ("matvec_pass_a", "matvec_pass_b", "matvec_pass_c")  # FFT passes
     mv_ms = sum(total_ms[k] for k in mv)
-    fft_gbs = (N * cg_total * sum(PASS_BYTES_F32[k] for k in mv)
+    fft_gbs = (N * cg_total * sum(pb[k] for k in mv)
                / (mv_ms * 1e-3) / 1e9) if all(launches[k] for k in mv) else None
     rm_f64 = (RM_FLOPS["eval64"] * rmc["evals"] + RM_FLOPS["step64"] * rmc["steps"]
               + RM_FLOPS["crystal64"] * rmc["crystal"]
@@ -923,11 +956,11 @@ def live_report(live, rmc, N, cg_total, sample=None):
     rm_flops = rm_f64 + rm_f32
 
     def hbm(k):
-        per_launch = N * PASS_BYTES_F32[k] * cg_total / launches[k]
+        per_launch = N * pb[k] * cg_total / launches[k]
         ach = per_launch / (avg_ms[k] * 1e-3) / 1e9
         return dict(kernel=k, bound="hbm", achieved=round(ach, 1),
                     peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(ach / HBM_PEAK_GBS, 4), traffic=pmc_traffic(k),
+                    frac=round(ach / HBM_PEAK_GBS, 4), traffic=pmc_traffic(k, fused),
                     bytes_per_launch=round(per_launch), avg_ms=round(avg_ms[k], 5),
                     launches=launches[k])
 
@@ -955,18 +988,18 @@ def live_report(live, rmc, N, cg_total, sample=None):
         share = {k: round(v / tot, 4) for k, v in
                  sorted(st.items(), key=lambda kv: -kv[1])}
         dom = max(st, key=lambda k: st[k])
-    if dom in LIVE_CLASSES or sample is None:
-        roof = (hbm(dom) if dom in PASS_BYTES_F32 else
+    if dom in live_classes(fused) or sample is None:
+        roof = (hbm(dom) if dom in pb else
                 (alu() if dom == "return_map" else None))
         if roof is not None:
             roof["timed_over"] = "timed region (HIP events per launch)"
     else:
         ms, n = sample["timing"][dom]
-        per_launch = N * PASS_BYTES_F32[dom] * sample["cg_total"] / n
+        per_launch = N * pb[dom] * sample["cg_total"] / n
         ach = per_launch / (ms / n * 1e-3) / 1e9
         roof = dict(kernel=dom, bound="hbm", achieved=round(ach, 1),
                     peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(ach / HBM_PEAK_GBS, 4), traffic=pmc_traffic(dom),
+                    frac=round(ach / HBM_PEAK_GBS, 4), traffic=pmc_traffic(dom, fused),
                     bytes_per_launch=round(per_launch),
                     avg_ms=round(ms / n, 5), launches=n,
                     timed_over=("increments %d-%d before the timed region, "
@@ -985,7 +1018,7 @@ def live_report(live, rmc, N, cg_total, sample=None):
     if share is not None:
         rep["kernel_time_share_sample"] = dict(
             increments=sample["increments"], share=share)
-    for k in PASS_BYTES_F32:
+    for k in pb:
         if launches[k] and k != dom:
             rep[k + "_roofline"] = hbm(k)
     if launches["return_map"] and dom != "return_map":
@@ -1102,7 +1135,8 @@ def main():
     live = chosen["live"]
     if live is not None:
         out.update(live_report(live, chosen["rm_counts"], N, cg_total,
-                               chosen["sample"]))
+                               chosen["sample"],
+                               bool(chosen["schedule"]["fused"])))
     if out.get("fft_gbps") is None and chosen["passes"]:
         out["fft_gbps"] = chosen["passes"]["fft_projection_passes"]["gbps"]
     if plain is not None:

@@ -424,17 +424,28 @@ rve_status rve_get_kernel_timing(rve_t h, double* ms_total, int64_t* launches,
    and whenever bit 4 is switched on. */
 rve_status rve_get_return_map_counts(rve_t h, int64_t out[4], int32_t reset);
 
-/* FFT schedule of the CG matvec (Sec. 2.1, Eq. 16): cpb components of the
-   tensor field per slab block in the z/y-transform passes (1 or 3) and tt
-   kz columns per block in the x-transform and projection pass (4, 8 or 16).
-   By default (0, 0) the handle times every valid schedule once on its own
-   buffers at the first CG solve and keeps the fastest.  rve_set_fft_schedule
-   forces one (or (0, 0) to tune again); RVE_EINVAL when the schedule does
-   not exist for the grid and precision.  rve_get_fft_schedule returns the
-   schedule in use (zeros before the first solve) and, in *ms (nullable),
-   the tuned matvec time in milliseconds (0 when forced). */
-rve_status rve_set_fft_schedule(rve_t h, int32_t cpb, int32_t tt);
-rve_status rve_get_fft_schedule(rve_t h, int32_t out[2], double* ms);
+/* Schedule of the CG matvec G(K : p) (Sec. 2.1, Eqs. 15-16): cpb
+   components of the tensor field per slab block in the z/y-transform
+   passes (1 or 3), tt kz columns per block in the x-transform and
+   projection pass (4, 8 or 16), and fused (0 or 1): whether the CG
+   direction step and K : p run in their own streaming kernel (0) or inside
+   the first transform pass (1), which then forms p = r + beta p_old for
+   all nine components of each voxel of its slab and transforms its own
+   rows of K : p.  Both give the same CG up to the order of the FP64 sum of
+   p . (K:p).  By default (0, 0, -) the handle times every valid schedule
+   once on its own buffers at the first CG solve and keeps the fastest.
+   rve_set_fft_schedule forces one (or (0, 0, -) to tune again);
+   RVE_EINVAL when the schedule does not exist for the grid and precision or
+   fused is not 0 or 1.  rve_get_fft_schedule writes (cpb, tt, fused) in use
+   (zeros before the first solve) and, in *ms (nullable), the tuned matvec
+   time in milliseconds (0 when forced). */
+rve_status rve_set_fft_schedule(rve_t h, int32_t cpb, int32_t tt,
+                                int32_t fused);
+rve_status rve_get_fft_schedule(rve_t h, int32_t out[3], double* ms);
+/* Tunes the schedule now (as the first CG solve would) on the handle's
+   buffers, so that a timed run does not include the tuning; the vectors it
+   touches are rewritten by the next solve.  Replaces a forced schedule. */
+rve_status rve_tune_fft_schedule(rve_t h);
 
 /* ---- learned warm start -------------------------------------------------
    A small network predicts the fluctuation increment of the next load
@@ -567,6 +578,23 @@ rve_status rve_batch_get_macro(rve_batch_t h, int32_t b, double out[29]);
    (NULL pointers). */
 rve_status rve_batch_debug_apply_G(rve_batch_t h, const double* in,
                                    double* out);
+/* Per-grid-edge schedule of the batched CG matvec (Sec. 2.1, Eqs. 15-16):
+   cpb components per slab block (1 or 3) and tt kz columns per pencil block
+   (4, 8 or 16), as for a single RVE (the direction step is always part of
+   the first pass in a batch).  Unless forced, every edge of the batch is
+   tuned at the first increment (or by rve_batch_tune_fft_schedule): each
+   valid candidate times one matvec of that edge's RVEs alone through the
+   batched passes, and the fastest is kept.  rve_batch_set_fft_schedule
+   forces edge's schedule, or with (0, 0) tunes it again at the next
+   increment; rve_batch_get_fft_schedule writes edge's (cpb, tt) and in *ms
+   (nullable) the tuned matvec time of its RVEs in milliseconds (0 when
+   forced or not tuned yet).  Errors: RVE_EINVAL (no RVE of that edge in
+   the batch, a schedule that does not exist for it, NULL out). */
+rve_status rve_batch_tune_fft_schedule(rve_batch_t h);
+rve_status rve_batch_set_fft_schedule(rve_batch_t h, int32_t edge,
+                                      int32_t cpb, int32_t tt);
+rve_status rve_batch_get_fft_schedule(rve_batch_t h, int32_t edge,
+                                      int32_t out[2], double* ms);
 
 /* Host only (no device work, no GPU needed): the band lists that
    rve_get_nonlocal_fips uses, for a microstructure of n^3 voxels (phase,

@@ -154,7 +154,8 @@ def _load():
                                             C.c_int32]),
         "rve_get_return_map_counts": (C.c_int, [C.c_void_p, P(C.c_int64),
                                                 C.c_int32]),
-        "rve_set_fft_schedule": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+        "rve_set_fft_schedule": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32,
+                                           C.c_int32]),
         "rve_get_fft_schedule": (C.c_int, [C.c_void_p, P(C.c_int32),
                                            P(C.c_double)]),
         "rve_ws_create": (C.c_int, [P(RveWsConfig), P(C.c_void_p)]),
@@ -198,6 +199,12 @@ def _load():
                                            C.c_void_p, C.c_size_t, C.c_int32]),
         "rve_batch_debug_apply_G": (C.c_int, [C.c_void_p, P(C.c_double),
                                               P(C.c_double)]),
+        "rve_tune_fft_schedule": (C.c_int, [C.c_void_p]),
+        "rve_batch_tune_fft_schedule": (C.c_int, [C.c_void_p]),
+        "rve_batch_set_fft_schedule": (C.c_int, [C.c_void_p, C.c_int32,
+                                                 C.c_int32, C.c_int32]),
+        "rve_batch_get_fft_schedule": (C.c_int, [C.c_void_p, C.c_int32,
+                                                 P(C.c_int32), P(C.c_double)]),
         "rve_apply_G_noalloc": (C.c_int, [C.c_int32, P(C.c_double), C.c_int32,
                                           C.c_void_p, C.c_void_p,
                                           C.c_void_p]),
@@ -588,15 +595,21 @@ class Rve:
         return dict(steps=out[0], evals=out[1], crystal=out[2],
                     particle=out[3])
 
-    def set_fft_schedule(self, cpb=0, tt=0):
-        """Force the CG-matvec FFT schedule; (0, 0) tunes it again."""
-        self._check(LIB.rve_set_fft_schedule(self._h, int(cpb), int(tt)))
+    def set_fft_schedule(self, cpb=0, tt=0, fused=0):
+        """Force the CG-matvec schedule (fused: the direction step and K:p
+        inside the first transform pass); (0, 0) tunes it again."""
+        self._check(LIB.rve_set_fft_schedule(self._h, int(cpb), int(tt),
+                                             int(fused)))
+
+    def tune_fft_schedule(self):
+        """Tune the CG-matvec schedule now (outside a timed run)."""
+        self._check(LIB.rve_tune_fft_schedule(self._h))
 
     def fft_schedule(self):
-        out = (C.c_int32 * 2)()
+        out = (C.c_int32 * 3)()
         ms = C.c_double()
         self._check(LIB.rve_get_fft_schedule(self._h, out, C.byref(ms)))
-        return dict(cpb=out[0], tt=out[1], tuned_ms=ms.value)
+        return dict(cpb=out[0], tt=out[1], fused=out[2], tuned_ms=ms.value)
 
     def attach_warm_start(self, net):
         self._check(LIB.rve_attach_warm_start(self._h, net._h if net else None))
@@ -773,6 +786,27 @@ class BatchRve:
         for n in self.ns:
             res.append(out[pos:pos + 9 * n ** 3].reshape(9, n ** 3))
             pos += 9 * n ** 3
+        return res
+
+    def tune_fft_schedules(self):
+        """Tune every edge's CG-matvec schedule now (outside a timed run)."""
+        self._check(LIB.rve_batch_tune_fft_schedule(self._h))
+
+    def set_fft_schedule(self, edge, cpb=0, tt=0):
+        """Force the CG-matvec schedule of one grid edge; (0, 0) tunes it
+        again at the next increment."""
+        self._check(LIB.rve_batch_set_fft_schedule(self._h, int(edge),
+                                                   int(cpb), int(tt)))
+
+    def fft_schedules(self):
+        """{edge: dict(cpb, tt, tuned_ms)} for every edge of the batch."""
+        res = {}
+        for e in sorted(set(self.ns)):
+            out = (C.c_int32 * 2)()
+            ms = C.c_double()
+            self._check(LIB.rve_batch_get_fft_schedule(self._h, e, out,
+                                                       C.byref(ms)))
+            res[e] = dict(cpb=out[0], tt=out[1], tuned_ms=ms.value)
         return res
 
     def macro(self, b):

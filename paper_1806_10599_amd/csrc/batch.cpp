@@ -7,6 +7,7 @@
 #include "newton.hpp"
 
 #include <algorithm>
+#include <type_traits>
 
 #include <array>
 #include <chrono>
@@ -97,10 +98,11 @@ BatchEngine::BatchEngine(const rve_config& cfg, int count, const int32_t* n)
 
   // per-RVE FFT tables and descriptors
   std::vector<double> tw64, vt64;
-  std::vector<int64_t> twoff(B_), vtoff(B_);
+  twoff_.resize(B_);
+  vtoff_.resize(B_);
   for (int b = 0; b < B_; ++b) {
-    twoff[b] = tw64.size() / 2;
-    vtoff[b] = vt64.size();
+    twoff_[b] = tw64.size() / 2;
+    vtoff_[b] = vt64.size();
     std::vector<double> t = twiddles(n_[b]);
     std::vector<double> v = wave_vectors(n_[b], cfg_.L, cfg_.projection);
     tw64.insert(tw64.end(), t.begin(), t.end());
@@ -120,12 +122,10 @@ BatchEngine::BatchEngine(const rve_config& cfg, int count, const int32_t* n)
   for (int b = 0; b < B_; ++b) psn += 9 * n_[b];
   psum_ = (double*)alloc(psn * sizeof(double));
   psq_ = (double*)alloc(psn * sizeof(double));
-  // partial arenas: pass-C partials per RVE, then elementwise partials
+  // partial arenas: pass-C partials per RVE (room for one component per
+  // slab block, any schedule), then elementwise partials
   int64_t ppass = 0;
-  for (int b = 0; b < B_; ++b) {
-    const int a32 = slab_blocks(n_[b], false), a64 = slab_blocks(n_[b], true);
-    ppass += a32 > a64 ? a32 : a64;
-  }
+  for (int b = 0; b < B_; ++b) ppass += 9 * n_[b];
   std::vector<SegItem> seg(B_);
   int segb = 0;
   for (int b = 0; b < B_; ++b) {
@@ -140,74 +140,29 @@ BatchEngine::BatchEngine(const rve_config& cfg, int count, const int32_t* n)
   }
   seg_blocks_ = segb;
   partials_ = (double*)alloc((ppass + segb) * sizeof(double));
-  std::vector<SpecItem<float>> it32(B_);
-  std::vector<SpecItem<double>> it64(B_);
-  std::vector<RedItem> ri32(B_), ri64(B_), rseg(B_);
-  int a32 = 0, b32 = 0, a64 = 0, b64 = 0;
-  int64_t pp = 0, pso = 0;
-  ldsA32_ = ldsB32_ = ldsA64_ = ldsB64_ = 0;
-  for (int b = 0; b < B_; ++b) {
-    const int nb = n_[b];
-    const int64_t Nb = (int64_t)nb * nb * nb;
-    const int sA32 = slab_blocks(nb, false), sA64 = slab_blocks(nb, true);
-    auto fill = [&](auto& it, int& accA, int& accB, int sA, bool dbl) {
-      it.n = nb;
-      it.blk[0] = accA;
-      it.blk[1] = accB;
-      it.off = off_[b];
-      it.soff = soff_[b];
-      it.sc = sc_ + b;
-      it.partial = partials_ + pp;
-      it.psum = psum_ + pso;
-      it.psq = psq_ + pso;
-      accA += sA;
-      accB += pencil_blocks(nb, dbl);
-    };
-    fill(it32[b], a32, b32, sA32, false);
-    fill(it64[b], a64, b64, sA64, true);
-    it32[b].tw = (const cplx<float>*)tw32_ + twoff[b];
-    it64[b].tw = (const cplx<double>*)tw64_ + twoff[b];
-    it32[b].vt = (const float*)vt32_ + vtoff[b];
-    it64[b].vt = (const double*)vt64_ + vtoff[b];
-    ri32[b] = RedItem{partials_ + pp, sA32, psum_ + pso, psq_ + pso, nb, 1.0 / (double)Nb};
-    ri64[b] = RedItem{partials_ + pp, sA64, psum_ + pso, psq_ + pso, nb, 1.0 / (double)Nb};
-    pp += sA32 > sA64 ? sA32 : sA64;
-    pso += 9 * nb;
-    size_t s1, s2;
-    batch_lds<float>(nb, s1, s2);
-    ldsA32_ = s1 > ldsA32_ ? s1 : ldsA32_;
-    ldsB32_ = s2 > ldsB32_ ? s2 : ldsB32_;
-    batch_lds<double>(nb, s1, s2);
-    ldsA64_ = s1 > ldsA64_ ? s1 : ldsA64_;
-    ldsB64_ = s2 > ldsB64_ ? s2 : ldsB64_;
-  }
+  std::vector<RedItem> rseg(B_);
   for (int b = 0; b < B_; ++b) {
     seg[b].partial = partials_ + ppass + seg[b].blk0;
     seg[b].sc = sc_ + b;
     rseg[b] = RedItem{seg[b].partial, seg[b].nblk, nullptr, nullptr, 0, 0.0};
   }
-  if (ldsA32_ > 65536 || ldsB32_ > 65536) batch_allow_lds<float>(ldsA32_, ldsB32_);
-  if (ldsA64_ > 65536 || ldsB64_ > 65536) batch_allow_lds<double>(ldsA64_, ldsB64_);
-  blocksA32_ = a32;
-  blocksB32_ = b32;
-  blocksA64_ = a64;
-  blocksB64_ = b64;
   items32_ = alloc(B_ * sizeof(SpecItem<float>));
   items64_ = alloc(B_ * sizeof(SpecItem<double>));
+  tune_items_ = alloc(B_ * std::max(sizeof(SpecItem<float>), sizeof(SpecItem<double>)));
   seg_ = (SegItem*)alloc(B_ * sizeof(SegItem));
   red_inv32_ = (RedItem*)alloc(B_ * sizeof(RedItem));
   red_inv64_ = (RedItem*)alloc(B_ * sizeof(RedItem));
   red_seg_ = (RedItem*)alloc(B_ * sizeof(RedItem));
-  RVE_HIP(hipMemcpyAsync(items32_, it32.data(), B_ * sizeof(SpecItem<float>), hipMemcpyHostToDevice, st_));
-  RVE_HIP(hipMemcpyAsync(items64_, it64.data(), B_ * sizeof(SpecItem<double>), hipMemcpyHostToDevice, st_));
   RVE_HIP(hipMemcpyAsync(seg_, seg.data(), B_ * sizeof(SegItem), hipMemcpyHostToDevice, st_));
-  RVE_HIP(hipMemcpyAsync(red_inv32_, ri32.data(), B_ * sizeof(RedItem), hipMemcpyHostToDevice, st_));
-  RVE_HIP(hipMemcpyAsync(red_inv64_, ri64.data(), B_ * sizeof(RedItem), hipMemcpyHostToDevice, st_));
   RVE_HIP(hipMemcpyAsync(red_seg_, rseg.data(), B_ * sizeof(RedItem), hipMemcpyHostToDevice, st_));
   std::vector<uint8_t> vr(Nt_);
   for (int b = 0; b < B_; ++b)
     std::memset(vr.data() + off_[b], b, (size_t)n_[b] * n_[b] * n_[b]);
   RVE_HIP(hipMemcpyAsync(vrve_, vr.data(), Nt_, hipMemcpyHostToDevice, st_));
+  // the timed matvecs of the schedule tuner read these before the solver
+  // writes them: start from zeros
+  for (void* f : {K_, r_, p0_, p1_})
+    RVE_HIP(hipMemsetAsync(f, 0, (f == K_ ? 81 : 9) * Nt_ * tsz, st_));
   RVE_HIP(hipStreamSynchronize(st_));
 
   if (cfg_.use_graph) {
@@ -216,11 +171,9 @@ BatchEngine::BatchEngine(const rve_config& cfg, int count, const int32_t* n)
     // grid-barrier words of the persistent CG kernel, then its error flag
     bar_ = (unsigned*)alloc((kBatchBarWords + 1) * sizeof(unsigned));
     launch_fill_i32((int32_t*)bar_, 0, kBatchBarWords + 1, st_);
-    persist_lds_ = fp64_ ? std::max(ldsA64_, ldsB64_) : std::max(ldsA32_, ldsB32_);
-    persist_grid_ = fp64_ ? cg_batch_persistent_grid<double>(persist_lds_)
-                          : cg_batch_persistent_grid<float>(persist_lds_);
     RVE_HIP(hipStreamSynchronize(st_));
   }
+  build_tables();
   host_phase_.resize(B_);
   host_tables_.resize(B_);
   label_count_.assign(B_, 0);
@@ -236,6 +189,236 @@ BatchEngine::BatchEngine(const rve_config& cfg, int count, const int32_t* n)
       Fbar_[b][i] = (i % 4 == 0) ? 1.0 : 0.0;
       Pbar_[b][i] = 0.0;
     }
+}
+
+// The descriptor tables of the batched passes for the current schedules:
+// per RVE its edge, schedule, first blocks in the slab (A, C) and pencil (B)
+// grids, arena offsets, FFT tables, scalars and partials; the per-RVE
+// reductions of the pass-C partials; the dynamic LDS and grid sizes.  The
+// CG precision's table takes the per-edge schedules (sched_), the other
+// (the FP64 residual of a mixed batch) the defaults.
+void BatchEngine::build_tables() {
+  std::vector<SpecItem<float>> it32(B_);
+  std::vector<SpecItem<double>> it64(B_);
+  std::vector<RedItem> ri32(B_), ri64(B_);
+  int a32 = 0, b32 = 0, a64 = 0, b64 = 0;
+  int64_t pp = 0, pso = 0;
+  ldsA32_ = ldsB32_ = ldsA64_ = ldsB64_ = 0;
+  cpbs32_ = cpbs64_ = 0;
+  for (int b = 0; b < B_; ++b) {
+    const int nb = n_[b];
+    const int64_t Nb = (int64_t)nb * nb * nb;
+    auto fill = [&](auto& it, int& accA, int& accB, bool dbl, size_t& la,
+                    size_t& lb, RedItem& ri, int& cpbs) {
+      using T = std::remove_reference_t<decltype(it.tw[0].x)>;
+      int cpb = 0, tt = 0;
+      default_schedule(nb, dbl, cpb, tt);
+      if (dbl == fp64_) {
+        auto f = sched_.find(nb);
+        if (f != sched_.end() && f->second[0]) {
+          cpb = f->second[0];
+          tt = f->second[1];
+        }
+      }
+      const int sA = slab_blocks(nb, dbl, cpb);
+      cpbs |= cpb == 3 ? 2 : 1;
+      it.n = nb;
+      it.cpb = cpb;
+      it.tt = tt;
+      it.blk[0] = accA;
+      it.blk[1] = accB;
+      it.off = off_[b];
+      it.soff = soff_[b];
+      it.sc = sc_ + b;
+      it.partial = partials_ + pp;
+      it.psum = psum_ + pso;
+      it.psq = psq_ + pso;
+      it.tw = (const cplx<T>*)(dbl ? tw64_ : tw32_) + twoff_[b];
+      it.vt = (const T*)(dbl ? vt64_ : vt32_) + vtoff_[b];
+      accA += sA;
+      accB += pencil_blocks(nb, dbl, tt);
+      size_t s1, s2;
+      batch_lds<T>(nb, cpb, tt, s1, s2);
+      la = std::max(la, s1);
+      lb = std::max(lb, s2);
+      ri = RedItem{partials_ + pp, sA, psum_ + pso, psq_ + pso, nb,
+                   1.0 / (double)Nb};
+    };
+    fill(it32[b], a32, b32, false, ldsA32_, ldsB32_, ri32[b], cpbs32_);
+    fill(it64[b], a64, b64, true, ldsA64_, ldsB64_, ri64[b], cpbs64_);
+    pp += 9 * nb;
+    pso += 9 * nb;
+  }
+  if (ldsA32_ > 65536 || ldsB32_ > 65536) batch_allow_lds<float>(ldsA32_, ldsB32_);
+  if (ldsA64_ > 65536 || ldsB64_ > 65536) batch_allow_lds<double>(ldsA64_, ldsB64_);
+  blocksA32_ = a32;
+  blocksB32_ = b32;
+  blocksA64_ = a64;
+  blocksB64_ = b64;
+  host_it32_ = it32;
+  host_it64_ = it64;
+  RVE_HIP(hipMemcpyAsync(items32_, it32.data(), B_ * sizeof(SpecItem<float>), hipMemcpyHostToDevice, st_));
+  RVE_HIP(hipMemcpyAsync(items64_, it64.data(), B_ * sizeof(SpecItem<double>), hipMemcpyHostToDevice, st_));
+  RVE_HIP(hipMemcpyAsync(red_inv32_, ri32.data(), B_ * sizeof(RedItem), hipMemcpyHostToDevice, st_));
+  RVE_HIP(hipMemcpyAsync(red_inv64_, ri64.data(), B_ * sizeof(RedItem), hipMemcpyHostToDevice, st_));
+  if (cfg_.use_graph) {
+    persist_lds_ = fp64_ ? std::max(ldsA64_, ldsB64_) : std::max(ldsA32_, ldsB32_);
+    persist_grid_ = fp64_ ? cg_batch_persistent_grid<double>(persist_lds_)
+                          : cg_batch_persistent_grid<float>(persist_lds_);
+  }
+  // a captured increment holds the old tables' grid sizes
+  if (inc_graph_) {
+    RVE_HIP(hipGraphExecDestroy(inc_graph_));
+    inc_graph_ = nullptr;
+  }
+  if (inc_graph_def_) {
+    RVE_HIP(hipGraphDestroy(inc_graph_def_));
+    inc_graph_def_ = nullptr;
+  }
+  inc_graph_dt_ = -1.0;
+  RVE_HIP(hipStreamSynchronize(st_));
+}
+
+// Per grid edge of the batch (edges with a forced schedule excepted), the
+// fastest schedule of the CG matvec G(K : p) (components per slab block,
+// kz columns per pencil block): every valid candidate times one matvec of
+// this edge's RVEs alone, through the batched passes, with every RVE
+// active and beta = 0 (p = r + 0 p_old: the traffic of an iteration after
+// the first); three interleaved rounds, the best of each.  The scalars are
+// restored afterwards; the passes overwrite only the direction, the
+// spectrum, G(K:p) and the partials, all rewritten by the next solve.
+template <typename T>
+void BatchEngine::autotune() {
+  const bool dbl = sizeof(T) == sizeof(double);
+  read_scalars();
+  std::vector<Scalars> saved(sc_host_, sc_host_ + B_);
+  for (int b = 0; b < B_; ++b) {
+    sc_host_[b].done = 0;
+    sc_host_[b].inactive = 0;
+    sc_host_[b].first = 0;
+    sc_host_[b].beta = 0.0;
+  }
+  upload_scalars();
+  const std::vector<SpecItem<T>>& full =
+      *reinterpret_cast<const std::vector<SpecItem<T>>*>(dbl ? (const void*)&host_it64_
+                                                             : (const void*)&host_it32_);
+  hipEvent_t ev[2];
+  RVE_HIP(hipEventCreate(&ev[0]));
+  RVE_HIP(hipEventCreate(&ev[1]));
+  std::vector<int> edges(n_);
+  std::sort(edges.begin(), edges.end());
+  edges.erase(std::unique(edges.begin(), edges.end()), edges.end());
+  for (int e : edges) {
+    if (forced_.count(e)) continue;
+    struct Cand {
+      int cpb, tt;
+      std::vector<SpecItem<T>> items;
+      int bA, bB;
+      size_t lA, lB;
+    };
+    std::vector<Cand> cand;
+    for (int cpb : {1, 3})
+      for (int tt : {4, 8, 16}) {
+        if (!schedule_valid(e, dbl, cpb, tt)) continue;
+        Cand c{cpb, tt, {}, 0, 0, 0, 0};
+        for (int b = 0; b < B_; ++b) {
+          if (n_[b] != e) continue;
+          SpecItem<T> it = full[b];
+          it.cpb = cpb;
+          it.tt = tt;
+          it.blk[0] = c.bA;
+          it.blk[1] = c.bB;
+          c.bA += slab_blocks(e, dbl, cpb);
+          c.bB += pencil_blocks(e, dbl, tt);
+          c.items.push_back(it);
+        }
+        batch_lds<T>(e, cpb, tt, c.lA, c.lB);
+        if (c.lA > 65536 || c.lB > 65536) batch_allow_lds<T>(c.lA, c.lB);
+        cand.push_back(std::move(c));
+      }
+    std::vector<float> best(cand.size(), 0.f);
+    constexpr int reps = 4;
+    for (int round = 0; round < 3; ++round)
+      for (size_t c = 0; c < cand.size(); ++c) {
+        RVE_HIP(hipMemcpyAsync(tune_items_, cand[c].items.data(),
+                               cand[c].items.size() * sizeof(SpecItem<T>),
+                               hipMemcpyHostToDevice, st_));
+        BatchSpec<T> bs = spec<T>(true, 0);
+        bs.items = (const SpecItem<T>*)tune_items_;
+        bs.nitems = (int)cand[c].items.size();
+        bs.cpbs = cand[c].cpb == 3 ? 2 : 1;
+        auto matvec = [&] {
+          launch_G_batch<T>(bs, SRC_KP, (T*)Ap_, nullptr, cand[c].bA,
+                            cand[c].bB, cand[c].lA, cand[c].lB, st_);
+        };
+        matvec();  // untimed first launch
+        RVE_HIP(hipEventRecord(ev[0], st_));
+        for (int i = 0; i < reps; ++i) matvec();
+        RVE_HIP(hipEventRecord(ev[1], st_));
+        RVE_HIP(hipEventSynchronize(ev[1]));
+        float t = 0.f;
+        RVE_HIP(hipEventElapsedTime(&t, ev[0], ev[1]));
+        if (round == 0 || t < best[c]) best[c] = t;
+      }
+    size_t bi = 0;
+    for (size_t c = 1; c < cand.size(); ++c)
+      if (best[c] < best[bi]) bi = c;
+    if (cand.empty()) throw Error(RVE_EINVAL, "no FFT schedule for a batch edge");
+    sched_[e] = {cand[bi].cpb, cand[bi].tt};
+    sched_ms_[e] = best[bi] / reps;
+  }
+  RVE_HIP(hipGetLastError());
+  hipEventDestroy(ev[0]);
+  hipEventDestroy(ev[1]);
+  std::copy(saved.begin(), saved.end(), sc_host_);
+  upload_scalars();
+  build_tables();
+}
+
+void BatchEngine::tune() {
+  RVE_HIP(hipStreamSynchronize(st_));
+  if (fp64_) autotune<double>(); else autotune<float>();
+  tuned_ = true;
+}
+
+void BatchEngine::ensure_tuned() {
+  if (!tuned_) tune();
+}
+
+void BatchEngine::set_schedule(int edge, int cpb, int tt) {
+  if (std::find(n_.begin(), n_.end(), edge) == n_.end())
+    throw Error(RVE_EINVAL, "no RVE of this grid edge in the batch");
+  if (cpb || tt) {
+    if (!schedule_valid(edge, fp64_, cpb, tt))
+      throw Error(RVE_EINVAL, "no such FFT schedule for this grid edge and precision");
+    RVE_HIP(hipStreamSynchronize(st_));
+    sched_[edge] = {cpb, tt};
+    sched_ms_[edge] = 0.0;
+    forced_.insert(edge);
+  } else {
+    // tune this edge again (with the others) at the next solve
+    RVE_HIP(hipStreamSynchronize(st_));
+    sched_.erase(edge);
+    sched_ms_.erase(edge);
+    forced_.erase(edge);
+    tuned_ = false;
+  }
+  build_tables();
+}
+
+void BatchEngine::get_schedule(int edge, int out[2], double* ms) const {
+  if (std::find(n_.begin(), n_.end(), edge) == n_.end())
+    throw Error(RVE_EINVAL, "no RVE of this grid edge in the batch");
+  for (int b = 0; b < B_; ++b)
+    if (n_[b] == edge) {
+      out[0] = fp64_ ? host_it64_[b].cpb : host_it32_[b].cpb;
+      out[1] = fp64_ ? host_it64_[b].tt : host_it32_[b].tt;
+      break;
+    }
+  if (ms) {
+    auto f = sched_ms_.find(edge);
+    *ms = f == sched_ms_.end() ? 0.0 : f->second;
+  }
 }
 
 BatchEngine::~BatchEngine() {
@@ -394,6 +577,7 @@ BatchSpec<T> BatchEngine::spec(bool cg, int parity) const {
   const bool dbl = sizeof(T) == sizeof(double);
   b.items = (const SpecItem<T>*)(dbl ? items64_ : items32_);
   b.nitems = B_;
+  b.cpbs = dbl ? cpbs64_ : cpbs32_;
   b.cs = Nt_;
   if (cg) {
     b.K = (const T*)K_;
@@ -455,6 +639,7 @@ int BatchEngine::increment(const double* Fbar_all, double dt,
                            rve_increment_info* info) {
   for (int b = 0; b < B_; ++b)
     if (!have_micro_[b]) throw Error(RVE_ESTATE, "every RVE needs a microstructure");
+  ensure_tuned();
   if (cfg_.use_graph) return increment_device(Fbar_all, dt, info);
   if (!(dt > 0.0) || !std::isfinite(dt)) throw Error(RVE_EINVAL, "dt must be > 0");
   for (int b = 0; b < B_; ++b) {
@@ -839,6 +1024,7 @@ void BatchEngine::debug_apply_G(const double* in, double* out) {
     BatchSpec<double> rs{};
     rs.items = (const SpecItem<double>*)items64_;
     rs.nitems = B_;
+    rs.cpbs = cpbs64_;
     rs.cs = Nt_;
     rs.field = r64_;
     rs.spec = (cplx<double>*)spec64_;
@@ -849,6 +1035,7 @@ void BatchEngine::debug_apply_G(const double* in, double* out) {
     BatchSpec<float> rs{};
     rs.items = (const SpecItem<float>*)items32_;
     rs.nitems = B_;
+    rs.cpbs = cpbs32_;
     rs.cs = Nt_;
     rs.field = (const float*)x_;
     rs.spec = (cplx<float>*)spec_;

@@ -4,6 +4,8 @@
 #pragma once
 
 #include <array>
+#include <map>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -31,6 +33,11 @@ class BatchEngine {
   int count() const { return B_; }
   // test hook: out = G(in) with the batched passes in the batch's precision
   void debug_apply_G(const double* in, double* out);
+  // per-edge schedule of the batched CG matvec: tuned at the first
+  // increment (or now, by tune) unless forced; (0, 0) tunes the edge again
+  void tune();
+  void set_schedule(int edge, int cpb, int tt);
+  void get_schedule(int edge, int out[2], double* ms) const;
 
  private:
   void* alloc(size_t bytes);
@@ -52,6 +59,10 @@ class BatchEngine {
   void newton_solve_device(int it, const LawParams& lp);
   void newton_eval_device(int it, const LawParams& lp, const double* dg_start);
   void read_logs();
+  void build_tables();
+  template <typename T>
+  void autotune();
+  void ensure_tuned();
 
   rve_config cfg_;
   int B_;
@@ -87,11 +98,20 @@ class BatchEngine {
   void *items32_, *items64_;
   int blocksA32_, blocksB32_, blocksA64_, blocksB64_;
   size_t ldsA32_, ldsB32_, ldsA64_, ldsB64_;
+  int cpbs32_ = 3, cpbs64_ = 3;  // slab schedules present (BatchSpec::cpbs)
   double* partials_;
   SegItem* seg_;
   int seg_blocks_;
   RedItem *red_inv32_, *red_inv64_, *red_seg_;
-  void *tw32_, *tw64_, *vt32_, *vt64_;  // per distinct edge, concatenated
+  void *tw32_, *tw64_, *vt32_, *vt64_;  // per RVE, concatenated
+  std::vector<int64_t> twoff_, vtoff_;  // each RVE's offsets in them
+  std::vector<SpecItem<float>> host_it32_;
+  std::vector<SpecItem<double>> host_it64_;
+  void* tune_items_;                    // the tuner's sub-batch table
+  std::map<int, std::array<int, 2>> sched_;  // edge -> (cpb, tt), CG precision
+  std::map<int, double> sched_ms_;           // tuned matvec ms per edge
+  std::set<int> forced_;
+  bool tuned_ = false;
   double *psum_, *psq_;
   // host macro state per RVE
   std::vector<std::array<double, 9>> Fbar_, Pbar_;

@@ -418,20 +418,29 @@ rve_status rve_get_return_map_counts(rve_t h, int64_t out[4], int32_t reset) {
   });
 }
 
-rve_status rve_set_fft_schedule(rve_t h, int32_t cpb, int32_t tt) {
+rve_status rve_set_fft_schedule(rve_t h, int32_t cpb, int32_t tt,
+                                int32_t fused) {
   return guarded(h, [&] {
-    h->eng->set_schedule(cpb, tt);
+    h->eng->set_schedule(cpb, tt, fused);
     return RVE_OK;
   });
 }
 
-rve_status rve_get_fft_schedule(rve_t h, int32_t out[2], double* ms) {
+rve_status rve_tune_fft_schedule(rve_t h) {
+  return guarded(h, [&] {
+    h->eng->tune();
+    return RVE_OK;
+  });
+}
+
+rve_status rve_get_fft_schedule(rve_t h, int32_t out[3], double* ms) {
   return guarded(h, [&] {
     if (!out) throw rve::Error(RVE_EINVAL, "null output");
-    int o[2];
+    int o[3];
     h->eng->get_schedule(o, ms);
     out[0] = o[0];
     out[1] = o[1];
+    out[2] = o[2];
     return RVE_OK;
   });
 }
@@ -524,6 +533,33 @@ rve_status rve_batch_debug_apply_G(rve_batch_t h, const double* in,
                                    double* out) {
   return guarded(h, [&] {
     h->eng->debug_apply_G(in, out);
+    return RVE_OK;
+  });
+}
+
+rve_status rve_batch_tune_fft_schedule(rve_batch_t h) {
+  return guarded(h, [&] {
+    h->eng->tune();
+    return RVE_OK;
+  });
+}
+
+rve_status rve_batch_set_fft_schedule(rve_batch_t h, int32_t edge,
+                                      int32_t cpb, int32_t tt) {
+  return guarded(h, [&] {
+    h->eng->set_schedule(edge, cpb, tt);
+    return RVE_OK;
+  });
+}
+
+rve_status rve_batch_get_fft_schedule(rve_batch_t h, int32_t edge,
+                                      int32_t out[2], double* ms) {
+  return guarded(h, [&] {
+    if (!out) throw rve::Error(RVE_EINVAL, "null output");
+    int o[2];
+    h->eng->get_schedule(edge, o, ms);
+    out[0] = o[0];
+    out[1] = o[1];
     return RVE_OK;
   });
 }

@@ -103,11 +103,16 @@ Engine::Engine(const rve_config& cfg) : cfg_(cfg) {
   // room for the partials of any schedule (one component per slab block)
   partial_inv_ = (double*)alloc(9 * n_ * sizeof(double));
   partial_red_ = (double*)alloc(kRedBlocks * sizeof(double));
-  partial_kp_ = (double*)alloc(kKpMaxBlocks * sizeof(double));
+  // the direction kernel's partials, or pass A's when it is folded in
+  partial_kp_ = (double*)alloc(std::max(kKpMaxBlocks, 9 * n_) * sizeof(double));
   psum_ = (double*)alloc(9 * n_ * sizeof(double));
   psq_ = (double*)alloc(9 * n_ * sizeof(double));
   sc_ = (Scalars*)alloc(sizeof(Scalars));
   RVE_HIP(hipMemsetAsync(sc_, 0, sizeof(Scalars), st_));
+  // the timed matvecs of the schedule tuner may read these before the
+  // solver writes them: start from zeros
+  for (void* f : {K_, r_, x_, p0_, p1_})
+    RVE_HIP(hipMemsetAsync(f, 0, (f == K_ ? 81 : 9) * N_ * tsz, st_));
   phase_ = (int32_t*)alloc(N_ * sizeof(int32_t));
   order_ = (int32_t*)alloc(N_ * sizeof(int32_t));
   table_ = nullptr;
@@ -434,19 +439,30 @@ void Engine::cg_iteration_steps(int parity, Run&& run) {
   const bool dbl = sizeof(T) == sizeof(double);
   T* p_new = (T*)(parity ? p0_ : p1_);
   const int nslab = slab_blocks(n_, dbl, sched_cpb_);
+  const T* p_old = (const T*)(parity ? p1_ : p0_);
   // beta from the last inverse pass's r.r partials, the previous
   // iteration's x += alpha p_old, p = r + beta p_old and y = K : p with the
-  // p . y partials, in one streaming pass
-  run(7, [&] {
-    launch_kp<T>((const T*)K_, (const T*)r_, (const T*)(parity ? p1_ : p0_),
-                 p_new, (T*)Kp_, sc_, N_, st_, partial_inv_, nslab, parity,
-                 (T*)x_, partial_kp_);
-  });
-  // G(y); pass A publishes alpha = r.r / p.y, pass C applies r -= alpha G(y)
-  // and writes the new r.r partials
+  // p . y partials, in one streaming pass (or folded into pass A)
+  if (!sched_fused_)
+    run(7, [&] {
+      launch_kp<T>((const T*)K_, (const T*)r_, p_old, p_new, (T*)Kp_, sc_, N_,
+                   st_, partial_inv_, nslab, parity, (T*)x_, partial_kp_);
+    });
+  // G(y); pass A (pass B when fused) publishes alpha = r.r / p.y, pass C
+  // applies r -= alpha G(y) and writes the new r.r partials
   SpectralLaunch<T> L;
-  L.src = SRC_FIELD;
-  L.in_field = (const T*)Kp_;
+  if (sched_fused_) {
+    L.src = SRC_KP;
+    L.K = (const T*)K_;
+    L.r = (const T*)r_;
+    L.p_old = p_old;
+    L.x = (T*)x_;
+    L.pinv = partial_inv_;
+    L.pinv_count = nslab;
+  } else {
+    L.src = SRC_FIELD;
+    L.in_field = (const T*)Kp_;
+  }
   L.p_new = p_new;
   L.spec = (cplx<T>*)spec_;
   L.tw = (const cplx<T>*)(dbl ? tw64_ : tw32_);
@@ -454,7 +470,7 @@ void Engine::cg_iteration_steps(int parity, Run&& run) {
   L.dst = DST_CG;
   L.r_io = (T*)r_;
   L.pkp = partial_kp_;
-  L.pkp_count = kp_blocks(N_);
+  L.pkp_count = sched_fused_ ? nslab : kp_blocks(N_);
   L.parity = parity;
   L.partial_inv = partial_inv_;
   L.sc = sc_;
@@ -536,24 +552,30 @@ void Engine::capture_graph() {
   RVE_HIP(hipGraphInstantiate(&graph_, graph_def_, nullptr, nullptr, 0));
 }
 
-// Picks the fastest FFT schedule (components per slab block in passes A
-// and C, kz columns per pass-B block) for this grid and precision by timing
-// the three FFT passes of one CG matvec G(K : p) for each valid candidate,
-// on the live buffers (the CG vectors are re-initialised afterwards).
+// Picks the fastest schedule of the CG matvec G(K : p) for this grid and
+// precision (components per slab block in passes A and C, kz columns per
+// pass-B block, and whether the direction kernel is folded into pass A) by
+// timing one matvec with each valid candidate on the live buffers, with
+// alpha = beta = 0 (p = r + 0 p_old, x += 0 p_old: the memory traffic of
+// an iteration after the first; the CG vectors are re-initialised
+// afterwards): the direction kernel and the three passes, or the three
+// passes with the folded pass A.
 template <typename T>
 void Engine::autotune() {
   const bool dbl = sizeof(T) == sizeof(double);
   hipEvent_t ev[2];
   RVE_HIP(hipEventCreate(&ev[0]));
   RVE_HIP(hipEventCreate(&ev[1]));
-  std::vector<std::pair<int, int>> cand;
-  for (int cpb : {1, 3})
-    for (int tt : {4, 8, 16})
-      if (schedule_valid(n_, dbl, cpb, tt)) cand.push_back({cpb, tt});
-  // alpha = 0 in every slot: the timed passes leave r unchanged
+  struct Cand {
+    int cpb, tt, fused;
+  };
+  std::vector<Cand> cand;
+  for (int fused : {0, 1})
+    for (int cpb : {1, 3})
+      for (int tt : {4, 8, 16})
+        if (schedule_valid(n_, dbl, cpb, tt)) cand.push_back({cpb, tt, fused});
+  // alpha = 0 in every slot: the timed passes leave r and x unchanged
   launch_bench_scalars(sc_, st_);
-  launch_kp<T>((const T*)K_, (const T*)r_, (const T*)p0_, (T*)p1_, (T*)Kp_,
-               sc_, N_, st_);
   // three interleaved rounds, the best of each candidate's timings: robust
   // against clock and cache drift between candidates
   std::vector<float> tbest(cand.size(), 0.f);
@@ -561,8 +583,16 @@ void Engine::autotune() {
   for (int round = 0; round < 3; ++round)
     for (size_t c = 0; c < cand.size(); ++c) {
       SpectralLaunch<T> L;
-      L.src = SRC_FIELD;
-      L.in_field = (const T*)Kp_;
+      if (cand[c].fused) {
+        L.src = SRC_KP;
+        L.K = (const T*)K_;
+        L.r = (const T*)r_;
+        L.p_old = (const T*)p0_;
+        L.x = (T*)x_;
+      } else {
+        L.src = SRC_FIELD;
+        L.in_field = (const T*)Kp_;
+      }
       L.p_new = (T*)p1_;
       L.spec = (cplx<T>*)spec_;
       L.tw = (const cplx<T>*)(dbl ? tw64_ : tw32_);
@@ -571,11 +601,18 @@ void Engine::autotune() {
       L.r_io = (T*)r_;
       L.partial_inv = partial_inv_;
       L.sc = sc_;
-      L.cpb = cand[c].first;
-      L.tt = cand[c].second;
-      launch_G<T>(n_, L, st_);  // untimed first launch
+      L.cpb = cand[c].cpb;
+      L.tt = cand[c].tt;
+      auto matvec = [&] {
+        if (!cand[c].fused)
+          launch_kp<T>((const T*)K_, (const T*)r_, (const T*)p0_, (T*)p1_,
+                       (T*)Kp_, sc_, N_, st_, nullptr, 0, 0, (T*)x_,
+                       partial_kp_);
+        launch_G<T>(n_, L, st_);
+      };
+      matvec();  // untimed first launch
       RVE_HIP(hipEventRecord(ev[0], st_));
-      for (int i = 0; i < reps; ++i) launch_G<T>(n_, L, st_);
+      for (int i = 0; i < reps; ++i) matvec();
       RVE_HIP(hipEventRecord(ev[1], st_));
       RVE_HIP(hipEventSynchronize(ev[1]));
       float t = 0.f;
@@ -583,22 +620,29 @@ void Engine::autotune() {
       if (round == 0 || t < tbest[c]) tbest[c] = t;
     }
   float best = 0.f;
-  int bc = 0, bt = 0;
+  int bi = -1;
   for (size_t c = 0; c < cand.size(); ++c)
-    if (bc == 0 || tbest[c] < best) {
+    if (bi < 0 || tbest[c] < best) {
       best = tbest[c];
-      bc = cand[c].first;
-      bt = cand[c].second;
+      bi = (int)c;
     }
   hipEventDestroy(ev[0]);
   hipEventDestroy(ev[1]);
-  if (bc == 0) throw Error(RVE_EINVAL, "no FFT schedule for this grid");
-  sched_cpb_ = bc;
-  sched_tt_ = bt;
-  sched_ms_ = best / 4.0;
+  if (bi < 0) throw Error(RVE_EINVAL, "no FFT schedule for this grid");
+  sched_cpb_ = cand[bi].cpb;
+  sched_tt_ = cand[bi].tt;
+  sched_fused_ = cand[bi].fused;
+  sched_ms_ = best / reps;
 }
 
-void Engine::set_schedule(int cpb, int tt) {
+void Engine::tune() {
+  set_schedule(0, 0, 0);  // drops a captured graph
+  if (fp64_) autotune<double>(); else autotune<float>();
+}
+
+void Engine::set_schedule(int cpb, int tt, int fused) {
+  if (fused != 0 && fused != 1)
+    throw Error(RVE_EINVAL, "fused must be 0 or 1");
   if (cpb || tt) {
     if (!schedule_valid(n_, fp64_, cpb, tt))
       throw Error(RVE_EINVAL, "no such FFT schedule for this grid and precision");
@@ -615,6 +659,8 @@ void Engine::set_schedule(int cpb, int tt) {
   timer_.recycle(graph_pairs_);
   sched_cpb_ = cpb;
   sched_tt_ = tt;
+  sched_fused_ = (cpb || tt) ? fused : 0;
+  sched_ms_ = 0.0;
 }
 
 // CG on G(K : x) = b with b = -r64 (text after Eq. 16), from x = 0
@@ -1250,12 +1296,13 @@ void Engine::debug_set_field(int field, const double* src, size_t bytes) {
 }
 
 // Kernel classes of the live timing and of bench_kernels:
-//   0 pass A (z/y FFT of K:p)                   1 pass B (x FFT, projection)
+//   0 pass A (z/y FFT of K:p; under a fused schedule also the direction,
+//     the previous x update and K:p)            1 pass B (x FFT, projection)
 //   2 pass C (inverse y/z FFT, r -= alpha G(K:p), r.r)
-//   3 unused (the vector update rides on classes 2 and 7)
+//   3 unused (the vector update rides on classes 2 and 7, or 0)
 //   4 return mapping (FP64)                     5 tangent
 //   6 FP64 residual G(P) (three passes + reduction)
-//   7 direction, previous x update and K:p
+//   7 direction, previous x update and K:p (unfused schedules)
 void Engine::set_timing(uint32_t mask) {
   if (mask == timer_.mask()) return;
   // captured CG graphs hold (or lack) the timing events: capture again
@@ -1353,8 +1400,16 @@ void Engine::bench_kernels(int reps, double* ms, int count) {
     using T = decltype(tag);
     const bool dbl = sizeof(T) == sizeof(double);
     SpectralLaunch<T> L;
-    L.src = SRC_FIELD;
-    L.in_field = (const T*)Kp_;
+    if (sched_fused_) {
+      L.src = SRC_KP;
+      L.K = (const T*)K_;
+      L.r = (const T*)r_;
+      L.p_old = (const T*)p0_;
+      L.x = (T*)x_;
+    } else {
+      L.src = SRC_FIELD;
+      L.in_field = (const T*)Kp_;
+    }
     L.p_new = (T*)p1_;
     L.spec = (cplx<T>*)spec_;
     L.tw = (const cplx<T>*)(dbl ? tw64_ : tw32_);
@@ -1368,10 +1423,11 @@ void Engine::bench_kernels(int reps, double* ms, int count) {
     L.tt = sched_tt_;
     launch_G<T>(n_, L, st_);
   };
-  // the CG kernels as a CG run launches them, with alpha = 0 and p = r
-  // (x += 0 p_old, r -= 0 G(y)): the vectors keep their values
+  // the CG kernels as a CG run launches them after its first iteration,
+  // with alpha = beta = 0 (p = r + 0 p_old, x += 0 p_old, r -= 0 G(y)): the
+  // vectors keep their values
   launch_bench_scalars(sc_, st_);
-  timed(7, [&] {
+  if (!sched_fused_) timed(7, [&] {
     if (fp64_)
       launch_kp<double>((const double*)K_, (const double*)r_,
                         (const double*)p0_, (double*)p1_, (double*)Kp_, sc_,

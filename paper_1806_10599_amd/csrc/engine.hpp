@@ -49,11 +49,14 @@ class Engine {
   void set_timing(uint32_t mask);
   void get_timing(double* ms, int64_t* launches, int count, bool reset);
   void get_rm_counts(int64_t out[4], bool reset);
-  // FFT schedule of the CG matvec: (0, 0) = autotune at the next solve
-  void set_schedule(int cpb, int tt);
-  void get_schedule(int out[2], double* ms) const {
+  // FFT schedule of the CG matvec: (0, 0) = autotune at the next solve;
+  // fused: the direction kernel folded into pass A
+  void set_schedule(int cpb, int tt, int fused);
+  void tune();
+  void get_schedule(int out[3], double* ms) const {
     out[0] = sched_cpb_;
     out[1] = sched_tt_;
+    out[2] = sched_fused_;
     if (ms) *ms = sched_ms_;
   }
 
@@ -137,6 +140,7 @@ class Engine {
   void *tw32_, *tw64_, *vt32_, *vt64_;
   int nslab32_, nslab64_;
   int sched_cpb_ = 0, sched_tt_ = 0;   // 0: not tuned yet
+  int sched_fused_ = 0;
   double sched_ms_ = 0.0;
   int labels_ = 0;
   bool have_micro_ = false;

@@ -30,6 +30,24 @@ struct SlabFwdArgs {
   int pkp_count = 0;
   int parity = 0;
   Scalars* scw = nullptr;
+  // SRC_KP in a single-RVE CG run (the direction kernel folded into pass A):
+  // the r.r partials of the last inverse pass (beta), the iterate x (the
+  // previous iteration's x += alpha p_old on this block's components) and
+  // the per-block partials of p . (K:p) written for pass B's alpha
+  const double* pinv = nullptr;
+  int pinv_count = 0;
+  T* x = nullptr;
+  double* pkp_out = nullptr;
+};
+
+// The direction step a pass-A block applies with SRC_KP: p = r (first) or
+// r + beta p_old, and with upd the pending x += alpha p_old
+template <typename T>
+struct KpStep {
+  bool first;
+  T beta;
+  bool upd;
+  T alpha;
 };
 
 template <typename T>
@@ -39,6 +57,12 @@ struct PencilArgs {
   const T* vt;         // [3][N] wave-vector components per axis
   T invN3;
   const Scalars* sc;   // optional early exit
+  // optional (fused single-RVE CG run): block 0 reduces pass A's p.(K:p)
+  // partials and publishes alpha in slot `parity` of scw
+  const double* pkp = nullptr;
+  int pkp_count = 0;
+  int parity = 0;
+  Scalars* scw = nullptr;
 };
 
 template <typename T, typename TO>
@@ -73,12 +97,19 @@ struct SpectralLaunch {
   double* out_d = nullptr;
   double* partial_inv = nullptr;
   Scalars* sc = nullptr;
-  // CG run (dst = DST_CG): the p.(K:p) partials for pass A's alpha, the
-  // residual updated in place by pass C, and the iteration's parity
+  // CG run (dst = DST_CG): the p.(K:p) partials for alpha (published by
+  // pass A with src = SRC_FIELD, by pass B with src = SRC_KP, whose pass A
+  // writes them), the residual updated in place by pass C, and the
+  // iteration's parity
   const double* pkp = nullptr;
   int pkp_count = 0;
   T* r_io = nullptr;
   int parity = 0;
+  // fused CG run (src = SRC_KP): the r.r partials of the last pass C and the
+  // iterate x, as the direction kernel takes them
+  const double* pinv = nullptr;
+  int pinv_count = 0;
+  T* x = nullptr;
   int passes = 7;   // bit 0: pass A, bit 1: pass B, bit 2: pass C
   int cpb = 0;      // components per slab block in passes A and C (1 or 3;
                     // 0: the default of the grid edge and precision)
@@ -102,6 +133,8 @@ template <typename T>
 struct SpecItem {
   int n;
   int blk[2];
+  int cpb;              // components per slab block (1 or 3)
+  int tt;               // kz columns per pencil block (4, 8 or 16)
   int pad;
   int64_t off;          // voxel offset in the arena
   int64_t soff;         // complex offset of the spectrum
@@ -117,6 +150,8 @@ template <typename T>
 struct BatchSpec {
   const SpecItem<T>* items;
   int nitems;
+  int cpbs = 3;         // slab schedules among the items (bit 0: cpb 1,
+                        // bit 1: cpb 3)
   int64_t cs;           // voxels in the arena (component stride)
   const T* field;       // SRC_FIELD input
   const T* K;
@@ -132,8 +167,11 @@ template <typename T>
 void launch_G_batch(const BatchSpec<T>& b, int src, T* out_T, double* out_d,
                     int blocksA, int blocksB, size_t ldsA, size_t ldsB,
                     hipStream_t s);
+// dynamic LDS of the batched slab and pencil passes of one grid edge
+// under a schedule (throws for an invalid one)
 template <typename T>
-void batch_lds(int n, size_t& slab, size_t& pencil);
+void batch_lds(int n, int cpb, int tt, size_t& slab, size_t& pencil);
+void default_schedule(int n, bool fp64, int& cpb, int& tt);
 
 
 bool batch_supported(int n);

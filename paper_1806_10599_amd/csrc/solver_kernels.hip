@@ -254,9 +254,10 @@ __global__ void init_scalars_kernel(Scalars* sc, int max_iters, double eta) {
 
 __global__ void bench_scalars_kernel(Scalars* sc) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    // a matvec on p = r that leaves the vectors unchanged (alpha = 0)
+    // a matvec on p = r + 0 p_old that leaves the vectors unchanged
+    // (alpha = beta = 0) and reads p_old as every iteration after the first
     sc->done = 0;
-    sc->first = 1;
+    sc->first = 0;
     sc->alpha = 0.0;
     sc->beta = 0.0;
     sc->alphas[0] = sc->alphas[1] = 0.0;

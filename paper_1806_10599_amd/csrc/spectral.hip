@@ -91,7 +91,8 @@ __device__ __forceinline__ void load_twiddles(cplx<T>* tw,
 template <typename T, int N, int CPB, int SRC>
 __device__ __forceinline__ void slab_fwd_body(const SlabFwdArgs<T>& a, int lb,
                                               cplx<T>* lds, cplx<T>* tw,
-                                              double* red) {
+                                              double* red,
+                                              const KpStep<T>& st) {
   constexpr int H = N / 2;
   constexpr int NG = 9 / CPB;
   const int64_t cs = a.cs;
@@ -144,8 +145,7 @@ __device__ __forceinline__ void slab_fwd_body(const SlabFwdArgs<T>& a, int lb,
       }
     }
   }
-  const bool first = (SRC == SRC_KP) ? (a.sc->first != 0) : true;
-  const T beta = (SRC == SRC_KP) ? T(a.sc->beta) : T(0);
+  double kacc = 0.0;  // p . (K:p) over this block's components
   for (int t = threadIdx.x; SRC == SRC_KP && t < H * N; t += blockDim.x) {
     const int yp = t / N, z = t - (t / N) * N;
     T out[2][CPB];
@@ -161,17 +161,19 @@ __device__ __forceinline__ void slab_fwd_body(const SlabFwdArgs<T>& a, int lb,
 #pragma unroll
         for (int d = 0; d < 9; ++d) {
           T val = a.r[d * cs + v];
-          if (!first) val += beta * a.p_old[d * cs + v];
+          if (!st.first) val += st.beta * a.p_old[d * cs + v];
           pd[d] = val;
         }
 #pragma unroll
         for (int q = 0; q < CPB; ++q) {
           const int c = grp * CPB + q;
+          if (st.upd) a.x[c * cs + v] += st.alpha * a.p_old[c * cs + v];
           a.p_new[c * cs + v] = pd[c];
           T acc = T(0);
 #pragma unroll
           for (int d = 0; d < 9; ++d) acc += a.K[(9 * c + d) * cs + v] * pd[d];
           out[hh][q] = acc;
+          kacc += double(pd[c]) * double(acc);
         }
       }
     }
@@ -222,6 +224,10 @@ __device__ __forceinline__ void slab_fwd_body(const SlabFwdArgs<T>& a, int lb,
     const int ky = rem / H, kz = rem - (rem / H) * H;
     const int c = grp * CPB + q;
     a.spec[((size_t)(c * N + x) * N + ky) * H + kz] = lds[cm(q * H + kz, ky)];
+  }
+  if (SRC == SRC_KP && a.pkp_out) {
+    const double t1 = block_sum(kacc, red);
+    if (threadIdx.x == 0) a.pkp_out[lb] = t1;
   }
   if (a.psum) {
     // per-slab, per-component sum and sum of squares: [9][N]
@@ -471,23 +477,90 @@ struct SpectralTraits {
 };
 
 // ---------------------------------------------------- single-RVE kernels
+// the direction step of an SRC_KP pass A that takes it from the scalars
+// (p = r or r + beta p_old, no x update)
+template <typename T>
+__device__ __forceinline__ KpStep<T> kp_step_of(const Scalars* sc) {
+  if (!sc) return KpStep<T>{true, T(0), false, T(0)};
+  return KpStep<T>{sc->first != 0, T(sc->beta), false, T(0)};
+}
+
 template <typename T, int N, int CPB, int SRC>
 __global__ __launch_bounds__(kBlock) void slab_fwd_kernel(SlabFwdArgs<T> a) {
   __shared__ cplx<T> lds[CPB * SlabGeom<N>::PLANE];
   __shared__ cplx<T> tw[N];
   __shared__ double red[kBlock];
   if (a.sc && a.sc->done) return;
-  slab_fwd_body<T, N, CPB, SRC>(a, xcd_remap(blockIdx.x, gridDim.x), lds, tw, red);
+  KpStep<T> st = kp_step_of<T>(SRC == SRC_KP ? a.sc : nullptr);
+  if (SRC == SRC_KP && a.x) {  // timing of the folded pass: x += alpha p_old
+    st.upd = true;
+    st.alpha = T(a.sc->alpha);
+  }
+  slab_fwd_body<T, N, CPB, SRC>(a, xcd_remap(blockIdx.x, gridDim.x), lds, tw,
+                                red, st);
   if (a.pkp && blockIdx.x == 0)
     cg_alpha_publish(a.pkp, a.pkp_count, a.scw, a.parity, red);
+}
+
+// Pass A of a single-RVE CG iteration with the direction kernel folded in
+// (Sec. 2.1, Eqs. 15-16): every block takes the CG decision of the
+// direction kernel itself from the r.r partials of the last pass C (the
+// same fixed-order sum in every block, cg_beta_consume), applies the
+// previous iteration's x += alpha p_old on its own components, forms
+// p = r + beta p_old at each voxel of its slab (all nine components: the
+// nine blocks of a slab run on one XCD and share r and p_old through its
+// L2), writes its components of p and transforms its rows of K : p, and
+// writes its partial of p . (K:p) for the alpha that pass B publishes.  It
+// returns at once after a halted iteration, and applies only the pending x
+// update when this iteration stops the run.
+template <typename T, int N, int CPB>
+__global__ __launch_bounds__(kBlock) void slab_fwd_cg_kernel(SlabFwdArgs<T> a) {
+  __shared__ cplx<T> lds[CPB * SlabGeom<N>::PLANE];
+  __shared__ cplx<T> tw[N];
+  __shared__ double red[kBlock];
+  Scalars* sc = a.scw;
+  // every flag read here was written by an earlier launch: block 0 of this
+  // launch publishes slot `parity` (and done), which no block reads
+  const int q = a.parity ^ 1;
+  if (sc->halt[q]) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->halt[a.parity] = 1;
+    return;
+  }
+  const BetaStep d = cg_beta_consume(a.pinv, a.pinv_count, sc, a.parity, red);
+  if (d.first && sc->done) return;  // b = 0: nothing to solve
+  const KpStep<T> st{d.first, T(d.beta), !d.first && a.x != nullptr,
+                     T(sc->alphas[q])};
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  if (d.stop) {
+    if (st.upd) {
+      constexpr int NG = 9 / CPB;
+      const int x0 = lb / NG, grp = lb - (lb / NG) * NG;
+      for (int t = threadIdx.x; t < N * N; t += blockDim.x) {
+        const int64_t v = (int64_t)x0 * N * N + t;
+#pragma unroll
+        for (int qq = 0; qq < CPB; ++qq) {
+          const int c = grp * CPB + qq;
+          a.x[c * a.cs + v] += st.alpha * a.p_old[c * a.cs + v];
+        }
+      }
+    }
+    return;
+  }
+  slab_fwd_body<T, N, CPB, SRC_KP>(a, lb, lds, tw, red, st);
 }
 
 template <typename T, int N, int TT>
 __global__ __launch_bounds__(kBlock) void pencil_proj_kernel(PencilArgs<T> a) {
   __shared__ cplx<T> lds[3 * (N * (TT + 1) + TT)];
   __shared__ cplx<T> tw[N];
+  __shared__ double red[kBlock];
   if (a.sc && a.sc->done) return;
   pencil_body<T, N, TT>(a, xcd_remap(blockIdx.x, gridDim.x), lds, tw);
+  // fused CG run: alpha = r.r / p.(K:p) from pass A's partials (a breakdown
+  // sets done, which the pass-B blocks that already started ignore: their
+  // spectrum is not used, pass C returns)
+  if (a.pkp && blockIdx.x == 0)
+    cg_alpha_publish(a.pkp, a.pkp_count, a.scw, a.parity, red);
 }
 
 template <typename T, typename TO, int N, int CPB, int DST>
@@ -500,9 +573,21 @@ __global__ __launch_bounds__(kBlock) void slab_inv_kernel(SlabInvArgs<T, TO> a) 
                                     tw, red);
 }
 
+// three component planes per slab block fit the LDS budget of one block
+template <typename T, int N>
+constexpr bool cpb3_fits() {
+  return 3 * SlabGeom<N>::PLANE * (int)sizeof(cplx<T>) <= 64 * 1024;
+}
+template <typename T, int N, int TT>
+constexpr bool pencil_fits() {
+  return (3 * (N * (TT + 1) + TT) + N) * (int)sizeof(cplx<T>) +
+             kBlock * (int)sizeof(double) <= 64 * 1024;
+}
+
 // ------------------------------------------------------- batched kernels
 // Every RVE of a batch in one launch: block -> (RVE, local block) through
-// the descriptor table; the RVE's edge selects the compiled FFT plan.
+// the descriptor table; the RVE's edge and schedule (components per slab
+// block, kz columns per pencil block) select the compiled FFT plan.
 // Converged or retired RVEs (Scalars::done for CG work, ::inactive for the
 // residual) return at once.
 #define RVE_BATCH_SIZES(X) X(16) X(24) X(32) X(40) X(48) X(64)
@@ -515,9 +600,37 @@ __device__ __forceinline__ int batch_item(const BatchSpec<T>& b, int pass,
   return r;
 }
 
+// one RVE's pass bodies in the dynamic LDS of a batched launch
+template <typename T, int NN, int CPB, int SRC>
+__device__ __forceinline__ void slab_fwd_item(const SlabFwdArgs<T>& a, int lb,
+                                              unsigned char* smem,
+                                              const KpStep<T>& st) {
+  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem);
+  cplx<T>* tw = lds + CPB * SlabGeom<NN>::PLANE;
+  double* red = reinterpret_cast<double*>(tw + NN);
+  slab_fwd_body<T, NN, CPB, SRC>(a, lb, lds, tw, red, st);
+}
+template <typename T, typename TO, int NN, int CPB, int DST>
+__device__ __forceinline__ void slab_inv_item(const SlabInvArgs<T, TO>& a,
+                                              int lb, unsigned char* smem) {
+  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem);
+  cplx<T>* tw = lds + CPB * SlabGeom<NN>::PLANE;
+  double* red = reinterpret_cast<double*>(tw + NN);
+  slab_inv_body<T, TO, NN, CPB, DST>(a, lb, lds, tw, red);
+}
+template <typename T, int NN, int TT>
+__device__ __forceinline__ void pencil_item(const PencilArgs<T>& a, int lb,
+                                            unsigned char* smem) {
+  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem);
+  pencil_body<T, NN, TT>(a, lb, lds, lds + 3 * (NN * (TT + 1) + TT));
+}
+
 // Each pass as a block body (blk: the block it plays, a launch's blockIdx.x
 // or a virtual block of the persistent CG kernel) and a one-launch kernel.
-template <typename T, int SRC>
+// CPBS: the slab schedules compiled in (bit 0: one component per block,
+// bit 1: three), so that a launch whose RVEs all use one of them does not
+// carry the registers of the other
+template <typename T, int SRC, int CPBS = 3>
 __device__ __forceinline__ void slab_fwd_batch_block(const BatchSpec<T>& b,
                                                      int blk,
                                                      unsigned char* smem) {
@@ -537,24 +650,27 @@ __device__ __forceinline__ void slab_fwd_batch_block(const BatchSpec<T>& b,
   a.psum = it.psum;
   a.psq = it.psq;
   a.sc = it.sc;
+  const KpStep<T> st = kp_step_of<T>(SRC == SRC_KP ? it.sc : nullptr);
   switch (it.n) {
 #define RVE_CASE(NN)                                                         \
-  case NN: {                                                                 \
-    constexpr int CPB = SpectralTraits<T, NN>::CPB;                          \
-    cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem);                         \
-    cplx<T>* tw = lds + CPB * SlabGeom<NN>::PLANE;                           \
-    double* red = reinterpret_cast<double*>(tw + NN);                        \
-    slab_fwd_body<T, NN, CPB, SRC>(a, lb, lds, tw, red);                     \
-  } break;
+  case NN:                                                                   \
+    if constexpr ((CPBS & 2) && cpb3_fits<T, NN>())                          \
+      if (it.cpb == 3) {                                                     \
+        slab_fwd_item<T, NN, 3, SRC>(a, lb, smem, st);                       \
+        break;                                                               \
+      }                                                                      \
+    if constexpr ((CPBS & 1) || !cpb3_fits<T, NN>())                         \
+      slab_fwd_item<T, NN, 1, SRC>(a, lb, smem, st);                         \
+    break;
     RVE_BATCH_SIZES(RVE_CASE)
 #undef RVE_CASE
   }
 }
 
-template <typename T, int SRC>
+template <typename T, int SRC, int CPBS>
 __global__ __launch_bounds__(kBlock) void slab_fwd_batch_kernel(BatchSpec<T> b) {
   extern __shared__ __align__(16) unsigned char smem[];
-  slab_fwd_batch_block<T, SRC>(b, blockIdx.x, smem);
+  slab_fwd_batch_block<T, SRC, CPBS>(b, blockIdx.x, smem);
 }
 
 template <typename T>
@@ -572,12 +688,18 @@ __device__ __forceinline__ void pencil_batch_block(const BatchSpec<T>& b,
   a.sc = nullptr;
   switch (it.n) {
 #define RVE_CASE(NN)                                                         \
-  case NN: {                                                                 \
-    constexpr int TT = SpectralTraits<T, NN>::TT;                            \
+  case NN:                                                                   \
     a.invN3 = T(1.0 / (double(NN) * NN * NN));                               \
-    cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem);                         \
-    pencil_body<T, NN, TT>(a, lb, lds, lds + 3 * (NN * (TT + 1) + TT));             \
-  } break;
+    if constexpr (pencil_fits<T, NN, 16>())                                  \
+      if (it.tt == 16) {                                                     \
+        pencil_item<T, NN, 16>(a, lb, smem);                                 \
+        break;                                                               \
+      }                                                                      \
+    if (it.tt == 4)                                                          \
+      pencil_item<T, NN, 4>(a, lb, smem);                                    \
+    else                                                                     \
+      pencil_item<T, NN, 8>(a, lb, smem);                                    \
+    break;
     RVE_BATCH_SIZES(RVE_CASE)
 #undef RVE_CASE
   }
@@ -590,7 +712,7 @@ __global__ __launch_bounds__(kBlock) void pencil_batch_kernel(BatchSpec<T> b,
   pencil_batch_block<T>(b, cg, blockIdx.x, smem);
 }
 
-template <typename T, typename TO, int DST>
+template <typename T, typename TO, int DST, int CPBS = 3>
 __device__ __forceinline__ void slab_inv_batch_block(const BatchSpec<T>& b,
                                                      TO* out, int blk,
                                                      unsigned char* smem) {
@@ -608,23 +730,25 @@ __device__ __forceinline__ void slab_inv_batch_block(const BatchSpec<T>& b,
   a.sc = nullptr;
   switch (it.n) {
 #define RVE_CASE(NN)                                                         \
-  case NN: {                                                                 \
-    constexpr int CPB = SpectralTraits<T, NN>::CPB;                          \
-    cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem);                         \
-    cplx<T>* tw = lds + CPB * SlabGeom<NN>::PLANE;                           \
-    double* red = reinterpret_cast<double*>(tw + NN);                        \
-    slab_inv_body<T, TO, NN, CPB, DST>(a, lb, lds, tw, red);                 \
-  } break;
+  case NN:                                                                   \
+    if constexpr ((CPBS & 2) && cpb3_fits<T, NN>())                          \
+      if (it.cpb == 3) {                                                     \
+        slab_inv_item<T, TO, NN, 3, DST>(a, lb, smem);                       \
+        break;                                                               \
+      }                                                                      \
+    if constexpr ((CPBS & 1) || !cpb3_fits<T, NN>())                         \
+      slab_inv_item<T, TO, NN, 1, DST>(a, lb, smem);                         \
+    break;
     RVE_BATCH_SIZES(RVE_CASE)
 #undef RVE_CASE
   }
 }
 
-template <typename T, typename TO, int DST>
+template <typename T, typename TO, int DST, int CPBS>
 __global__ __launch_bounds__(kBlock) void slab_inv_batch_kernel(BatchSpec<T> b,
                                                                 TO* out) {
   extern __shared__ __align__(16) unsigned char smem[];
-  slab_inv_batch_block<T, TO, DST>(b, out, blockIdx.x, smem);
+  slab_inv_batch_block<T, TO, DST, CPBS>(b, out, blockIdx.x, smem);
 }
 
 // ------------------------------------------------- persistent batched CG
@@ -789,15 +913,6 @@ template int cg_batch_persistent_grid<float>(size_t);
 template int cg_batch_persistent_grid<double>(size_t);
 
 // ---------------------------------------------------------------- launchers
-// three component planes per slab block fit the LDS budget of one block
-template <typename T, int N>
-constexpr bool cpb3_fits() {
-  return 3 * SlabGeom<N>::PLANE * (int)sizeof(cplx<T>) <= 64 * 1024;
-}
-template <typename T, int N, int TT>
-constexpr bool pencil_fits() {
-  return (3 * (N * (TT + 1) + TT) + N) * (int)sizeof(cplx<T>) <= 64 * 1024;
-}
 
 template <typename T, int N, int CPB, int TT>
 void launch_G_passes(const SpectralLaunch<T>& L, hipStream_t s) {
@@ -834,8 +949,22 @@ void launch_G_passes(const SpectralLaunch<T>& L, hipStream_t s) {
     fa.psum = nullptr;
     fa.psq = nullptr;
     fa.sc = L.sc;
-    launch((slab_fwd_kernel<T, N, CPB, SRC_KP>), dim3(nslab),
-                       dim3(kBlock), 0, s, fa);
+    if (L.pinv) {
+      // fused CG run: pass A writes the p.(K:p) partials that pass B reduces
+      fa.pinv = L.pinv;
+      fa.pinv_count = L.pinv_count;
+      fa.x = L.x;
+      fa.pkp_out = const_cast<double*>(L.pkp);
+      fa.parity = L.parity;
+      fa.scw = L.sc;
+      launch((slab_fwd_cg_kernel<T, N, CPB>), dim3(nslab), dim3(kBlock), 0, s,
+             fa);
+    } else {
+      // direction and K:p from the scalars (with x: x += alpha p_old too)
+      fa.x = L.x;
+      launch((slab_fwd_kernel<T, N, CPB, SRC_KP>), dim3(nslab),
+                         dim3(kBlock), 0, s, fa);
+    }
   }
   if (L.passes & 2) {
   PencilArgs<T> pa{};
@@ -844,6 +973,12 @@ void launch_G_passes(const SpectralLaunch<T>& L, hipStream_t s) {
   pa.vt = L.vt;
   pa.invN3 = T(1.0 / (double(N) * N * N));
   pa.sc = L.sc;
+  if (L.src == SRC_KP && L.pinv && L.pkp) {
+    pa.pkp = L.pkp;
+    pa.pkp_count = L.pkp_count;
+    pa.parity = L.parity;
+    pa.scw = L.sc;
+  }
   launch((pencil_proj_kernel<T, N, TT>), dim3(N * NTILE * 3),
                      dim3(kBlock), 0, s, pa);
   }
@@ -977,52 +1112,87 @@ bool batch_supported(int n) {
 }
 
 template <typename T>
-void batch_lds(int n, size_t& slab, size_t& pencil) {
-  switch (n) {
-#define RVE_CASE(NN)                                   \
-  case NN:                                             \
-    slab = SpectralTraits<T, NN>::SLAB_LDS;            \
-    pencil = SpectralTraits<T, NN>::PENCIL_LDS;        \
+void batch_lds(int n, int cpb, int tt, size_t& slab, size_t& pencil) {
+  if (!batch_supported(n)) throw Error(-1, "grid edge not supported in a batch");
+  if (!schedule_valid(n, sizeof(T) == 8, cpb, tt))
+    throw Error(-1, "no such FFT schedule for this grid edge and precision");
+  // the layouts of slab_fwd_item / slab_inv_item and pencil_item
+  const size_t plane = (size_t)(n / 2) * (n + 1);
+  slab = (cpb * plane + n) * sizeof(cplx<T>) + kBlock * sizeof(double);
+  pencil = (3 * ((size_t)n * (tt + 1) + tt) + n) * sizeof(cplx<T>);
+}
+
+// the default schedule of a grid edge and precision
+void default_schedule(int n, bool fp64, int& cpb, int& tt) {
+  auto pick = [&](auto tag) {
+    using T = decltype(tag);
+    switch (n) {
+#define RVE_DEF(NN)                          \
+  case NN:                                   \
+    cpb = SpectralTraits<T, NN>::CPB;        \
+    tt = SpectralTraits<T, NN>::TT;          \
     return;
-    RVE_BATCH_SIZES(RVE_CASE)
-#undef RVE_CASE
+      RVE_DEF(16) RVE_DEF(24) RVE_DEF(32) RVE_DEF(40) RVE_DEF(48)
+      RVE_DEF(64) RVE_DEF(96) RVE_DEF(128)
+#undef RVE_DEF
+    }
+    throw Error(-1, "grid edge not supported");
+  };
+  if (fp64) pick(double{}); else pick(float{});
+}
+
+template <typename T, int CPBS>
+void launch_G_batch_cpbs(const BatchSpec<T>& b, int src, T* out_T,
+                         double* out_d, int blocksA, int blocksB, size_t ldsA,
+                         size_t ldsB, hipStream_t s) {
+  if (src == SRC_FIELD) {
+    hipLaunchKernelGGL((slab_fwd_batch_kernel<T, SRC_FIELD, CPBS>),
+                       dim3(blocksA), dim3(kBlock), ldsA, s, b);
+    hipLaunchKernelGGL((pencil_batch_kernel<T>), dim3(blocksB), dim3(kBlock),
+                       ldsB, s, b, 0);
+    hipLaunchKernelGGL((slab_inv_batch_kernel<T, double, DST_NORM, CPBS>),
+                       dim3(blocksA), dim3(kBlock), ldsA, s, b, out_d);
+  } else {
+    hipLaunchKernelGGL((slab_fwd_batch_kernel<T, SRC_KP, CPBS>), dim3(blocksA),
+                       dim3(kBlock), ldsA, s, b);
+    hipLaunchKernelGGL((pencil_batch_kernel<T>), dim3(blocksB), dim3(kBlock),
+                       ldsB, s, b, 1);
+    hipLaunchKernelGGL((slab_inv_batch_kernel<T, T, DST_DOT, CPBS>),
+                       dim3(blocksA), dim3(kBlock), ldsA, s, b, out_T);
   }
-  throw Error(-1, "grid edge not supported in a batch");
 }
 
 template <typename T>
 void launch_G_batch(const BatchSpec<T>& b, int src, T* out_T, double* out_d,
                     int blocksA, int blocksB, size_t ldsA, size_t ldsB,
                     hipStream_t s) {
-  if (src == SRC_FIELD) {
-    hipLaunchKernelGGL((slab_fwd_batch_kernel<T, SRC_FIELD>), dim3(blocksA),
-                       dim3(kBlock), ldsA, s, b);
-    hipLaunchKernelGGL((pencil_batch_kernel<T>), dim3(blocksB), dim3(kBlock),
-                       ldsB, s, b, 0);
-    hipLaunchKernelGGL((slab_inv_batch_kernel<T, double, DST_NORM>),
-                       dim3(blocksA), dim3(kBlock), ldsA, s, b, out_d);
-  } else {
-    hipLaunchKernelGGL((slab_fwd_batch_kernel<T, SRC_KP>), dim3(blocksA),
-                       dim3(kBlock), ldsA, s, b);
-    hipLaunchKernelGGL((pencil_batch_kernel<T>), dim3(blocksB), dim3(kBlock),
-                       ldsB, s, b, 1);
-    hipLaunchKernelGGL((slab_inv_batch_kernel<T, T, DST_DOT>), dim3(blocksA),
-                       dim3(kBlock), ldsA, s, b, out_T);
-  }
+  if (b.cpbs == 1)
+    launch_G_batch_cpbs<T, 1>(b, src, out_T, out_d, blocksA, blocksB, ldsA, ldsB, s);
+  else if (b.cpbs == 2)
+    launch_G_batch_cpbs<T, 2>(b, src, out_T, out_d, blocksA, blocksB, ldsA, ldsB, s);
+  else
+    launch_G_batch_cpbs<T, 3>(b, src, out_T, out_d, blocksA, blocksB, ldsA, ldsB, s);
 }
 
-// Dynamic LDS above the default 64 KiB (FP64 slabs of edge 64) must be
-// allowed per kernel before the first launch.
-template <typename T>
-void batch_allow_lds(size_t slab, size_t pencil) {
+// Dynamic LDS above the default 64 KiB must be allowed per kernel before
+// the first launch.
+template <typename T, int CPBS>
+void batch_allow_lds_cpbs(size_t slab) {
   const void* slabs[] = {
-      reinterpret_cast<const void*>(&slab_fwd_batch_kernel<T, SRC_FIELD>),
-      reinterpret_cast<const void*>(&slab_fwd_batch_kernel<T, SRC_KP>),
-      reinterpret_cast<const void*>(&slab_inv_batch_kernel<T, double, DST_NORM>),
-      reinterpret_cast<const void*>(&slab_inv_batch_kernel<T, T, DST_DOT>)};
+      reinterpret_cast<const void*>(&slab_fwd_batch_kernel<T, SRC_FIELD, CPBS>),
+      reinterpret_cast<const void*>(&slab_fwd_batch_kernel<T, SRC_KP, CPBS>),
+      reinterpret_cast<const void*>(&slab_inv_batch_kernel<T, double, DST_NORM, CPBS>),
+      reinterpret_cast<const void*>(&slab_inv_batch_kernel<T, T, DST_DOT, CPBS>)};
   for (const void* f : slabs)
     RVE_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)slab));
+}
+
+template <typename T>
+void batch_allow_lds(size_t slab, size_t pencil) {
+  batch_allow_lds_cpbs<T, 1>(slab);
+  batch_allow_lds_cpbs<T, 2>(slab);
+  batch_allow_lds_cpbs<T, 3>(slab);
   RVE_HIP(hipFuncSetAttribute(
       reinterpret_cast<const void*>(&pencil_batch_kernel<T>),
       hipFuncAttributeMaxDynamicSharedMemorySize, (int)pencil));
@@ -1036,8 +1206,8 @@ template void launch_G_batch<float>(const BatchSpec<float>&, int, float*,
 template void launch_G_batch<double>(const BatchSpec<double>&, int, double*,
                                      double*, int, int, size_t, size_t,
                                      hipStream_t);
-template void batch_lds<float>(int, size_t&, size_t&);
-template void batch_lds<double>(int, size_t&, size_t&);
+template void batch_lds<float>(int, int, int, size_t&, size_t&);
+template void batch_lds<double>(int, int, int, size_t&, size_t&);
 template void launch_G<float>(int, const SpectralLaunch<float>&, hipStream_t);
 template void launch_G<double>(int, const SpectralLaunch<double>&, hipStream_t);
 

@@ -246,3 +246,57 @@ def test_device_controlled_batch_past_the_captured_iterations():
         assert b.macro(0)["increments"] == 0
     finally:
         b.close()
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_schedules_tuned_per_edge_and_forced_agree(graph):
+    """Each grid edge of a batch gets its own CG-matvec schedule, tuned at
+    the first increment (a valid one, with a positive tuned time) or
+    forced; every forced combination gives the increments of the tuned
+    batch (same Newton counts, sigma_bar to 1e-6: only the order of the
+    p.Ap partial sums differs), on the host-driven and device-controlled
+    paths.  Invalid schedules and edges are rejected; (0, 0) re-tunes."""
+    from paper_1806_10599_amd.binding import RveError
+    micros = _micros()[:2]          # edges 16 and 24
+    hist = config_by_name("C1").history()[:2]
+    ref = _batch(micros, "discrete", "mixed", use_graph=graph)
+    try:
+        ri = [ref.increment(inc["F_bar"], inc["dt"]) for inc in hist]
+        sch = ref.fft_schedules()
+        assert set(sch) == {16, 24}
+        for e, s in sch.items():
+            assert s["cpb"] in (1, 3) and s["tt"] in (4, 8, 16), (e, s)
+            assert s["tuned_ms"] > 0.0
+        sref = [ref.macro(j)["sigma_bar"] for j in range(2)]
+    finally:
+        ref.close()
+    combos = [((1, 4), (3, 16)), ((3, 8), (1, 8)), ((1, 16), (3, 4))]
+    for s16, s24 in combos:
+        b = _batch(micros, "discrete", "mixed", use_graph=graph)
+        try:
+            b.set_fft_schedule(16, *s16)
+            b.set_fft_schedule(24, *s24)
+            for inc, a in zip(hist, ri):
+                infos = b.increment(inc["F_bar"], inc["dt"])
+                for i, ia in zip(infos, a):
+                    assert i["status"] == 0
+                    assert i["newton_iters"] == ia["newton_iters"]
+            got = b.fft_schedules()
+            assert (got[16]["cpb"], got[16]["tt"]) == s16
+            assert (got[24]["cpb"], got[24]["tt"]) == s24
+            assert got[16]["tuned_ms"] == 0.0
+            for j in range(2):
+                assert rel_maxnorm(b.macro(j)["sigma_bar"], sref[j]) < 1e-6
+            with pytest.raises(RveError):
+                b.set_fft_schedule(16, 2, 8)
+            with pytest.raises(RveError):
+                b.set_fft_schedule(32, 1, 8)
+            b.set_fft_schedule(16, 0, 0)
+            inc = config_by_name("C1").history()[2]
+            assert all(i["status"] == 0
+                       for i in b.increment(inc["F_bar"], inc["dt"]))
+            assert b.fft_schedules()[16]["tuned_ms"] > 0.0
+            assert (b.fft_schedules()[24]["cpb"],
+                    b.fft_schedules()[24]["tt"]) == s24
+        finally:
+            b.close()

@@ -50,13 +50,19 @@ def test_homogeneous_medium_single_evaluation():
         r.close()
 
 
-# the whole C1 cycle is compared in test_gpu_vs_oracle.py
-@pytest.mark.parametrize("cfg,ninc", [("C1", 2), ("C2", 2)])
-def test_fp64_increments_match_oracle(cfg, ninc):
+# the whole C1 cycle is compared in test_gpu_vs_oracle.py; sched forces the
+# CG matvec with the direction step and K:p folded into the first transform
+# pass (one and three components per slab block)
+@pytest.mark.parametrize("cfg,ninc,sched", [
+    ("C1", 2, None), ("C2", 2, None), ("C1", 3, (1, 8, 1)),
+    ("C1", 3, (3, 8, 1)), ("C2", 2, (1, 8, 1))])
+def test_fp64_increments_match_oracle(cfg, ninc, sched):
     c = config_by_name(cfg)
     micro = c.microstructure()
     hist = c.history()[:ninc]
     r = make_rve(micro, c.operator, "fp64", **TIGHT)
+    if sched:
+        r.set_fft_schedule(*sched)
     o = oracle_for(micro, c.operator)
     try:
         for inc in hist:
@@ -66,6 +72,8 @@ def test_fp64_increments_match_oracle(cfg, ninc):
             assert info["status"] == 0 and oi.status == 0
             _compare_state(r, o)
             assert rel_maxnorm(info["P_bar"], oi.P_bar) < 1e-10
+        if sched:
+            assert r.fft_schedule()["fused"] == sched[2]
     finally:
         r.close()
 
@@ -211,9 +219,11 @@ def test_live_kernel_timing_counts_and_leaves_results_unchanged(graph):
 
 
 def test_fft_schedules_agree_and_autotune_picks_one():
-    """Every valid CG-matvec schedule gives the same increments (the
-    schedules regroup the same per-component transforms; only the order of
-    the p.Ap partial sums differs); the default tunes one."""
+    """Every valid CG-matvec schedule, with the direction step in its own
+    kernel or folded into the first transform pass, gives the same
+    increments (the schedules regroup the same per-component transforms;
+    only the order of the p.Ap partial sums differs); the default tunes
+    one."""
     from paper_1806_10599_amd.binding import RveError
     c = config_by_name("C1")
     micro = c.microstructure()
@@ -223,25 +233,29 @@ def test_fft_schedules_agree_and_autotune_picks_one():
         ri = [ref.increment(inc["F_bar"], inc["dt"]) for inc in hist]
         sch = ref.fft_schedule()
         assert sch["cpb"] in (1, 3) and sch["tt"] in (4, 8, 16)
+        assert sch["fused"] in (0, 1)
         assert sch["tuned_ms"] > 0.0
     finally:
         ref.close()
-    for cpb in (1, 3):
-        for tt in (4, 8, 16):
-            r = make_rve(micro, c.operator, "mixed")
-            try:
-                r.set_fft_schedule(cpb, tt)
-                for inc, a in zip(hist, ri):
-                    b = r.increment(inc["F_bar"], inc["dt"])
-                    assert b["status"] == 0
-                    assert b["newton_iters"] == a["newton_iters"]
-                    assert rel_maxnorm(b["sigma_bar"], a["sigma_bar"]) < 1e-6
-                assert r.fft_schedule()["cpb"] == cpb
-                assert r.fft_schedule()["tt"] == tt
-                with pytest.raises(RveError):
-                    r.set_fft_schedule(2, 8)
-            finally:
-                r.close()
+    for fused in (0, 1):
+        for cpb in (1, 3):
+            for tt in (4, 8, 16):
+                r = make_rve(micro, c.operator, "mixed")
+                try:
+                    r.set_fft_schedule(cpb, tt, fused)
+                    for inc, a in zip(hist, ri):
+                        b = r.increment(inc["F_bar"], inc["dt"])
+                        assert b["status"] == 0
+                        assert b["newton_iters"] == a["newton_iters"]
+                        assert rel_maxnorm(b["sigma_bar"], a["sigma_bar"]) < 1e-6
+                    got = r.fft_schedule()
+                    assert (got["cpb"], got["tt"], got["fused"]) == (cpb, tt, fused)
+                    with pytest.raises(RveError):
+                        r.set_fft_schedule(2, 8)
+                    with pytest.raises(RveError):
+                        r.set_fft_schedule(1, 8, 2)
+                finally:
+                    r.close()
 
 
 def test_full_size_chosen_path_against_oracle(oracle_map):

@@ -254,6 +254,42 @@ def test_batched_G_every_batch_edge(precision, tol):
             assert err < tol, (op, n, err)
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("mixed", 3e-6)])
+def test_batched_G_every_schedule(precision, tol):
+    """G through the batched passes under every schedule an edge can take
+    (one or three components per slab block, 4, 8 or 16 kz columns per
+    pencil block), forced per edge, element by element against the
+    oracle's G (discrete operator)."""
+    from oracle.projection import apply_G
+    from paper_1806_10599_amd.binding import BatchRve, RveError
+    ns = [16, 24, 40, 64]
+    rng = np.random.default_rng(4049)
+    A = [rng.standard_normal((9, n ** 3)) for n in ns]
+    ref = [apply_G(a.reshape(3, 3, n, n, n), (1, 1, 1), "discrete")
+           .reshape(9, -1) for n, a in zip(ns, A)]
+    b = BatchRve(ns, projection="discrete", precision=precision)
+    try:
+        tried = 0
+        for cpb in (1, 3):
+            for tt in (4, 8, 16):
+                ok = []
+                for n in ns:
+                    try:
+                        b.set_fft_schedule(n, cpb, tt)
+                        ok.append(n)
+                    except RveError:   # does not fit this edge's LDS
+                        b.set_fft_schedule(n, 1, 8)
+                out = b.debug_apply_G(A)
+                for n, o, rf, a in zip(ns, out, ref, A):
+                    if n in ok:
+                        err = np.max(np.abs(o - rf)) / np.max(np.abs(a))
+                        assert err < tol, (cpb, tt, n, err)
+                        tried += 1
+        assert tried >= 20
+    finally:
+        b.close()
+
+
 @pytest.mark.oracle_jobs("g128_discrete", "g128_continuous")
 @pytest.mark.parametrize("op", ["discrete", "continuous"])
 def test_apply_G_largest_grid_matches_oracle(oracle_run, op):
