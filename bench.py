@@ -10,10 +10,13 @@ warm-start network never saw in training); the increments before them run
 untimed to reach that state.
 
 * chosen: FP32 FFT/projection/CG, FP64 return mapping/residual/averages,
-  learned warm start with the homogeneous predictor as fallback (the
-  shipped weights), FFT schedule tuned on the live buffers.  Direct launches: replaying the
-  CG chunks from captured graphs (--graph) measures the same rate here, and
-  direct launches let each timed kernel record its own start and end.
+  learned warm start (the shipped network's correction to the extrapolated
+  fluctuation increment, kept at once when well below the homogeneous
+  predictor's last residual, with the homogeneous predictor as fallback),
+  inexact-Newton forcing (mode 2), CG schedule tuned on the live buffers.
+  Direct launches: replaying the CG chunks from captured graphs (--graph)
+  measures the same rate here, and direct launches let each timed kernel
+  record its own start and end.
 * plain:  FP64 everywhere, direct launches, same kernels, same inputs.
 
 ``value`` is the chosen path's voxel-increments/s.  Inside its timed region
@@ -87,6 +90,11 @@ RM_FLOPS = {"eval64": 1206, "eval32": 72, "step64": 60, "step32": 2350,
 # the sample increments before the timed region (one event pair per launch
 # of four CG kernels costs several per cent of the throughput).
 LIVE_CLASSES = ("return_map", "tangent", "residual_fp64", "matvec_kp")
+# the K:p kernel (one launch per CG iteration) is timed on one launch in
+# seven in the timed region: an event pair on every launch cost about 8 % of
+# the throughput; seven is prime to the CG chunk length of eight, so the
+# sample walks through every position of a chunk
+LIVE_CG_STRIDE = 7
 # learned warm start: a candidate well below the homogeneous predictor's
 # last residual is kept without evaluating the homogeneous predictor
 WARM_MODE = 2
@@ -236,7 +244,7 @@ def run_path(micro, hist, precision, use_graph, steps, warmup, stream,
         r.set_kernel_timing(())
     fused = bool(r.fft_schedule()["fused"])
     if live:
-        r.set_kernel_timing(live_classes(fused))
+        r.set_kernel_timing(live_classes(fused), cg_stride=LIVE_CG_STRIDE)
     torch.cuda.synchronize()
     r.kernel_timing(reset=True)
     r.return_map_counts(reset=True)
@@ -268,6 +276,7 @@ def run_path(micro, hist, precision, use_graph, steps, warmup, stream,
                    F=after["F"], P=after["P"], dg=after["dgamma"],
                    residual_rel=timed[-1]["residual_rel"])
     live_t = r.kernel_timing() if live else None
+    seen = r.kernel_launches() if live else None
     counts = r.return_map_counts() if live else None
     sched = r.fft_schedule()
     nonlocal_ = nonlocal_fips_report(r, micro.n) if with_fips else None
@@ -279,7 +288,8 @@ def run_path(micro, hist, precision, use_graph, steps, warmup, stream,
         r.attach_warm_start(None)
         net.close()
     r.close()
-    return dict(elapsed=elapsed, infos=timed, live=live_t, rm_counts=counts,
+    return dict(elapsed=elapsed, infos=timed, live=live_t, seen=seen,
+                rm_counts=counts,
                 sigma11=sig, schedule=sched, start=start, nonlocal_=nonlocal_,
                 passes=passes, check=chk, sample=sample)
 
@@ -332,10 +342,13 @@ def nonlocal_fips_report(r, n, width_voxels=2.0):
 
 def batch_run(steps, stream):
     """The batch workload: 32 RVEs of edges 24-48 (20-150 grains each, about
-    1.8 M voxels), one launch per pass for the whole batch, CG chunks replayed
-    from a captured graph; then the same RVEs and increments solved one after
-    another with single-RVE handles (same precision, operator and
-    tolerances).  Both timed over the first ``steps`` increments."""
+    1.8 M voxels), one launch per pass for the whole batch with a CG
+    schedule tuned per edge and the host checking each CG chunk; the same
+    batch with the device-controlled increment (one persistent launch per
+    linear solve, captured graph); then the same RVEs and increments solved
+    one after another with single-RVE handles (same precision, operator and
+    tolerances).  All timed over the first ``steps`` increments, schedules
+    tuned beforehand."""
     import torch
     from paper_1806_10599_amd.binding import BatchRve, Rve
     from synthetic import config_by_name, material_params
@@ -929,7 +942,7 @@ def pmc_traffic(kernel, fused=False):
         return None
 
 
-def live_report(live, rmc, N, cg_total, sample=None, fused=False):
+def live_report(live, rmc, N, cg_total, sample=None, fused=False, seen=None):
     """Per-kernel live durations, FFT bandwidth and the dominant kernel's
     roofline from the event timings of the timed region.  The dominant
     kernel is the one with the largest total time per increment over the
@@ -940,8 +953,11 @@ def live_report(live, rmc, N, cg_total, sample=None, fused=False):
     sample's."""
     pb = pass_bytes(fused)
     avg_ms = {k: (ms / n if n else None) for k, (ms, n) in live.items()}
-    total_ms = {k: ms for k, (ms, n) in live.items()}
     launches = {k: n for k, (ms, n) in live.items()}
+    # every launch of a class (the CG classes are timed on a sample of them)
+    allk = {k: (seen[k] if seen and seen.get(k) else launches[k]) for k in live}
+    # time of all launches: the sampled average times every launch
+    total_ms = {k: (avg_ms[k] * allk[k] if avg_ms[k] else 0.0) for k in live}
     # matvec passes: bytes actually streamed = per-voxel bytes x voxels x
     # CG iterations done (launches past convergence in a replayed chunk
     # return at once and move nothing)
@@ -956,13 +972,13 @@ def live_report(live, rmc, N, cg_total, sample=None, fused=False):
     rm_flops = rm_f64 + rm_f32
 
     def hbm(k):
-        per_launch = N * pb[k] * cg_total / launches[k]
+        per_launch = N * pb[k] * cg_total / allk[k]
         ach = per_launch / (avg_ms[k] * 1e-3) / 1e9
         return dict(kernel=k, bound="hbm", achieved=round(ach, 1),
                     peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(ach / HBM_PEAK_GBS, 4), traffic=pmc_traffic(k, fused),
                     bytes_per_launch=round(per_launch), avg_ms=round(avg_ms[k], 5),
-                    launches=launches[k])
+                    launches=allk[k], launches_timed=launches[k])
 
     def alu():
         # FP32 work is charged at the FP64 rate: this build disables the
@@ -992,7 +1008,10 @@ def live_report(live, rmc, N, cg_total, sample=None, fused=False):
         roof = (hbm(dom) if dom in pb else
                 (alu() if dom == "return_map" else None))
         if roof is not None:
-            roof["timed_over"] = "timed region (HIP events per launch)"
+            roof["timed_over"] = (
+                "timed region (HIP events on the launch"
+                + (f"; one launch in {LIVE_CG_STRIDE} of the CG kernels)"
+                   if roof["kernel"].startswith("matvec") else ")"))
     else:
         ms, n = sample["timing"][dom]
         per_launch = N * pb[dom] * sample["cg_total"] / n
@@ -1010,7 +1029,8 @@ def live_report(live, rmc, N, cg_total, sample=None, fused=False):
         "kernel_avg_ms_live": {k: (round(v, 5) if v else v)
                                for k, v in avg_ms.items()},
         "kernel_total_ms_live": {k: round(v, 3) for k, v in total_ms.items()},
-        "kernel_launches_live": launches,
+        "kernel_launches_live": allk,
+        "kernel_launches_timed_live": launches,
         "return_map_work": dict(rmc, flops=rm_flops, flops_fp64=rm_f64,
                                 flops_fp32=rm_f32),
         "roofline": roof,
@@ -1136,7 +1156,8 @@ def main():
     if live is not None:
         out.update(live_report(live, chosen["rm_counts"], N, cg_total,
                                chosen["sample"],
-                               bool(chosen["schedule"]["fused"])))
+                               bool(chosen["schedule"]["fused"]),
+                               chosen["seen"]))
     if out.get("fft_gbps") is None and chosen["passes"]:
         out["fft_gbps"] = chosen["passes"]["fft_projection_passes"]["gbps"]
     if plain is not None:

@@ -417,6 +417,19 @@ rve_status rve_bench_kernels(rve_t h, int32_t reps, double* ms_out,
 rve_status rve_set_kernel_timing(rve_t h, uint32_t mask);
 rve_status rve_get_kernel_timing(rve_t h, double* ms_total, int64_t* launches,
                                  int32_t count, int32_t reset);
+/* Times only one direct launch in every `stride` (1 to 1024; 1, the
+   default, times every launch) of each CG-iteration class (0-3 and 7,
+   counted per class from this call), so that the events cost little of a
+   timed solve; the other classes and graph-replayed chunks are timed at
+   every launch.  rve_get_kernel_timing then reports the timed launches
+   only.  RVE_EINVAL for a stride out of range. */
+rve_status rve_set_kernel_timing_stride(rve_t h, int32_t stride);
+/* Every direct launch of each timed class [0, count) since the last reset,
+   timed or skipped by the stride (graph replays not included); zeroes these
+   counts and the timing sums when reset != 0.  RVE_EINVAL for count out of
+   [0, 8]. */
+rve_status rve_get_kernel_launches(rve_t h, int64_t* launches, int32_t count,
+                                   int32_t reset);
 /* Work of the return mappings timed while bit 4 (return mapping) is set:
    out[0] local Newton steps and out[1] residual evaluations summed over
    crystal voxels and launches, out[2] crystal and out[3] particle voxel

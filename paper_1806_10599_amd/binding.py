@@ -149,6 +149,9 @@ def _load():
         "rve_bench_kernels": (C.c_int, [C.c_void_p, C.c_int32,
                                         P(C.c_double), C.c_int32]),
         "rve_set_kernel_timing": (C.c_int, [C.c_void_p, C.c_uint32]),
+        "rve_set_kernel_timing_stride": (C.c_int, [C.c_void_p, C.c_int32]),
+        "rve_get_kernel_launches": (C.c_int, [C.c_void_p, P(C.c_int64),
+                                              C.c_int32, C.c_int32]),
         "rve_get_kernel_timing": (C.c_int, [C.c_void_p, P(C.c_double),
                                             P(C.c_int64), C.c_int32,
                                             C.c_int32]),
@@ -570,11 +573,13 @@ class Rve:
         return dict(zip(KERNEL_CLASSES, out.tolist()))
 
     # --------------------------------------------------- learned warm start
-    def set_kernel_timing(self, classes):
-        """Time the given kernel classes live (names of KERNEL_CLASSES)."""
+    def set_kernel_timing(self, classes, cg_stride=1):
+        """Time the given kernel classes live (names of KERNEL_CLASSES);
+        the CG-iteration classes one launch in every cg_stride."""
         mask = 0
         for c in classes:
             mask |= 1 << KERNEL_CLASSES.index(c)
+        self._check(LIB.rve_set_kernel_timing_stride(self._h, int(cg_stride)))
         self._check(LIB.rve_set_kernel_timing(self._h, mask))
 
     def kernel_timing(self, reset=False):
@@ -585,6 +590,15 @@ class Rve:
         self._check(LIB.rve_get_kernel_timing(self._h, ms, cnt, n,
                                               1 if reset else 0))
         return {k: (ms[i], cnt[i]) for i, k in enumerate(KERNEL_CLASSES)}
+
+    def kernel_launches(self, reset=False):
+        """{class: every launch since the last reset, timed or skipped by the
+        CG stride} for the timed classes."""
+        n = len(KERNEL_CLASSES)
+        cnt = (C.c_int64 * n)()
+        self._check(LIB.rve_get_kernel_launches(self._h, cnt, n,
+                                                1 if reset else 0))
+        return {k: cnt[i] for i, k in enumerate(KERNEL_CLASSES)}
 
     def return_map_counts(self, reset=False):
         """Local Newton steps, residual evaluations, crystal and particle

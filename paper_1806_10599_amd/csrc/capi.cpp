@@ -401,11 +401,27 @@ rve_status rve_set_kernel_timing(rve_t h, uint32_t mask) {
   });
 }
 
+rve_status rve_set_kernel_timing_stride(rve_t h, int32_t stride) {
+  return guarded(h, [&] {
+    h->eng->set_timing_stride(stride);
+    return RVE_OK;
+  });
+}
+
 rve_status rve_get_kernel_timing(rve_t h, double* ms_total, int64_t* launches,
                                  int32_t count, int32_t reset) {
   return guarded(h, [&] {
     if (count > 8) throw rve::Error(RVE_EINVAL, "count > 8");
     h->eng->get_timing(ms_total, launches, count, reset != 0);
+    return RVE_OK;
+  });
+}
+
+rve_status rve_get_kernel_launches(rve_t h, int64_t* launches, int32_t count,
+                                   int32_t reset) {
+  return guarded(h, [&] {
+    if (count > 8 || count < 0) throw rve::Error(RVE_EINVAL, "count out of range");
+    h->eng->get_timing(nullptr, nullptr, count, reset != 0, launches);
     return RVE_OK;
   });
 }

@@ -1328,6 +1328,13 @@ void Engine::set_timing(uint32_t mask) {
   timer_.set_mask(mask);
 }
 
+// one launch in every `stride` of the CG-iteration classes is timed (direct
+// launches; graph-replayed chunks time every launch)
+void Engine::set_timing_stride(int stride) {
+  if (stride < 1 || stride > 1024) throw Error(RVE_EINVAL, "stride must be in [1, 1024]");
+  timer_.set_stride(stride, kCgClasses);
+}
+
 void Engine::get_rm_counts(int64_t out[4], bool reset) {
   unsigned long long h[4] = {0, 0, 0, 0};
   if (rm_stats_) {
@@ -1341,9 +1348,10 @@ void Engine::get_rm_counts(int64_t out[4], bool reset) {
   for (int k = 0; k < 4; ++k) out[k] = (int64_t)h[k];
 }
 
-void Engine::get_timing(double* ms, int64_t* launches, int count, bool reset) {
+void Engine::get_timing(double* ms, int64_t* launches, int count, bool reset,
+                        int64_t* seen) {
   if (count < 0) throw Error(RVE_EINVAL, "negative count");
-  timer_.read(ms, launches, count, reset);
+  timer_.read(ms, launches, count, reset, seen);
 }
 
 void Engine::bench_kernels(int reps, double* ms, int count) {

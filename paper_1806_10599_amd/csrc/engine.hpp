@@ -47,7 +47,9 @@ class Engine {
   void debug_set_field(int field, const double* src, size_t bytes);
   void bench_kernels(int reps, double* ms, int count);
   void set_timing(uint32_t mask);
-  void get_timing(double* ms, int64_t* launches, int count, bool reset);
+  void set_timing_stride(int stride);
+  void get_timing(double* ms, int64_t* launches, int count, bool reset,
+                  int64_t* seen = nullptr);
   void get_rm_counts(int64_t out[4], bool reset);
   // FFT schedule of the CG matvec: (0, 0) = autotune at the next solve;
   // fused: the direction kernel folded into pass A

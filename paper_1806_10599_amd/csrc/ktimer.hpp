@@ -24,17 +24,31 @@ class KernelTimer {
   uint32_t mask() const { return mask_; }
   void set_mask(uint32_t m) { mask_ = m & ((1u << kClasses) - 1); }
   bool on(int k) const { return (mask_ >> k) & 1u; }
+  // direct launches of the classes in `sampled` are timed one in every
+  // `stride` (per class, from the first), the others every launch
+  void set_stride(int stride, uint32_t sampled) {
+    stride_ = stride < 1 ? 1 : stride;
+    sampled_ = sampled;
+    for (int k = 0; k < kClasses; ++k) seq_[k] = 0;
+  }
+  int stride() const { return stride_; }
 
   // times the next kernel launched through rve::launch as class k (no-op
-  // when k is off): the launch records the events itself
+  // when k is off or not sampled this time): the launch records the events
+  // itself
   void begin(int k, hipStream_t) {
+    active_ = false;
     if (!on(k)) return;
+    ++seen_[k];
+    if (((sampled_ >> k) & 1u) && (seq_[k]++ % stride_) != 0) return;
+    active_ = true;
     open_ = take();
     close_ = take();
     g_next_launch_events = NextLaunchEvents{open_, close_};
   }
   void end(int k, hipStream_t) {
-    if (!on(k)) return;
+    if (!on(k) || !active_) return;
+    active_ = false;
     if (g_next_launch_events.start) {
       g_next_launch_events = NextLaunchEvents{};
       throw Error(-1, "timed kernel class was not launched through rve::launch");
@@ -84,15 +98,20 @@ class KernelTimer {
     replay_.clear();
   }
 
-  void read(double* ms, int64_t* count, int n, bool reset) {
+  // summed ms and counts of the timed launches; `seen`: every direct
+  // launch of a timed class, sampled or not (graph replays not included)
+  void read(double* ms, int64_t* count, int n, bool reset,
+            int64_t* seen = nullptr) {
     for (int k = 0; k < n && k < kClasses; ++k) {
       if (ms) ms[k] = ms_[k];
       if (count) count[k] = count_[k];
+      if (seen) seen[k] = seen_[k];
     }
     if (reset)
       for (int k = 0; k < kClasses; ++k) {
         ms_[k] = 0.0;
         count_[k] = 0;
+        seen_[k] = 0;
       }
   }
 
@@ -127,6 +146,11 @@ class KernelTimer {
   }
 
   uint32_t mask_ = 0;
+  int stride_ = 1;
+  uint32_t sampled_ = 0;
+  int64_t seq_[kClasses] = {};
+  int64_t seen_[kClasses] = {};
+  bool active_ = false;
   hipEvent_t open_ = nullptr, close_ = nullptr;
   std::vector<hipEvent_t> all_, free_;
   std::vector<Pair> pending_, replay_;

@@ -888,7 +888,8 @@ __global__ __launch_bounds__(256) void rm_count_kernel(
   if (threadIdx.x < 4) atomicAdd(&stats[threadIdx.x], red[threadIdx.x][0]);
 }
 
-// FP32 linear algebra (mixed mode) fits two waves per SIMD without spills
+// FP32 linear algebra (mixed mode): two waves per SIMD with 448 B of scratch
+// per lane beat one wave without (0.336 against 0.382 ms at 64^3)
 template <typename TK>
 __global__ __launch_bounds__(128, sizeof(TK) == 4 ? RVE_TAN_MINB32 : 1) void
 tangent_kernel(TangentArgs<TK> A) {

@@ -196,8 +196,12 @@ def test_live_kernel_timing_counts_and_leaves_results_unchanged(graph):
         # launches past convergence: the rest of the converging chunk and
         # the chunk queued ahead of the host check (they return at once)
         chunk = 8
-        for k in ("matvec_kp", "matvec_pass_a", "matvec_pass_b",
-                  "matvec_pass_c"):
+        fused = b.fft_schedule()["fused"]   # K:p inside pass A: no K:p kernel
+        cgk = ("matvec_pass_a", "matvec_pass_b", "matvec_pass_c") + (
+            () if fused else ("matvec_kp",))
+        if fused:
+            assert t["matvec_kp"] == (0.0, 0)
+        for k in cgk:
             ms, n = t[k]
             assert ms > 0.0
             if graph:   # whole chunks are replayed
@@ -211,7 +215,23 @@ def test_live_kernel_timing_counts_and_leaves_results_unchanged(graph):
         b.set_kernel_timing(())
         inc = c.history()[3]
         ib = b.increment(inc["F_bar"], inc["dt"])
+        ia = a.increment(inc["F_bar"], inc["dt"])
         assert ib["status"] == 0
+        assert all(v == (0.0, 0) for v in b.kernel_timing().values())
+        # one launch in seven of the CG classes: counted all, timed a sample
+        b.set_kernel_timing(KERNEL_CLASSES, cg_stride=7)
+        inc = c.history()[4]
+        ib = b.increment(inc["F_bar"], inc["dt"])
+        ia = a.increment(inc["F_bar"], inc["dt"])
+        assert ib["residuals"] == ia["residuals"]
+        t, seen = b.kernel_timing(), b.kernel_launches(reset=True)
+        assert t["return_map"][1] == seen["return_map"] == ib["newton_iters"] + 1
+        for k in cgk:
+            if graph:   # replayed chunks time every launch (not counted)
+                assert seen[k] == 0 and t[k][1] % 8 == 0 and t[k][1] > 0
+            else:
+                assert seen[k] >= ib["cg_iters_total"]
+                assert t[k][1] == (seen[k] + 6) // 7 and t[k][0] > 0.0
         assert all(v == (0.0, 0) for v in b.kernel_timing().values())
     finally:
         a.close()
