@@ -197,9 +197,9 @@ def test_gradients_match_oracle_elementwise():
 
 def test_training_follows_the_oracle():
     """Forty Adam steps on the GPU track forty Adam steps of the FP64
-    oracle network from the same parameters and data (the GPU rounds
-    weights and activations to bf16, hence the loose tolerance), and the
-    loss falls."""
+    oracle network from the same parameters and data, step by step (the GPU
+    rounds weights and activations to bf16, hence the 3 % tolerance), and
+    the loss falls with the oracle's."""
     import torch
     from paper_1806_10599_amd.warmstart import init_params, unflatten
     n, steps, lr = 16, 40, 1e-3
@@ -219,9 +219,12 @@ def test_training_follows_the_oracle():
         L, g = ref.loss_and_grads(Xref, Tref)
         ref_losses.append(L)
         ref.params = conv.adam_step(ref.params, g, state, lr=lr)
-    for k in (0, 10, 20, steps - 1):
+    # every step of the trajectory, and the oracle's own loss falls, so the
+    # GPU's falls with it
+    for k in range(steps):
         assert abs(losses[k] - ref_losses[k]) <= 0.03 * ref_losses[k], (
             k, losses[k], ref_losses[k])
+    assert ref_losses[-1] < 0.85 * ref_losses[0], (ref_losses[0], ref_losses[-1])
     assert losses[-1] < 0.85 * losses[0], (losses[0], losses[-1])
 
 
