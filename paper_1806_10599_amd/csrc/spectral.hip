@@ -490,6 +490,10 @@ __global__ __launch_bounds__(kBlock) void slab_fwd_kernel(SlabFwdArgs<T> a) {
   __shared__ cplx<T> lds[CPB * SlabGeom<N>::PLANE];
   __shared__ cplx<T> tw[N];
   __shared__ double red[kBlock];
+  // done comes from an earlier launch, except after a breakdown that block
+  // 0 of this launch publishes at its end (cg_alpha_publish): blocks that
+  // read done before that write and go on only fill the spectrum, which
+  // the inverse pass of a stopped run never reads (it returns on done)
   if (a.sc && a.sc->done) return;
   KpStep<T> st = kp_step_of<T>(SRC == SRC_KP ? a.sc : nullptr);
   if (SRC == SRC_KP && a.x) {  // timing of the folded pass: x += alpha p_old
