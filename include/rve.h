@@ -348,7 +348,9 @@ const char* rve_last_error(rve_t h);
    rve_debug_constitutive: evaluates the point law (Sec. 2.1, Eq. 2; Eq. 13
    tangent) at F[9][N] with the committed internal variables and time step dt,
    writing P[9][N], K[81][N] (component 9*(3i+j) + (3k+l) = dP_ij/dF_kl) and
-   the trial slips dg[12][N]; returns the failed-voxel count in *fails.
+   the trial slips dg[12][N]; returns the failed-voxel count in *fails.  K is
+   the tangent as the handle's solver forms it: in FP64, or in mixed mode
+   the FP32 tangent (FP32 linear algebra at the FP64 state), widened.
    rve_debug_set_field: overwrites one committed field (F, FPINV, CHI, PCYC,
    PCYC_LIT or WCYC) from host memory, e.g. to inject a failure or given
    indicator fields. */

@@ -1248,19 +1248,9 @@ void Engine::debug_constitutive(const double* F, double dt, double* P, double* K
   a.order = order_;
   a.N = N_;
   launch_return_map(a, st_);
+  // the tangent the solver itself forms (FP32 in mixed mode)
   if (K) {
-    if (!fp64_ && !dbgK64_) dbgK64_ = alloc(81 * N_ * sizeof(double));
-    TangentArgs<double> t{};
-    t.F = F_;
-    t.Fpi0 = Fpi_c_;
-    t.chi0 = chi_c_;
-    t.dg = dg_t_;
-    t.phase = phase_;
-    t.table = table_;
-    t.K = (double*)(fp64_ ? K_ : dbgK64_);
-    t.lp = law_params(dt);
-    t.N = N_;
-    launch_tangent<double>(t, st_);
+    if (fp64_) tangent<double>(dt); else tangent<float>(dt);
   }
   RVE_HIP(hipGetLastError());
   Scalars h;
@@ -1268,13 +1258,20 @@ void Engine::debug_constitutive(const double* F, double dt, double* P, double* K
   if (fails) *fails = h.fails;
   if (P)
     RVE_HIP(hipMemcpyAsync(P, P_, 9 * N_ * sizeof(double), hipMemcpyDeviceToHost, st_));
-  if (K)
-    RVE_HIP(hipMemcpyAsync(K, fp64_ ? K_ : dbgK64_, 81 * N_ * sizeof(double),
+  std::vector<float> K32;
+  if (K && fp64_)
+    RVE_HIP(hipMemcpyAsync(K, K_, 81 * N_ * sizeof(double),
                            hipMemcpyDeviceToHost, st_));
+  if (K && !fp64_) {
+    K32.resize(81 * N_);
+    RVE_HIP(hipMemcpyAsync(K32.data(), K_, 81 * N_ * sizeof(float),
+                           hipMemcpyDeviceToHost, st_));
+  }
   if (dg)
     RVE_HIP(hipMemcpyAsync(dg, dg_t_, 12 * N_ * sizeof(double),
                            hipMemcpyDeviceToHost, st_));
   RVE_HIP(hipStreamSynchronize(st_));
+  for (size_t i = 0; i < K32.size(); ++i) K[i] = (double)K32[i];
 }
 
 void Engine::debug_set_field(int field, const double* src, size_t bytes) {

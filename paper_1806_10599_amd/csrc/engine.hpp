@@ -164,7 +164,6 @@ class Engine {
   hipStream_t own_stream_ = nullptr;
   void* dbg32_ = nullptr;
   void* dbgspec32_ = nullptr;
-  void* dbgK64_ = nullptr;
   hipGraphExec_t graph_ = nullptr;
   hipGraph_t graph_def_ = nullptr;
   KernelTimer timer_;
