@@ -357,6 +357,82 @@ def test_full_size_chosen_path_against_oracle(oracle_map):
         net.close()
 
 
+def test_learned_form_at_128_validity(oracle_map):
+    """The 128^3 workload (1000 grains, 5 % particles, discrete operator)
+    in the benchmarked configuration (mixed precision, learned start kept
+    directly, forcing mode 2, CG chunks of 8) over its first two increments
+    (the second starts from the network).  After each, the oracle's point
+    law at 16384 seeded voxels (grains and particles) from the GPU's
+    converged F and the previous committed state; ||G(P)|| <= tol ||P||
+    and F - F_bar compatible with the FP64 G of the library (compared
+    element by element with the oracle's at 128^3 in
+    test_apply_G_largest_grid_matches_oracle); <F> - F_bar within the FP32
+    bound of test_full_size_chosen_path_against_oracle."""
+    import oracle_jobs
+    from paper_1806_10599_amd.binding import Rve, WarmStartNet
+    from paper_1806_10599_amd.warmstart import trained_params
+    c = config_by_name("C5")
+    micro = c.microstructure()
+    hist = c.history()[:2]
+    N = micro.n ** 3
+    law = micro.law[micro.phase]
+    rng = np.random.default_rng(128)
+    idx = np.sort(np.concatenate([
+        rng.choice(np.nonzero(law == 0)[0], 14336, replace=False),
+        rng.choice(np.nonzero(law == 1)[0], 2048, replace=False)]))
+    chunks = np.array_split(idx, 8)
+    net = WarmStartNet()
+    net.set_params(trained_params())
+    r = Rve(micro.n, projection=c.operator, precision="mixed", warm_start=2,
+            cg_forcing=2, cg_chunk=8)
+    r.set_microstructure(micro.phase, micro.quat, micro.law, material_params())
+    r.attach_warm_start(net)
+    try:
+        prev = r.fields("F", "Fpinv", "chi")
+        drift = np.zeros(9)
+        Fb_prev = np.eye(3)
+        for k, inc in enumerate(hist):
+            print(f"C5 increment {inc['k']}", flush=True)
+            info = r.increment(inc["F_bar"], inc["dt"])
+            assert info["status"] == 0 and info["residual_rel"] <= 1e-6
+            if k > 0:
+                assert info["used_learned"] == 1
+            got = r.fields("F", "P", "dgamma", "Fpinv", "chi")
+            res = oracle_map(oracle_jobs.point_law, [
+                (got["F"][:, ix].T.reshape(-1, 3, 3),
+                 prev["Fpinv"][:, ix].T.reshape(-1, 3, 3), prev["chi"][:, ix].T,
+                 micro.phase[ix], micro.quat, micro.law, inc["dt"])
+                for ix in chunks])
+            Pref = np.concatenate([x[0] for x in res]).reshape(-1, 9)
+            dgref = np.concatenate([x[1] for x in res])
+            assert all(x[2].all() for x in res)
+            err = np.max(np.abs(got["P"][:, idx].T - Pref)) / np.max(np.abs(Pref))
+            derr = np.max(np.abs(got["dgamma"][:, idx].T - dgref)) / max(
+                np.max(np.abs(dgref)), 1e-300)
+            print(f"  point law at {idx.size} voxels: P {err:.1e}, slips {derr:.1e}")
+            assert err < 1e-9 and derr < 1e-9, (err, derr)
+            P = got["P"]
+            resid = np.linalg.norm(r.debug_apply_G(P)) / np.linalg.norm(P)
+            assert resid <= 1e-6 * (1 + 1e-6), resid
+            Fb = np.asarray(inc["F_bar"]).reshape(3, 3)
+            fl = got["F"] - Fb.reshape(9, 1)
+            comp = np.linalg.norm(r.debug_apply_G(fl) - fl) / np.linalg.norm(fl)
+            assert comp < 1e-5, comp
+            dfl = got["F"] - prev["F"] - (Fb - Fb_prev).reshape(9, 1)
+            bound = info["cg_iters_total"] * 2.0 ** -24 * 2 * np.max(np.abs(dfl))
+            step = (got["F"].mean(axis=1) - Fb.reshape(9)) - drift
+            print(f"  ||G(P)||/||P|| {resid:.2e}, incompatibility {comp:.1e}, "
+                  f"<F> - F_bar grew by {np.max(np.abs(step)):.1e} (bound {bound:.1e})")
+            assert np.max(np.abs(step)) <= bound
+            drift = got["F"].mean(axis=1) - Fb.reshape(9)
+            prev = {key: got[key] for key in ("F", "Fpinv", "chi")}
+            Fb_prev = Fb
+    finally:
+        r.attach_warm_start(None)
+        r.close()
+        net.close()
+
+
 def test_cg_forcing_reaches_the_same_equilibrium_with_fewer_cg_iterations():
     """cg_forcing = 1 solves Newton iteration k only to
     min(0.1, max(cg_tol, newton_tol / (4 r_k))), cg_forcing = 2 to
