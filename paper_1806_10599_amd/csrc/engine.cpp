@@ -509,7 +509,7 @@ void Engine::capture_graph() {
     RVE_HIP(hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal));
     for (int j = 0; j < cfg_.cg_chunk; ++j) cg_iteration<T>(j & 1);
     launch_cg_close(partial_inv_, slab_blocks(n_, sizeof(T) == 8, sched_cpb_),
-                    sc_, st_);
+                    sc_, 0, st_);
     RVE_HIP(hipStreamEndCapture(st_, &graph_def_));
   } else {
     RVE_HIP(hipGraphCreate(&graph_def_, 0));
@@ -546,7 +546,7 @@ void Engine::capture_graph() {
     for (int j = 0; j < cfg_.cg_chunk; ++j) cg_iteration_steps<T>(j & 1, step);
     step(-1, [&] {
       launch_cg_close(partial_inv_,
-                      slab_blocks(n_, sizeof(T) == 8, sched_cpb_), sc_, st_);
+                      slab_blocks(n_, sizeof(T) == 8, sched_cpb_), sc_, 0, st_);
     });
   }
   RVE_HIP(hipGraphInstantiate(&graph_, graph_def_, nullptr, nullptr, 0));
@@ -675,10 +675,12 @@ void Engine::cg_solve(int& iters, bool& breakdown, double eta) {
   // Chunks are queued one ahead of the host's convergence check: chunk k+1
   // is enqueued before the scalars of chunk k are waited for, so the device
   // never idles during that round trip.  A chunk queued after convergence
-  // does nothing (every CG kernel returns at once when `done` is set).
-  // With direct launches the length of the chunk queued ahead (even, at
-  // most cg_chunk, at least 2) follows the r.r decay seen so far, so that
-  // little is queued past the expected convergence.
+  // does nothing (every CG kernel returns at once when `done` is set), but
+  // each of its launches still costs a dispatch.  With direct launches the
+  // length of the chunk queued ahead (at most cg_chunk) follows the r.r
+  // decay seen so far: the iterations expected to remain after the chunk in
+  // flight, at least one, since the direction kernel that follows a chunk
+  // whose closing kernel stops the run applies the last x += alpha p.
   int parity = 0;
   auto enqueue = [&](int slot, int len) {
     if (cfg_.use_graph) {
@@ -691,7 +693,8 @@ void Engine::cg_solve(int& iters, bool& breakdown, double eta) {
         parity ^= 1;
       }
       launch_cg_close(partial_inv_,
-                      slab_blocks(n_, sizeof(T) == 8, sched_cpb_), sc_, st_);
+                      slab_blocks(n_, sizeof(T) == 8, sched_cpb_), sc_, parity,
+                      st_);
     }
     RVE_HIP(hipMemcpyAsync(sc_host_ + 1 + slot, sc_, sizeof(Scalars),
                            hipMemcpyDeviceToHost, st_));
@@ -711,9 +714,7 @@ void Engine::cg_solve(int& iters, bool& breakdown, double eta) {
     const double need = std::log(eta2bb / rr1) / lrho;  // iterations left
     const double after = need - inflight;
     if (!std::isfinite(after)) return full;
-    int m = (int)std::ceil(after);
-    m += m & 1;
-    return std::min(full, std::max(2, m));
+    return std::min(full, std::max(1, (int)std::ceil(after)));
   };
   Scalars h;
   int k = 0;

@@ -291,9 +291,10 @@ void launch_kp(const T* K, const T* r, const T* p_old, T* p_new, T* y,
                T* x = nullptr, double* pkp = nullptr);
 constexpr int kKpMaxBlocks = 4096;
 int kp_blocks(int64_t N);
-// the CG decision after the last update of a chunk (even chunk length)
+// the CG decision after the last update of a chunk; parity: that of the
+// iteration that would follow
 void launch_cg_close(const double* partial, int count, Scalars* sc,
-                     hipStream_t s);
+                     int parity, hipStream_t s);
 template <typename T>
 void launch_add_to_F(double* F, const T* x, int64_t n9, hipStream_t s);
 template <typename T>

@@ -220,20 +220,23 @@ __global__ __launch_bounds__(kBlock) void reduce_kernel(
   cg_scalar_update(op, tot, sc);
 }
 
-// End of a CG chunk: the decision the next direction kernel would take
-// (the chunk length is even, so the next iteration has parity 0), published
-// for the host.
+// End of a CG chunk: the decision the direction kernel of the next
+// iteration (parity p) would take, published for the host; it writes only
+// slot p, which that kernel rewrites with the same values.  When it stops
+// the run, that direction kernel (always queued after it) still applies the
+// pending x += alpha p.
 __global__ __launch_bounds__(kBlock) void cg_close_kernel(
-    const double* __restrict__ partial, int count, Scalars* __restrict__ sc) {
+    const double* __restrict__ partial, int count, Scalars* __restrict__ sc,
+    int p) {
   __shared__ double red[kBlock];
   if (sc->done) return;
-  (void)cg_beta_consume(partial, count, sc, 0, red);
+  (void)cg_beta_consume(partial, count, sc, p, red);
 }
 
 void launch_cg_close(const double* partial, int count, Scalars* sc,
-                     hipStream_t s) {
+                     int parity, hipStream_t s) {
   hipLaunchKernelGGL(cg_close_kernel, dim3(1), dim3(kBlock), 0, s, partial,
-                     count, sc);
+                     count, sc, parity);
 }
 
 void launch_reduce(int op, const double* partial, int count,
