@@ -71,12 +71,12 @@ __device__ __forceinline__ void cg_scalar_update(int op, double tot,
 
 // ---- reductions consumed by the next kernel ----------------------------------
 // Instead of a one-block reduction launch between two kernels, every block
-// of the consuming kernel sums the producer's partials itself (the same
-// fixed order as cg_sum_partials, so every block and the stand-alone
-// reduction get the same number) and takes the scalar decision locally;
-// block 0 alone publishes the result.  Iteration k (parity p = k & 1) reads
-// slot p ^ 1 and publishes slot p, so no block reads what another block of
-// the same launch writes.
+// of the consuming kernel sums the producer's partials itself in a fixed
+// order (every consumer of the same partials in the same order, so all get
+// the same number) and takes the scalar decision locally; block 0 alone
+// publishes the result.  Iteration k (parity p = k & 1) reads slot p ^ 1
+// and publishes slot p, so no block reads what another block of the same
+// launch writes.
 
 struct BetaStep {
   bool first;   // iteration 0: the direction is r itself
@@ -84,21 +84,45 @@ struct BetaStep {
   double beta;
 };
 
-// In the direction kernel of parity p (and in the chunk-closing kernel):
-// reduce the r.r partials of the last inverse pass (RED_BETA's decision),
-// unless this is iteration 0.
-__device__ __forceinline__ BetaStep cg_beta_consume(const double* partial,
-                                                    int count, Scalars* sc,
-                                                    int p, double* red) {
+// The r.r partials of the last inverse pass are summed by every wavefront
+// of the consumer on its own: lane l adds partial[l], partial[l + 64], ...
+// in index order, then a butterfly over the wavefront (both lanes of a pair
+// add the same two numbers), so every wavefront of every consuming kernel
+// gets the same bits, with no barrier or LDS.  The first PU loads of each
+// lane can be issued early (load), away from the sum (sum).
+template <int PU>
+struct RrPartials {
+  double v[PU];
+  __device__ __forceinline__ void load(const double* __restrict__ partial,
+                                       int count) {
+    const int l = threadIdx.x & 63;
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+      const int i = l + 64 * u;
+      v[u] = partial[i < count ? i : count - 1];  // clamped: no branch
+    }
+  }
+  __device__ __forceinline__ double sum(const double* __restrict__ partial,
+                                        int count) const {
+    const int l = threadIdx.x & 63;
+    double acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < PU; ++u) acc += (l + 64 * u < count) ? v[u] : 0.0;
+    for (int i = l + 64 * PU; i < count; i += 64) acc += partial[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    return acc;
+  }
+};
+
+// The CG decision of the direction kernel of parity p (RED_BETA's
+// decision) from rr, the sum of the last inverse pass's r.r partials;
+// prev = its[p ^ 1] >= 0 (not iteration 0).
+__device__ __forceinline__ BetaStep cg_beta_step(Scalars* sc, int p, int prev,
+                                                 double rr) {
   BetaStep d{false, false, 0.0};
   const int q = p ^ 1;
-  const int prev = sc->its[q];
-  if (prev < 0) {
-    d.first = true;
-    return d;
-  }
   const int k = prev + 1;
-  const double rr = cg_sum_partials(partial, count, red);
   const double rr_prev = sc->rrs[q];
   const bool conv = rr <= sc->eta2bb;
   d.stop = conv || k >= sc->max_iters || !isfinite(rr);
@@ -119,6 +143,19 @@ __device__ __forceinline__ BetaStep cg_beta_consume(const double* partial,
     }
   }
   return d;
+}
+
+// In the direction kernel of parity p (and in the chunk-closing kernel and
+// the fused forward pass): reduce the r.r partials of the last inverse pass
+// and take the decision, unless this is iteration 0.
+__device__ __forceinline__ BetaStep cg_beta_consume(const double* partial,
+                                                    int count, Scalars* sc,
+                                                    int p) {
+  const int prev = sc->its[p ^ 1];
+  if (prev < 0) return BetaStep{true, false, 0.0};
+  RrPartials<8> rp;
+  rp.load(partial, count);
+  return cg_beta_step(sc, p, prev, rp.sum(partial, count));
 }
 
 // In block 0 of the forward pass of parity p: reduce the p.(K:p) partials of

@@ -104,7 +104,7 @@ Engine::Engine(const rve_config& cfg) : cfg_(cfg) {
   partial_inv_ = (double*)alloc(9 * n_ * sizeof(double));
   partial_red_ = (double*)alloc(kRedBlocks * sizeof(double));
   // the direction kernel's partials, or pass A's when it is folded in
-  partial_kp_ = (double*)alloc(std::max(kKpMaxBlocks, 9 * n_) * sizeof(double));
+  partial_kp_ = (double*)alloc(std::max(kp_blocks(N_), 9 * n_) * sizeof(double));
   psum_ = (double*)alloc(9 * n_ * sizeof(double));
   psq_ = (double*)alloc(9 * n_ * sizeof(double));
   sc_ = (Scalars*)alloc(sizeof(Scalars));

@@ -289,8 +289,7 @@ void launch_kp(const T* K, const T* r, const T* p_old, T* p_new, T* y,
                Scalars* sc, int64_t N, hipStream_t s,
                const double* partial = nullptr, int count = 0, int parity = 0,
                T* x = nullptr, double* pkp = nullptr);
-constexpr int kKpMaxBlocks = 4096;
-int kp_blocks(int64_t N);
+int kp_blocks(int64_t N);  // one voxel per thread
 // the CG decision after the last update of a chunk; parity: that of the
 // iteration that would follow
 void launch_cg_close(const double* partial, int count, Scalars* sc,

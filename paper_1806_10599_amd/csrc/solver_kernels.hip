@@ -64,24 +64,48 @@ void launch_cg_init(const double* r64, T* r, T* x, double* partial, int nblk,
 
 // CG direction and material product (Sec. 2.1, Eqs. 15-16): per voxel
 // p = r (first iteration) or r + beta p_old, then y = K : p
-// (y_c = sum_d K[9c + d] p_d); streams K once, coalesced per component.
-// With partial != null (a CG run) the kernel first reduces the r.r partials
-// of the last inverse pass itself (cg_beta_consume) and, from the second
-// iteration on, applies the previous iteration's x += alpha p_old (its alpha
-// was published by that iteration's forward pass) while p_old streams by;
-// it returns at once when the previous iteration halted the run, and applies
-// only the pending x update when this one stops it.  Without partial it
-// takes first, beta and alpha from the scalars (kernel timing).  With pkp
-// != null each block writes its partial of p . (K : p).
-template <typename T>
+// (y_c = sum_d K[9c + d] p_d); one voxel per thread, K streamed once,
+// coalesced per component.  With partial != null (a CG run) the kernel
+// takes the CG decision itself from the r.r partials of the last inverse
+// pass and, from the second iteration on, applies the previous iteration's
+// x += alpha p_old (its alpha was published by that iteration's forward
+// pass); it returns at once when the previous iteration halted the run, and
+// applies only the pending x update when this one stops it.  The decision
+// waits for the partials while the voxel's r, p_old and first KP entries of
+// K are already in flight: their loads are issued first, unconditionally
+// (clamped indices), so that the partial sum's latency hides behind them.
+// Without partial it takes first, beta and alpha from the scalars (kernel
+// timing).  With pkp != null each block writes its partial of p . (K : p).
+template <typename T, int PU>
 __global__ __launch_bounds__(kBlock) void kp_kernel(
     const T* __restrict__ K, const T* __restrict__ r,
     const T* __restrict__ p_old, T* __restrict__ p_new, T* __restrict__ y,
     T* __restrict__ x, Scalars* __restrict__ sc, int64_t N,
     const double* __restrict__ partial, int count,
     double* __restrict__ pkp, int parity) {
+  // FP32: the voxel's r, p_old and first KP entries of K loaded before the
+  // decision, the rest of K right after it (about 120 VGPRs, four waves per
+  // SIMD); FP64: everything after it, K read inside the product (holding
+  // the data across the decision would halve the occupancy)
+  constexpr bool kEarly = sizeof(T) == 4;
+  constexpr int KP = kEarly ? 36 : 0;
   __shared__ double red[kBlock];
-  bool first, upd;
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t vl = v < N ? v : N - 1;
+  RrPartials<kEarly ? PU : 1> rp;
+  if (partial && kEarly) rp.load(partial, count);
+  T kv[81], rv[9], pv[9];
+  auto load_vectors = [&] {
+#pragma unroll
+    for (int d = 0; d < 9; ++d) {
+      rv[d] = r[d * N + vl];
+      pv[d] = p_old[d * N + vl];
+    }
+  };
+  if constexpr (kEarly) load_vectors();
+#pragma unroll
+  for (int i = 0; i < KP; ++i) kv[i] = K[i * N + vl];
+  bool first, upd, stop = false;
   T beta, alpha_prev;
   if (partial) {
     // every flag read here was written by an earlier launch: block 0 of this
@@ -91,20 +115,17 @@ __global__ __launch_bounds__(kBlock) void kp_kernel(
       if (blockIdx.x == 0 && threadIdx.x == 0) sc->halt[parity] = 1;
       return;
     }
-    const BetaStep d = cg_beta_consume(partial, count, sc, parity, red);
-    first = d.first;
+    const int prev = sc->its[q];
+    first = prev < 0;
+    BetaStep d{first, false, 0.0};
+    if (!first) {
+      if constexpr (!kEarly) rp.load(partial, count);
+      d = cg_beta_step(sc, parity, prev, rp.sum(partial, count));
+    }
     if (first && sc->done) return;  // b = 0: nothing to solve
     upd = !first && x != nullptr;
     alpha_prev = T(sc->alphas[q]);
-    if (d.stop) {
-      for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-           upd && v < N; v += (int64_t)gridDim.x * blockDim.x) {
-#pragma unroll
-        for (int dd = 0; dd < 9; ++dd)
-          x[dd * N + v] += alpha_prev * p_old[dd * N + v];
-      }
-      return;
-    }
+    stop = d.stop;
     beta = T(d.beta);
   } else {
     if (sc->done) return;
@@ -113,18 +134,25 @@ __global__ __launch_bounds__(kBlock) void kp_kernel(
     upd = x != nullptr;
     alpha_prev = T(sc->alpha);
   }
+  if constexpr (!kEarly) load_vectors();
   double acc = 0.0;
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < N;
-       v += (int64_t)gridDim.x * blockDim.x) {
+  if (v < N) {
+    if (stop) {
+#pragma unroll
+      for (int d = 0; d < 9; ++d)
+        if (upd) x[d * N + v] += alpha_prev * pv[d];
+      return;
+    }
+    if constexpr (kEarly) {
+#pragma unroll
+      for (int i = KP; i < 81; ++i) kv[i] = K[i * N + v];
+    }
     T pd[9];
 #pragma unroll
     for (int d = 0; d < 9; ++d) {
-      T val = r[d * N + v];
-      if (!first || upd) {
-        const T po = p_old[d * N + v];
-        if (!first) val += beta * po;
-        if (upd) x[d * N + v] += alpha_prev * po;
-      }
+      T val = rv[d];
+      if (!first) val += beta * pv[d];
+      if (upd) x[d * N + v] += alpha_prev * pv[d];
       pd[d] = val;
       p_new[d * N + v] = val;
     }
@@ -132,28 +160,34 @@ __global__ __launch_bounds__(kBlock) void kp_kernel(
     for (int c = 0; c < 9; ++c) {
       T acc_c = T(0);
 #pragma unroll
-      for (int d = 0; d < 9; ++d) acc_c += K[(9 * c + d) * N + v] * pd[d];
+      for (int d = 0; d < 9; ++d)
+        acc_c += (kEarly ? kv[9 * c + d] : K[(9 * c + d) * N + v]) * pd[d];
       y[c * N + v] = acc_c;
       acc += double(pd[c]) * double(acc_c);
     }
   }
+  if (stop) return;
   if (pkp) {
     const double t = block_reduce(acc, red);
     if (threadIdx.x == 0) pkp[blockIdx.x] = t;
   }
 }
 
-int kp_blocks(int64_t N) {
-  const int64_t g = (N + kBlock - 1) / kBlock;
-  return (int)(g < kKpMaxBlocks ? g : kKpMaxBlocks);
-}
+int kp_blocks(int64_t N) { return (int)((N + kBlock - 1) / kBlock); }
 
 template <typename T>
 void launch_kp(const T* K, const T* r, const T* p_old, T* p_new, T* y,
                Scalars* sc, int64_t N, hipStream_t s, const double* partial,
                int count, int parity, T* x, double* pkp) {
-  launch((kp_kernel<T>), dim3((unsigned)kp_blocks(N)), dim3(kBlock), 0, s, K,
-         r, p_old, p_new, y, x, sc, N, partial, count, pkp, parity);
+  // early partial loads per lane: all of them up to 576 (64^3 with one
+  // component per slab block) or 1152 partials
+  const dim3 grid((unsigned)kp_blocks(N));
+  if (count <= 9 * 64)
+    launch((kp_kernel<T, 9>), grid, dim3(kBlock), 0, s, K, r, p_old, p_new, y,
+           x, sc, N, partial, count, pkp, parity);
+  else
+    launch((kp_kernel<T, 18>), grid, dim3(kBlock), 0, s, K, r, p_old, p_new,
+           y, x, sc, N, partial, count, pkp, parity);
 }
 
 template void launch_kp<float>(const float*, const float*, const float*,
@@ -228,9 +262,8 @@ __global__ __launch_bounds__(kBlock) void reduce_kernel(
 __global__ __launch_bounds__(kBlock) void cg_close_kernel(
     const double* __restrict__ partial, int count, Scalars* __restrict__ sc,
     int p) {
-  __shared__ double red[kBlock];
   if (sc->done) return;
-  (void)cg_beta_consume(partial, count, sc, p, red);
+  (void)cg_beta_consume(partial, count, sc, p);
 }
 
 void launch_cg_close(const double* partial, int count, Scalars* sc,

@@ -530,7 +530,7 @@ __global__ __launch_bounds__(kBlock) void slab_fwd_cg_kernel(SlabFwdArgs<T> a) {
     if (blockIdx.x == 0 && threadIdx.x == 0) sc->halt[a.parity] = 1;
     return;
   }
-  const BetaStep d = cg_beta_consume(a.pinv, a.pinv_count, sc, a.parity, red);
+  const BetaStep d = cg_beta_consume(a.pinv, a.pinv_count, sc, a.parity);
   if (d.first && sc->done) return;  // b = 0: nothing to solve
   const KpStep<T> st{d.first, T(d.beta), !d.first && a.x != nullptr,
                      T(sc->alphas[q])};
