@@ -80,25 +80,72 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 template <typename T>
 constexpr int kStage = sizeof(T) == 4 ? 8 : 1;
 
-template <typename T, int N>
-__device__ __forceinline__ void load_twiddles(cplx<T>* tw,
-                                              const cplx<T>* __restrict__ g) {
-  for (int i = threadIdx.x; i < N; i += blockDim.x) tw[i] = g[i];
+// The twiddles of a body.  DEFER (an FP32 body whose data loads are one
+// chunk per thread): loaded into a register at its start (one per thread,
+// N <= kBlock) and written to LDS once the data loads are in flight, so
+// that their latency overlaps that of the data; otherwise written to LDS
+// at once (kept in a register across a loop of chunks, the value would be
+// parked in scratch memory).
+template <typename T>
+constexpr bool kDeferTw(int per) {
+  return sizeof(T) == 4 && per <= kStage<T>;
+}
+template <typename T, int N, bool DEFER>
+struct TwiddleStage {
+  static_assert(N <= kBlock, "one twiddle per thread");
+  cplx<T> v;
+  __device__ __forceinline__ void load(const cplx<T>* __restrict__ g,
+                                       cplx<T>* tw) {
+    if constexpr (DEFER)
+      v = g[(int)threadIdx.x < N ? (int)threadIdx.x : N - 1];  // no branch
+    else if ((int)threadIdx.x < N)
+      tw[threadIdx.x] = g[threadIdx.x];
+  }
+  __device__ __forceinline__ void store(cplx<T>* tw) const {
+    if constexpr (DEFER)
+      if ((int)threadIdx.x < N) tw[threadIdx.x] = v;
+  }
+};
+
+// A run's stop flag, read when a body starts and consulted once its first
+// data loads are issued (a stopped CG run's passes return without work).
+// The relaxed atomic read makes it a vector load issued ahead of the data
+// loads, whose in-order completion lets the check wait for it alone; a
+// scalar load would be waited for together with the kernel arguments,
+// before any data load is issued.
+__device__ __forceinline__ int32_t stop_flag(const Scalars* gate) {
+  return gate ? __hip_atomic_load(&gate->done, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT)
+              : 0;
+}
+// The flag's first use: an empty statement that takes the register, so
+// that the compiler neither tests the flag (and waits for its load) before
+// this point nor moves the data loads above it.
+__device__ __forceinline__ bool stopped_now(int32_t f) {
+  asm volatile("" : "+v"(f));
+  return f != 0;
 }
 
 // ------------------------------------------------------------------ pass A
 // lb: logical block within this RVE's pass-A grid
+// gate: the run's scalars when the pass must return at once on a stopped
+// run (returns false then); with SRC_KP the check precedes all work
 template <typename T, int N, int CPB, int SRC>
-__device__ __forceinline__ void slab_fwd_body(const SlabFwdArgs<T>& a, int lb,
+__device__ __forceinline__ bool slab_fwd_body(const SlabFwdArgs<T>& a, int lb,
                                               cplx<T>* lds, cplx<T>* tw,
                                               double* red,
-                                              const KpStep<T>& st) {
+                                              const KpStep<T>& st,
+                                              const Scalars* gate = nullptr) {
   constexpr int H = N / 2;
   constexpr int NG = 9 / CPB;
   const int64_t cs = a.cs;
   const int x = lb / NG;
   const int grp = lb - x * NG;
-  load_twiddles<T, N>(tw, a.tw);
+  const int32_t stopped = stop_flag(gate);
+  if (SRC == SRC_KP && stopped_now(stopped)) return false;
+  constexpr int PER0 = (H * N + kBlock - 1) / kBlock;
+  TwiddleStage<T, N, SRC == SRC_FIELD && kDeferTw<T>(PER0)> tws;
+  tws.load(a.tw, tw);
   double ss[CPB], s1[CPB];
 #pragma unroll
   for (int q = 0; q < CPB; ++q) ss[q] = s1[q] = 0.0;
@@ -145,6 +192,8 @@ __device__ __forceinline__ void slab_fwd_body(const SlabFwdArgs<T>& a, int lb,
       }
     }
   }
+  tws.store(tw);
+  if (stopped_now(stopped)) return false;
   double kacc = 0.0;  // p . (K:p) over this block's components
   for (int t = threadIdx.x; SRC == SRC_KP && t < H * N; t += blockDim.x) {
     const int yp = t / N, z = t - (t / N) * N;
@@ -242,12 +291,14 @@ __device__ __forceinline__ void slab_fwd_body(const SlabFwdArgs<T>& a, int lb,
       }
     }
   }
+  return true;
 }
 
 // ------------------------------------------------------------------ pass B
 template <typename T, int N, int TT>
-__device__ __forceinline__ void pencil_body(const PencilArgs<T>& a, int lb,
-                                            cplx<T>* lds, cplx<T>* tw) {
+__device__ __forceinline__ bool pencil_body(const PencilArgs<T>& a, int lb,
+                                            cplx<T>* lds, cplx<T>* tw,
+                                            const Scalars* gate = nullptr) {
   constexpr int H = N / 2;
   constexpr int TP = TT + 1;  // LDS pitch of a kx row (complex)
   // component planes of the pencil start TT slots apart in the LDS banks, so
@@ -260,8 +311,10 @@ __device__ __forceinline__ void pencil_body(const PencilArgs<T>& a, int lb,
   const int ky = rest / NTILE;
   const int kz0 = tile * TT;
   const int ncol = (H - kz0) < TT ? (H - kz0) : TT;
+  const int32_t stopped = stop_flag(gate);
 
   if (ky == H) {  // Nyquist ky: the projection is zero there
+    if (stopped_now(stopped)) return false;
     for (int t = threadIdx.x; t < 3 * N * TT; t += blockDim.x) {
       const int j = t / (N * TT);
       const int rem = t - j * N * TT;
@@ -269,11 +322,13 @@ __device__ __forceinline__ void pencil_body(const PencilArgs<T>& a, int lb,
       if (tt < ncol)
         a.spec[((size_t)((3 * i + j) * N + kx) * N + ky) * H + kz0 + tt] = {T(0), T(0)};
     }
-    return;
+    return true;
   }
-  load_twiddles<T, N>(tw, a.tw);
+  constexpr int PER0 = (3 * N * TT + kBlock - 1) / kBlock;
+  TwiddleStage<T, N, kDeferTw<T>(PER0)> tws;
+  tws.load(a.tw, tw);
   {
-    constexpr int PER = (3 * N * TT + kBlock - 1) / kBlock;
+    constexpr int PER = PER0;
     constexpr int CH = PER < kStage<T> ? PER : kStage<T>;
     for (int c0 = 0; c0 < PER; c0 += CH) {
       cplx<T> val[CH];
@@ -301,6 +356,8 @@ __device__ __forceinline__ void pencil_body(const PencilArgs<T>& a, int lb,
       }
     }
   }
+  tws.store(tw);
+  if (stopped_now(stopped)) return false;
   __syncthreads();
   auto pm = [](int line, int kx) {
     const int j = line / TT;
@@ -338,22 +395,54 @@ __device__ __forceinline__ void pencil_body(const PencilArgs<T>& a, int lb,
       a.spec[((size_t)((3 * i + j) * N + kx) * N + ky) * H + kz0 + tt] =
           lds[j * CPS + kx * TP + tt];
   }
+  return true;
 }
 
 // ------------------------------------------------------------------ pass C
 template <typename T, typename TO, int N, int CPB, int DST>
-__device__ __forceinline__ void slab_inv_body(const SlabInvArgs<T, TO>& a,
+__device__ __forceinline__ bool slab_inv_body(const SlabInvArgs<T, TO>& a,
                                               int lb, cplx<T>* lds,
-                                              cplx<T>* tw, double* red) {
+                                              cplx<T>* tw, double* red,
+                                              const Scalars* gate = nullptr) {
   constexpr int H = N / 2;
   constexpr int NG = 9 / CPB;
   const int64_t cs = a.cs;
   const int x = lb / NG;
   const int grp = lb - x * NG;
-  load_twiddles<T, N>(tw, a.tw);
+  const int32_t stopped = stop_flag(gate);
+  constexpr int PER0 = (CPB * N * H + kBlock - 1) / kBlock;
+  TwiddleStage<T, N, kDeferTw<T>(PER0)> tws;
+  tws.load(a.tw, tw);
+  // the real-space operand of the output step (r of a CG run, or the dot
+  // product's field): when it is one chunk per thread of one component,
+  // its loads are issued now and their latency hides behind the transforms
+  // (three components would hold 48 more registers across them)
+  constexpr int PER2 = (H * N + kBlock - 1) / kBlock;
+  constexpr int CH2 = PER2 < kStage<T> ? PER2 : kStage<T>;
+  constexpr bool kSrc = DST == DST_DOT || DST == DST_CG;
+  constexpr bool kEarly = kSrc && PER2 <= CH2 && CPB == 1;
+  T pve[kEarly ? CH2 : 1][CPB][2];
+  auto load_src = [&](int c0, auto& pv) {
+    const T* src = (DST == DST_CG) ? a.rio : a.pdot;
+#pragma unroll
+    for (int u = 0; u < CH2; ++u) {
+      const int t = threadIdx.x + (c0 + u) * kBlock;
+      if (c0 + u < PER2 && t < H * N) {
+        const int yp = t / N, z = t - (t / N) * N;
+#pragma unroll
+        for (int q = 0; q < CPB; ++q)
+#pragma unroll
+          for (int hh = 0; hh < 2; ++hh) {
+            const int64_t v = ((int64_t)x * N + yp + hh * H) * N + z;
+            pv[u][q][hh] = src[(grp * CPB + q) * cs + v];
+          }
+      }
+    }
+  };
+  if constexpr (kEarly) load_src(0, pve);
   const ColMap<N> cm;
   {
-    constexpr int PER = (CPB * N * H + kBlock - 1) / kBlock;
+    constexpr int PER = PER0;
     constexpr int CH = PER < kStage<T> ? PER : kStage<T>;
     for (int c0 = 0; c0 < PER; c0 += CH) {
       cplx<T> val[CH];
@@ -380,6 +469,10 @@ __device__ __forceinline__ void slab_inv_body(const SlabInvArgs<T, TO>& a,
       }
     }
   }
+  tws.store(tw);
+  if (stopped_now(stopped)) return false;
+  T alpha = T(0);
+  if constexpr (DST == DST_CG) alpha = T(a.sc->alphas[a.parity]);
   __syncthreads();
   fft_lines<N, +1>(lds, tw, CPB * H, ColMap<N>());
 
@@ -403,32 +496,14 @@ __device__ __forceinline__ void slab_inv_body(const SlabInvArgs<T, TO>& a,
   fft_lines<N, +1>(lds, tw, CPB * H, RowMap<N>());
 
   double acc = 0.0;
-  T alpha = T(0);
-  if constexpr (DST == DST_CG) alpha = T(a.sc->alphas[a.parity]);
   {
     // the p (or r) loads of a chunk are issued together (same order of the
     // sum)
-    constexpr int PER = (H * N + kBlock - 1) / kBlock;
-    constexpr int CH = PER < kStage<T> ? PER : kStage<T>;
+    constexpr int PER = PER2;
+    constexpr int CH = CH2;
     for (int c0 = 0; c0 < PER; c0 += CH) {
-      T pv[CH][CPB][2];
-      if constexpr (DST == DST_DOT || DST == DST_CG) {
-        const T* src = (DST == DST_CG) ? a.rio : a.pdot;
-#pragma unroll
-        for (int u = 0; u < CH; ++u) {
-          const int t = threadIdx.x + (c0 + u) * kBlock;
-          if (c0 + u < PER && t < H * N) {
-            const int yp = t / N, z = t - (t / N) * N;
-#pragma unroll
-            for (int q = 0; q < CPB; ++q)
-#pragma unroll
-              for (int hh = 0; hh < 2; ++hh) {
-                const int64_t v = ((int64_t)x * N + yp + hh * H) * N + z;
-                pv[u][q][hh] = src[(grp * CPB + q) * cs + v];
-              }
-          }
-        }
-      }
+      T pvl[CH2][CPB][2];
+      if constexpr (kSrc && !kEarly) load_src(c0, pvl);
 #pragma unroll
       for (int u = 0; u < CH; ++u) {
         const int t = threadIdx.x + (c0 + u) * kBlock;
@@ -442,13 +517,18 @@ __device__ __forceinline__ void slab_inv_body(const SlabInvArgs<T, TO>& a,
           for (int hh = 0; hh < 2; ++hh) {
             const int64_t v = ((int64_t)x * N + yp + hh * H) * N + z;
             const T val = hh ? zz.y : zz.x;
+            T src_v = T(0);
+            if constexpr (kEarly)
+              src_v = pve[u][q][hh];
+            else if constexpr (kSrc)
+              src_v = pvl[u][q][hh];
             if constexpr (DST == DST_CG) {
-              const T rn = pv[u][q][hh] - alpha * val;
+              const T rn = src_v - alpha * val;
               a.rio[c * cs + v] = rn;
               acc += double(rn) * double(rn);
             } else if constexpr (DST == DST_DOT) {
               a.out[c * cs + v] = TO(val);
-              acc += double(pv[u][q][hh]) * double(val);
+              acc += double(src_v) * double(val);
             } else {
               a.out[c * cs + v] = TO(val);
               acc += double(val) * double(val);
@@ -462,6 +542,7 @@ __device__ __forceinline__ void slab_inv_body(const SlabInvArgs<T, TO>& a,
     double tot = block_sum(acc, red);
     if (threadIdx.x == 0) a.partial[lb] = tot;
   }
+  return true;
 }
 
 template <typename T, int N>
@@ -493,15 +574,16 @@ __global__ __launch_bounds__(kBlock) void slab_fwd_kernel(SlabFwdArgs<T> a) {
   // done comes from an earlier launch, except after a breakdown that block
   // 0 of this launch publishes at its end (cg_alpha_publish): blocks that
   // read done before that write and go on only fill the spectrum, which
-  // the inverse pass of a stopped run never reads (it returns on done)
-  if (a.sc && a.sc->done) return;
+  // the inverse pass of a stopped run never reads (it returns on done).
+  // The body reads it and returns once its loads are issued.
   KpStep<T> st = kp_step_of<T>(SRC == SRC_KP ? a.sc : nullptr);
   if (SRC == SRC_KP && a.x) {  // timing of the folded pass: x += alpha p_old
     st.upd = true;
     st.alpha = T(a.sc->alpha);
   }
-  slab_fwd_body<T, N, CPB, SRC>(a, xcd_remap(blockIdx.x, gridDim.x), lds, tw,
-                                red, st);
+  if (!slab_fwd_body<T, N, CPB, SRC>(a, xcd_remap(blockIdx.x, gridDim.x), lds,
+                                     tw, red, st, a.sc))
+    return;
   if (a.pkp && blockIdx.x == 0)
     cg_alpha_publish(a.pkp, a.pkp_count, a.scw, a.parity, red);
 }
@@ -558,8 +640,9 @@ __global__ __launch_bounds__(kBlock) void pencil_proj_kernel(PencilArgs<T> a) {
   __shared__ cplx<T> lds[3 * (N * (TT + 1) + TT)];
   __shared__ cplx<T> tw[N];
   __shared__ double red[kBlock];
-  if (a.sc && a.sc->done) return;
-  pencil_body<T, N, TT>(a, xcd_remap(blockIdx.x, gridDim.x), lds, tw);
+  if (!pencil_body<T, N, TT>(a, xcd_remap(blockIdx.x, gridDim.x), lds, tw,
+                             a.sc))
+    return;
   // fused CG run: alpha = r.r / p.(K:p) from pass A's partials (a breakdown
   // sets done, which the pass-B blocks that already started ignore: their
   // spectrum is not used, pass C returns)
@@ -572,9 +655,8 @@ __global__ __launch_bounds__(kBlock) void slab_inv_kernel(SlabInvArgs<T, TO> a) 
   __shared__ cplx<T> lds[CPB * SlabGeom<N>::PLANE];
   __shared__ cplx<T> tw[N];
   __shared__ double red[kBlock];
-  if (a.sc && a.sc->done) return;
   slab_inv_body<T, TO, N, CPB, DST>(a, xcd_remap(blockIdx.x, gridDim.x), lds,
-                                    tw, red);
+                                    tw, red, a.sc);
 }
 
 // three component planes per slab block fit the LDS budget of one block
