@@ -69,6 +69,24 @@ __device__ __forceinline__ void cg_scalar_update(int op, double tot,
   }
 }
 
+// Copies the scalars into the host's coherent pinned buffer pub (plain
+// vector stores, which reach host memory uncached and are complete when
+// the kernel is; the host reads them after waiting for an event recorded
+// behind the kernel).  Called by every thread of the block: the barrier
+// orders the block's own writes to sc before the copy, which reads them
+// back from L2 rather than from the scalar cache.
+__device__ __forceinline__ void publish_scalars(const Scalars* sc,
+                                                Scalars* pub) {
+  static_assert(sizeof(Scalars) % 8 == 0, "Scalars copied in 8-byte words");
+  constexpr int W = (int)(sizeof(Scalars) / 8);
+  __syncthreads();
+  const unsigned long long* src = reinterpret_cast<const unsigned long long*>(sc);
+  unsigned long long* dst = reinterpret_cast<unsigned long long*>(pub);
+  for (int i = threadIdx.x; i < W; i += blockDim.x)
+    dst[i] = __hip_atomic_load(src + i, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // ---- reductions consumed by the next kernel ----------------------------------
 // Instead of a one-block reduction launch between two kernels, every block
 // of the consuming kernel sums the producer's partials itself in a fixed

@@ -117,7 +117,11 @@ Engine::Engine(const rve_config& cfg) : cfg_(cfg) {
   order_ = (int32_t*)alloc(N_ * sizeof(int32_t));
   table_ = nullptr;
   // slot 0: synchronous reads; slots 1, 2: the CG chunks' look-ahead reads
-  RVE_HIP(hipHostMalloc((void**)&sc_host_, 3 * sizeof(Scalars), hipHostMallocDefault));
+  // coherent: the chunk-closing and residual kernels write their slots
+  // directly (uncached), no copy kernel behind them
+  RVE_HIP(hipHostMalloc((void**)&sc_host_, 3 * sizeof(Scalars),
+                        hipHostMallocCoherent | hipHostMallocMapped));
+  RVE_HIP(hipHostGetDevicePointer((void**)&sc_pub_, sc_host_, 0));
   RVE_HIP(hipEventCreateWithFlags(&chunk_ev_[0], hipEventDisableTiming));
   RVE_HIP(hipEventCreateWithFlags(&chunk_ev_[1], hipEventDisableTiming));
 
@@ -344,7 +348,7 @@ LawParams Engine::law_params(double dt) const {
   return lp;
 }
 
-void Engine::residual_passes(const double* P) {
+void Engine::residual_passes(const double* P, Scalars* pub) {
   SpectralLaunch<double> L;
   L.src = SRC_FIELD;
   L.in_field = P;
@@ -358,7 +362,7 @@ void Engine::residual_passes(const double* P) {
   L.partial_inv = partial_inv_;
   launch_G<double>(n_, L, st_);
   launch_reduce(RED_RESID, partial_inv_, nslab64_, psum_, psq_, n_,
-                1.0 / (double)N_, sc_, sc_->pbar, st_);
+                1.0 / (double)N_, sc_, sc_->pbar, st_, pub);
 }
 
 // constitutive update at F_ with the committed state, then r64 = G(P)
@@ -396,11 +400,11 @@ int Engine::evaluate(const double* dg_start, double dt, double& rel,
     if (a.iters) launch_rm_count(rm_iters_, rm_evals_, N_, rm_stats_, st_);
   }
   timer_.begin_span(6, st_);
-  residual_passes(P_);
+  residual_passes(P_, sc_pub_);  // the reduction publishes into slot 0
   timer_.end_span(6, st_);
   RVE_HIP(hipGetLastError());
-  Scalars h;
-  read_scalars(h);
+  RVE_HIP(hipStreamSynchronize(st_));
+  const Scalars h = *sc_host_;
   timer_.flush();
   res = std::sqrt(h.res2);
   pn = std::sqrt(h.P2);
@@ -692,12 +696,14 @@ void Engine::cg_solve(int& iters, bool& breakdown, double eta) {
         cg_iteration<T>(parity);
         parity ^= 1;
       }
+      // the closing kernel copies the scalars into the slot itself
       launch_cg_close(partial_inv_,
                       slab_blocks(n_, sizeof(T) == 8, sched_cpb_), sc_, parity,
-                      st_);
+                      st_, sc_pub_ + 1 + slot);
     }
-    RVE_HIP(hipMemcpyAsync(sc_host_ + 1 + slot, sc_, sizeof(Scalars),
-                           hipMemcpyDeviceToHost, st_));
+    if (cfg_.use_graph)
+      RVE_HIP(hipMemcpyAsync(sc_host_ + 1 + slot, sc_, sizeof(Scalars),
+                             hipMemcpyDeviceToHost, st_));
     RVE_HIP(hipEventRecord(chunk_ev_[slot], st_));
     RVE_HIP(hipGetLastError());
   };

@@ -95,7 +95,7 @@ class Engine {
   void autotune();
   void read_scalars(Scalars& h);
   LawParams law_params(double dt) const;
-  void residual_passes(const double* P);
+  void residual_passes(const double* P, Scalars* pub = nullptr);
   int evaluate(const double* dg_start, double dt, double& rel,
                double& res, double& pn);
   void commit(double dt);
@@ -131,9 +131,12 @@ class Engine {
   void* Kp_;     // K : p of the current CG direction
   void* spec_;        // complex T
   void* spec64_;      // complex double (aliases spec_ in fp64 mode)
-  double *partial_inv_, *partial_red_, *partial_kp_, *psum_, *psq_, *pbar_;
+  double *partial_inv_, *partial_red_, *partial_kp_, *psum_, *psq_;
   Scalars* sc_;
-  Scalars* sc_host_ = nullptr;          // pinned: [0] sync reads, [1..2] chunks
+  // coherent pinned: [0] sync reads, [1..2] chunks; sc_pub_: its device
+  // address, where the closing and residual kernels write
+  Scalars* sc_host_ = nullptr;
+  Scalars* sc_pub_ = nullptr;
   hipEvent_t chunk_ev_[2] = {nullptr, nullptr};
   int32_t* phase_;
   int32_t* order_;                 // return-mapping work order (crystal first)

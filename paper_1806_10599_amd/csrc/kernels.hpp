@@ -291,18 +291,21 @@ void launch_kp(const T* K, const T* r, const T* p_old, T* p_new, T* y,
                T* x = nullptr, double* pkp = nullptr);
 int kp_blocks(int64_t N);  // one voxel per thread
 // the CG decision after the last update of a chunk; parity: that of the
-// iteration that would follow
+// iteration that would follow; pub (coherent pinned host memory, or null):
+// where the kernel also copies the scalars for the host
 void launch_cg_close(const double* partial, int count, Scalars* sc,
-                     int parity, hipStream_t s);
+                     int parity, hipStream_t s, Scalars* pub = nullptr);
 template <typename T>
 void launch_add_to_F(double* F, const T* x, int64_t n9, hipStream_t s);
 template <typename T>
 void launch_convert(const double* in, T* out, int64_t n, hipStream_t s);
 
 enum { RED_INIT = 0, RED_ALPHA = 1, RED_BETA = 2, RED_RESID = 3 };
+// pub: as for launch_cg_close (RED_RESID only)
 void launch_reduce(int op, const double* partial, int count,
                    const double* psum, const double* psq, int nslab_sums,
-                   double invN3, Scalars* sc, double* pbar, hipStream_t s);
+                   double invN3, Scalars* sc, double* pbar, hipStream_t s,
+                   Scalars* pub = nullptr);
 void launch_commit(const CommitArgs& a, hipStream_t s);
 void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 void launch_fill_f64(double* p, double v, int64_t n, hipStream_t s);

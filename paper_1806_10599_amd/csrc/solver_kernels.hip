@@ -230,7 +230,8 @@ void launch_convert(const double* in, T* out, int64_t n, hipStream_t s) {
 __global__ __launch_bounds__(kBlock) void reduce_kernel(
     int op, const double* __restrict__ partial, int count,
     const double* __restrict__ psum, const double* __restrict__ psq, int nss,
-    double invN3, Scalars* __restrict__ sc, double* __restrict__ pbar) {
+    double invN3, Scalars* __restrict__ sc, double* __restrict__ pbar,
+    Scalars* pub) {
   __shared__ double red[kBlock];
   if ((op == RED_ALPHA || op == RED_BETA) && sc->done) return;
   const double tot = cg_sum_partials(partial, count, red);
@@ -248,6 +249,7 @@ __global__ __launch_bounds__(kBlock) void reduce_kernel(
       sc->res2 = tot;
       sc->P2 = P2;
     }
+    if (pub) publish_scalars(sc, pub);
     return;
   }
   if (threadIdx.x != 0) return;
@@ -261,22 +263,23 @@ __global__ __launch_bounds__(kBlock) void reduce_kernel(
 // pending x += alpha p.
 __global__ __launch_bounds__(kBlock) void cg_close_kernel(
     const double* __restrict__ partial, int count, Scalars* __restrict__ sc,
-    int p) {
-  if (sc->done) return;
-  (void)cg_beta_consume(partial, count, sc, p);
+    int p, Scalars* pub) {
+  if (!sc->done) (void)cg_beta_consume(partial, count, sc, p);
+  if (pub) publish_scalars(sc, pub);
 }
 
 void launch_cg_close(const double* partial, int count, Scalars* sc,
-                     int parity, hipStream_t s) {
+                     int parity, hipStream_t s, Scalars* pub) {
   hipLaunchKernelGGL(cg_close_kernel, dim3(1), dim3(kBlock), 0, s, partial,
-                     count, sc, parity);
+                     count, sc, parity, pub);
 }
 
 void launch_reduce(int op, const double* partial, int count,
                    const double* psum, const double* psq, int nss,
-                   double invN3, Scalars* sc, double* pbar, hipStream_t s) {
+                   double invN3, Scalars* sc, double* pbar, hipStream_t s,
+                   Scalars* pub) {
   hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kBlock), 0, s, op, partial,
-                     count, psum, psq, nss, invN3, sc, pbar);
+                     count, psum, psq, nss, invN3, sc, pbar, pub);
 }
 
 __global__ void init_scalars_kernel(Scalars* sc, int max_iters, double eta) {
