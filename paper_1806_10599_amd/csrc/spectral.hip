@@ -76,9 +76,12 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return block_sum_fixed(v, red);
 }
 
-// items whose global loads are issued together before their LDS stores
-template <typename T>
-constexpr int kStage = sizeof(T) == 4 ? 8 : 1;
+// items whose global loads are issued together before their LDS stores:
+// FP32 eight, or 32 on grids of 128 (whose slab planes leave two blocks per
+// CU, so that the registers are there), which makes each pass's loads one
+// chunk in flight at once; FP64 one
+template <typename T, int N>
+constexpr int kStage = sizeof(T) == 4 ? (N >= 128 ? 32 : 8) : 1;
 
 // The twiddles of a body.  DEFER (an FP32 body whose data loads are one
 // chunk per thread): loaded into a register at its start (one per thread,
@@ -86,9 +89,9 @@ constexpr int kStage = sizeof(T) == 4 ? 8 : 1;
 // that their latency overlaps that of the data; otherwise written to LDS
 // at once (kept in a register across a loop of chunks, the value would be
 // parked in scratch memory).
-template <typename T>
+template <typename T, int N>
 constexpr bool kDeferTw(int per) {
-  return sizeof(T) == 4 && per <= kStage<T>;
+  return sizeof(T) == 4 && per <= kStage<T, N>;
 }
 template <typename T, int N, bool DEFER>
 struct TwiddleStage {
@@ -144,7 +147,7 @@ __device__ __forceinline__ bool slab_fwd_body(const SlabFwdArgs<T>& a, int lb,
   const int32_t stopped = stop_flag(gate);
   if (SRC == SRC_KP && stopped_now(stopped)) return false;
   constexpr int PER0 = (H * N + kBlock - 1) / kBlock;
-  TwiddleStage<T, N, SRC == SRC_FIELD && kDeferTw<T>(PER0)> tws;
+  TwiddleStage<T, N, SRC == SRC_FIELD && kDeferTw<T, N>(PER0)> tws;
   tws.load(a.tw, tw);
   double ss[CPB], s1[CPB];
 #pragma unroll
@@ -156,7 +159,7 @@ __device__ __forceinline__ bool slab_fwd_body(const SlabFwdArgs<T>& a, int lb,
     // the loads of a chunk of items are issued together, then the chunk is
     // written to LDS (same per-thread order of the sums as item by item)
     constexpr int PER = (H * N + kBlock - 1) / kBlock;
-    constexpr int CH = PER < kStage<T> ? PER : kStage<T>;
+    constexpr int CH = PER < kStage<T, N> ? PER : kStage<T, N>;
     for (int c0 = 0; c0 < PER; c0 += CH) {
       T val[CH][2][CPB];
 #pragma unroll
@@ -325,11 +328,11 @@ __device__ __forceinline__ bool pencil_body(const PencilArgs<T>& a, int lb,
     return true;
   }
   constexpr int PER0 = (3 * N * TT + kBlock - 1) / kBlock;
-  TwiddleStage<T, N, kDeferTw<T>(PER0)> tws;
+  TwiddleStage<T, N, kDeferTw<T, N>(PER0)> tws;
   tws.load(a.tw, tw);
   {
     constexpr int PER = PER0;
-    constexpr int CH = PER < kStage<T> ? PER : kStage<T>;
+    constexpr int CH = PER < kStage<T, N> ? PER : kStage<T, N>;
     for (int c0 = 0; c0 < PER; c0 += CH) {
       cplx<T> val[CH];
 #pragma unroll
@@ -411,14 +414,14 @@ __device__ __forceinline__ bool slab_inv_body(const SlabInvArgs<T, TO>& a,
   const int grp = lb - x * NG;
   const int32_t stopped = stop_flag(gate);
   constexpr int PER0 = (CPB * N * H + kBlock - 1) / kBlock;
-  TwiddleStage<T, N, kDeferTw<T>(PER0)> tws;
+  TwiddleStage<T, N, kDeferTw<T, N>(PER0)> tws;
   tws.load(a.tw, tw);
   // the real-space operand of the output step (r of a CG run, or the dot
   // product's field): when it is one chunk per thread of one component,
   // its loads are issued now and their latency hides behind the transforms
   // (three components would hold 48 more registers across them)
   constexpr int PER2 = (H * N + kBlock - 1) / kBlock;
-  constexpr int CH2 = PER2 < kStage<T> ? PER2 : kStage<T>;
+  constexpr int CH2 = PER2 < kStage<T, N> ? PER2 : kStage<T, N>;
   constexpr bool kSrc = DST == DST_DOT || DST == DST_CG;
   constexpr bool kEarly = kSrc && PER2 <= CH2 && CPB == 1;
   T pve[kEarly ? CH2 : 1][CPB][2];
@@ -443,7 +446,7 @@ __device__ __forceinline__ bool slab_inv_body(const SlabInvArgs<T, TO>& a,
   const ColMap<N> cm;
   {
     constexpr int PER = PER0;
-    constexpr int CH = PER < kStage<T> ? PER : kStage<T>;
+    constexpr int CH = PER < kStage<T, N> ? PER : kStage<T, N>;
     for (int c0 = 0; c0 < PER; c0 += CH) {
       cplx<T> val[CH];
 #pragma unroll
