@@ -91,10 +91,11 @@ RM_FLOPS = {"eval64": 1206, "eval32": 72, "step64": 60, "step32": 2350,
 # of four CG kernels costs several per cent of the throughput).
 LIVE_CLASSES = ("return_map", "tangent", "residual_fp64", "matvec_kp")
 # the K:p kernel (one launch per CG iteration) is timed on one launch in
-# seven in the timed region: an event pair on every launch cost about 8 % of
-# the throughput; seven is prime to the CG chunk length of eight, so the
-# sample walks through every position of a chunk
-LIVE_CG_STRIDE = 7
+# 29 in the timed region (about 120 timed launches over the 40 timed
+# increments): an event pair on every launch cost about 8 % of the
+# throughput, one in seven about 1 %; 29 is prime to every CG chunk length
+# (1 to 8), so the sample walks through every position of a chunk
+LIVE_CG_STRIDE = 29
 # learned warm start: a candidate well below the homogeneous predictor's
 # last residual is kept without evaluating the homogeneous predictor
 WARM_MODE = 2
@@ -113,6 +114,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-live", action="store_true",
                     help="no live kernel timing (no events in the timed region)")
+    ap.add_argument("--live-cg-stride", type=int, default=LIVE_CG_STRIDE,
+                    help="time one K:p launch in this many in the timed region")
     ap.add_argument("--start", type=int, default=None,
                     help="first timed increment (0-based; default: the last "
                          "--steps increments of the history are timed)")
@@ -981,8 +984,9 @@ def live_report(live, rmc, N, cg_total, sample=None, fused=False, seen=None):
                     launches=allk[k], launches_timed=launches[k])
 
     def alu():
-        # FP32 work is charged at the FP64 rate: this build disables the
-        # packed FP32 instructions that double the FP32 vector peak
+        # FP32 work is charged at the FP64 rate: the library is compiled
+        # without the packed FP32 instructions that double the FP32 vector
+        # peak
         per_launch = rm_flops / launches["return_map"]
         ach = per_launch / (avg_ms["return_map"] * 1e-3) / 1e12
         return dict(kernel="return_map", bound="alu", achieved=round(ach, 3),
@@ -1053,13 +1057,16 @@ def progress(msg):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; "
-                          "multi-GPU runs are not part of it (see the design "
+        print(json.dumps({"error": "the benchmark runs on exactly one GPU; "
+                          "multi-GPU runs are not implemented (see the design "
                           "notes for how the path would shard)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
-    global FORCING
+    global FORCING, LIVE_CG_STRIDE
     FORCING = args.forcing_mode
+    if args.live_cg_stride < 1:
+        raise SystemExit("--live-cg-stride must be at least 1")
+    LIVE_CG_STRIDE = args.live_cg_stride
     import torch
     from synthetic import config_by_name
     cfg = config_by_name(args.config)
