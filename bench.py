@@ -70,9 +70,9 @@ def pass_bytes(fused):
 
 
 def live_classes(fused):
-    """Kernel classes timed live in the timed region: the once-per-Newton
-    kernels and the K:p kernel (pass A when K:p is folded into it)."""
-    return LIVE_CLASSES[:3] + (("matvec_pass_a",) if fused else ("matvec_kp",))
+    """Kernel classes timed live in the timed region: the return mapping and
+    the K:p kernel (pass A when K:p is folded into it)."""
+    return LIVE_CLASSES[:1] + (("matvec_pass_a",) if fused else ("matvec_kp",))
 # algorithmic flops of the return mapping (add, mul, div, sqrt and each
 # elementary function count 1, a fused multiply-add 2; counted once per voxel
 # from the algorithm, not from the instruction stream), FP64 and FP32 apart:
@@ -84,12 +84,15 @@ def live_classes(fused):
 # P) and per particle voxel
 RM_FLOPS = {"eval64": 1206, "eval32": 72, "step64": 60, "step32": 2350,
             "crystal64": 825, "particle64": 90}
-# kernel classes timed live in the timed region (one event pair per launch):
-# the K:p direction kernel (the dominant kernel of the CG iteration) and the
-# once-per-Newton-step kernels.  The three FFT passes are timed live over
-# the sample increments before the timed region (one event pair per launch
-# of four CG kernels costs several per cent of the throughput).
-LIVE_CLASSES = ("return_map", "tangent", "residual_fp64", "matvec_kp")
+# kernel classes timed live in the timed region: the K:p direction kernel
+# (the dominant kernel, on a sample of its launches) and the return mapping
+# (every launch: its ALU roofline needs the local Newton steps of the same
+# launches).  Every class, the tangent, the FP64 residual and the three FFT
+# passes included, is timed on every launch over the sample increments
+# before the timed region: an event pair costs 12-18 us of the stream's
+# time, and timing the tangent and the residual in the timed region as well
+# cost 1.2 % of the throughput.
+LIVE_CLASSES = ("return_map", "matvec_kp")
 # the K:p kernel (one launch per CG iteration) is timed on one launch in
 # 29 in the timed region (about 120 timed launches over the 40 timed
 # increments): an event pair on every launch cost about 8 % of the
@@ -1042,6 +1045,8 @@ def live_report(live, rmc, N, cg_total, sample=None, fused=False, seen=None):
     if share is not None:
         rep["kernel_time_share_sample"] = dict(
             increments=sample["increments"], share=share)
+        rep["kernel_avg_ms_sample"] = {
+            k: round(ms / n, 5) for k, (ms, n) in sample["timing"].items() if n}
     for k in pb:
         if launches[k] and k != dom:
             rep[k + "_roofline"] = hbm(k)
